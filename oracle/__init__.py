@@ -1,0 +1,19 @@
+"""FP64 CPU oracle of the IBDL hot path, restated from the thesis.
+
+TEST INFRASTRUCTURE ONLY.  This package is the checker, not the product: only
+the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import it.  It shares no code with the HIP library; the two meet only in the
+seeded input generators.
+
+Modules: delta (regularized delta kernels), ib (grid, S, S*), grid
+(finite-difference / spectral operators and inverses), ibdl (boundary
+operators A, right-hand sides, grid recovery, dense assembly), gmres
+(textbook GMRES), norms (error norms).
+
+Parity status: every function is pinned by tests/test_oracle_*.py against
+closed forms, kernel identities, adjointness, real-space stencils, PDE
+residuals and the iteration counts the thesis prints.  The 3-D operator has
+no printed thesis value; it is pinned by closed-form convergence only.
+"""
+from . import delta, gmres, grid, ib, ibdl, norms  # noqa: F401
+from .ibdl import Setup  # noqa: F401
