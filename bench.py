@@ -1,0 +1,209 @@
+#!/usr/bin/env python
+"""IBDL throughput on one MI355X: operator applies/s and GMRES solves/s at 1e-8, with the
+roofline of the dominant kernel and the FP64 CPU oracle timed on the host beside it.
+
+A step is one whole IBDL solve through the C ABI (ibdl_solve): right-hand side
+b = U_b - S* L^-1 g~, GMRES to ||b - A q|| / ||b|| <= 1e-8 (every iteration one operator apply:
+spread -> FFT passes with the fused multiplier -> interpolation), the double-precision true
+residual and the grid recovery u = L^-1 (g~ - S~ q).  Inputs are resident on the GPU before the
+timed region starts.
+
+Default workload: 3-D screened Poisson (kappa = 10) on a 256^3 periodic grid, sphere r = 0.3
+with 73,962 icosphere markers, Peskin 4-point kernel, finite differences, float grid work with
+double-precision Krylov (the mixed path).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "IBDL operator applies/sec + GMRES solves/sec at 1e-8 residual; % HBM peak"
+
+
+def workload(name):
+    from workloads import problems as P
+    if name == "sphere256":
+        return P.cfg3_sphere(256, 86), "mixed", (
+            "3-D IBDL screened Poisson kappa=10, 256^3 periodic grid, sphere r=0.3, 73962 icosphere markers, "
+            "Peskin 4-point, FD2, float grid/spread/FFT + double GMRES, tol 1e-8")
+    if name == "star1024":
+        return P.cfg2_star_poisson(1024, 4096), "fp64", (
+            "2-D IBDL Poisson Dirichlet, 1024^2 grid, star r=0.3(1+0.2cos5t), 4096 markers, Peskin 4-point, FD2, "
+            "double precision, tol 1e-8")
+    if name == "circle64":
+        return P.cfg1_circle_cos4(), "fp64", (
+            "2-D IBDL screened Poisson kappa=1, 64^2 grid, circle r=0.25, 200 markers, cosine 4-point, FD2, "
+            "double precision, tol 1e-10")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def stage_bytes(spec, prec, pr):
+    """Algorithmic HBM bytes per launch of each stage of one operator apply."""
+    t = 4 if prec == "mixed" else 8
+    ntot = pr.grid_points
+    nxh = spec.n[0] // 2 + 1
+    nspec = ntot // spec.n[0] * nxh
+    R, C = ntot * t, nspec * 2 * t
+    scalar_fd = spec.pde != "stokes" and spec.disc == "fd2"
+    c = 1 if scalar_fd else (5 if spec.pde == "stokes" else spec.dim + (1 if spec.eta > 0 else 0))
+    o = pr.nq
+    marker = spec.n_ib * (12 + 24 + 8 * pr.nq + 8 * spec.dim + 8)
+    taps = 4 ** spec.dim
+    b = {
+        "spread": c * R + marker,
+        "fft_x_fwd": c * (R + C),
+        "fused_last_axis": (c + o) * C,
+        "fft_x_inv": o * (C + R),
+        "interp": spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2),
+    }
+    if spec.dim == 3:
+        b["fft_y_fwd"] = 2 * c * C
+        b["fft_y_inv"] = 2 * o * C
+    return b
+
+
+def cpu_baseline(spec, budget_s=20.0):
+    """Time the FP64 numpy oracle's operator apply on this host (bounded sample)."""
+    import numpy as np
+    import oracle
+    from workloads.problems import random_density
+    o = oracle.Setup.from_spec(spec)
+    q = random_density(spec, seed=0)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        o.apply(q)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s / 2 or reps >= 5:
+            break
+    cpu = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": reps / el, "unit": "applies/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} FP64 operator applies of the same workload by the numpy oracle "
+                      f"(single-threaded numpy/pocketfft) in {el:.1f} s on {cpu} ({os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sphere256", choices=["sphere256", "star1024", "circle64"])
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the IBDL library has no multi-GPU path (see the design notes); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2210_07403_amd as ibdl
+    from workloads.problems import random_density
+
+    spec, prec, desc = workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m = spec.markers
+    print(f"# workload {args.workload}: {desc}", file=sys.stderr, flush=True)
+    pr = ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, m.nrm, m.ds, pde=spec.pde, kappa=spec.kappa,
+                      mu=spec.mu, bc=spec.bc, eta=spec.eta, kernel=spec.kernel, disc=spec.disc, precision=prec,
+                      device=dev)
+    gdt = torch.float32 if prec == "mixed" else torch.float64
+    data = torch.as_tensor(np.asarray(spec.data, dtype=np.float64), device=dev)
+    g = torch.as_tensor(spec.g, device=dev).to(gdt).reshape((pr.nq,) + pr.grid_shape) if spec.g is not None else None
+    tol = spec.tol
+
+    for _ in range(args.warmup):
+        pr.solve(data, g, tol=tol, maxit=100)
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} solves)", file=sys.stderr, flush=True)
+
+    iters, relres = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, info = pr.solve(data, g, tol=tol, maxit=100)
+        iters.append(info.iters)
+        relres.append(info.true_relres_fp64)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(f"# timed {args.steps} solves in {el:.3f} s, iterations {iters}", file=sys.stderr, flush=True)
+
+    # operator applies alone, and per-stage HIP-event timing on the handle's stream
+    q = torch.as_tensor(random_density(spec, seed=0), device=dev)
+    for _ in range(5):
+        pr.apply(q)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(pr.stream)
+    for _ in range(args.apply_reps):
+        pr.apply(q)
+    ev1.record(pr.stream)
+    ev1.synchronize()
+    apply_ms = ev0.elapsed_time(ev1) / args.apply_reps
+    pr.set_timing(True)
+    for _ in range(args.apply_reps):
+        pr.apply(q)
+    stages = pr.timing()
+    pr.set_timing(False)
+    sb = stage_bytes(spec, prec, pr)
+    per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items() if v[1]}
+    dom = max(per, key=per.get)
+    ach = sb[dom] / (per[dom] * 1e-3) / 1e9
+    stage_report = {k: {"ms": round(per[k], 5), "GB": round(sb.get(k, 0) / 1e9, 5),
+                        "GB_s": round(sb.get(k, 0) / (per[k] * 1e-3) / 1e9, 1) if per[k] > 0 else None}
+                    for k in per}
+    apply_bytes = sum(sb.values())
+
+    total_applies = int(sum(iters))
+    out = {
+        "metric": METRIC,
+        "value": round(total_applies / el, 2),
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 grid + f64 Krylov" if prec == "mixed" else "f64",
+        "data": "synthetic (seeded geometry and manufactured boundary data; no dataset)",
+        "config": {"workload": desc, "grid": list(spec.n), "n_ib": spec.n_ib, "n_aug": pr.n_aug,
+                   "tol": tol, "precision": prec},
+        "solves_per_sec": round(args.steps / el, 3),
+        "gmres_iterations": iters,
+        "true_relres_fp64": max(relres),
+        "apply_only_per_sec": round(1e3 / apply_ms, 2),
+        "apply_ms": round(apply_ms, 5),
+        "apply_effective_GB_s": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1),
+        "apply_frac_hbm_peak": round(apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "stages": stage_report,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    pr.close()
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,157 @@
+/*
+ * ibdl.h -- C ABI of the MI355X (gfx950) Immersed Boundary Double Layer library.
+ *
+ * The library applies and inverts the IBDL boundary operator of
+ * B. J. Leathers, "The Immersed Boundary Double Layer (IBDL) Method" (2022, arXiv 2210.07403):
+ *
+ *   scalar Dirichlet   A Q = -S* L^-1 S~ Q + Q/2                 (Sec. 5.3.2, eq. ibdl schur again)
+ *   scalar Neumann     A U = -S* L^-1 S~ U - U/2                 (Sec. 5.2, eq. Neumann saddle point)
+ *   completed scalar   + eta S in the dipole spread, + u_bar and a border row (Sec. 5.3.3)
+ *   Brinkman / Stokes  A Q = S* u[Q] + Q/2 (+ u_bar),             (Sec. 6.3.2 eq. brink ibdl eqn,
+ *                      u[Q] = -grad D0^-1 S(Q.n) - L^-1 P (eta S Q + mu div S A)    Sec. 6.3.3)
+ *
+ * with S the spread (Sec. 2.2.2, eq. spread operator again2), S* the interpolation
+ * (eq. interpolation again), S~ Q = div(S(Q n)) (Sec. 5.3.1, eq. Stilde), L = Delta - kappa^2
+ * (scalar) or mu Delta - k^2 (Stokes) on a periodic grid, D0^-1 the mean-zero inverse Laplacian
+ * (Sec. 2.2.4) and P = I - grad D0^-1 div (Sec. 2.3.2).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller (e.g. a PyTorch tensor's
+ *     data pointer).  The handle owns only its internal workspaces.
+ *   - Grid arrays are row-major [component][z][y][x] (x fastest; 2-D: [component][y][x]).  Their
+ *     element type is double under IBDL_FP64 and float under IBDL_MIXED.
+ *   - Marker arrays are double: X and nrm are [n_ib][dim]; ds is [n_ib].  Densities and boundary
+ *     data are double [n_ib][nq] (nq = 1 scalar, nq = dim Stokes) followed, in the unknown vector
+ *     only, by u_bar ([nq]) when the method carries it: n_aug = n_ib*nq + (has_ubar ? nq : 0),
+ *     has_ubar = (eta > 0 && kappa == 0).
+ *   - nrm is the unit normal pointing out of the PDE domain Omega (Sec. 5.1.1); ds are the
+ *     quadrature weights (arclength in 2-D, area in 3-D).
+ *   - All calls are asynchronous on cfg.stream (a hipStream_t; NULL = the default stream), except
+ *     ibdl_create / ibdl_set_markers (which synchronise once) and ibdl_solve, which synchronises to
+ *     run the Krylov iteration and to fill ibdl_info_t.
+ *   - One host thread per handle at a time.  Calls that overlap on one handle race.
+ *   - Errors: a negative status; outputs are then unspecified and ibdl_last_error() describes the
+ *     failure.  Arguments are validated on the host; device data are not inspected.
+ */
+#ifndef IBDL_H
+#define IBDL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibdl_s* ibdl_t;
+
+typedef enum {
+  IBDL_OK = 0,
+  IBDL_NOT_CONVERGED = 1,      /* warning: maxit reached; outputs hold the best iterate      */
+  IBDL_ERR_ARG = -1,           /* invalid argument (null pointer, size, enum value)          */
+  IBDL_ERR_UNSUPPORTED = -2,   /* valid but not implemented (e.g. 3-D Stokes, N not 2^k)     */
+  IBDL_ERR_NOMEM = -3,         /* device allocation failed                                   */
+  IBDL_ERR_HIP = -4,           /* a HIP runtime call failed                                  */
+  IBDL_ERR_NONFINITE = -5,     /* non-finite value met on the host side                      */
+  IBDL_ERR_STATE = -6          /* call not valid in the handle's state                       */
+} ibdl_status_t;
+
+enum { IBDL_PDE_SCREENED = 0, IBDL_PDE_POISSON = 1, IBDL_PDE_STOKES = 2 };
+enum { IBDL_BC_DIRICHLET = 0, IBDL_BC_NEUMANN = 1 };
+enum { IBDL_K_PESKIN4 = 0, IBDL_K_COS4 = 1, IBDL_K_BSPLINE6 = 2 };
+enum { IBDL_DISC_FD2 = 0, IBDL_DISC_SPECTRAL = 1 };
+enum { IBDL_FP64 = 0, IBDL_MIXED = 1 };
+
+typedef struct {
+  int32_t dim;        /* 2 or 3                                                             */
+  int64_t n[3];       /* grid points per axis (x, y, z): powers of two in [16, 1024]        */
+  double  L[3];       /* box lengths; h = L[d]/n[d] must be equal on every axis (Sec. 2.2.1) */
+  double  origin[3];  /* nodes at origin + j*h                                              */
+  int32_t pde;        /* IBDL_PDE_SCREENED (L = Delta - kappa^2, kappa > 0),
+                         IBDL_PDE_POISSON (L = Delta, mean-zero inverse),
+                         IBDL_PDE_STOKES (L = mu Delta - kappa^2; kappa = 0 is Stokes; 2-D only) */
+  double  kappa;      /* screening constant, or the Brinkman k for Stokes                   */
+  double  mu;         /* viscosity (Stokes); ignored for scalar problems                    */
+  int32_t bc;         /* IBDL_BC_DIRICHLET or IBDL_BC_NEUMANN (scalar, eta = 0 only)        */
+  double  eta;        /* 0 = plain IBDL; > 0 = completed IBDL (Sec. 5.3.3, 6.1.3)           */
+  int32_t kernel;     /* IBDL_K_PESKIN4 (Sec. 2.2.2), IBDL_K_COS4, IBDL_K_BSPLINE6 (Sec. 6.3.1;
+                         spectral discretisation only)                                      */
+  int32_t disc;       /* IBDL_DISC_FD2 (5/7-point Laplacian, centred differences) or
+                         IBDL_DISC_SPECTRAL (Fourier; derivative symbol 0 at Nyquist)       */
+  int32_t precision;  /* IBDL_FP64, or IBDL_MIXED: float grid, spread, FFT and interpolation;
+                         double marker data and Krylov iteration                            */
+  void*   stream;     /* hipStream_t                                                        */
+} ibdl_config_t;
+
+typedef struct {
+  int32_t iters;              /* Arnoldi steps taken                                          */
+  int32_t status;             /* IBDL_OK or IBDL_NOT_CONVERGED                                */
+  double  krylov_relres;      /* GMRES residual estimate ||b - A q|| / ||b|| at exit          */
+  double  true_relres_fp64;   /* ||b - A q|| / ||b|| recomputed with a double-precision apply */
+  double* history;            /* optional HOST array: relative residual per iteration, or NULL */
+  int32_t history_cap;        /* capacity of history                                          */
+} ibdl_info_t;
+
+/* Create a handle for one problem (grid, PDE, markers).  X, nrm, ds: device double arrays as
+ * above; they are copied, so the caller may free them afterwards.  Builds the per-marker stencil
+ * data and the tile bins used by the spread.  Returns IBDL_ERR_UNSUPPORTED for combinations not
+ * implemented (3-D Stokes, Neumann with Stokes or eta > 0, B-spline with FD2). */
+ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* X,
+                          const double* nrm, const double* ds, ibdl_t* out);
+
+/* Replace the markers (same n_ib) and rebuild stencils and bins. */
+ibdl_status_t ibdl_set_markers(ibdl_t h, const double* X, const double* nrm, const double* ds);
+
+/* Release the handle and its workspaces (synchronises its stream first). */
+ibdl_status_t ibdl_destroy(ibdl_t h);
+
+/* Spread S (Sec. 2.2.2): grid[c][x] = sum_i f[i][c] delta_h(x - X_i) ds_i, c < nc <= 5.
+ * f: device double [n_ib][nc]; grid: device [nc][grid] of the handle's grid type. */
+ibdl_status_t ibdl_spread(ibdl_t h, const double* f, int32_t nc, void* grid);
+
+/* Interpolation S* (Sec. 2.2.2): f[i][c] = sum_x grid[c][x] delta_h(x - X_i) h^dim, c < nc <= 5. */
+ibdl_status_t ibdl_interp(ibdl_t h, const void* grid, int32_t nc, double* f);
+
+/* Periodic grid solve: scalar u = L^-1 rhs (mean-zero branch when L has a null space);
+ * Stokes u = L^-1 P rhs with rhs, u of dim components.  rhs and u may alias. */
+ibdl_status_t ibdl_grid_solve(ibdl_t h, const void* rhs, void* u);
+
+/* y = A q for the handle's operator; q, y: device double [n_aug] (must not alias). */
+ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y);
+
+/* Solve A q = b with GMRES (x0 = 0, no restart, double-precision Arnoldi with classical
+ * Gram-Schmidt applied twice, Givens rotations) to ||b - A q|| / ||b|| <= tol, maxit <= 200.
+ *   data: Dirichlet U_b or Neumann V_b, device double [n_ib][nq];
+ *   g_grid: extended forcing g~ on the grid ([nq][grid], grid type) or NULL for zero;
+ *   q: output density (device double [n_aug]); u_grid: output grid solution ([nq][grid], grid
+ *   type, Sec. 5.3.2 and 5.3.3 grid recovery) or NULL; info: optional host struct.
+ * The right-hand side is b = U_b - S* L^-1 g~ (Dirichlet; Stokes with P), b = S* L^-1 (S V_b - g~)
+ * (Neumann), plus h^dim sum(g~) in the border rows.  Returns IBDL_NOT_CONVERGED if maxit is
+ * reached (outputs hold the last iterate). */
+ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, double tol,
+                         int32_t maxit, double* q, void* u_grid, ibdl_info_t* info);
+
+/* Sizes of the handle: n_aug (unknowns), grid points per component, grid components of the
+ * solution (nq).  Any output pointer may be NULL. */
+ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq);
+
+/* Profiling: enable (1) or disable (0) per-stage timing with HIP events recorded on the handle's
+ * stream around every kernel stage (resets the accumulated times).  Costs a few microseconds per
+ * stage; leave it off outside profiling. */
+ibdl_status_t ibdl_set_timing(ibdl_t h, int32_t enable);
+
+/* Accumulated milliseconds and launch counts per stage since ibdl_set_timing(h, 1), stage ids:
+ * 0 spread, 1 x-axis forward FFT, 2 y-axis forward FFT (3-D), 3 fused last-axis FFT + multiplier,
+ * 4 y-axis inverse FFT (3-D), 5 x-axis inverse FFT, 6 interpolation, 7 Krylov vectors, 8 other.
+ * ms and count are host arrays of cap entries (cap >= 9 returns every stage).  Synchronises on the
+ * recorded events. */
+ibdl_status_t ibdl_get_timing(ibdl_t h, double* ms, int64_t* count, int32_t cap);
+
+/* Message of the last failure on this handle (or of the last failed ibdl_create when h is NULL).
+ * The string stays valid until the next call on the handle. */
+const char* ibdl_last_error(ibdl_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBDL_H */

@@ -1,0 +1,175 @@
+"""MI355X-native Immersed Boundary Double Layer (IBDL) operator library.
+
+Python surface over the C ABI of include/ibdl.h.  PyTorch supplies device memory and the
+stream; the spread, FFT passes, Fourier multipliers, interpolation and Krylov vectors all run
+in the HIP library (libibdl.so, built in-tree for gfx950).  There is no CPU fallback: without
+the library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+__all__ = ["Problem", "SolveInfo", "IBDLError"]
+
+IBDLError = B.IBDLError
+
+
+def _dev_f64(a, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    status: int
+    krylov_relres: float
+    true_relres_fp64: float
+    history: list
+
+
+class Problem:
+    """One IBDL problem on a periodic grid: ibdl_create / ibdl_destroy around a handle.
+
+    X, nrm: (n_ib, dim) marker positions and unit normals pointing out of Omega; ds: (n_ib,)
+    quadrature weights.  Grid tensors are (ncomp, [nz,] ny, nx) of float64 (precision="fp64") or
+    float32 (precision="mixed").
+    """
+
+    def __init__(self, dim, n, L, origin, X, nrm, ds, pde="screened", kappa=0.0, mu=1.0, bc="dirichlet",
+                 eta=0.0, kernel="peskin4", disc="fd2", precision="fp64", device="cuda"):
+        lib = B.load()
+        self.device = torch.device(device)
+        self.dim = int(dim)
+        self.n = tuple(int(v) for v in n)
+        self.precision = precision
+        self.grid_dtype = torch.float64 if precision == "fp64" else torch.float32
+        cfg = B.Config()
+        cfg.dim = self.dim
+        for d in range(3):
+            cfg.n[d] = self.n[d] if d < self.dim else 1
+            cfg.L[d] = float(L[d]) if d < self.dim else 1.0
+            cfg.origin[d] = float(origin[d]) if d < self.dim else 0.0
+        cfg.pde = B.PDE[pde]
+        cfg.kappa = float(kappa)
+        cfg.mu = float(mu)
+        cfg.bc = B.BC[bc]
+        cfg.eta = float(eta)
+        cfg.kernel = B.KERNEL[kernel]
+        cfg.disc = B.DISC[disc]
+        cfg.precision = B.PRECISION[precision]
+        self.stream = torch.cuda.current_stream(self.device)
+        cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        self._cfg = cfg
+        Xd, Nd, Dd = _dev_f64(X, self.device), _dev_f64(nrm, self.device), _dev_f64(ds, self.device)
+        self.n_ib = int(Dd.shape[0])
+        self._h = ctypes.c_void_p()
+        B.check(lib.ibdl_create(ctypes.byref(cfg), self.n_ib, Xd.data_ptr(), Nd.data_ptr(), Dd.data_ptr(),
+                                ctypes.byref(self._h)), None)
+        n_aug, pts, nq = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        B.check(lib.ibdl_query(self._h, ctypes.byref(n_aug), ctypes.byref(pts), ctypes.byref(nq)), self._h)
+        self.n_aug, self.grid_points, self.nq = int(n_aug.value), int(pts.value), int(nq.value)
+        self.grid_shape = tuple(reversed(self.n))
+
+    # ---------------------------------------------------------------- helpers
+    def _grid(self, ncomp):
+        return torch.empty((ncomp,) + self.grid_shape, dtype=self.grid_dtype, device=self.device)
+
+    def _as_grid(self, g, ncomp):
+        t = g if isinstance(g, torch.Tensor) else torch.as_tensor(np.asarray(g))
+        t = t.to(device=self.device, dtype=self.grid_dtype).contiguous()
+        if t.numel() != ncomp * self.grid_points:
+            raise ValueError(f"grid array must hold {ncomp} x {self.grid_shape}")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            B.load().ibdl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- operations
+    def set_markers(self, X, nrm, ds):
+        Xd, Nd, Dd = _dev_f64(X, self.device), _dev_f64(nrm, self.device), _dev_f64(ds, self.device)
+        B.check(B.load().ibdl_set_markers(self._h, Xd.data_ptr(), Nd.data_ptr(), Dd.data_ptr()), self._h)
+
+    def spread(self, f):
+        """S: marker values (n_ib,) or (n_ib, nc) -> grid (nc, ...)."""
+        ft = _dev_f64(f, self.device)
+        nc = 1 if ft.dim() == 1 else int(ft.shape[1])
+        out = self._grid(nc)
+        B.check(B.load().ibdl_spread(self._h, ft.data_ptr(), nc, out.data_ptr()), self._h)
+        return out
+
+    def interp(self, grid, nc=None):
+        """S*: grid (nc, ...) -> marker values (n_ib, nc)."""
+        nc = nc or (grid.shape[0] if grid.dim() == self.dim + 1 else 1)
+        g = self._as_grid(grid, nc)
+        out = torch.empty((self.n_ib, nc), dtype=torch.float64, device=self.device)
+        B.check(B.load().ibdl_interp(self._h, g.data_ptr(), nc, out.data_ptr()), self._h)
+        return out
+
+    def grid_solve(self, rhs):
+        """L^-1 rhs (scalar) or L^-1 P rhs (Stokes)."""
+        g = self._as_grid(rhs, self.nq)
+        out = self._grid(self.nq)
+        B.check(B.load().ibdl_grid_solve(self._h, g.data_ptr(), out.data_ptr()), self._h)
+        return out
+
+    def apply(self, q):
+        qt = _dev_f64(q, self.device).reshape(-1)
+        if qt.numel() != self.n_aug:
+            raise ValueError(f"q must have n_aug = {self.n_aug} entries")
+        y = torch.empty_like(qt)
+        B.check(B.load().ibdl_apply(self._h, qt.data_ptr(), y.data_ptr()), self._h)
+        return y
+
+    def set_timing(self, enable=True):
+        B.check(B.load().ibdl_set_timing(self._h, 1 if enable else 0), self._h)
+
+    def timing(self):
+        """{stage: (total_ms, launches)} accumulated since set_timing(True)."""
+        ms = (ctypes.c_double * 9)()
+        cnt = (ctypes.c_int64 * 9)()
+        B.check(B.load().ibdl_get_timing(self._h, ms, cnt, 9), self._h)
+        return {B.STAGES[i]: (ms[i], cnt[i]) for i in range(9)}
+
+    def solve(self, data, g=None, tol=1e-8, maxit=100, want_u=True):
+        """GMRES solve of the IBDL system; returns (q, u or None, SolveInfo)."""
+        dt = _dev_f64(data, self.device).reshape(-1)
+        if dt.numel() != self.n_ib * self.nq:
+            raise ValueError("data must have n_ib * nq entries")
+        gt = self._as_grid(g, self.nq) if g is not None else None
+        q = torch.empty(self.n_aug, dtype=torch.float64, device=self.device)
+        u = self._grid(self.nq) if want_u else None
+        hist = (ctypes.c_double * 256)()
+        info = B.Info()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = 256
+        st = B.load().ibdl_solve(self._h, dt.data_ptr(), gt.data_ptr() if gt is not None else None, float(tol),
+                                 int(maxit), q.data_ptr(), u.data_ptr() if u is not None else None,
+                                 ctypes.byref(info))
+        B.check(st, self._h)
+        res = SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64,
+                        [hist[i] for i in range(min(info.iters, 256))])
+        if u is not None and self.nq == 1:
+            u = u[0]
+        return q, u, res

@@ -1,0 +1,740 @@
+// Host runtime and C ABI: handle lifecycle, per-precision grid workspaces, the IBDL operator
+// pipelines (spread -> FFT passes with the fused multiplier -> interpolation), right-hand sides,
+// grid recovery and the device-resident GMRES.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ibdl.h"
+#include "kernels.h"
+
+using namespace ibdl;
+
+namespace {
+
+template <typename T> struct GridWork {
+  cplx<T>* tw[3] = {nullptr, nullptr, nullptr};
+  T* sig[3] = {nullptr, nullptr, nullptr};
+  T* kt[3] = {nullptr, nullptr, nullptr};
+  T* real = nullptr;
+  cplx<T>* spec = nullptr;
+  int nfields = 0;
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct ibdl_s {
+  ibdl_config_t cfg{};
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  double h = 0;
+  int64_t ntot = 0, nxh = 0, nspec = 0;
+  int64_t n_ib = 0;
+  int nq = 1;
+  bool has_ubar = false;
+  int64_t n_aug = 0;
+  hipStream_t st = nullptr;
+  double *X = nullptr, *nrm = nullptr, *ds = nullptr;
+  int* s = nullptr;
+  double* f = nullptr;
+  int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
+  MarkerGeom geom{};
+  std::unique_ptr<GridWork<float>> w32;
+  std::unique_ptr<GridWork<double>> w64;
+  double* V = nullptr;
+  int vcap = 0;
+  double* small = nullptr;    // 1024 doubles of small device scratch
+  double* partial = nullptr;  // partial sums
+  int pcap = 0;
+  double* vb = nullptr;       // right-hand side
+  double* vr = nullptr;       // residual scratch
+  double* hostbuf = nullptr;  // pinned host scratch (1024 doubles)
+  std::vector<void*> allocs;
+  std::string err;
+  // optional per-stage timing with HIP events on the handle's stream
+  bool timing = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> evpool;
+  double stage_ms[16] = {0};
+  int64_t stage_n[16] = {0};
+  hipEvent_t take_event() {
+    if (evpool.empty()) {
+      hipEvent_t e;
+      IBDL_HIP(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = evpool.back();
+    evpool.pop_back();
+    return e;
+  }
+  void collect() {
+    for (auto& p : pending) {
+      float ms = 0;
+      IBDL_HIP(hipEventSynchronize(p.second.second));
+      IBDL_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+      stage_ms[p.first] += ms;
+      stage_n[p.first] += 1;
+      evpool.push_back(p.second.first);
+      evpool.push_back(p.second.second);
+    }
+    pending.clear();
+  }
+
+  template <typename T> void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    IBDL_HIP(hipMalloc(&p, bytes));
+    allocs.push_back(p);
+    return p;
+  }
+  ~ibdl_s() {
+    if (!allocs.empty()) {
+      if (st) (void)hipStreamSynchronize(st);
+      else (void)hipDeviceSynchronize();
+    }
+    for (void* p : allocs) (void)hipFree(p);
+    if (hostbuf) (void)hipHostFree(hostbuf);
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+  }
+  bool mixed() const { return cfg.precision == IBDL_MIXED; }
+  bool stokes() const { return cfg.pde == IBDL_PDE_STOKES; }
+  bool neumann() const { return cfg.bc == IBDL_BC_NEUMANN; }
+  bool fd() const { return cfg.disc == IBDL_DISC_FD2; }
+  double kappa() const { return cfg.pde == IBDL_PDE_POISSON ? 0.0 : cfg.kappa; }
+  // grid fields needed at once (real and spectral)
+  int fields_needed() const {
+    if (stokes()) return 5;
+    if (fd()) return 1;
+    return dim + 1;
+  }
+  template <typename T> GridWork<T>& work();
+};
+
+template <> GridWork<float>& ibdl_s::work<float>() {
+  if (!w32) w32.reset(new GridWork<float>());
+  return *w32;
+}
+template <> GridWork<double>& ibdl_s::work<double>() {
+  if (!w64) w64.reset(new GridWork<double>());
+  return *w64;
+}
+
+namespace {
+
+// Stage ids reported by ibdl_get_timing.
+enum Stage { ST_SPREAD = 0, ST_FFT_X_FWD = 1, ST_FFT_Y_FWD = 2, ST_FUSED = 3, ST_FFT_Y_INV = 4, ST_FFT_X_INV = 5,
+             ST_INTERP = 6, ST_KRYLOV = 7, ST_OTHER = 8, ST_COUNT = 9 };
+
+struct StageTimer {
+  ibdl_s* h;
+  int id;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(ibdl_s* h_, int id_) : h(h_), id(id_) {
+    if (h->timing) {
+      a = h->take_event();
+      b = h->take_event();
+      IBDL_HIP(hipEventRecord(a, h->st));
+    }
+  }
+  ~StageTimer() {
+    if (a) {
+      (void)hipEventRecord(b, h->st);
+      h->pending.push_back({id, {a, b}});
+    }
+  }
+};
+
+template <typename T> GridWork<T>& ensure_work(ibdl_s* h) {
+  GridWork<T>& W = h->work<T>();
+  if (W.real) return W;
+  const int nf = h->fields_needed();
+  W.nfields = nf;
+  W.real = (T*)h->dalloc<T>(sizeof(T) * h->ntot * nf);
+  W.spec = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->nspec * nf);
+  for (int d = 0; d < h->dim; ++d) {
+    const int n = h->n[d];
+    std::vector<cplx<T>> tw(n);
+    for (int m = 0; m < n; ++m) {
+      const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+      tw[m].x = (T)cosl(a);
+      tw[m].y = (T)(-sinl(a));
+    }
+    W.tw[d] = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * n);
+    IBDL_HIP(hipMemcpy(W.tw[d], tw.data(), sizeof(cplx<T>) * n, hipMemcpyHostToDevice));
+    const int len = (d == 0) ? (int)h->nxh : n;
+    std::vector<T> sg(len), kt(len);
+    for (int j = 0; j < len; ++j) {
+      const long double th = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+      if (h->fd()) {
+        sg[j] = (T)((2.0L * cosl(th) - 2.0L) / ((long double)h->h * h->h));
+        kt[j] = (T)(sinl(th) / (long double)h->h);
+      } else {
+        const int m = (j < n / 2) ? j : j - n;
+        const long double k = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)h->cfg.L[d];
+        sg[j] = (T)(-k * k);
+        kt[j] = (j == n / 2) ? (T)0 : (T)k;
+      }
+    }
+    W.sig[d] = (T*)h->dalloc<T>(sizeof(T) * len);
+    W.kt[d] = (T*)h->dalloc<T>(sizeof(T) * len);
+    IBDL_HIP(hipMemcpy(W.sig[d], sg.data(), sizeof(T) * len, hipMemcpyHostToDevice));
+    IBDL_HIP(hipMemcpy(W.kt[d], kt.data(), sizeof(T) * len, hipMemcpyHostToDevice));
+  }
+  return W;
+}
+
+template <typename T> MultDesc base_desc(ibdl_s* h, GridWork<T>& W) {
+  MultDesc md{};
+  md.dim = h->dim;
+  md.nxh = (int)h->nxh;
+  md.sc = 1.0 / (double)h->ntot;
+  md.mu = h->cfg.mu;
+  for (int d = 0; d < 3; ++d) {
+    md.sig[d] = d < h->dim ? W.sig[d] : W.sig[0];
+    md.kt[d] = d < h->dim ? W.kt[d] : W.kt[0];
+  }
+  if (h->stokes()) {
+    md.stokes = 1;
+    md.c2 = h->cfg.mu;
+    md.c0 = h->cfg.kappa * h->cfg.kappa;
+  } else {
+    md.stokes = 0;
+    md.c2 = 1.0;
+    md.c0 = h->kappa() * h->kappa();
+  }
+  return md;
+}
+
+// real fields src[0..nin) -> spectra -> fused multiplier -> real fields dst[0..nout)
+template <typename T>
+void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md) {
+  const int64_t rows_per_field = h->ntot / h->n[0];
+  {
+    StageTimer t(h, ST_FFT_X_FWD);
+    fft_x_r2c<T>(src, W.spec, h->n[0], rows_per_field * nin, W.tw[0], h->st);
+  }
+  if (h->dim == 3) {
+    StageTimer t(h, ST_FFT_Y_FWD);
+    fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, false,
+                   W.tw[1], h->st);
+  }
+  const int last = h->dim - 1;
+  const int64_t P = h->nspec / h->n[last];
+  {
+    StageTimer t(h, ST_FUSED);
+    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st);
+  }
+  if (h->dim == 3) {
+    StageTimer t(h, ST_FFT_Y_INV);
+    fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, true,
+                   W.tw[1], h->st);
+  }
+  {
+    StageTimer t(h, ST_FFT_X_INV);
+    fft_x_c2r<T>(W.spec, dst, h->n[0], rows_per_field * nout, W.tw[0], h->st);
+  }
+}
+
+SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
+  SpreadArgs a{};
+  a.g = h->geom;
+  a.kernel = h->cfg.kernel;
+  a.mode = mode;
+  a.nf = nf;
+  a.eta = h->cfg.eta;
+  a.tile_off = h->tile_off;
+  a.list = h->list;
+  a.s = h->s;
+  a.f = h->f;
+  a.q = q;
+  a.nrm = h->nrm;
+  a.ds = h->ds;
+  return a;
+}
+
+InterpArgs interp_args(ibdl_s* h, int nf, double a, double b, const double* x, const double* ub) {
+  InterpArgs ia{};
+  ia.g = h->geom;
+  ia.kernel = h->cfg.kernel;
+  ia.nf = nf;
+  ia.n_ib = h->n_ib;
+  ia.s = h->s;
+  ia.f = h->f;
+  ia.a = a;
+  ia.b = b;
+  ia.x = x;
+  ia.ub = ub;
+  return ia;
+}
+
+void ensure_partial(ibdl_s* h, int need) {
+  if (h->pcap >= need) return;
+  h->partial = (double*)h->dalloc<double>(sizeof(double) * need);
+  h->pcap = need;
+}
+
+// Density q (device, [n_ib][nq]) -> grid field u[q] induced by it (plus optional mass values m and
+// forcing g as in the grid recovery), written to dst (nq fields).
+template <typename T>
+void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T* dst) {
+  GridWork<T>& W = ensure_work<T>(h);
+  MultDesc md = base_desc<T>(h, W);
+  if (h->stokes()) {
+    const int nf = (h->cfg.eta > 0 || g) ? 5 : 3;
+    SpreadArgs a = spread_args(h, SP_STOKES, nf, q);
+    {
+      StageTimer t(h, ST_SPREAD);
+      spread<T>(a, W.real, h->st);
+    }
+    if (g) grid_axpby<T>(W.real + 3 * h->ntot, -1.0, g, 1.0, 2 * h->ntot, h->st);
+    md.nc = nf;
+    const int kinds[5] = {FK_A11, FK_A12, FK_A22, FK_G1, FK_G2};
+    for (int i = 0; i < nf; ++i) md.fk[i] = kinds[i];
+    md.alpha = 1.0;
+    pipeline<T>(h, W, W.real, nf, dst, 2, md);
+    return;
+  }
+  const bool mass = h->cfg.eta > 0 || m != nullptr || g != nullptr;
+  if (h->fd()) {
+    SpreadArgs a = spread_args(h, SP_FDDIV, 1, q);
+    a.mass = (h->cfg.eta > 0 || m != nullptr) ? 1 : 0;
+    a.m = m;
+    {
+      StageTimer t(h, ST_SPREAD);
+      spread<T>(a, W.real, h->st);
+    }
+    if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
+    md.nc = 1;
+    md.fk[0] = FK_MASS;
+  } else {
+    const int nf = h->dim + (mass ? 1 : 0);
+    SpreadArgs a = spread_args(h, SP_SCALAR_VEC, nf, q);
+    a.mass = mass ? 1 : 0;
+    a.m = m;
+    {
+      StageTimer t(h, ST_SPREAD);
+      spread<T>(a, W.real, h->st);
+    }
+    if (g) grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
+    md.nc = nf;
+    for (int d = 0; d < h->dim; ++d) md.fk[d] = FK_DX + d;
+    if (mass) md.fk[h->dim] = FK_MASS;
+  }
+  md.alpha = -1.0;
+  pipeline<T>(h, W, W.real, md.nc, dst, 1, md);
+}
+
+// y = A q
+template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
+  GridWork<T>& W = ensure_work<T>(h);
+  density_to_grid<T>(h, q, nullptr, nullptr, W.real);
+  const double half = h->neumann() ? -0.5 : 0.5;
+  const double* ub = h->has_ubar ? q + h->n_ib * h->nq : nullptr;
+  InterpArgs ia = interp_args(h, h->nq, 1.0, half, q, ub);
+  {
+    StageTimer t(h, ST_INTERP);
+    interp<T>(ia, W.real, y, h->st);
+  }
+  if (h->has_ubar) {
+    const int nblk = kr_nblk(h->n_ib);
+    ensure_partial(h, nblk * h->nq);
+    kr_border(q, h->ds, h->n_ib, h->nq, h->cfg.eta, y + h->n_ib * h->nq, h->partial, nblk, h->st);
+  }
+}
+
+// u = L^-1 rhs (scalar) or L^-1 P rhs (Stokes)
+template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u) {
+  GridWork<T>& W = ensure_work<T>(h);
+  MultDesc md = base_desc<T>(h, W);
+  if (h->stokes()) {
+    md.nc = 2;
+    md.fk[0] = FK_G1;
+    md.fk[1] = FK_G2;
+    md.alpha = -1.0;
+    pipeline<T>(h, W, rhs, 2, u, 2, md);
+  } else {
+    md.nc = 1;
+    md.fk[0] = FK_MASS;
+    md.alpha = 1.0;
+    pipeline<T>(h, W, rhs, 1, u, 1, md);
+  }
+}
+
+template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, double* b) {
+  GridWork<T>& W = ensure_work<T>(h);
+  const int64_t nb = h->n_ib * h->nq;
+  if (h->neumann()) {
+    SpreadArgs a = spread_args(h, SP_PLAIN, 1, data);
+    spread<T>(a, W.real, h->st);
+    if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
+    grid_solve_t<T>(h, W.real, W.real);
+    InterpArgs ia = interp_args(h, 1, 1.0, 0.0, nullptr, nullptr);
+    interp<T>(ia, W.real, b, h->st);
+  } else if (g) {
+    grid_solve_t<T>(h, g, W.real);
+    InterpArgs ia = interp_args(h, h->nq, -1.0, 1.0, data, nullptr);
+    interp<T>(ia, W.real, b, h->st);
+  } else {
+    IBDL_HIP(hipMemcpyAsync(b, data, sizeof(double) * nb, hipMemcpyDeviceToDevice, h->st));
+  }
+  if (h->has_ubar) {
+    if (g) {
+      const int nblk = 256;
+      ensure_partial(h, nblk * h->nq);
+      grid_sum<T>(g, h->nq, h->ntot, h->partial, nblk, b + nb, h->st);
+      const double hD = pow(h->h, (double)h->dim);
+      kr_scale(b + nb, hD, b + nb, h->nq, h->st);
+    } else {
+      IBDL_HIP(hipMemsetAsync(b + nb, 0, sizeof(double) * h->nq, h->st));
+    }
+  }
+}
+
+template <typename T> void recover_t(ibdl_s* h, const double* q, const double* data, const T* g, T* u) {
+  density_to_grid<T>(h, q, h->neumann() ? data : nullptr, g, u);
+  if (h->has_ubar) grid_add_const<T>(u, q + h->n_ib * h->nq, h->nq, h->ntot, h->st);
+}
+
+void apply_any(ibdl_s* h, const double* q, double* y, bool force64) {
+  if (h->mixed() && !force64) apply_t<float>(h, q, y);
+  else apply_t<double>(h, q, y);
+}
+
+double host_norm(ibdl_s* h, const double* v, int64_t n) {
+  const int nblk = kr_nblk(n);
+  ensure_partial(h, nblk);
+  kr_multidot(v, n, 1, v, n, h->partial, nblk, h->small, h->st);
+  IBDL_HIP(hipMemcpyAsync(h->hostbuf, h->small, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  IBDL_HIP(hipStreamSynchronize(h->st));
+  return sqrt(h->hostbuf[0]);
+}
+
+// GMRES, x0 = 0, no restart; classical Gram-Schmidt twice on the device; Givens on the host.
+int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
+          double* relres) {
+  const int64_t n = h->n_aug;
+  if (h->vcap < maxit + 1) {
+    h->V = (double*)h->dalloc<double>(sizeof(double) * n * (maxit + 1));
+    h->vcap = maxit + 1;
+  }
+  const int nblk = kr_nblk(n);
+  ensure_partial(h, nblk * (maxit + 2));
+  const double beta = host_norm(h, b, n);
+  *iters = 0;
+  *relres = 0.0;
+  if (!(beta > 0.0)) {
+    IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
+    if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
+    return IBDL_OK;
+  }
+  kr_scale(b, 1.0 / beta, h->V, n, h->st);
+  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0);
+  gv[0] = beta;
+  int k = 0;
+  double res = 1.0;
+  double* h1 = h->small;            // [maxit+1]
+  double* h2 = h->small + 256;      // [maxit+1]
+  double* hn = h->small + 512;      // norm^2
+  for (int j = 0; j < maxit; ++j) {
+    double* w = h->V + (int64_t)(j + 1) * n;
+    apply_any(h, h->V + (int64_t)j * n, w, false);
+    kr_multidot(h->V, n, j + 1, w, n, h->partial, nblk, h1, h->st);
+    kr_gemv_sub(h->V, n, j + 1, h1, w, n, h->st);
+    kr_multidot(h->V, n, j + 1, w, n, h->partial, nblk, h2, h->st);
+    kr_gemv_sub(h->V, n, j + 1, h2, w, n, h->st);
+    kr_multidot(w, n, 1, w, n, h->partial, nblk, hn, h->st);
+    IBDL_HIP(hipMemcpyAsync(h->hostbuf, h->small, sizeof(double) * 513, hipMemcpyDeviceToHost, h->st));
+    IBDL_HIP(hipStreamSynchronize(h->st));
+    double* Hj = &H[(size_t)j * (maxit + 1)];
+    for (int i = 0; i <= j; ++i) Hj[i] = h->hostbuf[i] + h->hostbuf[256 + i];
+    const double hnext = sqrt(std::max(h->hostbuf[512], 0.0));
+    if (!std::isfinite(hnext)) throw Error(IBDL_ERR_NONFINITE, "non-finite value in the Arnoldi process");
+    Hj[j + 1] = hnext;
+    const bool breakdown = !(hnext > 1e-300 * beta);
+    if (!breakdown) kr_scale(w, 1.0 / hnext, w, n, h->st);
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+      Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+      Hj[i] = t;
+    }
+    const double r = hypot(Hj[j], Hj[j + 1]);
+    cs[j] = Hj[j] / r;
+    sn[j] = Hj[j + 1] / r;
+    Hj[j] = r;
+    Hj[j + 1] = 0.0;
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+    k = j + 1;
+    res = fabs(gv[j + 1]) / beta;
+    if (info && info->history && j < info->history_cap) info->history[j] = res;
+    if (res <= tol || breakdown) break;
+  }
+  std::vector<double> y(k);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = gv[i];
+    for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (maxit + 1) + i] * y[c];
+    y[i] = s / H[(size_t)i * (maxit + 1) + i];
+  }
+  for (int i = 0; i < k; ++i) h->hostbuf[i] = y[i];
+  IBDL_HIP(hipMemcpyAsync(h->small + 768, h->hostbuf, sizeof(double) * k, hipMemcpyHostToDevice, h->st));
+  kr_lincomb(h->V, n, k, h->small + 768, x, n, h->st);
+  IBDL_HIP(hipStreamSynchronize(h->st));
+  *iters = k;
+  *relres = res;
+  return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;
+}
+
+bool pow2_in_range(int64_t v) { return v >= 16 && v <= 1024 && (v & (v - 1)) == 0; }
+
+void validate(const ibdl_config_t* c, int64_t n_ib) {
+  if (!c) throw Error(IBDL_ERR_ARG, "cfg is NULL");
+  if (c->dim != 2 && c->dim != 3) throw Error(IBDL_ERR_ARG, "dim must be 2 or 3");
+  if (n_ib < 1 || n_ib > (int64_t)1 << 30) throw Error(IBDL_ERR_ARG, "n_ib out of range");
+  double h0 = 0;
+  for (int d = 0; d < c->dim; ++d) {
+    if (!pow2_in_range(c->n[d])) throw Error(IBDL_ERR_UNSUPPORTED, "grid size must be a power of two in [16, 1024]");
+    if (!(c->L[d] > 0) || !std::isfinite(c->L[d]) || !std::isfinite(c->origin[d]))
+      throw Error(IBDL_ERR_ARG, "box lengths must be positive and finite");
+    const double hd = c->L[d] / (double)c->n[d];
+    if (d == 0) h0 = hd;
+    else if (fabs(hd - h0) > 1e-12 * h0) throw Error(IBDL_ERR_ARG, "grid spacing must be equal on every axis");
+  }
+  if (c->pde < 0 || c->pde > 2) throw Error(IBDL_ERR_ARG, "unknown pde");
+  if (!(c->kappa >= 0) || !std::isfinite(c->kappa)) throw Error(IBDL_ERR_ARG, "kappa must be finite and >= 0");
+  if (c->pde == IBDL_PDE_SCREENED && !(c->kappa > 0))
+    throw Error(IBDL_ERR_ARG, "screened Poisson needs kappa > 0 (use IBDL_PDE_POISSON)");
+  if (c->pde == IBDL_PDE_STOKES && (!(c->mu > 0) || !std::isfinite(c->mu))) throw Error(IBDL_ERR_ARG, "mu must be > 0");
+  if (c->pde == IBDL_PDE_STOKES && c->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "Stokes is implemented in 2-D");
+  if (c->bc != IBDL_BC_DIRICHLET && c->bc != IBDL_BC_NEUMANN) throw Error(IBDL_ERR_ARG, "unknown bc");
+  if (!(c->eta >= 0) || !std::isfinite(c->eta)) throw Error(IBDL_ERR_ARG, "eta must be finite and >= 0");
+  if (c->bc == IBDL_BC_NEUMANN && (c->pde == IBDL_PDE_STOKES || c->eta != 0))
+    throw Error(IBDL_ERR_UNSUPPORTED, "Neumann is implemented for the plain scalar operator");
+  if (c->kernel < 0 || c->kernel > 2) throw Error(IBDL_ERR_ARG, "unknown kernel");
+  if (c->disc != IBDL_DISC_FD2 && c->disc != IBDL_DISC_SPECTRAL) throw Error(IBDL_ERR_ARG, "unknown disc");
+  if (c->kernel == IBDL_K_BSPLINE6 && c->disc == IBDL_DISC_FD2 && c->pde != IBDL_PDE_STOKES)
+    throw Error(IBDL_ERR_UNSUPPORTED, "the B-spline kernel needs the spectral discretisation for scalar problems");
+  if (c->kernel == IBDL_K_BSPLINE6 && c->pde == IBDL_PDE_STOKES && c->disc == IBDL_DISC_FD2)
+    throw Error(IBDL_ERR_UNSUPPORTED, "finite-difference Stokes with the B-spline kernel is not implemented");
+  if (c->precision != IBDL_FP64 && c->precision != IBDL_MIXED) throw Error(IBDL_ERR_ARG, "unknown precision");
+}
+
+void build_markers(ibdl_s* h) {
+  markers_setup(h->geom, h->n_ib, h->X, h->s, h->f, h->tile_count, h->st);
+  markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->st);
+  IBDL_HIP(hipStreamSynchronize(h->st));
+}
+
+template <typename F> ibdl_status_t guarded(ibdl_s* h, F&& fn) {
+  if (!h) return IBDL_ERR_ARG;
+  try {
+    return (ibdl_status_t)fn();
+  } catch (const Error& e) {
+    h->err = e.what();
+    return (ibdl_status_t)e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return IBDL_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* X, const double* nrm,
+                          const double* ds, ibdl_t* out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return IBDL_ERR_ARG;
+  }
+  *out = nullptr;
+  std::unique_ptr<ibdl_s> h(new ibdl_s());
+  try {
+    validate(cfg, n_ib);
+    if (!X || !nrm || !ds) throw Error(IBDL_ERR_ARG, "marker arrays must be non-NULL device pointers");
+    h->cfg = *cfg;
+    h->st = (hipStream_t)cfg->stream;
+    h->dim = cfg->dim;
+    for (int d = 0; d < 3; ++d) h->n[d] = d < h->dim ? (int)cfg->n[d] : 1;
+    h->h = cfg->L[0] / (double)cfg->n[0];
+    h->ntot = (int64_t)h->n[0] * h->n[1] * h->n[2];
+    h->nxh = h->n[0] / 2 + 1;
+    h->nspec = h->nxh * h->n[1] * h->n[2];
+    h->n_ib = n_ib;
+    h->nq = h->stokes() ? h->dim : 1;
+    h->has_ubar = cfg->eta > 0 && h->kappa() == 0.0;
+    h->n_aug = n_ib * h->nq + (h->has_ubar ? h->nq : 0);
+    MarkerGeom& g = h->geom;
+    g.dim = h->dim;
+    g.h = h->h;
+    for (int d = 0; d < 3; ++d) {
+      g.n[d] = h->n[d];
+      g.origin[d] = d < h->dim ? cfg->origin[d] : 0.0;
+      g.tile[d] = d < h->dim ? (h->dim == 2 ? 16 : 8) : 1;
+      g.ntile[d] = g.n[d] / g.tile[d];
+    }
+    const int64_t ntile = (int64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
+    const int64_t maxlist = n_ib * (h->dim == 2 ? 4 : 8);
+    h->X = (double*)h->dalloc<double>(sizeof(double) * n_ib * h->dim);
+    h->nrm = (double*)h->dalloc<double>(sizeof(double) * n_ib * h->dim);
+    h->ds = (double*)h->dalloc<double>(sizeof(double) * n_ib);
+    h->s = (int*)h->dalloc<int>(sizeof(int) * n_ib * 3);
+    h->f = (double*)h->dalloc<double>(sizeof(double) * n_ib * 3);
+    h->tile_count = (int*)h->dalloc<int>(sizeof(int) * ntile);
+    h->tile_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
+    h->tile_cur = (int*)h->dalloc<int>(sizeof(int) * ntile);
+    h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
+    h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);
+    h->small = (double*)h->dalloc<double>(sizeof(double) * 1024);
+    h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
+    h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
+    IBDL_HIP(hipHostMalloc((void**)&h->hostbuf, sizeof(double) * 1024, hipHostMallocDefault));
+    IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
+    IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
+    IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * n_ib, hipMemcpyDeviceToDevice, h->st));
+    build_markers(h.get());
+    if (h->mixed()) ensure_work<float>(h.get());
+    else ensure_work<double>(h.get());
+  } catch (const Error& e) {
+    g_create_error = e.what();
+    return (ibdl_status_t)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return IBDL_ERR_HIP;
+  }
+  *out = h.release();
+  return IBDL_OK;
+}
+
+ibdl_status_t ibdl_set_markers(ibdl_t h, const double* X, const double* nrm, const double* ds) {
+  return guarded(h, [&]() {
+    if (!X || !nrm || !ds) throw Error(IBDL_ERR_ARG, "marker arrays must be non-NULL");
+    IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
+    IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
+    IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * h->n_ib, hipMemcpyDeviceToDevice, h->st));
+    build_markers(h);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_destroy(ibdl_t h) {
+  if (!h) return IBDL_ERR_ARG;
+  delete h;
+  return IBDL_OK;
+}
+
+ibdl_status_t ibdl_spread(ibdl_t h, const double* f, int32_t nc, void* grid) {
+  return guarded(h, [&]() {
+    if (!f || !grid) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (nc < 1 || nc > 5) throw Error(IBDL_ERR_ARG, "nc must be in [1, 5]");
+    SpreadArgs a = spread_args(h, SP_PLAIN, nc, f);
+    if (h->mixed()) spread<float>(a, (float*)grid, h->st);
+    else spread<double>(a, (double*)grid, h->st);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_interp(ibdl_t h, const void* grid, int32_t nc, double* f) {
+  return guarded(h, [&]() {
+    if (!f || !grid) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (nc < 1 || nc > 5) throw Error(IBDL_ERR_ARG, "nc must be in [1, 5]");
+    InterpArgs ia = interp_args(h, nc, 1.0, 0.0, nullptr, nullptr);
+    if (h->mixed()) interp<float>(ia, (const float*)grid, f, h->st);
+    else interp<double>(ia, (const double*)grid, f, h->st);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_grid_solve(ibdl_t h, const void* rhs, void* u) {
+  return guarded(h, [&]() {
+    if (!rhs || !u) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (h->mixed()) grid_solve_t<float>(h, (const float*)rhs, (float*)u);
+    else grid_solve_t<double>(h, (const double*)rhs, (double*)u);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y) {
+  return guarded(h, [&]() {
+    if (!q || !y) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (q == y) throw Error(IBDL_ERR_ARG, "q and y must not alias");
+    apply_any(h, q, y, false);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, double tol, int32_t maxit, double* q,
+                         void* u_grid, ibdl_info_t* info) {
+  return guarded(h, [&]() {
+    if (!data || !q) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (!(tol >= 0) || !std::isfinite(tol)) throw Error(IBDL_ERR_ARG, "tol must be finite and >= 0");
+    if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
+    if (h->mixed()) rhs_t<float>(h, data, (const float*)g_grid, h->vb);
+    else rhs_t<double>(h, data, (const double*)g_grid, h->vb);
+    int iters = 0;
+    double relres = 0;
+    const int status = gmres(h, h->vb, tol, maxit, q, info, &iters, &relres);
+    // true residual ||b - A q|| / ||b|| with a double-precision apply
+    apply_any(h, q, h->vr, true);
+    kr_axpby(h->vr, 1.0, h->vb, -1.0, h->n_aug, h->st);
+    const double rn = host_norm(h, h->vr, h->n_aug);
+    const double bn = host_norm(h, h->vb, h->n_aug);
+    if (u_grid) {
+      if (h->mixed()) recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
+      else recover_t<double>(h, q, data, (const double*)g_grid, (double*)u_grid);
+    }
+    if (info) {
+      info->iters = iters;
+      info->status = status;
+      info->krylov_relres = relres;
+      info->true_relres_fp64 = bn > 0 ? rn / bn : 0.0;
+    }
+    return status;
+  });
+}
+
+ibdl_status_t ibdl_set_timing(ibdl_t h, int32_t enable) {
+  return guarded(h, [&]() {
+    h->collect();
+    h->timing = enable != 0;
+    for (int i = 0; i < 16; ++i) {
+      h->stage_ms[i] = 0;
+      h->stage_n[i] = 0;
+    }
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_get_timing(ibdl_t h, double* ms, int64_t* count, int32_t cap) {
+  return guarded(h, [&]() {
+    if (!ms || !count || cap < 1) throw Error(IBDL_ERR_ARG, "NULL pointer or cap < 1");
+    h->collect();
+    for (int i = 0; i < cap && i < ST_COUNT; ++i) {
+      ms[i] = h->stage_ms[i];
+      count[i] = h->stage_n[i];
+    }
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq) {
+  if (!h) return IBDL_ERR_ARG;
+  if (n_aug) *n_aug = h->n_aug;
+  if (grid_points) *grid_points = h->ntot;
+  if (nq) *nq = h->nq;
+  return IBDL_OK;
+}
+
+const char* ibdl_last_error(ibdl_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

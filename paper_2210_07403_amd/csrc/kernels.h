@@ -1,0 +1,121 @@
+// Host-side launchers of the HIP kernels (implemented in fft.hip, ib.hip, krylov.hip).
+#pragma once
+
+#include "common.h"
+
+namespace ibdl {
+
+// ------------------------------------------------------------------ Fourier multiplier
+// Field kinds of the inputs of the fused last-axis pass.
+enum FieldKind {
+  FK_DX = 0, FK_DY = 1, FK_DZ = 2,   // scalar: contributes i k~_d F^ (spectral divergence)
+  FK_MASS = 3,                       // scalar: contributes F^
+  FK_A11 = 4, FK_A12 = 5, FK_A22 = 6,  // Stokes dipole tensor components
+  FK_G1 = 7, FK_G2 = 8               // Stokes single-layer / forcing components
+};
+
+struct MultDesc {
+  int dim;          // 2 or 3
+  int nxh;          // nx/2 + 1
+  int stokes;       // 0: scalar multiplier, 1: Stokes multiplier
+  int nc;           // input fields
+  int fk[8];        // kind of each input field
+  double sc;        // overall scale (1 / number of grid points)
+  double c0, c2;    // symbol of -L is c2 * ell(k) + c0 with ell = -sigma (scalar: L = c2 Delta - c0)
+  double mu;        // Stokes viscosity in the dipole term
+  double alpha;     // overall sign / factor
+  const void* sig[3];  // per-axis Laplacian symbol components (grid type)
+  const void* kt[3];   // per-axis derivative symbols k~ (grid type)
+};
+
+template <typename T>
+void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s);
+template <typename T>
+void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s);
+// in-place strided C2C pass: line l starts at (l / inner) * outer + (l % inner), element stride es
+template <typename T>
+void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es,
+                 bool inverse, const cplx<T>* tw, hipStream_t s);
+// in-place fused pass along the last axis (length n, plane size P): forward FFT of the nc input
+// fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1)
+template <typename T>
+void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw,
+                    hipStream_t s);
+int fft_supported(int n);
+
+// ------------------------------------------------------------------ markers, spread, interp
+enum KernelId { KID_PESKIN4 = 0, KID_COS4 = 1, KID_BSPLINE6 = 2 };
+
+struct MarkerGeom {
+  int dim;
+  int n[3];            // grid points per axis
+  double origin[3];
+  double h;
+  int tile[3];         // tile edge per axis
+  int ntile[3];        // tiles per axis
+};
+
+// marker setup: window start s[i][3] (wrapped), fractional offset f[i][3], tile counts
+void markers_setup(const MarkerGeom& g, int64_t n_ib, const double* X, int* s, double* f,
+                   int* tile_count, hipStream_t st);
+void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
+                 int* tile_off, int* tile_cur, int* list, int* list_tmp, hipStream_t st);
+
+enum SpreadMode {
+  SP_PLAIN = 0,     // nf fields: coef_c = f[i][c] ds_i h^-D
+  SP_FDDIV = 1,     // 1 field: FD divergence of S(q n) + (eta q + m) S-term, fused in the stencil
+  SP_SCALAR_VEC = 2,// dim (+1) fields: q n_d ds h^-D (and (eta q + m) ds h^-D)
+  SP_STOKES = 3     // 3 or 5 fields: A11, A12, A22 (and eta Q1, eta Q2), times ds h^-D
+};
+
+struct SpreadArgs {
+  MarkerGeom g;
+  int kernel;
+  int mode;
+  int nf;             // output fields
+  int mass;           // SP_FDDIV / SP_SCALAR_VEC: include the mass term
+  double eta;
+  const int* tile_off;
+  const int* list;
+  const int* s;
+  const double* f;
+  const double* q;    // densities [n_ib][nq] (or generic values [n_ib][nf] for SP_PLAIN)
+  const double* m;    // optional extra mass values [n_ib] (Neumann V_b), may be null
+  const double* nrm;  // [n_ib][dim]
+  const double* ds;   // [n_ib]
+};
+template <typename T> void spread(const SpreadArgs& a, T* out, hipStream_t st);
+
+struct InterpArgs {
+  MarkerGeom g;
+  int kernel;
+  int nf;
+  int64_t n_ib;
+  const int* s;
+  const double* f;
+  double a;            // out = a * S*u + b * x + ub
+  double b;
+  const double* x;     // [n_ib][nf] or null
+  const double* ub;    // [nf] or null
+};
+template <typename T> void interp(const InterpArgs& a, const T* u, double* out, hipStream_t st);
+
+// ------------------------------------------------------------------ grid elementwise
+template <typename T> void grid_axpby(T* y, double a, const T* x, double b, int64_t n, hipStream_t st);
+template <typename T> void grid_add_const(T* y, const double* c_dev, int ncomp, int64_t n, hipStream_t st);
+template <typename T> void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, double* out,
+                                    hipStream_t st);
+
+// ------------------------------------------------------------------ Krylov vectors (double)
+void kr_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial,
+                 int nblk, double* out, hipStream_t st);
+void kr_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n, hipStream_t st);
+void kr_lincomb(const double* V, int64_t ldv, int k, const double* y, double* x, int64_t n, hipStream_t st);
+void kr_scale(const double* src, double s, double* dst, int64_t n, hipStream_t st);
+void kr_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t st);
+void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double eta, double* out,
+               double* partial, int nblk, hipStream_t st);
+void kr_add(double* dst, const double* a, const double* b, int n, hipStream_t st);
+int kr_nblk(int64_t n);
+
+}  // namespace ibdl
