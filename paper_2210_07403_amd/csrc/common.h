@@ -17,6 +17,9 @@ template <typename T> using cplx = typename Cplx<T>::type;
 template <typename C> __host__ __device__ __forceinline__ C mk(decltype(C::x) re, decltype(C::x) im) {
   C c; c.x = re; c.y = im; return c;
 }
+template <typename V, typename S> __host__ __device__ __forceinline__ V mk4(S a, S b, S c, S d) {
+  V v; v.x = a; v.y = b; v.z = c; v.w = d; return v;
+}
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {

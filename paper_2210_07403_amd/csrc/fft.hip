@@ -313,7 +313,7 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
   }
 }
 
-template <typename T, int N, int NO>
+template <typename T, int N, int NO, bool STOKES>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                   const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
@@ -329,26 +329,32 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   // mode indices of this line: 2-D l = jx, e = jy; 3-D l = jy*nxh + jx, e = jz
   const int jx = (int)(valid ? l % md.nxh : 0);
   const int jy2 = (int)(valid ? l / md.nxh : 0);
-  const T* sg0 = static_cast<const T*>(md.sig[0]);
-  const T* sg1 = static_cast<const T*>(md.sig[1]);
-  const T* sg2 = static_cast<const T*>(md.sig[2]);
-  const T* kt0 = static_cast<const T*>(md.kt[0]);
-  const T* kt1 = static_cast<const T*>(md.kt[1]);
-  const T* kt2 = static_cast<const T*>(md.kt[2]);
-  T sig_l = sg0[jx];
+  const bool d3 = md.dim == 3;
+  const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);   // symbols along the line
+  const T* ktl_ = static_cast<const T*>(md.kt[d3 ? 2 : 1]);
+  T sig_l = static_cast<const T*>(md.sig[0])[jx];
   T ktl[3];
-  ktl[0] = kt0[jx];
+  ktl[0] = static_cast<const T*>(md.kt[0])[jx];
   ktl[1] = 0;
   ktl[2] = 0;
-  if (md.dim == 3) {
-    sig_l += sg1[jy2];
-    ktl[1] = kt1[jy2];
+  if (d3) {
+    sig_l += static_cast<const T*>(md.sig[1])[jy2];
+    ktl[1] = static_cast<const T*>(md.kt[1])[jy2];
   }
+  const int la = d3 ? 2 : 1;   // index of the line axis among the derivative components
   C acc[NO][RM];
 #pragma unroll
   for (int o = 0; o < NO; ++o)
 #pragma unroll
     for (int s = 0; s < RM; ++s) acc[o][s] = mk<C>(0, 0);
+  T gfac[RM];   // scalar multiplier alpha*sc / (c2 sigma - c0) of each register element
+  if constexpr (!STOKES) {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) {
+      const T den = (T)md.c2 * (sig_l + sgl[i + s * TT]) - (T)md.c0;
+      gfac[s] = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) / den;
+    }
+  }
 
   for (int f = 0; f < md.nc; ++f) {
     C v[RM];
@@ -356,20 +362,28 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
     for (int s = 0; s < RM; ++s) v[s] = valid ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
     fft_line<N, false>(v, i, lds + c, TC::W, tw, 1);
     const int fk = md.fk[f];
+    if constexpr (!STOKES) {
+      if (fk == FK_MASS) {
 #pragma unroll
-    for (int s = 0; s < RM; ++s) {
-      const int e = i + s * TT;
-      T kt[3] = {ktl[0], ktl[1], ktl[2]};
-      T sig;
-      if (md.dim == 3) {
-        sig = sig_l + sg2[e];
-        kt[2] = kt2[e];
-      } else {
-        sig = sig_l + sg1[e];
-        kt[1] = kt1[e];
+        for (int s = 0; s < RM; ++s) acc[0][s] = cadd(acc[0][s], cscale(v[s], gfac[s]));
+      } else if (fk == la) {   // derivative along the line axis: k~ varies per element
+#pragma unroll
+        for (int s = 0; s < RM; ++s) acc[0][s] = cadd(acc[0][s], mul_ir(v[s], gfac[s] * ktl_[i + s * TT]));
+      } else {                 // derivative across lines: k~ is constant on the line
+        const T kc = ktl[fk];
+#pragma unroll
+        for (int s = 0; s < RM; ++s) acc[0][s] = cadd(acc[0][s], mul_ir(v[s], gfac[s] * kc));
       }
+    } else {
 #pragma unroll
-      for (int o = 0; o < NO; ++o) acc[o][s] = cadd(acc[o][s], cmul(mult_coef<T>(md, fk, o, sig, kt), v[s]));
+      for (int s = 0; s < RM; ++s) {
+        const int e = i + s * TT;
+        T kt[3] = {ktl[0], ktl[1], ktl[2]};
+        kt[la] = ktl_[e];
+        const T sig = sig_l + sgl[e];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o][s] = cadd(acc[o][s], cmul(mult_coef<T>(md, fk, o, sig, kt), v[s]));
+      }
     }
   }
 #pragma unroll
@@ -379,6 +393,43 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 #pragma unroll
       for (int s = 0; s < RM; ++s) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[o][s];
     }
+  }
+}
+
+// Single scalar field (the finite-difference operator and the scalar grid solve): forward FFT,
+// multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
+template <typename T, int N>
+__global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
+                                                   const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TC = TileCfg<T, N>;
+  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int tid = threadIdx.x;
+  const int c = tid % TC::W, i = tid / TC::W;
+  const int64_t l = (int64_t)blockIdx.x * TC::W + c;
+  const bool valid = l < P;
+  const int jx = (int)(valid ? l % md.nxh : 0);
+  const int jy2 = (int)(valid ? l / md.nxh : 0);
+  const bool d3 = md.dim == 3;
+  const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
+  T sig_l = static_cast<const T*>(md.sig[0])[jx];
+  if (d3) sig_l += static_cast<const T*>(md.sig[1])[jy2];
+  C v[RM];
+#pragma unroll
+  for (int s = 0; s < RM; ++s) v[s] = valid ? data[l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+  fft_line<N, false>(v, i, lds + c, TC::W, tw, 1);
+  const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
+#pragma unroll
+  for (int s = 0; s < RM; ++s) {
+    const T den = c2 * (sig_l + sgl[i + s * TT]) - c0;
+    v[s] = cscale(v[s], den == (T)0 ? (T)0 : num / den);
+  }
+  fft_line<N, true>(v, i, lds + c, TC::W, tw, 1);
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) data[l + (int64_t)(i + s * TT) * P] = v[s];
   }
 }
 
@@ -450,12 +501,14 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
     using TC = TileCfg<T, N>;
     const int64_t nb = (P + TC::W - 1) / TC::W;
     const size_t lds = sizeof(cplx<T>) * N * TC::W;
-    if (no == 1)
-      hipLaunchKernelGGL((k_fused<T, N, 1>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
-    else if (no == 2)
-      hipLaunchKernelGGL((k_fused<T, N, 2>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
+    if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)
+      hipLaunchKernelGGL((k_fused1<T, N>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
+    else if (!md.stokes && no == 1)
+      hipLaunchKernelGGL((k_fused<T, N, 1, false>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
+    else if (md.stokes && no == 2)
+      hipLaunchKernelGGL((k_fused<T, N, 2, true>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
     else
-      throw Error(-2, "fused pass: unsupported output count");
+      throw Error(-2, "fused pass: unsupported multiplier / output count");
   });
   IBDL_LAUNCH_CHECK();
 }

@@ -13,7 +13,6 @@
 namespace ibdl {
 namespace {
 
-constexpr int kCH = 64;  // markers staged per LDS chunk
 
 __device__ __forceinline__ double phi_eval(int kernel, double r) {
   const double a = fabs(r);
@@ -35,23 +34,28 @@ __device__ __forceinline__ double phi_eval(int kernel, double r) {
 }
 
 // ------------------------------------------------------------------ marker setup and binning
-__device__ __forceinline__ void marker_tiles(const MarkerGeom& g, const int* s, int (&tl)[3][2], int (&nt)[3]) {
+// Tiles met by a marker's 6-node window along each axis: tile indices j0 .. j0 + cnt - 1 (mod ntile).
+__device__ __forceinline__ void marker_tiles(const MarkerGeom& g, const int* s, int (&j0)[3], int (&cnt)[3]) {
   for (int d = 0; d < 3; ++d) {
     if (d < g.dim) {
-      const int t0 = s[d] / g.tile[d];
-      const int t1 = ((s[d] + 5) & (g.n[d] - 1)) / g.tile[d];
-      tl[d][0] = t0;
-      tl[d][1] = t1;
-      nt[d] = (t1 != t0) ? 2 : 1;
+      j0[d] = s[d] / g.tile[d];
+      cnt[d] = (s[d] + 5) / g.tile[d] - j0[d] + 1;
+      if (cnt[d] > g.ntile[d]) cnt[d] = g.ntile[d];
     } else {
-      tl[d][0] = tl[d][1] = 0;
-      nt[d] = 1;
+      j0[d] = 0;
+      cnt[d] = 1;
     }
   }
 }
 
-__global__ void k_marker_setup(MarkerGeom g, int64_t n_ib, const double* __restrict__ X, int* __restrict__ s,
-                               double* __restrict__ f, int* __restrict__ tile_count) {
+__device__ __forceinline__ int tile_id(const MarkerGeom& g, const int (&j0)[3], int a, int b, int c) {
+  const int tz = (j0[2] + a) % g.ntile[2], ty = (j0[1] + b) % g.ntile[1], tx = (j0[0] + c) % g.ntile[0];
+  return (tz * g.ntile[1] + ty) * g.ntile[0] + tx;
+}
+
+__global__ void k_marker_setup(MarkerGeom g, int kernel, int64_t n_ib, const double* __restrict__ X,
+                               int* __restrict__ s, double* __restrict__ f, double* __restrict__ wt,
+                               int* __restrict__ tile_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_ib) return;
   int si[3] = {0, 0, 0};
@@ -71,14 +75,24 @@ __global__ void k_marker_setup(MarkerGeom g, int64_t n_ib, const double* __restr
     s[i * 3 + d] = 0;
     f[i * 3 + d] = 0.0;
   }
-  int tl[3][2], nt[3];
-  marker_tiles(g, si, tl, nt);
+  // kernel weights W[t] = phi((s + t) - X/h) on the 6-node window and centred differences
+  // G[t] = (W[t+1] - W[t-1]) / 2h (W = 0 outside the window), per axis; unit weight off-dimension
+  for (int d = 0; d < 3; ++d) {
+    double w[8];
+    w[0] = w[7] = 0.0;
+    for (int t = 0; t < 6; ++t)
+      w[t + 1] = d < g.dim ? phi_eval(kernel, (double)(t - 2) - f[i * 3 + d]) : (t == 2 ? 1.0 : 0.0);
+    double* row = wt + (i * 3 + d) * 12;
+    for (int t = 0; t < 6; ++t) {
+      row[t] = w[t + 1];
+      row[6 + t] = d < g.dim ? (w[t + 2] - w[t]) * (0.5 / g.h) : 0.0;
+    }
+  }
+  int j0[3], nt[3];
+  marker_tiles(g, si, j0, nt);
   for (int a = 0; a < nt[2]; ++a)
     for (int b = 0; b < nt[1]; ++b)
-      for (int c = 0; c < nt[0]; ++c) {
-        const int id = (tl[2][a] * g.ntile[1] + tl[1][b]) * g.ntile[0] + tl[0][c];
-        atomicAdd(&tile_count[id], 1);
-      }
+      for (int c = 0; c < nt[0]; ++c) atomicAdd(&tile_count[tile_id(g, j0, a, b, c)], 1);
 }
 
 __global__ void k_fill(MarkerGeom g, int64_t n_ib, const int* __restrict__ s, const int* __restrict__ off,
@@ -86,12 +100,12 @@ __global__ void k_fill(MarkerGeom g, int64_t n_ib, const int* __restrict__ s, co
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_ib) return;
   int si[3] = {s[i * 3], s[i * 3 + 1], s[i * 3 + 2]};
-  int tl[3][2], nt[3];
-  marker_tiles(g, si, tl, nt);
+  int j0[3], nt[3];
+  marker_tiles(g, si, j0, nt);
   for (int a = 0; a < nt[2]; ++a)
     for (int b = 0; b < nt[1]; ++b)
       for (int c = 0; c < nt[0]; ++c) {
-        const int id = (tl[2][a] * g.ntile[1] + tl[1][b]) * g.ntile[0] + tl[0][c];
+        const int id = tile_id(g, j0, a, b, c);
         const int pos = off[id] + atomicAdd(&cur[id], 1);
         list[pos] = (int)i;
       }
@@ -122,6 +136,17 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int*
   if (threadIdx.x == 0) off[n] = carry;
 }
 
+// ids of the tiles with at least one candidate, in increasing order (off is the exclusive scan of
+// the 0/1 flags computed by k_busy_flags)
+__global__ void k_busy_flags(const int* __restrict__ cnt, int* __restrict__ flag, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = cnt[i] > 0 ? 1 : 0;
+}
+__global__ void k_busy_ids(const int* __restrict__ cnt, const int* __restrict__ foff, int* __restrict__ busy, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && cnt[i] > 0) busy[foff[i]] = i;
+}
+
 // sort each tile's marker list ascending (rank sort; marker indices in a tile are unique)
 __global__ __launch_bounds__(256) void k_sort_tiles(const int* __restrict__ off, const int* __restrict__ tmp,
                                                     int* __restrict__ list) {
@@ -136,105 +161,222 @@ __global__ __launch_bounds__(256) void k_sort_tiles(const int* __restrict__ off,
 }
 
 // ------------------------------------------------------------------ spread
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_spread(SpreadArgs a, T* __restrict__ out) {
-  constexpr int TX = (D == 2) ? 16 : 8, TY = (D == 2) ? 16 : 8, TZ = (D == 2) ? 1 : 8;
-  constexpr int PPT = (TX * TY * TZ) / 256;  // nodes per thread: 1 (2-D) or 2 (3-D)
-  __shared__ int s_s[kCH][3];
-  __shared__ T s_w[kCH][3][6];
-  __shared__ T s_g[kCH][3][6];
-  __shared__ T s_c[kCH][5];
+// Owner-computes spread with the candidate list of a tile split over the 4 waves of a workgroup:
+// wave w accumulates candidates w, w+4, w+8, ... of the (sorted) list in registers, and the four
+// partial sums are added in wave order at the end, so the result is deterministic.  The loader
+// thread of each candidate evaluates the kernel weights W and the centred-difference weights G
+// at the tile's own node positions (zero outside the marker's window), so the accumulation loop
+// is branch-free and reads a handful of packed LDS vectors per candidate.
+constexpr int kT3X = 16, kT3Y = 4, kT3Z = 8;   // 3-D tile; lane (x, y) owns a z-column of 8
+constexpr int kT2X = 16, kT2Y = 16;            // 2-D tile; lane (x, y-group) owns 4 consecutive y
+
+template <typename T> struct Pack4;
+template <> struct Pack4<float> { using type = float4; };
+template <> struct Pack4<double> { using type = double4; };
+
+// W and G of one marker at LEN consecutive tile nodes org .. org+LEN-1 along one axis, looked up
+// in the marker's weight table row (W[0..5], G[0..5]); zero outside the marker's window
+template <int LEN, typename T2>
+__device__ __forceinline__ void tile_weights(const double* __restrict__ row, int org, int sd, int mask,
+                                             T2* __restrict__ wg) {
+  using T = decltype(T2::x);
+#pragma unroll
+  for (int j = 0; j < LEN; ++j) {
+    const int t = (org + j - sd) & mask;   // window tap of tile node j
+    wg[j] = t < 6 ? mk<T2>((T)row[t], (T)row[6 + t]) : mk<T2>((T)0, (T)0);
+  }
+}
+
+// per-marker coefficients of the spread fields (times ds / h^D)
+__device__ __forceinline__ void spread_coefs(const SpreadArgs& a, int m, int D, double base, double* cf) {
+  for (int c = 0; c < 8; ++c) cf[c] = 0.0;
+  if (a.mode == SP_PLAIN) {
+    for (int c = 0; c < 5; ++c)
+      if (c < a.nf) cf[c] = a.q[(int64_t)m * a.nf + c] * base;
+  } else if (a.mode == SP_STOKES) {
+    const double q1 = a.q[2 * (int64_t)m], q2 = a.q[2 * (int64_t)m + 1];
+    const double n1 = a.nrm[2 * (int64_t)m], n2 = a.nrm[2 * (int64_t)m + 1];
+    cf[0] = 2.0 * q1 * n1 * base;
+    cf[1] = (q1 * n2 + q2 * n1) * base;
+    cf[2] = 2.0 * q2 * n2 * base;
+    cf[3] = a.eta * q1 * base;
+    cf[4] = a.eta * q2 * base;
+  } else {  // SP_FDDIV: c_d = q n_d, mass in slot 3; SP_SCALAR_VEC: c_d = q n_d, mass in slot D
+    const double qm = a.q[m];
+    for (int d = 0; d < 3; ++d)
+      if (d < D) cf[d] = qm * a.nrm[(int64_t)m * D + d] * base;
+    const double mass = a.mass ? (a.eta * qm + (a.m ? a.m[m] : 0.0)) * base : 0.0;
+    cf[a.mode == SP_FDDIV ? 3 : D] = mass;
+  }
+}
+
+template <typename T> constexpr int spread_chunk() { return sizeof(T) == 4 ? 128 : 64; }
+
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, T* __restrict__ out) {
+  using T2 = cplx<T>;
+  using T4 = typename Pack4<T>::type;
+  constexpr int CH = spread_chunk<T>();
+  __shared__ T2 s_x[CH][kT3X];             // (W, G) at the tile's x nodes
+  __shared__ T2 s_y[CH][kT3Y];
+  __shared__ T4 s_z[CH][6];                // W z[8], G z[8], coefficients[8]
   const MarkerGeom& g = a.g;
-  const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tile = a.busy[blockIdx.x];
   const int tx = tile % g.ntile[0];
   const int ty = (tile / g.ntile[0]) % g.ntile[1];
   const int tz = tile / (g.ntile[0] * g.ntile[1]);
-  int jx[PPT], jy[PPT], jz[PPT];
+  const int x0 = tx * kT3X, y0 = ty * kT3Y, z0 = tz * kT3Z;
+  const int lx = lane % kT3X, ly = lane / kT3X;
+  const bool fddiv = NF == 1 && a.mode == SP_FDDIV;
+  T acc[kT3Z][NF];
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const int lp = tid + p * 256;
-    jx[p] = tx * TX + lp % TX;
-    jy[p] = ty * TY + (lp / TX) % TY;
-    jz[p] = tz * TZ + lp / (TX * TY);
-  }
-  T acc[PPT][5];
+  for (int z = 0; z < kT3Z; ++z)
 #pragma unroll
-  for (int p = 0; p < PPT; ++p)
-#pragma unroll
-    for (int c = 0; c < 5; ++c) acc[p][c] = 0;
+    for (int c = 0; c < NF; ++c) acc[z][c] = 0;
   const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
-  const double hD = (D == 2) ? g.h * g.h : g.h * g.h * g.h;
-  for (int c0 = beg; c0 < end; c0 += kCH) {
-    const int cnt = (end - c0) < kCH ? (end - c0) : kCH;
+  const double hD = g.h * g.h * g.h;
+  for (int c0 = beg; c0 < end; c0 += CH) {
+    const int cnt = (end - c0) < CH ? (end - c0) : CH;
     if (tid < cnt) {
       const int m = a.list[c0 + tid];
-      for (int d = 0; d < 3; ++d) {
-        s_s[tid][d] = a.s[m * 3 + d];
-        double w[8];
-        w[0] = 0.0;
-        w[7] = 0.0;
-        const double fr = a.f[m * 3 + d];
-        for (int t = 0; t < 6; ++t) w[t + 1] = (d < D) ? phi_eval(a.kernel, (double)(t - 2) - fr) : 0.0;
-        for (int t = 0; t < 6; ++t) {
-          s_w[tid][d][t] = (T)w[t + 1];
-          s_g[tid][d][t] = (T)((w[t + 2] - w[t]) / (2.0 * g.h));
-        }
-      }
-      const double base = a.ds[m] / hD;
-      double cf[5] = {0, 0, 0, 0, 0};
-      if (a.mode == SP_PLAIN) {
-        for (int c = 0; c < a.nf; ++c) cf[c] = a.q[(int64_t)m * a.nf + c] * base;
-      } else if (a.mode == SP_FDDIV || a.mode == SP_SCALAR_VEC) {
-        const double qm = a.q[m];
-        for (int d = 0; d < D; ++d) cf[d] = qm * a.nrm[(int64_t)m * D + d] * base;
-        const double mass = a.mass ? (a.eta * qm + (a.m ? a.m[m] : 0.0)) * base : 0.0;
-        cf[a.mode == SP_FDDIV ? 3 : D] = mass;
-      } else {  // SP_STOKES (2-D)
-        const double q1 = a.q[2 * (int64_t)m], q2 = a.q[2 * (int64_t)m + 1];
-        const double n1 = a.nrm[2 * (int64_t)m], n2 = a.nrm[2 * (int64_t)m + 1];
-        cf[0] = 2.0 * q1 * n1 * base;
-        cf[1] = (q1 * n2 + q2 * n1) * base;
-        cf[2] = 2.0 * q2 * n2 * base;
-        cf[3] = a.eta * q1 * base;
-        cf[4] = a.eta * q2 * base;
-      }
-      for (int c = 0; c < 5; ++c) s_c[tid][c] = (T)cf[c];
+      const double* row = a.wt + (int64_t)m * 36;
+      tile_weights<kT3X>(row, x0, a.s[m * 3 + 0], g.n[0] - 1, s_x[tid]);
+      tile_weights<kT3Y>(row + 12, y0, a.s[m * 3 + 1], g.n[1] - 1, s_y[tid]);
+      T2 zw[kT3Z];
+      tile_weights<kT3Z>(row + 24, z0, a.s[m * 3 + 2], g.n[2] - 1, zw);
+      double cf[8];
+      spread_coefs(a, m, 3, a.ds[m] / hD, cf);
+      s_z[tid][0] = mk4<T4>(zw[0].x, zw[1].x, zw[2].x, zw[3].x);
+      s_z[tid][1] = mk4<T4>(zw[4].x, zw[5].x, zw[6].x, zw[7].x);
+      s_z[tid][2] = mk4<T4>(zw[0].y, zw[1].y, zw[2].y, zw[3].y);
+      s_z[tid][3] = mk4<T4>(zw[4].y, zw[5].y, zw[6].y, zw[7].y);
+      s_z[tid][4] = mk4<T4>((T)cf[0], (T)cf[1], (T)cf[2], (T)cf[3]);
+      s_z[tid][5] = mk4<T4>((T)cf[4], (T)0, (T)0, (T)0);
     }
     __syncthreads();
-    for (int k = 0; k < cnt; ++k) {
-      const int sx = s_s[k][0], sy = s_s[k][1], sz = s_s[k][2];
+#pragma unroll 2
+    for (int k = wave; k < cnt; k += 4) {
+      const T2 xv = s_x[k][lx], yv = s_y[k][ly];
+      const T4 w0 = s_z[k][0], w1 = s_z[k][1], c4 = s_z[k][4];
+      const T wz[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+      if (fddiv) {
+        const T4 g0 = s_z[k][2], g1 = s_z[k][3];
+        const T gz[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+        const T A = c4.x * xv.y * yv.x + c4.y * xv.x * yv.y + c4.w * xv.x * yv.x;
+        const T B = c4.z * xv.x * yv.x;
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        const int ox = (jx[p] - sx) & (g.n[0] - 1);
-        const int oy = (jy[p] - sy) & (g.n[1] - 1);
-        const int oz = (D == 3) ? ((jz[p] - sz) & (g.n[2] - 1)) : 0;
-        if (ox < 6 && oy < 6 && oz < 6) {
-          const T wx = s_w[k][0][ox], wy = s_w[k][1][oy];
-          const T wz = (D == 3) ? s_w[k][2][oz] : (T)1;
-          if (a.mode == SP_FDDIV) {
-            const T gx = s_g[k][0][ox], gy = s_g[k][1][oy];
-            T v = s_c[k][0] * gx * wy * wz + s_c[k][1] * wx * gy * wz + s_c[k][3] * wx * wy * wz;
-            if (D == 3) v += s_c[k][2] * wx * wy * s_g[k][2][oz];
-            acc[p][0] += v;
-          } else {
-            const T w = wx * wy * wz;
+        for (int z = 0; z < kT3Z; ++z) acc[z][0] += A * wz[z] + B * gz[z];
+      } else {
+        const T4 c5 = s_z[k][5];
+        const T w2 = xv.x * yv.x;
+        const T cw[5] = {c4.x * w2, c4.y * w2, c4.z * w2, c4.w * w2, c5.x * w2};
 #pragma unroll
-            for (int c = 0; c < 5; ++c)
-              if (c < a.nf) acc[p][c] += s_c[k][c] * w;
-          }
-        }
+        for (int z = 0; z < kT3Z; ++z)
+#pragma unroll
+          for (int c = 0; c < NF; ++c)
+            if (c < a.nf) acc[z][c] += cw[c] * wz[z];
       }
     }
     __syncthreads();
   }
-  const int64_t ntot = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+  // fixed-order reduction of the four waves' partial sums, one field at a time
+  T* red = reinterpret_cast<T*>(&s_x[0][0]);   // needs 4 * 8 * 64 values
+  const int64_t ntot = (int64_t)g.n[0] * g.n[1] * g.n[2];
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    if (jx[p] < g.n[0] && jy[p] < g.n[1] && (D == 2 || jz[p] < g.n[2])) {
-      const int64_t idx = ((int64_t)jz[p] * g.n[1] + jy[p]) * g.n[0] + jx[p];
-      for (int c = 0; c < a.nf; ++c) out[c * ntot + idx] = acc[p][c];
+  for (int c = 0; c < NF; ++c) {
+    if (c >= a.nf) break;
+#pragma unroll
+    for (int z = 0; z < kT3Z; ++z) red[(wave * kT3Z + z) * 64 + lane] = acc[z][c];
+    __syncthreads();
+    for (int o = tid; o < kT3Z * 64; o += 256) {
+      const int z = o >> 6, l = o & 63;
+      const T v = ((red[(0 * kT3Z + z) * 64 + l] + red[(1 * kT3Z + z) * 64 + l]) + red[(2 * kT3Z + z) * 64 + l]) +
+                  red[(3 * kT3Z + z) * 64 + l];
+      const int64_t idx = ((int64_t)(z0 + z) * g.n[1] + (y0 + l / kT3X)) * g.n[0] + x0 + l % kT3X;
+      out[c * ntot + idx] = v;
     }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, T* __restrict__ out) {
+  using T2 = cplx<T>;
+  using T4 = typename Pack4<T>::type;
+  constexpr int CH = spread_chunk<T>();
+  __shared__ T2 s_x[CH][kT2X];
+  __shared__ T2 s_y[CH][kT2Y];
+  __shared__ T4 s_c[CH][2];
+  const MarkerGeom& g = a.g;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tile = a.busy[blockIdx.x];
+  const int tx = tile % g.ntile[0];
+  const int ty = tile / g.ntile[0];
+  const int x0 = tx * kT2X, y0 = ty * kT2Y;
+  const int lx = lane % kT2X, yg = lane / kT2X;   // lane owns y = 4*yg + j, j < 4
+  const bool fddiv = NF == 1 && a.mode == SP_FDDIV;
+  T acc[4][NF];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int c = 0; c < NF; ++c) acc[j][c] = 0;
+  const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
+  const double hD = g.h * g.h;
+  for (int c0 = beg; c0 < end; c0 += CH) {
+    const int cnt = (end - c0) < CH ? (end - c0) : CH;
+    if (tid < cnt) {
+      const int m = a.list[c0 + tid];
+      const double* row = a.wt + (int64_t)m * 36;
+      tile_weights<kT2X>(row, x0, a.s[m * 3 + 0], g.n[0] - 1, s_x[tid]);
+      tile_weights<kT2Y>(row + 12, y0, a.s[m * 3 + 1], g.n[1] - 1, s_y[tid]);
+      double cf[8];
+      spread_coefs(a, m, 2, a.ds[m] / hD, cf);
+      s_c[tid][0] = mk4<T4>((T)cf[0], (T)cf[1], (T)cf[2], (T)cf[3]);
+      s_c[tid][1] = mk4<T4>((T)cf[4], (T)0, (T)0, (T)0);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = wave; k < cnt; k += 4) {
+      const T2 xv = s_x[k][lx];
+      const T4 c4 = s_c[k][0];
+      T2 yv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yv[j] = s_y[k][4 * yg + j];
+      if (fddiv) {
+        // v = c_x G_x W_y + c_y W_x G_y + c_mass W_x W_y
+        const T ax = c4.x * xv.y, am = c4.w * xv.x, ay = c4.y * xv.x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j][0] += (ax + am) * yv[j].x + ay * yv[j].y;
+      } else {
+        const T4 c5 = s_c[k][1];
+        const T cw[5] = {c4.x * xv.x, c4.y * xv.x, c4.z * xv.x, c4.w * xv.x, c5.x * xv.x};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < NF; ++c)
+            if (c < a.nf) acc[j][c] += cw[c] * yv[j].x;
+      }
+    }
+    __syncthreads();
+  }
+  T* red = reinterpret_cast<T*>(&s_x[0][0]);   // needs 4 * 4 * 64 values
+  const int64_t ntot = (int64_t)g.n[0] * g.n[1];
+#pragma unroll
+  for (int c = 0; c < NF; ++c) {
+    if (c >= a.nf) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[(wave * 4 + j) * 64 + lane] = acc[j][c];
+    __syncthreads();
+    {
+      const int o = tid;                // 256 tile nodes, one per thread
+      const int j = o >> 6, l = o & 63; // l: (x, y-group), j: y within the group
+      const T v = ((red[(0 * 4 + j) * 64 + l] + red[(1 * 4 + j) * 64 + l]) + red[(2 * 4 + j) * 64 + l]) +
+                  red[(3 * 4 + j) * 64 + l];
+      const int x = l % kT2X, y = 4 * (l / kT2X) + j;
+      out[c * ntot + (int64_t)(y0 + y) * g.n[0] + x0 + x] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -247,12 +389,13 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a, const T* __restric
   constexpr int T0 = (K == 4) ? 1 : 0;
   T w[3][K];
   int ix[3][K];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double fr = a.f[i * 3 + d];
+    const double* row = a.wt + (i * 3 + d) * 12;
     const int s = a.s[i * 3 + d];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-      w[d][t] = (d < D) ? (T)phi_eval(a.kernel, (double)(t + T0 - 2) - fr) : (T)(t == 0);
+      w[d][t] = (d < D) ? (T)row[t + T0] : (T)(t == 0);
       ix[d][t] = (d < D) ? ((s + t + T0) & (g.n[d] - 1)) : 0;
     }
   }
@@ -285,6 +428,12 @@ template <typename T>
 __global__ void k_axpby(T* __restrict__ y, double a, const T* __restrict__ x, double b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     y[e] = (T)(a * (double)x[e] + b * (double)y[e]);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ y, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = (T)0;
 }
 
 template <typename T>
@@ -326,19 +475,25 @@ inline unsigned grid_blocks(int64_t n) {
 
 }  // namespace
 
-void markers_setup(const MarkerGeom& g, int64_t n_ib, const double* X, int* s, double* f, int* tile_count,
-                   hipStream_t st) {
+void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* X, int* s, double* f, double* wt,
+                   int* tile_count, hipStream_t st) {
   const int64_t ntile = (int64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
   IBDL_HIP(hipMemsetAsync(tile_count, 0, sizeof(int) * ntile, st));
   if (n_ib > 0)
-    hipLaunchKernelGGL(k_marker_setup, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, g, n_ib, X, s, f,
-                       tile_count);
+    hipLaunchKernelGGL(k_marker_setup, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, g, kernel, n_ib, X,
+                       s, f, wt, tile_count);
   IBDL_LAUNCH_CHECK();
 }
 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count, int* tile_off,
-                 int* tile_cur, int* list, int* list_tmp, hipStream_t st) {
+                 int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off, hipStream_t st) {
   const int ntile = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  hipLaunchKernelGGL(k_busy_flags, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, tile_cur, ntile);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_cur, busy_off, ntile);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_busy_ids, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, busy_off, busy, ntile);
+  IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_count, tile_off, ntile);
   IBDL_LAUNCH_CHECK();
   IBDL_HIP(hipMemsetAsync(tile_cur, 0, sizeof(int) * ntile, st));
@@ -352,11 +507,19 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
 
 template <typename T>
 void spread(const SpreadArgs& a, T* out, hipStream_t st) {
-  const int ntile = a.g.ntile[0] * a.g.ntile[1] * a.g.ntile[2];
-  if (a.g.dim == 2)
-    hipLaunchKernelGGL((k_spread<T, 2>), dim3(ntile), dim3(256), 0, st, a, out);
-  else
-    hipLaunchKernelGGL((k_spread<T, 3>), dim3(ntile), dim3(256), 0, st, a, out);
+  // every node outside the non-empty tiles is zero: clear the fields, then spread tile by tile
+  const int64_t n = (int64_t)a.g.n[0] * a.g.n[1] * a.g.n[2] * a.nf;
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_blocks(n)), dim3(256), 0, st, out, n);
+  IBDL_LAUNCH_CHECK();
+  if (a.nbusy == 0) return;
+  const bool one = a.nf == 1;
+  if (a.g.dim == 2) {
+    if (one) hipLaunchKernelGGL((k_spread2<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, out);
+    else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, out);
+  } else {
+    if (one) hipLaunchKernelGGL((k_spread3<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, out);
+    else hipLaunchKernelGGL((k_spread3<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, out);
+  }
   IBDL_LAUNCH_CHECK();
 }
 

@@ -43,7 +43,10 @@ struct ibdl_s {
   double *X = nullptr, *nrm = nullptr, *ds = nullptr;
   int* s = nullptr;
   double* f = nullptr;
+  double* wt = nullptr;   // per-marker kernel weight table [n_ib][3][12]
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
+  int *busy = nullptr, *busy_off = nullptr;
+  int nbusy = 0;
   MarkerGeom geom{};
   std::unique_ptr<GridWork<float>> w32;
   std::unique_ptr<GridWork<double>> w64;
@@ -254,8 +257,11 @@ SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
   a.eta = h->cfg.eta;
   a.tile_off = h->tile_off;
   a.list = h->list;
+  a.busy = h->busy;
+  a.nbusy = h->nbusy;
   a.s = h->s;
   a.f = h->f;
+  a.wt = h->wt;
   a.q = q;
   a.nrm = h->nrm;
   a.ds = h->ds;
@@ -270,6 +276,7 @@ InterpArgs interp_args(ibdl_s* h, int nf, double a, double b, const double* x, c
   ia.n_ib = h->n_ib;
   ia.s = h->s;
   ia.f = h->f;
+  ia.wt = h->wt;
   ia.a = a;
   ia.b = b;
   ia.x = x;
@@ -529,9 +536,14 @@ void validate(const ibdl_config_t* c, int64_t n_ib) {
 }
 
 void build_markers(ibdl_s* h) {
-  markers_setup(h->geom, h->n_ib, h->X, h->s, h->f, h->tile_count, h->st);
-  markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->st);
+  markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
+  markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
+              h->busy_off, h->st);
+  const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
+  int nb = 0;
+  IBDL_HIP(hipMemcpyAsync(&nb, h->busy_off + ntile, sizeof(int), hipMemcpyDeviceToHost, h->st));
   IBDL_HIP(hipStreamSynchronize(h->st));
+  h->nbusy = nb;
 }
 
 template <typename F> ibdl_status_t guarded(ibdl_s* h, F&& fn) {
@@ -580,19 +592,23 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     for (int d = 0; d < 3; ++d) {
       g.n[d] = h->n[d];
       g.origin[d] = d < h->dim ? cfg->origin[d] : 0.0;
-      g.tile[d] = d < h->dim ? (h->dim == 2 ? 16 : 8) : 1;
+      const int t3[3] = {16, 4, 8};
+      g.tile[d] = d < h->dim ? (h->dim == 2 ? 16 : t3[d]) : 1;
       g.ntile[d] = g.n[d] / g.tile[d];
     }
     const int64_t ntile = (int64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    const int64_t maxlist = n_ib * (h->dim == 2 ? 4 : 8);
+    const int64_t maxlist = n_ib * (h->dim == 2 ? 4 : 12);   // tiles one 6-node window can meet
     h->X = (double*)h->dalloc<double>(sizeof(double) * n_ib * h->dim);
     h->nrm = (double*)h->dalloc<double>(sizeof(double) * n_ib * h->dim);
     h->ds = (double*)h->dalloc<double>(sizeof(double) * n_ib);
     h->s = (int*)h->dalloc<int>(sizeof(int) * n_ib * 3);
     h->f = (double*)h->dalloc<double>(sizeof(double) * n_ib * 3);
+    h->wt = (double*)h->dalloc<double>(sizeof(double) * n_ib * 36);
     h->tile_count = (int*)h->dalloc<int>(sizeof(int) * ntile);
     h->tile_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->tile_cur = (int*)h->dalloc<int>(sizeof(int) * ntile);
+    h->busy = (int*)h->dalloc<int>(sizeof(int) * ntile);
+    h->busy_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->small = (double*)h->dalloc<double>(sizeof(double) * 1024);

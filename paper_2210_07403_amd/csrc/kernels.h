@@ -51,15 +51,19 @@ struct MarkerGeom {
   int n[3];            // grid points per axis
   double origin[3];
   double h;
-  int tile[3];         // tile edge per axis
+  int tile[3];         // tile edge per axis (2-D: 16 x 16; 3-D: 16 x 4 x 8)
   int ntile[3];        // tiles per axis
 };
 
-// marker setup: window start s[i][3] (wrapped), fractional offset f[i][3], tile counts
-void markers_setup(const MarkerGeom& g, int64_t n_ib, const double* X, int* s, double* f,
-                   int* tile_count, hipStream_t st);
+// marker setup: window start s[i][3] (wrapped), fractional offset f[i][3], weight table
+// wt[i][3][12] (kernel weights W[0..5] and centred differences G[0..5] on the window), tile counts
+void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* X, int* s, double* f,
+                   double* wt, int* tile_count, hipStream_t st);
+// bin markers by tile (sorted candidate lists) and list the non-empty tiles: busy[0..nbusy) with
+// nbusy = busy_off[ntile]
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
-                 int* tile_off, int* tile_cur, int* list, int* list_tmp, hipStream_t st);
+                 int* tile_off, int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off,
+                 hipStream_t st);
 
 enum SpreadMode {
   SP_PLAIN = 0,     // nf fields: coef_c = f[i][c] ds_i h^-D
@@ -77,8 +81,11 @@ struct SpreadArgs {
   double eta;
   const int* tile_off;
   const int* list;
+  const int* busy;    // non-empty tile ids
+  int nbusy;
   const int* s;
   const double* f;
+  const double* wt;   // per-marker weight table [n_ib][3][12]
   const double* q;    // densities [n_ib][nq] (or generic values [n_ib][nf] for SP_PLAIN)
   const double* m;    // optional extra mass values [n_ib] (Neumann V_b), may be null
   const double* nrm;  // [n_ib][dim]
@@ -93,6 +100,7 @@ struct InterpArgs {
   int64_t n_ib;
   const int* s;
   const double* f;
+  const double* wt;    // per-marker weight table [n_ib][3][12]
   double a;            // out = a * S*u + b * x + ub
   double b;
   const double* x;     // [n_ib][nf] or null
