@@ -136,6 +136,16 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int*
   if (threadIdx.x == 0) off[n] = carry;
 }
 
+// per-precision weight table: (W[t], G[t]) pairs, t < 6, padded with zeros at t = 6, 7
+template <typename T>
+__global__ void k_wtab(const double* __restrict__ wt, int64_t n_ib, cplx<T>* __restrict__ tab) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (marker, axis, tap)
+  if (e >= n_ib * 24) return;
+  const int64_t r = e >> 3;
+  const int t = (int)(e & 7);
+  tab[e] = t < 6 ? mk<cplx<T>>((T)wt[r * 12 + t], (T)wt[r * 12 + 6 + t]) : mk<cplx<T>>((T)0, (T)0);
+}
+
 // ids of the tiles with at least one candidate, in increasing order (off is the exclusive scan of
 // the 0/1 flags computed by k_busy_flags)
 __global__ void k_busy_flags(const int* __restrict__ cnt, int* __restrict__ flag, int n) {
@@ -174,19 +184,6 @@ template <typename T> struct Pack4;
 template <> struct Pack4<float> { using type = float4; };
 template <> struct Pack4<double> { using type = double4; };
 
-// W and G of one marker at LEN consecutive tile nodes org .. org+LEN-1 along one axis, looked up
-// in the marker's weight table row (W[0..5], G[0..5]); zero outside the marker's window
-template <int LEN, typename T2>
-__device__ __forceinline__ void tile_weights(const double* __restrict__ row, int org, int sd, int mask,
-                                             T2* __restrict__ wg) {
-  using T = decltype(T2::x);
-#pragma unroll
-  for (int j = 0; j < LEN; ++j) {
-    const int t = (org + j - sd) & mask;   // window tap of tile node j
-    wg[j] = t < 6 ? mk<T2>((T)row[t], (T)row[6 + t]) : mk<T2>((T)0, (T)0);
-  }
-}
-
 // per-marker coefficients of the spread fields (times ds / h^D)
 __device__ __forceinline__ void spread_coefs(const SpreadArgs& a, int m, int D, double base, double* cf) {
   for (int c = 0; c < 8; ++c) cf[c] = 0.0;
@@ -210,24 +207,40 @@ __device__ __forceinline__ void spread_coefs(const SpreadArgs& a, int m, int D, 
   }
 }
 
-template <typename T> constexpr int spread_chunk() { return sizeof(T) == 4 ? 128 : 64; }
+// Lanes used per wave for candidates in one pass (LDS budget: 32 KiB / 48 KiB per block).
+template <typename T> constexpr int spread_lanes() { return sizeof(T) == 4 ? 64 : 32; }
 
+// broadcast a lane's value to the whole wave (scalar register), any 32/64-bit type
+template <typename T> __device__ __forceinline__ T bcast(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  }
+}
+
+// Each wave takes the candidates c0 + 4*l + wave (l < LW) of the tile's sorted list, one per lane:
+// the lane keeps the candidate's uniform data (window start, the tile-aligned z column of (W, G),
+// field coefficients) in registers, and the accumulation loop broadcasts them with readlane; only
+// the lane-varying x / y weights come from LDS rows written by the owning lane.
 template <typename T, int NF>
-__global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
   using T2 = cplx<T>;
-  using T4 = typename Pack4<T>::type;
-  constexpr int CH = spread_chunk<T>();
-  __shared__ T2 s_x[CH][kT3X];             // (W, G) at the tile's x nodes
-  __shared__ T2 s_y[CH][kT3Y];
-  __shared__ T4 s_z[CH][6];                // W z[8], G z[8], coefficients[8]
+  constexpr int LW = spread_lanes<T>();
+  __shared__ T2 s_r[4][LW][2][8];          // x and y window rows (W, G), zero at taps 6 and 7
   const MarkerGeom& g = a.g;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tile = a.busy[blockIdx.x];
   const int tx = tile % g.ntile[0];
   const int ty = (tile / g.ntile[0]) % g.ntile[1];
   const int tz = tile / (g.ntile[0] * g.ntile[1]);
   const int x0 = tx * kT3X, y0 = ty * kT3Y, z0 = tz * kT3Z;
   const int lx = lane % kT3X, ly = lane / kT3X;
+  const int mx = g.n[0] - 1, my = g.n[1] - 1, mz = g.n[2] - 1;
   const bool fddiv = NF == 1 && a.mode == SP_FDDIV;
   T acc[kT3Z][NF];
 #pragma unroll
@@ -236,52 +249,60 @@ __global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, T* __restrict__ o
     for (int c = 0; c < NF; ++c) acc[z][c] = 0;
   const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
   const double hD = g.h * g.h * g.h;
-  for (int c0 = beg; c0 < end; c0 += CH) {
-    const int cnt = (end - c0) < CH ? (end - c0) : CH;
-    if (tid < cnt) {
-      const int m = a.list[c0 + tid];
-      const double* row = a.wt + (int64_t)m * 36;
-      tile_weights<kT3X>(row, x0, a.s[m * 3 + 0], g.n[0] - 1, s_x[tid]);
-      tile_weights<kT3Y>(row + 12, y0, a.s[m * 3 + 1], g.n[1] - 1, s_y[tid]);
-      T2 zw[kT3Z];
-      tile_weights<kT3Z>(row + 24, z0, a.s[m * 3 + 2], g.n[2] - 1, zw);
-      double cf[8];
-      spread_coefs(a, m, 3, a.ds[m] / hD, cf);
-      s_z[tid][0] = mk4<T4>(zw[0].x, zw[1].x, zw[2].x, zw[3].x);
-      s_z[tid][1] = mk4<T4>(zw[4].x, zw[5].x, zw[6].x, zw[7].x);
-      s_z[tid][2] = mk4<T4>(zw[0].y, zw[1].y, zw[2].y, zw[3].y);
-      s_z[tid][3] = mk4<T4>(zw[4].y, zw[5].y, zw[6].y, zw[7].y);
-      s_z[tid][4] = mk4<T4>((T)cf[0], (T)cf[1], (T)cf[2], (T)cf[3]);
-      s_z[tid][5] = mk4<T4>((T)cf[4], (T)0, (T)0, (T)0);
+  for (int c0 = beg; c0 < end; c0 += 4 * LW) {
+    // candidates of this wave in this pass
+    const int left = end - c0 - wave;
+    const int cnt = left <= 0 ? 0 : ((left + 3) / 4 < LW ? (left + 3) / 4 : LW);
+    int sx = 0, sy = 0;
+    T2 zr[kT3Z];
+    T cf[5];
+#pragma unroll
+    for (int z = 0; z < kT3Z; ++z) zr[z] = mk<T2>((T)0, (T)0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) cf[c] = 0;
+    if (lane < cnt) {
+      const int m = a.list[c0 + 4 * lane + wave];
+      const T2* row = wtab + (int64_t)m * 24;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        s_r[wave][lane][0][t] = row[t];
+        s_r[wave][lane][1][t] = row[8 + t];
+      }
+      sx = a.s[m * 3 + 0];
+      sy = a.s[m * 3 + 1];
+      const int sz = a.s[m * 3 + 2];
+#pragma unroll
+      for (int z = 0; z < kT3Z; ++z) zr[z] = row[16 + min((z0 + z - sz) & mz, 6)];
+      double c8[8];
+      spread_coefs(a, m, 3, a.ds[m] / hD, c8);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) cf[c] = (T)c8[c];
     }
     __syncthreads();
-#pragma unroll 2
-    for (int k = wave; k < cnt; k += 4) {
-      const T2 xv = s_x[k][lx], yv = s_y[k][ly];
-      const T4 w0 = s_z[k][0], w1 = s_z[k][1], c4 = s_z[k][4];
-      const T wz[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    for (int j = 0; j < cnt; ++j) {
+      const int bx = bcast(sx, j), by = bcast(sy, j);
+      const T2 xv = s_r[wave][j][0][min((x0 + lx - bx) & mx, 6)];
+      const T2 yv = s_r[wave][j][1][min((y0 + ly - by) & my, 6)];
       if (fddiv) {
-        const T4 g0 = s_z[k][2], g1 = s_z[k][3];
-        const T gz[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-        const T A = c4.x * xv.y * yv.x + c4.y * xv.x * yv.y + c4.w * xv.x * yv.x;
-        const T B = c4.z * xv.x * yv.x;
+        const T A = bcast(cf[0], j) * xv.y * yv.x + bcast(cf[1], j) * xv.x * yv.y + bcast(cf[3], j) * xv.x * yv.x;
+        const T B = bcast(cf[2], j) * xv.x * yv.x;
 #pragma unroll
-        for (int z = 0; z < kT3Z; ++z) acc[z][0] += A * wz[z] + B * gz[z];
+        for (int z = 0; z < kT3Z; ++z) acc[z][0] += A * bcast(zr[z].x, j) + B * bcast(zr[z].y, j);
       } else {
-        const T4 c5 = s_z[k][5];
         const T w2 = xv.x * yv.x;
-        const T cw[5] = {c4.x * w2, c4.y * w2, c4.z * w2, c4.w * w2, c5.x * w2};
 #pragma unroll
-        for (int z = 0; z < kT3Z; ++z)
+        for (int z = 0; z < kT3Z; ++z) {
+          const T wz = w2 * bcast(zr[z].x, j);
 #pragma unroll
           for (int c = 0; c < NF; ++c)
-            if (c < a.nf) acc[z][c] += cw[c] * wz[z];
+            if (c < a.nf) acc[z][c] += bcast(cf[c], j) * wz;
+        }
       }
     }
     __syncthreads();
   }
   // fixed-order reduction of the four waves' partial sums, one field at a time
-  T* red = reinterpret_cast<T*>(&s_x[0][0]);   // needs 4 * 8 * 64 values
+  T* red = reinterpret_cast<T*>(&s_r[0][0][0][0]);   // needs 4 * 8 * 64 values
   const int64_t ntot = (int64_t)g.n[0] * g.n[1] * g.n[2];
 #pragma unroll
   for (int c = 0; c < NF; ++c) {
@@ -300,21 +321,23 @@ __global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, T* __restrict__ o
   }
 }
 
+// 2-D: lane (x, y-group) owns y = 4*yg + j' (j' < 4); the owning lane of a candidate writes its x row
+// and its tile-aligned y column (16 pairs) to LDS; coefficients and the x window start are broadcast.
 template <typename T, int NF>
-__global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
   using T2 = cplx<T>;
-  using T4 = typename Pack4<T>::type;
-  constexpr int CH = spread_chunk<T>();
-  __shared__ T2 s_x[CH][kT2X];
-  __shared__ T2 s_y[CH][kT2Y];
-  __shared__ T4 s_c[CH][2];
+  constexpr int LW = spread_lanes<T>();
+  __shared__ T2 s_x[4][LW][8];
+  __shared__ T2 s_y[4][LW][kT2Y];
   const MarkerGeom& g = a.g;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tile = a.busy[blockIdx.x];
   const int tx = tile % g.ntile[0];
   const int ty = tile / g.ntile[0];
   const int x0 = tx * kT2X, y0 = ty * kT2Y;
-  const int lx = lane % kT2X, yg = lane / kT2X;   // lane owns y = 4*yg + j, j < 4
+  const int lx = lane % kT2X, yg = lane / kT2X;
+  const int mx = g.n[0] - 1, my = g.n[1] - 1;
   const bool fddiv = NF == 1 && a.mode == SP_FDDIV;
   T acc[4][NF];
 #pragma unroll
@@ -323,57 +346,66 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, T* __restrict__ o
     for (int c = 0; c < NF; ++c) acc[j][c] = 0;
   const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
   const double hD = g.h * g.h;
-  for (int c0 = beg; c0 < end; c0 += CH) {
-    const int cnt = (end - c0) < CH ? (end - c0) : CH;
-    if (tid < cnt) {
-      const int m = a.list[c0 + tid];
-      const double* row = a.wt + (int64_t)m * 36;
-      tile_weights<kT2X>(row, x0, a.s[m * 3 + 0], g.n[0] - 1, s_x[tid]);
-      tile_weights<kT2Y>(row + 12, y0, a.s[m * 3 + 1], g.n[1] - 1, s_y[tid]);
-      double cf[8];
-      spread_coefs(a, m, 2, a.ds[m] / hD, cf);
-      s_c[tid][0] = mk4<T4>((T)cf[0], (T)cf[1], (T)cf[2], (T)cf[3]);
-      s_c[tid][1] = mk4<T4>((T)cf[4], (T)0, (T)0, (T)0);
+  for (int c0 = beg; c0 < end; c0 += 4 * LW) {
+    const int left = end - c0 - wave;
+    const int cnt = left <= 0 ? 0 : ((left + 3) / 4 < LW ? (left + 3) / 4 : LW);
+    int sx = 0;
+    T cf[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) cf[c] = 0;
+    if (lane < cnt) {
+      const int m = a.list[c0 + 4 * lane + wave];
+      const T2* row = wtab + (int64_t)m * 24;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s_x[wave][lane][t] = row[t];
+      sx = a.s[m * 3 + 0];
+      const int sy = a.s[m * 3 + 1];
+#pragma unroll
+      for (int y = 0; y < kT2Y; ++y) s_y[wave][lane][y] = row[8 + min((y0 + y - sy) & my, 6)];
+      double c8[8];
+      spread_coefs(a, m, 2, a.ds[m] / hD, c8);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) cf[c] = (T)c8[c];
     }
     __syncthreads();
-#pragma unroll 2
-    for (int k = wave; k < cnt; k += 4) {
-      const T2 xv = s_x[k][lx];
-      const T4 c4 = s_c[k][0];
+    for (int j = 0; j < cnt; ++j) {
+      const int bx = bcast(sx, j);
+      const T2 xv = s_x[wave][j][min((x0 + lx - bx) & mx, 6)];
       T2 yv[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) yv[j] = s_y[k][4 * yg + j];
+      for (int q = 0; q < 4; ++q) yv[q] = s_y[wave][j][4 * yg + q];
       if (fddiv) {
         // v = c_x G_x W_y + c_y W_x G_y + c_mass W_x W_y
-        const T ax = c4.x * xv.y, am = c4.w * xv.x, ay = c4.y * xv.x;
+        const T ax = bcast(cf[0], j) * xv.y + bcast(cf[3], j) * xv.x, ay = bcast(cf[1], j) * xv.x;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j][0] += (ax + am) * yv[j].x + ay * yv[j].y;
+        for (int q = 0; q < 4; ++q) acc[q][0] += ax * yv[q].x + ay * yv[q].y;
       } else {
-        const T4 c5 = s_c[k][1];
-        const T cw[5] = {c4.x * xv.x, c4.y * xv.x, c4.z * xv.x, c4.w * xv.x, c5.x * xv.x};
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int c = 0; c < NF; ++c) {
+          if (c < a.nf) {
+            const T cx = bcast(cf[c], j) * xv.x;
 #pragma unroll
-          for (int c = 0; c < NF; ++c)
-            if (c < a.nf) acc[j][c] += cw[c] * yv[j].x;
+            for (int q = 0; q < 4; ++q) acc[q][c] += cx * yv[q].x;
+          }
+        }
       }
     }
     __syncthreads();
   }
-  T* red = reinterpret_cast<T*>(&s_x[0][0]);   // needs 4 * 4 * 64 values
+  T* red = reinterpret_cast<T*>(&s_y[0][0][0]);   // needs 4 * 4 * 64 values
   const int64_t ntot = (int64_t)g.n[0] * g.n[1];
 #pragma unroll
   for (int c = 0; c < NF; ++c) {
     if (c >= a.nf) break;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[(wave * 4 + j) * 64 + lane] = acc[j][c];
+    for (int q = 0; q < 4; ++q) red[(wave * 4 + q) * 64 + lane] = acc[q][c];
     __syncthreads();
     {
       const int o = tid;                // 256 tile nodes, one per thread
-      const int j = o >> 6, l = o & 63; // l: (x, y-group), j: y within the group
-      const T v = ((red[(0 * 4 + j) * 64 + l] + red[(1 * 4 + j) * 64 + l]) + red[(2 * 4 + j) * 64 + l]) +
-                  red[(3 * 4 + j) * 64 + l];
-      const int x = l % kT2X, y = 4 * (l / kT2X) + j;
+      const int q = o >> 6, l = o & 63; // l: (x, y-group), q: y within the group
+      const T v = ((red[(0 * 4 + q) * 64 + l] + red[(1 * 4 + q) * 64 + l]) + red[(2 * 4 + q) * 64 + l]) +
+                  red[(3 * 4 + q) * 64 + l];
+      const int x = l % kT2X, y = 4 * (l / kT2X) + q;
       out[c * ntot + (int64_t)(y0 + y) * g.n[0] + x0 + x] = v;
     }
     __syncthreads();
@@ -420,6 +452,46 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a, const T* __restric
     if (a.x) v += a.b * a.x[i * a.nf + c];
     if (a.ub) v += a.ub[c];
     out[i * a.nf + c] = v;
+  }
+}
+
+// 4-point kernels: a group of RL = 4^(D-1) lanes per marker, lane r of the group sums the 4 x-taps of
+// stencil row r; the row sums are reduced across the group by a fixed butterfly (deterministic).
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __restrict__ wtab, const T* __restrict__ u,
+                                                 double* __restrict__ out) {
+  constexpr int RL = (D == 3) ? 16 : 4;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / RL;
+  const int r = (int)(gid % RL);
+  const bool valid = i < a.n_ib;
+  const int64_t im = valid ? i : 0;
+  const MarkerGeom& g = a.g;
+  const cplx<T>* row = wtab + im * 24;       // axis d taps at row[d*8 + t], t = 1..4 non-zero
+  const int sx = a.s[im * 3 + 0], sy = a.s[im * 3 + 1], sz = a.s[im * 3 + 2];
+  const int ty = r & 3, tz = r >> 2;         // stencil row (y tap, z tap)
+  const T wyz = row[8 + 1 + ty].x * (D == 3 ? row[16 + 1 + tz].x : (T)1);
+  const int64_t base = ((int64_t)(D == 3 ? ((sz + 1 + tz) & (g.n[2] - 1)) : 0) * g.n[1] +
+                        ((sy + 1 + ty) & (g.n[1] - 1))) * g.n[0];
+  int ix[4];
+  T wx[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ix[t] = (sx + 1 + t) & (g.n[0] - 1);
+    wx[t] = row[1 + t].x;
+  }
+  const int64_t ntot = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+  for (int c = 0; c < a.nf; ++c) {
+    const T* uc = u + c * ntot + base;
+    T v = ((uc[ix[0]] * wx[0] + uc[ix[1]] * wx[1]) + uc[ix[2]] * wx[2] + uc[ix[3]] * wx[3]) * wyz;
+#pragma unroll
+    for (int off = 1; off < RL; off <<= 1) v += __shfl_xor(v, off, RL);
+    if (valid && r == 0) {
+      double o = a.a * (double)v;
+      if (a.x) o += a.b * a.x[i * a.nf + c];
+      if (a.ub) o += a.ub[c];
+      out[i * a.nf + c] = o;
+    }
   }
 }
 
@@ -506,7 +578,7 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
 }
 
 template <typename T>
-void spread(const SpreadArgs& a, T* out, hipStream_t st) {
+void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
   // every node outside the non-empty tiles is zero: clear the fields, then spread tile by tile
   const int64_t n = (int64_t)a.g.n[0] * a.g.n[1] * a.g.n[2] * a.nf;
   hipLaunchKernelGGL((k_fill<T>), dim3(grid_blocks(n)), dim3(256), 0, st, out, n);
@@ -514,26 +586,35 @@ void spread(const SpreadArgs& a, T* out, hipStream_t st) {
   if (a.nbusy == 0) return;
   const bool one = a.nf == 1;
   if (a.g.dim == 2) {
-    if (one) hipLaunchKernelGGL((k_spread2<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, out);
-    else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, out);
+    if (one) hipLaunchKernelGGL((k_spread2<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+    else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   } else {
-    if (one) hipLaunchKernelGGL((k_spread3<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, out);
-    else hipLaunchKernelGGL((k_spread3<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, out);
+    if (one) hipLaunchKernelGGL((k_spread3<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+    else hipLaunchKernelGGL((k_spread3<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   }
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
-void interp(const InterpArgs& a, const T* u, double* out, hipStream_t st) {
+void weight_table(const double* wt, int64_t n_ib, cplx<T>* tab, hipStream_t st) {
+  const int64_t n = n_ib * 24;
+  if (n > 0) hipLaunchKernelGGL((k_wtab<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, wt, n_ib, tab);
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
+void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, hipStream_t st) {
   if (a.n_ib == 0) return;
-  const dim3 grid((unsigned)((a.n_ib + 255) / 256));
   const bool six = a.kernel == KID_BSPLINE6;
-  if (a.g.dim == 2) {
-    if (six) hipLaunchKernelGGL((k_interp<T, 2, 6>), grid, dim3(256), 0, st, a, u, out);
-    else hipLaunchKernelGGL((k_interp<T, 2, 4>), grid, dim3(256), 0, st, a, u, out);
+  if (six) {
+    const dim3 grid((unsigned)((a.n_ib + 255) / 256));
+    if (a.g.dim == 2) hipLaunchKernelGGL((k_interp<T, 2, 6>), grid, dim3(256), 0, st, a, u, out);
+    else hipLaunchKernelGGL((k_interp<T, 3, 6>), grid, dim3(256), 0, st, a, u, out);
   } else {
-    if (six) hipLaunchKernelGGL((k_interp<T, 3, 6>), grid, dim3(256), 0, st, a, u, out);
-    else hipLaunchKernelGGL((k_interp<T, 3, 4>), grid, dim3(256), 0, st, a, u, out);
+    const int64_t lanes = a.n_ib * (a.g.dim == 3 ? 16 : 4);
+    const dim3 grid((unsigned)((lanes + 255) / 256));
+    if (a.g.dim == 2) hipLaunchKernelGGL((k_interp4<T, 2>), grid, dim3(256), 0, st, a, wtab, u, out);
+    else hipLaunchKernelGGL((k_interp4<T, 3>), grid, dim3(256), 0, st, a, wtab, u, out);
   }
   IBDL_LAUNCH_CHECK();
 }
@@ -559,8 +640,9 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
 }
 
 #define IBDL_IB_INST(T)                                                                   \
-  template void spread<T>(const SpreadArgs&, T*, hipStream_t);                            \
-  template void interp<T>(const InterpArgs&, const T*, double*, hipStream_t);             \
+  template void spread<T>(const SpreadArgs&, const cplx<T>*, T*, hipStream_t);            \
+  template void weight_table<T>(const double*, int64_t, cplx<T>*, hipStream_t);           \
+  template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
   template void grid_add_const<T>(T*, const double*, int, int64_t, hipStream_t);          \
   template void grid_sum<T>(const T*, int, int64_t, double*, int, double*, hipStream_t);

@@ -22,6 +22,7 @@ template <typename T> struct GridWork {
   T* kt[3] = {nullptr, nullptr, nullptr};
   T* real = nullptr;
   cplx<T>* spec = nullptr;
+  cplx<T>* wtab = nullptr;   // marker weight table in this precision
   int nfields = 0;
 };
 
@@ -164,6 +165,8 @@ template <typename T> GridWork<T>& ensure_work(ibdl_s* h) {
   W.nfields = nf;
   W.real = (T*)h->dalloc<T>(sizeof(T) * h->ntot * nf);
   W.spec = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->nspec * nf);
+  W.wtab = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->n_ib * 24);
+  weight_table<T>(h->wt, h->n_ib, W.wtab, h->st);
   for (int d = 0; d < h->dim; ++d) {
     const int n = h->n[d];
     std::vector<cplx<T>> tw(n);
@@ -301,7 +304,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     SpreadArgs a = spread_args(h, SP_STOKES, nf, q);
     {
       StageTimer t(h, ST_SPREAD);
-      spread<T>(a, W.real, h->st);
+      spread<T>(a, W.wtab, W.real, h->st);
     }
     if (g) grid_axpby<T>(W.real + 3 * h->ntot, -1.0, g, 1.0, 2 * h->ntot, h->st);
     md.nc = nf;
@@ -318,7 +321,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     a.m = m;
     {
       StageTimer t(h, ST_SPREAD);
-      spread<T>(a, W.real, h->st);
+      spread<T>(a, W.wtab, W.real, h->st);
     }
     if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
     md.nc = 1;
@@ -330,7 +333,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     a.m = m;
     {
       StageTimer t(h, ST_SPREAD);
-      spread<T>(a, W.real, h->st);
+      spread<T>(a, W.wtab, W.real, h->st);
     }
     if (g) grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
     md.nc = nf;
@@ -350,7 +353,7 @@ template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
   InterpArgs ia = interp_args(h, h->nq, 1.0, half, q, ub);
   {
     StageTimer t(h, ST_INTERP);
-    interp<T>(ia, W.real, y, h->st);
+    interp<T>(ia, W.wtab, W.real, y, h->st);
   }
   if (h->has_ubar) {
     const int nblk = kr_nblk(h->n_ib);
@@ -382,15 +385,15 @@ template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, doub
   const int64_t nb = h->n_ib * h->nq;
   if (h->neumann()) {
     SpreadArgs a = spread_args(h, SP_PLAIN, 1, data);
-    spread<T>(a, W.real, h->st);
+    spread<T>(a, W.wtab, W.real, h->st);
     if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
     grid_solve_t<T>(h, W.real, W.real);
     InterpArgs ia = interp_args(h, 1, 1.0, 0.0, nullptr, nullptr);
-    interp<T>(ia, W.real, b, h->st);
+    interp<T>(ia, W.wtab, W.real, b, h->st);
   } else if (g) {
     grid_solve_t<T>(h, g, W.real);
     InterpArgs ia = interp_args(h, h->nq, -1.0, 1.0, data, nullptr);
-    interp<T>(ia, W.real, b, h->st);
+    interp<T>(ia, W.wtab, W.real, b, h->st);
   } else {
     IBDL_HIP(hipMemcpyAsync(b, data, sizeof(double) * nb, hipMemcpyDeviceToDevice, h->st));
   }
@@ -544,6 +547,8 @@ void build_markers(ibdl_s* h) {
   IBDL_HIP(hipMemcpyAsync(&nb, h->busy_off + ntile, sizeof(int), hipMemcpyDeviceToHost, h->st));
   IBDL_HIP(hipStreamSynchronize(h->st));
   h->nbusy = nb;
+  if (h->w32 && h->w32->wtab) weight_table<float>(h->wt, h->n_ib, h->w32->wtab, h->st);
+  if (h->w64 && h->w64->wtab) weight_table<double>(h->wt, h->n_ib, h->w64->wtab, h->st);
 }
 
 template <typename F> ibdl_status_t guarded(ibdl_s* h, F&& fn) {
@@ -654,8 +659,8 @@ ibdl_status_t ibdl_spread(ibdl_t h, const double* f, int32_t nc, void* grid) {
     if (!f || !grid) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (nc < 1 || nc > 5) throw Error(IBDL_ERR_ARG, "nc must be in [1, 5]");
     SpreadArgs a = spread_args(h, SP_PLAIN, nc, f);
-    if (h->mixed()) spread<float>(a, (float*)grid, h->st);
-    else spread<double>(a, (double*)grid, h->st);
+    if (h->mixed()) spread<float>(a, ensure_work<float>(h).wtab, (float*)grid, h->st);
+    else spread<double>(a, ensure_work<double>(h).wtab, (double*)grid, h->st);
     return IBDL_OK;
   });
 }
@@ -665,8 +670,8 @@ ibdl_status_t ibdl_interp(ibdl_t h, const void* grid, int32_t nc, double* f) {
     if (!f || !grid) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (nc < 1 || nc > 5) throw Error(IBDL_ERR_ARG, "nc must be in [1, 5]");
     InterpArgs ia = interp_args(h, nc, 1.0, 0.0, nullptr, nullptr);
-    if (h->mixed()) interp<float>(ia, (const float*)grid, f, h->st);
-    else interp<double>(ia, (const double*)grid, f, h->st);
+    if (h->mixed()) interp<float>(ia, ensure_work<float>(h).wtab, (const float*)grid, f, h->st);
+    else interp<double>(ia, ensure_work<double>(h).wtab, (const double*)grid, f, h->st);
     return IBDL_OK;
   });
 }

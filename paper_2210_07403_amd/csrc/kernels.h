@@ -91,7 +91,9 @@ struct SpreadArgs {
   const double* nrm;  // [n_ib][dim]
   const double* ds;   // [n_ib]
 };
-template <typename T> void spread(const SpreadArgs& a, T* out, hipStream_t st);
+// wtab: per-precision weight table [n_ib][3][8] of (W, G) pairs (weight_table)
+template <typename T> void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st);
+template <typename T> void weight_table(const double* wt, int64_t n_ib, cplx<T>* tab, hipStream_t st);
 
 struct InterpArgs {
   MarkerGeom g;
@@ -106,7 +108,7 @@ struct InterpArgs {
   const double* x;     // [n_ib][nf] or null
   const double* ub;    // [nf] or null
 };
-template <typename T> void interp(const InterpArgs& a, const T* u, double* out, hipStream_t st);
+template <typename T> void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, hipStream_t st);
 
 // ------------------------------------------------------------------ grid elementwise
 template <typename T> void grid_axpby(T* y, double a, const T* x, double b, int64_t n, hipStream_t st);
