@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}   # MI355X dense vector FP32 / FP64
 METRIC = "IBDL operator applies/sec + GMRES solves/sec at 1e-8 residual; % HBM peak"
 
 
@@ -46,8 +47,9 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def stage_bytes(spec, prec, pr):
-    """Algorithmic HBM bytes per launch of each stage of one operator apply."""
+def stage_cost(spec, prec, pr):
+    """Algorithmic cost per launch of each stage of one operator apply: HBM bytes for the
+    memory-bound passes, floating-point operations for the spread (bound by vector ALU issue)."""
     t = 4 if prec == "mixed" else 8
     ntot = pr.grid_points
     nxh = spec.n[0] // 2 + 1
@@ -56,19 +58,48 @@ def stage_bytes(spec, prec, pr):
     scalar_fd = spec.pde != "stokes" and spec.disc == "fd2"
     c = 1 if scalar_fd else (5 if spec.pde == "stokes" else spec.dim + (1 if spec.eta > 0 else 0))
     o = pr.nq
-    marker = spec.n_ib * (12 + 24 + 8 * pr.nq + 8 * spec.dim + 8)
     taps = 4 ** spec.dim
     b = {
-        "spread": c * R + marker,
-        "fft_x_fwd": c * (R + C),
-        "fused_last_axis": (c + o) * C,
-        "fft_x_inv": o * (C + R),
-        "interp": spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2),
+        "fill": ("hbm", c * R),
+        "fft_x_fwd": ("hbm", c * (R + C)),
+        "fused_last_axis": ("hbm", (c + o) * C),
+        "fft_x_inv": ("hbm", o * (C + R)),
+        "interp": ("hbm", spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2)),
     }
     if spec.dim == 3:
-        b["fft_y_fwd"] = 2 * c * C
-        b["fft_y_inv"] = 2 * o * C
+        b["fft_y_fwd"] = ("hbm", 2 * c * C)
+        b["fft_y_inv"] = ("hbm", 2 * o * C)
+    # spread: per marker and window node, D-1 products per term and one add per term; the
+    # finite-difference dipole spread has D derivative terms (+ mass), other modes c fields
+    if scalar_fd:
+        flops = spec.n_ib * 6 ** spec.dim * ((spec.dim + 1) * spec.dim)
+    else:
+        flops = spec.n_ib * taps * c * spec.dim
+    b["spread"] = ("alu", flops)
     return b
+
+
+def sources_digest():
+    import hashlib
+    hsh = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2210_07403_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        hsh.update(open(os.path.join(csrc, f), "rb").read())
+    return hsh.hexdigest()[:16]
+
+
+def load_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources") != sources_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(spec, budget_s=20.0):
@@ -106,6 +137,8 @@ def main():
     ap.add_argument("--workload", default="sphere256", choices=["sphere256", "star1024", "circle64"])
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the IBDL library has no multi-GPU path (see the design notes); "
@@ -162,14 +195,34 @@ def main():
         pr.apply(q)
     stages = pr.timing()
     pr.set_timing(False)
-    sb = stage_bytes(spec, prec, pr)
+    cost = stage_cost(spec, prec, pr)
     per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items() if v[1]}
     dom = max(per, key=per.get)
-    ach = sb[dom] / (per[dom] * 1e-3) / 1e9
-    stage_report = {k: {"ms": round(per[k], 5), "GB": round(sb.get(k, 0) / 1e9, 5),
-                        "GB_s": round(sb.get(k, 0) / (per[k] * 1e-3) / 1e9, 1) if per[k] > 0 else None}
-                    for k in per}
-    apply_bytes = sum(sb.values())
+    stage_report = {}
+    for k in per:
+        kind, amount = cost.get(k, ("hbm", 0))
+        rate = amount / (per[k] * 1e-3) if per[k] > 0 else 0.0
+        stage_report[k] = {"ms": round(per[k], 5), "bound": kind,
+                           ("GB" if kind == "hbm" else "GFLOP"): round(amount / 1e9, 5),
+                           ("GB_s" if kind == "hbm" else "TFLOP_s"): round(rate / (1e9 if kind == "hbm" else 1e12), 3)}
+    kind, amount = cost[dom]
+    if kind == "hbm":
+        ach = amount / (per[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4)}
+    else:
+        ach = amount / (per[dom] * 1e-3) / 1e12
+        peak = VALU_PEAK_TFLOPS[prec]
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 5)}
+    roof["traffic"] = load_traffic(args.workload, dom)
+    apply_bytes = sum(v[1] for k, v in cost.items() if v[0] == "hbm")
+    if args.calibrate_copy:
+        x = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev).fill_(1.0)   # 256 MiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
 
     total_applies = int(sum(iters))
     out = {
@@ -195,8 +248,7 @@ def main():
         "apply_effective_GB_s": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1),
         "apply_frac_hbm_peak": round(apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "stages": stage_report,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline": roof,
     }
     pr.close()
     if not args.no_cpu_baseline:

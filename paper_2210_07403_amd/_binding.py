@@ -72,7 +72,7 @@ def header_symbols(path: str = HEADER):
 
 
 STAGES = ["spread", "fft_x_fwd", "fft_y_fwd", "fused_last_axis", "fft_y_inv", "fft_x_inv", "interp",
-          "krylov", "other"]
+          "krylov", "fill"]
 
 
 class IBDLError(RuntimeError):

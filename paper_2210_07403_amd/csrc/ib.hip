@@ -578,11 +578,14 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
 }
 
 template <typename T>
-void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
-  // every node outside the non-empty tiles is zero: clear the fields, then spread tile by tile
-  const int64_t n = (int64_t)a.g.n[0] * a.g.n[1] * a.g.n[2] * a.nf;
-  hipLaunchKernelGGL((k_fill<T>), dim3(grid_blocks(n)), dim3(256), 0, st, out, n);
+void grid_fill_zero(T* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_blocks(n)), dim3(256), 0, st, y, n);
   IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
+void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
+  // nodes outside the non-empty tiles are not written: the caller clears the fields first
   if (a.nbusy == 0) return;
   const bool one = a.nf == 1;
   if (a.g.dim == 2) {
@@ -642,6 +645,7 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
 #define IBDL_IB_INST(T)                                                                   \
   template void spread<T>(const SpreadArgs&, const cplx<T>*, T*, hipStream_t);            \
   template void weight_table<T>(const double*, int64_t, cplx<T>*, hipStream_t);           \
+  template void grid_fill_zero<T>(T*, int64_t, hipStream_t);                              \
   template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
   template void grid_add_const<T>(T*, const double*, int, int64_t, hipStream_t);          \

@@ -137,7 +137,7 @@ namespace {
 
 // Stage ids reported by ibdl_get_timing.
 enum Stage { ST_SPREAD = 0, ST_FFT_X_FWD = 1, ST_FFT_Y_FWD = 2, ST_FUSED = 3, ST_FFT_Y_INV = 4, ST_FFT_X_INV = 5,
-             ST_INTERP = 6, ST_KRYLOV = 7, ST_OTHER = 8, ST_COUNT = 9 };
+             ST_INTERP = 6, ST_KRYLOV = 7, ST_FILL = 8, ST_COUNT = 9 };
 
 struct StageTimer {
   ibdl_s* h;
@@ -303,6 +303,10 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     const int nf = (h->cfg.eta > 0 || g) ? 5 : 3;
     SpreadArgs a = spread_args(h, SP_STOKES, nf, q);
     {
+      StageTimer t(h, ST_FILL);
+      grid_fill_zero<T>(W.real, h->ntot * a.nf, h->st);
+    }
+    {
       StageTimer t(h, ST_SPREAD);
       spread<T>(a, W.wtab, W.real, h->st);
     }
@@ -320,6 +324,10 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     a.mass = (h->cfg.eta > 0 || m != nullptr) ? 1 : 0;
     a.m = m;
     {
+      StageTimer t(h, ST_FILL);
+      grid_fill_zero<T>(W.real, h->ntot * a.nf, h->st);
+    }
+    {
       StageTimer t(h, ST_SPREAD);
       spread<T>(a, W.wtab, W.real, h->st);
     }
@@ -331,6 +339,10 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     SpreadArgs a = spread_args(h, SP_SCALAR_VEC, nf, q);
     a.mass = mass ? 1 : 0;
     a.m = m;
+    {
+      StageTimer t(h, ST_FILL);
+      grid_fill_zero<T>(W.real, h->ntot * a.nf, h->st);
+    }
     {
       StageTimer t(h, ST_SPREAD);
       spread<T>(a, W.wtab, W.real, h->st);
@@ -385,6 +397,7 @@ template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, doub
   const int64_t nb = h->n_ib * h->nq;
   if (h->neumann()) {
     SpreadArgs a = spread_args(h, SP_PLAIN, 1, data);
+    grid_fill_zero<T>(W.real, h->ntot, h->st);
     spread<T>(a, W.wtab, W.real, h->st);
     if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
     grid_solve_t<T>(h, W.real, W.real);
@@ -659,8 +672,13 @@ ibdl_status_t ibdl_spread(ibdl_t h, const double* f, int32_t nc, void* grid) {
     if (!f || !grid) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (nc < 1 || nc > 5) throw Error(IBDL_ERR_ARG, "nc must be in [1, 5]");
     SpreadArgs a = spread_args(h, SP_PLAIN, nc, f);
-    if (h->mixed()) spread<float>(a, ensure_work<float>(h).wtab, (float*)grid, h->st);
-    else spread<double>(a, ensure_work<double>(h).wtab, (double*)grid, h->st);
+    if (h->mixed()) {
+      grid_fill_zero<float>((float*)grid, h->ntot * nc, h->st);
+      spread<float>(a, ensure_work<float>(h).wtab, (float*)grid, h->st);
+    } else {
+      grid_fill_zero<double>((double*)grid, h->ntot * nc, h->st);
+      spread<double>(a, ensure_work<double>(h).wtab, (double*)grid, h->st);
+    }
     return IBDL_OK;
   });
 }

@@ -91,7 +91,10 @@ struct SpreadArgs {
   const double* nrm;  // [n_ib][dim]
   const double* ds;   // [n_ib]
 };
-// wtab: per-precision weight table [n_ib][3][8] of (W, G) pairs (weight_table)
+// Spread over the non-empty tiles only: nodes of empty tiles are left untouched, so the caller
+// clears the nf output fields first (grid_fill_zero).  wtab: per-precision weight table
+// [n_ib][3][8] of (W, G) pairs (weight_table).
+template <typename T> void grid_fill_zero(T* y, int64_t n, hipStream_t st);
 template <typename T> void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st);
 template <typename T> void weight_table(const double* wt, int64_t n_ib, cplx<T>* tab, hipStream_t st);
 
