@@ -79,6 +79,21 @@ def stage_cost(spec, prec, pr):
     return b
 
 
+def model_bytes(spec, prec, pr):
+    """Bytes of one apply when every stage is materialised in HBM with the unfused field counts
+    (c spread fields: D divergence components (+1 mass), Stokes 5; o = nq inverse fields), and
+    the fused floor that keeps only the FFT passes over the half spectra."""
+    t = 4 if prec == "mixed" else 8
+    ntot = pr.grid_points
+    nspec = ntot // spec.n[0] * (spec.n[0] // 2 + 1)
+    R, C = ntot * t, nspec * 2 * t
+    c = 5 if spec.pde == "stokes" else spec.dim + (1 if spec.eta > 0 else 0)
+    o = pr.nq
+    if spec.dim == 3:
+        return (2 * c + o) * R + (4 * c + 4 * o) * C, (4 * c + 4 * o) * C
+    return (2 * c + o) * R + (2 * c + 2 * o) * C, (2 * c + 2 * o) * C
+
+
 def sources_digest():
     import hashlib
     hsh = hashlib.sha256()
@@ -217,6 +232,7 @@ def main():
                 "frac": round(ach / peak, 5)}
     roof["traffic"] = load_traffic(args.workload, dom)
     apply_bytes = sum(v[1] for k, v in cost.items() if v[0] == "hbm")
+    mu, mf = model_bytes(spec, prec, pr)
     if args.calibrate_copy:
         x = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev).fill_(1.0)   # 256 MiB
         y = torch.empty_like(x)
@@ -247,6 +263,10 @@ def main():
         "apply_ms": round(apply_ms, 5),
         "apply_effective_GB_s": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1),
         "apply_frac_hbm_peak": round(apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "model_U_GB": round(mu / 1e9, 4),
+        "model_U_effective_GB_s": round(mu / (apply_ms * 1e-3) / 1e9, 1),
+        "model_U_frac_hbm_peak": round(mu / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "model_F_effective_GB_s": round(mf / (apply_ms * 1e-3) / 1e9, 1),
         "stages": stage_report,
         "roofline": roof,
     }
