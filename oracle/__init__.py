@@ -8,12 +8,15 @@ seeded input generators.
 Modules: delta (regularized delta kernels), ib (grid, S, S*), grid
 (finite-difference / spectral operators and inverses), ibdl (boundary
 operators A, right-hand sides, grid recovery, dense assembly), gmres
-(textbook GMRES), norms (error norms).
+(textbook GMRES), norms (error norms), adjoint (exact gradients of a loss of the
+grid solution with respect to the markers and the boundary data, by forward-mode
+differentiation of the forward map with dense solves).
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
 closed forms, kernel identities, adjointness, real-space stencils, PDE
-residuals and the iteration counts the thesis prints.  The 3-D operator has
+residuals and the iteration counts the thesis prints; the gradients by central
+differences of the pinned forward map (tests/test_oracle_adjoint.py).  The 3-D operator has
 no printed thesis value; it is pinned by closed-form convergence only.
 """
-from . import delta, gmres, grid, ib, ibdl, norms  # noqa: F401
+from . import adjoint, delta, gmres, grid, ib, ibdl, norms  # noqa: F401
 from .ibdl import Setup  # noqa: F401

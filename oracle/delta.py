@@ -42,6 +42,49 @@ def phi_bspline6(r):
     return out
 
 
+def dphi_peskin4(r):
+    """d phi / d r of the 4-point kernel (derivative of each piece in |r|, times sign r)."""
+    r = np.asarray(r, dtype=np.float64)
+    a = np.abs(r)
+    out = np.zeros_like(a)
+    m1 = a <= 1.0
+    m2 = (a > 1.0) & (a < 2.0)
+    x = a[m1]
+    out[m1] = (-2.0 + (4.0 - 8.0 * x) / (2.0 * np.sqrt(1.0 + 4.0 * x - 4.0 * x ** 2))) / 8.0
+    x = a[m2]
+    out[m2] = (-2.0 - (12.0 - 8.0 * x) / (2.0 * np.sqrt(np.maximum(-7.0 + 12.0 * x - 4.0 * x ** 2, 1e-300)))) / 8.0
+    return np.sign(r) * out
+
+
+def dphi_cos4(r):
+    r = np.asarray(r, dtype=np.float64)
+    return np.where(np.abs(r) < 2.0, -0.125 * np.pi * np.sin(0.5 * np.pi * r), 0.0)
+
+
+def dphi_bspline6(r):
+    r = np.asarray(r, dtype=np.float64)
+    a = np.abs(r)
+    out = np.zeros_like(a)
+    m1 = a <= 1.0
+    m2 = (a > 1.0) & (a <= 2.0)
+    m3 = (a > 2.0) & (a < 3.0)
+    x = a[m1]
+    out[m1] = -x + x ** 3 - 5 * x ** 4 / 12
+    x = a[m2]
+    out[m2] = 5 / 8 - 7 * x / 2 + 15 * x ** 2 / 4 - 3 * x ** 3 / 2 + 5 * x ** 4 / 24
+    x = a[m3]
+    out[m3] = -27 / 8 + 9 * x / 2 - 9 * x ** 2 / 4 + x ** 3 / 2 - x ** 4 / 24
+    return np.sign(r) * out
+
+
+DERIVATIVES = {"peskin4": dphi_peskin4, "cos4": dphi_cos4, "bspline6": dphi_bspline6}
+
+
+def dkernel(name):
+    """phi' of the named kernel (used for derivatives with respect to marker positions)."""
+    return DERIVATIVES[name]
+
+
 KERNELS = {
     "peskin4": (phi_peskin4, 2),
     "cos4": (phi_cos4, 2),

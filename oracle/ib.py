@@ -16,7 +16,7 @@ import itertools
 
 import numpy as np
 
-from .delta import kernel as _kernel
+from .delta import dkernel as _dkernel, kernel as _kernel
 
 
 class Grid:
@@ -97,4 +97,62 @@ def interp(grid: Grid, X, u, kname):
         where = tuple(idx[d][:, taps[d]] for d in reversed(range(grid.dim)))
         for c in range(u2.shape[0]):
             out[:, c] += u2[c][where] * wt
+    return out if vec else out[:, 0]
+
+
+def _weights_dX(grid: Grid, X, kname):
+    """Stencil of `stencil` plus d/dX_d of each weight: d phi((x_j - X)/h) / dX = -phi'(r) / h."""
+    idx, w = stencil(grid, X, kname)
+    dphi = _dkernel(kname)
+    _, S = _kernel(kname)
+    offs = np.arange(-S + 1, S + 1)
+    dw = []
+    for d in range(grid.dim):
+        xi = (X[:, d] - grid.origin[d]) / grid.h
+        j = np.floor(xi).astype(np.int64)[:, None] + offs[None, :]
+        dw.append(-dphi(j - xi[:, None]) / grid.h)
+    return idx, w, dw
+
+
+def spread_dX(grid: Grid, X, ds, F, kname, dX):
+    """Directional derivative d/dt S(X + t dX) F at t = 0 (S as in `spread`, ds held fixed)."""
+    F = np.asarray(F, dtype=np.float64)
+    vec = F.ndim == 2
+    F2 = F if vec else F[:, None]
+    nc = F2.shape[1]
+    idx, w, dw = _weights_dX(grid, X, kname)
+    out = np.zeros((nc,) + grid.shape)
+    ntap = idx[0].shape[1]
+    scale = ds / grid.h ** grid.dim
+    for taps in itertools.product(range(ntap), repeat=grid.dim):
+        dwt = np.zeros(X.shape[0])
+        for e in range(grid.dim):          # product rule over the D factors
+            t = np.ones(X.shape[0])
+            for d, k in enumerate(taps):
+                t = t * (dw[d][:, k] if d == e else w[d][:, k])
+            dwt = dwt + dX[:, e] * t
+        where = tuple(idx[d][:, taps[d]] for d in reversed(range(grid.dim)))
+        for c in range(nc):
+            np.add.at(out[c], where, F2[:, c] * scale * dwt)
+    return out if vec else out[0]
+
+
+def interp_dX(grid: Grid, X, u, kname, dX):
+    """Directional derivative d/dt S*(X + t dX) u at t = 0."""
+    u = np.asarray(u, dtype=np.float64)
+    vec = u.ndim == grid.dim + 1
+    u2 = u if vec else u[None]
+    idx, w, dw = _weights_dX(grid, X, kname)
+    out = np.zeros((X.shape[0], u2.shape[0]))
+    ntap = idx[0].shape[1]
+    for taps in itertools.product(range(ntap), repeat=grid.dim):
+        dwt = np.zeros(X.shape[0])
+        for e in range(grid.dim):
+            t = np.ones(X.shape[0])
+            for d, k in enumerate(taps):
+                t = t * (dw[d][:, k] if d == e else w[d][:, k])
+            dwt = dwt + dX[:, e] * t
+        where = tuple(idx[d][:, taps[d]] for d in reversed(range(grid.dim)))
+        for c in range(u2.shape[0]):
+            out[:, c] += u2[c][where] * dwt
     return out if vec else out[:, 0]
