@@ -130,6 +130,28 @@ ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y);
 ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, double tol,
                          int32_t maxit, double* q, void* u_grid, ibdl_info_t* info);
 
+/* y = A^T p, the transpose of the operator of ibdl_apply (same layout and precision rules).
+ * With Phi the interpolation matrix (S* = Phi, Sec. 2.2.2), S = h^-D Phi^T diag(ds) and the grid
+ * operators' transposes (L^-1 symmetric, D_d^T = -D_d with the Nyquist reading of the spectral
+ * derivative), A^T p = J p/2 + K^T Phi^T p (+ eta ds p_ubar; u_bar rows: sum_i p_i), where K is the
+ * density-to-grid map of the operator.  p, y: device double [n_aug], must not alias. */
+ibdl_status_t ibdl_apply_transpose(ibdl_t h, const double* p, double* y);
+
+/* Gradients of a loss L(u) of the grid solution of ibdl_solve with respect to the marker positions
+ * and the boundary data, normals and weights held fixed (the thesis's forward map, Sec. 5.3.2,
+ * 5.3.3, 6.3.3, differentiated by the adjoint method):
+ *   solve A^T mu = (du/dq)^T psi with GMRES (tol, maxit as in ibdl_solve), dL/ddata = mu,
+ *   dL/dX_ie = -sum_c mu_ic (Phi'_e u_c)_i + (kernel-derivative gathers of the adjoint fields),
+ * where Phi'_e holds the derivatives of the interpolation weights, -phi'(r_e)/h prod_{d!=e} phi(r_d).
+ *   q: the forward solution (device double [n_aug]); u_grid: the forward grid solution
+ *   ([nq][grid], grid type) for the handle's current markers; dL_du: psi, the gradient of L with
+ *   respect to the grid values ([nq][grid], grid type); dL_dX: output device double [n_ib][dim]
+ *   or NULL; dL_ddata: output device double [n_ib][nq] or NULL; info: the adjoint GMRES.
+ * Dirichlet problems (scalar, completed, Brinkman/Stokes); IBDL_ERR_UNSUPPORTED for Neumann.
+ * Synchronises like ibdl_solve. */
+ibdl_status_t ibdl_backward(ibdl_t h, const double* q, const void* u_grid, const void* dL_du, double tol,
+                            int32_t maxit, double* dL_dX, double* dL_ddata, ibdl_info_t* info);
+
 /* Sizes of the handle: n_aug (unknowns), grid points per component, grid components of the
  * solution (nq).  Any output pointer may be NULL. */
 ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq);

@@ -15,7 +15,7 @@ import torch
 
 from . import _binding as B
 
-__all__ = ["Problem", "SolveInfo", "IBDLError"]
+__all__ = ["Problem", "SolveInfo", "IBDLError", "IBDLSolve", "ibdl_solve"]
 
 IBDLError = B.IBDLError
 
@@ -110,6 +110,7 @@ class Problem:
     def set_markers(self, X, nrm, ds):
         Xd, Nd, Dd = _dev_f64(X, self.device), _dev_f64(nrm, self.device), _dev_f64(ds, self.device)
         B.check(B.load().ibdl_set_markers(self._h, Xd.data_ptr(), Nd.data_ptr(), Dd.data_ptr()), self._h)
+        self._markers_token = object()
 
     def spread(self, f):
         """S: marker values (n_ib,) or (n_ib, nc) -> grid (nc, ...)."""
@@ -142,6 +143,30 @@ class Problem:
         B.check(B.load().ibdl_apply(self._h, qt.data_ptr(), y.data_ptr()), self._h)
         return y
 
+    def apply_transpose(self, p):
+        pt = _dev_f64(p, self.device).reshape(-1)
+        if pt.numel() != self.n_aug:
+            raise ValueError(f"p must have n_aug = {self.n_aug} entries")
+        y = torch.empty_like(pt)
+        B.check(B.load().ibdl_apply_transpose(self._h, pt.data_ptr(), y.data_ptr()), self._h)
+        return y
+
+    def backward(self, q, u, dL_du, tol=1e-8, maxit=100):
+        """Adjoint gradients (dL/dX (n_ib, dim), dL/ddata (n_ib * nq,), SolveInfo of the adjoint
+        GMRES) for the forward solution q, u of the current markers and dL/du on the grid."""
+        qt = _dev_f64(q, self.device).reshape(-1)
+        if qt.numel() != self.n_aug:
+            raise ValueError(f"q must have n_aug = {self.n_aug} entries")
+        ut = self._as_grid(u, self.nq)
+        gt = self._as_grid(dL_du, self.nq)
+        dX = torch.empty((self.n_ib, self.dim), dtype=torch.float64, device=self.device)
+        dd = torch.empty(self.n_ib * self.nq, dtype=torch.float64, device=self.device)
+        info = B.Info()
+        st = B.load().ibdl_backward(self._h, qt.data_ptr(), ut.data_ptr(), gt.data_ptr(), float(tol), int(maxit),
+                                    dX.data_ptr(), dd.data_ptr(), ctypes.byref(info))
+        B.check(st, self._h)
+        return dX, dd, SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64, [])
+
     def set_timing(self, enable=True):
         B.check(B.load().ibdl_set_timing(self._h, 1 if enable else 0), self._h)
 
@@ -173,3 +198,38 @@ class Problem:
         if u is not None and self.nq == 1:
             u = u[0]
         return q, u, res
+
+
+class IBDLSolve(torch.autograd.Function):
+    """u = the IBDL grid solution for markers X and boundary data (normals, weights and forcing
+    held fixed), differentiable in X and data through ibdl_backward.
+
+    Call as IBDLSolve.apply(problem, X, nrm, ds, data, g, tol, maxit) or via ibdl_solve(...)."""
+
+    @staticmethod
+    def forward(ctx, problem, X, nrm, ds, data, g, tol, maxit):
+        problem.set_markers(X.detach(), nrm, ds)
+        q, u, _ = problem.solve(data.detach(), g, tol=tol, maxit=maxit)
+        ctx.problem, ctx.tol, ctx.maxit = problem, tol, maxit
+        ctx.token = problem._markers_token
+        ctx.shapes = (X.shape, data.shape)
+        ctx.save_for_backward(X.detach().to(torch.float64), torch.as_tensor(nrm, dtype=torch.float64),
+                              torch.as_tensor(ds, dtype=torch.float64), q, u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        X, nrm, ds, q, u = ctx.saved_tensors
+        pr = ctx.problem
+        if getattr(pr, "_markers_token", None) is not ctx.token:
+            pr.set_markers(X, nrm, ds)
+            ctx.token = pr._markers_token
+        dX, dd, _ = pr.backward(q, u, grad_u.contiguous(), tol=ctx.tol, maxit=ctx.maxit)
+        xs, ds_shape = ctx.shapes
+        return (None, dX.reshape(xs) if ctx.needs_input_grad[1] else None, None, None,
+                dd.reshape(ds_shape) if ctx.needs_input_grad[4] else None, None, None, None)
+
+
+def ibdl_solve(problem, X, nrm, ds, data, g=None, tol=1e-8, maxit=100):
+    """Differentiable IBDL solve: returns the grid solution u (see IBDLSolve)."""
+    return IBDLSolve.apply(problem, X, nrm, ds, data, g, tol, maxit)

@@ -43,6 +43,9 @@ _SIGS = {
     "ibdl_apply": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                              ctypes.POINTER(Info)]),
+    "ibdl_apply_transpose": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ibdl_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
+                                ctypes.POINTER(Info)]),
     "ibdl_query": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64), ctypes.POINTER(c_int32)]),
     "ibdl_last_error": (ctypes.c_char_p, [c_void_p]),
     "ibdl_set_timing": (c_int32, [c_void_p, c_int32]),

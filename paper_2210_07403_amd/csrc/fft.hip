@@ -433,6 +433,71 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   }
 }
 
+// Transposed / multi-output pass: the NI input spectra stay in registers after their forward
+// FFTs and the no outputs are formed, inverse transformed and stored one at a time (inputs are
+// all read before the first store, and each workgroup owns its lines in every field).
+template <typename T, int N, int NI, int MODE>
+__global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data, int64_t P, int no, MultDesc md,
+                                                      const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TC = TileCfg<T, N>;
+  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int tid = threadIdx.x;
+  const int c = tid % TC::W, i = tid / TC::W;
+  const int64_t l = (int64_t)blockIdx.x * TC::W + c;
+  const bool valid = l < P;
+  const int64_t FS = P * N;
+  const int jx = (int)(valid ? l % md.nxh : 0);
+  const int jy2 = (int)(valid ? l / md.nxh : 0);
+  const bool d3 = md.dim == 3;
+  const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
+  const T* ktl_ = static_cast<const T*>(md.kt[d3 ? 2 : 1]);
+  T sig_l = static_cast<const T*>(md.sig[0])[jx];
+  T ktl[3];
+  ktl[0] = static_cast<const T*>(md.kt[0])[jx];
+  ktl[1] = 0;
+  ktl[2] = 0;
+  if (d3) {
+    sig_l += static_cast<const T*>(md.sig[1])[jy2];
+    ktl[1] = static_cast<const T*>(md.kt[1])[jy2];
+  }
+  const int la = d3 ? 2 : 1;
+  C v[NI][RM];
+#pragma unroll
+  for (int f = 0; f < NI; ++f) {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) v[f][s] = valid ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+    fft_line<N, false>(v[f], i, lds + c, TC::W, tw, 1);
+  }
+  for (int o = 0; o < no; ++o) {
+    C acc[RM];
+#pragma unroll
+    for (int s = 0; s < RM; ++s) {
+      const int e = i + s * TT;
+      T kt[3] = {ktl[0], ktl[1], ktl[2]};
+      kt[la] = ktl_[e];
+      const T sig = sig_l + sgl[e];
+      if constexpr (MODE == 1) {
+        const T den = (T)md.c2 * sig - (T)md.c0;
+        const T g = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) / den;
+        const T ko = o == 0 ? kt[0] : (o == 1 ? kt[1] : kt[2]);
+        acc[s] = o < md.dim ? mul_ir(v[0][s], g * ko) : cscale(v[0][s], g);
+      } else {
+        acc[s] = mk<C>(0, 0);
+#pragma unroll
+        for (int f = 0; f < NI; ++f) acc[s] = cadd(acc[s], cmul(cconj(mult_coef<T>(md, md.fk[o], f, sig, kt)), v[f][s]));
+      }
+    }
+    fft_line<N, true>(acc, i, lds + c, TC::W, tw, 1);
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < RM; ++s) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[s];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ dispatch helpers
 template <typename F> void dispatch_n(int n, F&& f) {
   switch (n) {
@@ -501,7 +566,13 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
     using TC = TileCfg<T, N>;
     const int64_t nb = (P + TC::W - 1) / TC::W;
     const size_t lds = sizeof(cplx<T>) * N * TC::W;
-    if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)
+    if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1)
+      hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, no, md, tw);
+    else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5)
+      hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, no, md, tw);
+    else if (md.mode != 0)
+      throw Error(-2, "fused pass: unsupported transposed multiplier");
+    else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)
       hipLaunchKernelGGL((k_fused1<T, N>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
     else if (!md.stokes && no == 1)
       hipLaunchKernelGGL((k_fused<T, N, 1, false>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);

@@ -33,6 +33,22 @@ __device__ __forceinline__ double phi_eval(int kernel, double r) {
   return 0.0;
 }
 
+// d phi / d r, the derivative of each piece in |r| times the sign of r
+__device__ __forceinline__ double dphi_eval(int kernel, double r) {
+  const double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+  double v = 0.0;
+  if (kernel == KID_PESKIN4) {
+    if (a <= 1.0) v = (-2.0 + (4.0 - 8.0 * a) / (2.0 * sqrt(1.0 + 4.0 * a - 4.0 * a * a))) * 0.125;
+    else if (a < 2.0) v = (-2.0 - (12.0 - 8.0 * a) / (2.0 * sqrt(fmax(-7.0 + 12.0 * a - 4.0 * a * a, 1e-300)))) * 0.125;
+    return sg * v;
+  }
+  if (kernel == KID_COS4) return a < 2.0 ? -0.125 * M_PI * sinpi(0.5 * r) : 0.0;
+  if (a <= 1.0) v = -a + a * a * a - 5.0 * a * a * a * a / 12.0;
+  else if (a <= 2.0) v = 5.0 / 8.0 - 7.0 * a / 2.0 + 15.0 * a * a / 4.0 - 3.0 * a * a * a / 2.0 + 5.0 * a * a * a * a / 24.0;
+  else if (a < 3.0) v = -27.0 / 8.0 + 9.0 * a / 2.0 - 9.0 * a * a / 4.0 + a * a * a / 2.0 - a * a * a * a / 24.0;
+  return sg * v;
+}
+
 // ------------------------------------------------------------------ marker setup and binning
 // Tiles met by a marker's 6-node window along each axis: tile indices j0 .. j0 + cnt - 1 (mod ntile).
 __device__ __forceinline__ void marker_tiles(const MarkerGeom& g, const int* s, int (&j0)[3], int (&cnt)[3]) {
@@ -274,7 +290,7 @@ __global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, const cplx<T>* __
 #pragma unroll
       for (int z = 0; z < kT3Z; ++z) zr[z] = row[16 + min((z0 + z - sz) & mz, 6)];
       double c8[8];
-      spread_coefs(a, m, 3, a.ds[m] / hD, c8);
+      spread_coefs(a, m, 3, a.raw ? 1.0 : a.ds[m] / hD, c8);
 #pragma unroll
       for (int c = 0; c < 5; ++c) cf[c] = (T)c8[c];
     }
@@ -363,7 +379,7 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
 #pragma unroll
       for (int y = 0; y < kT2Y; ++y) s_y[wave][lane][y] = row[8 + min((y0 + y - sy) & my, 6)];
       double c8[8];
-      spread_coefs(a, m, 2, a.ds[m] / hD, c8);
+      spread_coefs(a, m, 2, a.raw ? 1.0 : a.ds[m] / hD, c8);
 #pragma unroll
       for (int c = 0; c < 5; ++c) cf[c] = (T)c8[c];
     }
@@ -495,6 +511,52 @@ __global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __
   }
 }
 
+// ------------------------------------------------------------------ kernel-derivative gather
+// One thread per marker over its K^D window (K = 4: taps 1..4 of the 6-node window; K = 6: all),
+// in double: out[i][e] = sum_x F_i(x) (-phi'(r_e)/h) prod_{d != e} phi(r_d), r_d = (x_d - X_id)/h.
+template <typename T, int D, int K>
+__global__ __launch_bounds__(256) void k_gather_dx(GatherArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_ib) return;
+  const MarkerGeom& g = a.g;
+  constexpr int T0 = (K == 4) ? 1 : 0;
+  double w[3][K], dw[3][K];
+  int ix[3][K];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int s = a.s[i * 3 + d];
+    const double fr = a.f[i * 3 + d];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double r = (double)(t + T0 - 2) - fr;
+      w[d][t] = d < D ? phi_eval(a.kernel, r) : (t == 0 ? 1.0 : 0.0);
+      dw[d][t] = d < D ? -dphi_eval(a.kernel, r) / g.h : 0.0;
+      ix[d][t] = d < D ? ((s + t + T0) & (g.n[d] - 1)) : 0;
+    }
+  }
+  double cf[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) cf[k] = k < a.nfield ? a.coef[i * a.nfield + k] : 0.0;
+  double acc[3] = {0.0, 0.0, 0.0};
+  constexpr int KZ = (D == 3) ? K : 1;
+  for (int tz = 0; tz < KZ; ++tz) {
+    for (int ty = 0; ty < K; ++ty) {
+      const int64_t row = ((int64_t)(D == 3 ? ix[2][tz] : 0) * g.n[1] + ix[1][ty]) * g.n[0];
+      const double wz = D == 3 ? w[2][tz] : 1.0, dwz = D == 3 ? dw[2][tz] : 0.0;
+      for (int tx = 0; tx < K; ++tx) {
+        const int64_t idx = row + ix[0][tx];
+        double F = 0.0;
+        for (int k = 0; k < a.nfield; ++k) F += cf[k] * (double)static_cast<const T*>(a.field[k])[idx];
+        acc[0] += F * dw[0][tx] * w[1][ty] * wz;
+        acc[1] += F * w[0][tx] * dw[1][ty] * wz;
+        if (D == 3) acc[2] += F * w[0][tx] * w[1][ty] * dwz;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < D; ++e) a.out[i * D + e] = acc[e];
+}
+
 // ------------------------------------------------------------------ grid elementwise
 template <typename T>
 __global__ void k_axpby(T* __restrict__ y, double a, const T* __restrict__ x, double b, int64_t n) {
@@ -623,6 +685,22 @@ void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, h
 }
 
 template <typename T>
+void gather_dx(const GatherArgs& a, hipStream_t st) {
+  if (a.n_ib == 0) return;
+  if (a.nfield < 1 || a.nfield > 8) throw Error(-1, "gather_dx: 1..8 fields");
+  const dim3 grid((unsigned)((a.n_ib + 255) / 256));
+  const bool six = a.kernel == KID_BSPLINE6;
+  if (a.g.dim == 2) {
+    if (six) hipLaunchKernelGGL((k_gather_dx<T, 2, 6>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gather_dx<T, 2, 4>), grid, dim3(256), 0, st, a);
+  } else {
+    if (six) hipLaunchKernelGGL((k_gather_dx<T, 3, 6>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gather_dx<T, 3, 4>), grid, dim3(256), 0, st, a);
+  }
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
 void grid_axpby(T* y, double a, const T* x, double b, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_axpby<T>), dim3(grid_blocks(n)), dim3(256), 0, st, y, a, x, b, n);
   IBDL_LAUNCH_CHECK();
@@ -648,6 +726,7 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
   template void grid_fill_zero<T>(T*, int64_t, hipStream_t);                              \
   template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
+  template void gather_dx<T>(const GatherArgs&, hipStream_t);                             \
   template void grid_add_const<T>(T*, const double*, int, int64_t, hipStream_t);          \
   template void grid_sum<T>(const T*, int, int64_t, double*, int, double*, hipStream_t);
 IBDL_IB_INST(float)

@@ -59,6 +59,8 @@ struct ibdl_s {
   double* vb = nullptr;       // right-hand side
   double* vr = nullptr;       // residual scratch
   double* hostbuf = nullptr;  // pinned host scratch (1024 doubles)
+  double* adj_m = nullptr;    // adjoint: interpolated fields / gather weights [n_ib][8]
+  double* adj_mu = nullptr;   // adjoint solution [n_aug]
   std::vector<void*> allocs;
   std::string err;
   // optional per-stage timing with HIP events on the handle's stream
@@ -90,6 +92,16 @@ struct ibdl_s {
     pending.clear();
   }
 
+  void dfree(void* p) {
+    if (!p) return;
+    for (size_t k = 0; k < allocs.size(); ++k)
+      if (allocs[k] == p) {
+        if (st) IBDL_HIP(hipStreamSynchronize(st));
+        IBDL_HIP(hipFree(p));
+        allocs.erase(allocs.begin() + (long)k);
+        return;
+      }
+  }
   template <typename T> void* dalloc(size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 16;
@@ -196,6 +208,18 @@ template <typename T> GridWork<T>& ensure_work(ibdl_s* h) {
     IBDL_HIP(hipMemcpy(W.sig[d], sg.data(), sizeof(T) * len, hipMemcpyHostToDevice));
     IBDL_HIP(hipMemcpy(W.kt[d], kt.data(), sizeof(T) * len, hipMemcpyHostToDevice));
   }
+  return W;
+}
+
+// grow the real and spectral work arrays to nf fields (contents are not kept)
+template <typename T> GridWork<T>& ensure_fields(ibdl_s* h, int nf) {
+  GridWork<T>& W = ensure_work<T>(h);
+  if (W.nfields >= nf) return W;
+  h->dfree(W.real);
+  h->dfree(W.spec);
+  W.real = (T*)h->dalloc<T>(sizeof(T) * h->ntot * nf);
+  W.spec = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->nspec * nf);
+  W.nfields = nf;
   return W;
 }
 
@@ -428,7 +452,134 @@ template <typename T> void recover_t(ibdl_s* h, const double* q, const double* d
   if (h->has_ubar) grid_add_const<T>(u, q + h->n_ib * h->nq, h->nq, h->ntot, h->st);
 }
 
-void apply_any(ibdl_s* h, const double* q, double* y, bool force64) {
+// ------------------------------------------------------------------ transposed operator
+// The operator is A = [[J/2 + Phi K, ubar columns], [border rows]] with Phi the interpolation
+// matrix (S* = Phi), K the density-to-grid map u[Q] (scalar: -L^-1 (S~ + eta S); Stokes: the
+// Sec. 6.3.2 map) and J = +-I.  Its transpose needs K^T, which is, per marker, h^-D ds_i times the
+// derivative of the spread coefficients applied to Phi (transposed multiplier) of a grid field:
+//   scalar:  K^T v = h^-D ds (.) (sum_d n_d Phi D_d L^-1 v - eta Phi L^-1 v)   (D_d^T = -D_d)
+//   Stokes:  K^T v = h^-D ds (.) sum_f (d c_f / d Q) Phi T_f^T v
+// adj_grid applies the grid part to the nq fields at src and leaves its nout fields at dst.
+int adj_nout(ibdl_s* h) {
+  if (h->stokes()) return h->cfg.eta > 0 ? 5 : 3;
+  return h->dim + (h->cfg.eta > 0 ? 1 : 0);
+}
+
+template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst) {
+  MultDesc md = base_desc<T>(h, W);
+  const int nout = adj_nout(h);
+  md.alpha = 1.0;
+  if (h->stokes()) {
+    md.mode = 2;
+    md.nc = 2;
+    const int kinds[5] = {FK_A11, FK_A12, FK_A22, FK_G1, FK_G2};
+    for (int o = 0; o < nout; ++o) md.fk[o] = kinds[o];
+  } else {
+    md.mode = 1;
+    md.nc = 1;
+    md.fk[0] = FK_MASS;
+  }
+  pipeline<T>(h, W, src, md.nc, dst, nout, md);
+}
+
+void ensure_adj(ibdl_s* h) {
+  if (h->adj_m) return;
+  h->adj_m = (double*)h->dalloc<double>(sizeof(double) * h->n_ib * 8);
+  h->adj_mu = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
+}
+
+// interpolate the nout adjoint fields at W.real and combine them per marker into y (+ b p, ubar terms)
+template <typename T> void adj_markers(ibdl_s* h, GridWork<T>& W, const double* p, double b, const double* pu,
+                                       double* y) {
+  const int nout = adj_nout(h);
+  InterpArgs ia = interp_args(h, nout, 1.0, 0.0, nullptr, nullptr);
+  {
+    StageTimer t(h, ST_INTERP);
+    interp<T>(ia, W.wtab, W.real, h->adj_m, h->st);
+  }
+  const double hDinv = 1.0 / pow(h->h, (double)h->dim);
+  adj_combine(h->stokes() ? 1 : 0, h->dim, h->n_ib, nout, hDinv, h->cfg.eta, h->adj_m, h->nrm, h->ds, p, b, pu, y,
+              h->st);
+}
+
+// y = A^T p
+template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
+  GridWork<T>& W = ensure_fields<T>(h, std::max(adj_nout(h), h->nq));
+  ensure_adj(h);
+  SpreadArgs a = spread_args(h, SP_PLAIN, h->nq, p);
+  a.raw = 1;
+  {
+    StageTimer t(h, ST_FILL);
+    grid_fill_zero<T>(W.real, h->ntot * h->nq, h->st);
+  }
+  {
+    StageTimer t(h, ST_SPREAD);
+    spread<T>(a, W.wtab, W.real, h->st);
+  }
+  adj_grid<T>(h, W, W.real, W.real);
+  const double half = h->neumann() ? -0.5 : 0.5;
+  const double* pu = h->has_ubar ? p + h->n_ib * h->nq : nullptr;
+  adj_markers<T>(h, W, p, half, pu, y);
+  if (h->has_ubar) {
+    const int nblk = kr_nblk(h->n_ib);
+    ensure_partial(h, nblk * h->nq);
+    kr_border(p, nullptr, h->n_ib, h->nq, 1.0, y + h->n_ib * h->nq, h->partial, nblk, h->st);
+  }
+}
+
+// right-hand side of the adjoint system: the gradient of <psi, u> with respect to q
+template <typename T> void adj_rhs_t(ibdl_s* h, const T* psi, double* g) {
+  GridWork<T>& W = ensure_fields<T>(h, std::max(adj_nout(h), h->nq));
+  ensure_adj(h);
+  IBDL_HIP(hipMemcpyAsync(W.real, psi, sizeof(T) * h->ntot * h->nq, hipMemcpyDeviceToDevice, h->st));
+  adj_grid<T>(h, W, W.real, W.real);
+  adj_markers<T>(h, W, nullptr, 0.0, nullptr, g);
+  if (h->has_ubar) {
+    const int nblk = 256;
+    ensure_partial(h, nblk * h->nq);
+    grid_sum<T>(psi, h->nq, h->ntot, h->partial, nblk, g + h->n_ib * h->nq, h->st);
+  }
+}
+
+// dL/dX from the adjoint solution mu, the forward density q and grid solution u:
+//   dL/dX_ie = -sum_c mu_ic (Phi'_e u_c)_i + sum_k coef_ik (Phi'_e R_k)_i
+// with R the adjoint fields of r = L^-1 (Phi^T mu - psi) (scalar: D_d r and r) or of
+// r = psi - Phi^T mu (Stokes: T_f^T r), and Phi'_e the derivative of the interpolation weights.
+template <typename T> void grad_X_t(ibdl_s* h, const double* q, const T* u, const T* psi, double* dX) {
+  GridWork<T>& W = ensure_fields<T>(h, std::max(adj_nout(h), h->nq));
+  ensure_adj(h);
+  SpreadArgs a = spread_args(h, SP_PLAIN, h->nq, h->adj_mu);
+  a.raw = 1;
+  grid_fill_zero<T>(W.real, h->ntot * h->nq, h->st);
+  spread<T>(a, W.wtab, W.real, h->st);
+  if (h->stokes()) grid_axpby<T>(W.real, 1.0, psi, -1.0, h->ntot * h->nq, h->st);
+  else grid_axpby<T>(W.real, -1.0, psi, 1.0, h->ntot, h->st);
+  adj_grid<T>(h, W, W.real, W.real);
+  const int nout = adj_nout(h);
+  const int nc = h->nq + nout;
+  const double hDinv = 1.0 / pow(h->h, (double)h->dim);
+  adj_coefs(h->stokes() ? 1 : 0, h->dim, h->n_ib, nc, hDinv, h->cfg.eta, h->adj_mu, q, h->nrm, h->ds, h->adj_m,
+            h->st);
+  GatherArgs ga{};
+  ga.g = h->geom;
+  ga.kernel = h->cfg.kernel;
+  ga.n_ib = h->n_ib;
+  ga.s = h->s;
+  ga.f = h->f;
+  ga.nfield = nc;
+  for (int c = 0; c < h->nq; ++c) ga.field[c] = u + c * h->ntot;
+  for (int k = 0; k < nout; ++k) ga.field[h->nq + k] = W.real + k * h->ntot;
+  ga.coef = h->adj_m;
+  ga.out = dX;
+  gather_dx<T>(ga, h->st);
+}
+
+void apply_any(ibdl_s* h, const double* q, double* y, bool force64, bool trans = false) {
+  if (trans) {
+    if (h->mixed() && !force64) apply_adj_t<float>(h, q, y);
+    else apply_adj_t<double>(h, q, y);
+    return;
+  }
   if (h->mixed() && !force64) apply_t<float>(h, q, y);
   else apply_t<double>(h, q, y);
 }
@@ -444,7 +595,7 @@ double host_norm(ibdl_s* h, const double* v, int64_t n) {
 
 // GMRES, x0 = 0, no restart; classical Gram-Schmidt twice on the device; Givens on the host.
 int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
-          double* relres) {
+          double* relres, bool trans = false) {
   const int64_t n = h->n_aug;
   if (h->vcap < maxit + 1) {
     h->V = (double*)h->dalloc<double>(sizeof(double) * n * (maxit + 1));
@@ -470,7 +621,7 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   double* hn = h->small + 512;      // norm^2
   for (int j = 0; j < maxit; ++j) {
     double* w = h->V + (int64_t)(j + 1) * n;
-    apply_any(h, h->V + (int64_t)j * n, w, false);
+    apply_any(h, h->V + (int64_t)j * n, w, false, trans);
     kr_multidot(h->V, n, j + 1, w, n, h->partial, nblk, h1, h->st);
     kr_gemv_sub(h->V, n, j + 1, h1, w, n, h->st);
     kr_multidot(h->V, n, j + 1, w, n, h->partial, nblk, h2, h->st);
@@ -515,6 +666,33 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   *iters = k;
   *relres = res;
   return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;
+}
+
+// Gradients of a loss of the recovered grid solution (dL/du = psi) with respect to the marker
+// positions and the boundary data, by the adjoint method: A^T mu = (du/dq)^T psi, dL/ddata = mu.
+template <typename T>
+int backward_t(ibdl_s* h, const double* q, const T* u, const T* psi, double tol, int maxit, double* dX,
+               double* ddata, ibdl_info_t* info) {
+  ensure_adj(h);
+  adj_rhs_t<T>(h, psi, h->vb);
+  int iters = 0;
+  double relres = 0.0;
+  const int status = gmres(h, h->vb, tol, maxit, h->adj_mu, info, &iters, &relres, true);
+  apply_any(h, h->adj_mu, h->vr, true, true);
+  kr_axpby(h->vr, 1.0, h->vb, -1.0, h->n_aug, h->st);
+  const double rn = host_norm(h, h->vr, h->n_aug);
+  const double bn = host_norm(h, h->vb, h->n_aug);
+  if (ddata)
+    IBDL_HIP(hipMemcpyAsync(ddata, h->adj_mu, sizeof(double) * h->n_ib * h->nq, hipMemcpyDeviceToDevice, h->st));
+  if (dX) grad_X_t<T>(h, q, u, psi, dX);
+  IBDL_HIP(hipStreamSynchronize(h->st));
+  if (info) {
+    info->iters = iters;
+    info->status = status;
+    info->krylov_relres = relres;
+    info->true_relres_fp64 = bn > 0 ? rn / bn : 0.0;
+  }
+  return status;
 }
 
 bool pow2_in_range(int64_t v) { return v >= 16 && v <= 1024 && (v & (v - 1)) == 0; }
@@ -739,6 +917,28 @@ ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, doubl
       info->true_relres_fp64 = bn > 0 ? rn / bn : 0.0;
     }
     return status;
+  });
+}
+
+ibdl_status_t ibdl_backward(ibdl_t h, const double* q, const void* u_grid, const void* dL_du, double tol,
+                            int32_t maxit, double* dL_dX, double* dL_ddata, ibdl_info_t* info) {
+  return guarded(h, [&]() {
+    if (!q || !u_grid || !dL_du) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (!(tol >= 0) || !std::isfinite(tol)) throw Error(IBDL_ERR_ARG, "tol must be finite and >= 0");
+    if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
+    if (h->neumann()) throw Error(IBDL_ERR_UNSUPPORTED, "the adjoint is implemented for Dirichlet problems");
+    if (h->mixed())
+      return backward_t<float>(h, q, (const float*)u_grid, (const float*)dL_du, tol, maxit, dL_dX, dL_ddata, info);
+    return backward_t<double>(h, q, (const double*)u_grid, (const double*)dL_du, tol, maxit, dL_dX, dL_ddata, info);
+  });
+}
+
+ibdl_status_t ibdl_apply_transpose(ibdl_t h, const double* p, double* y) {
+  return guarded(h, [&]() {
+    if (!p || !y) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (p == y) throw Error(IBDL_ERR_ARG, "p and y must not alias");
+    apply_any(h, p, y, false, true);
+    return IBDL_OK;
   });
 }
 

@@ -15,6 +15,7 @@ enum FieldKind {
 };
 
 struct MultDesc {
+  int mode;         // 0: forward multiplier; 1: scalar gradient outputs; 2: transposed Stokes
   int dim;          // 2 or 3
   int nxh;          // nx/2 + 1
   int stokes;       // 0: scalar multiplier, 1: Stokes multiplier
@@ -37,7 +38,10 @@ template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es,
                  bool inverse, const cplx<T>* tw, hipStream_t s);
 // in-place fused pass along the last axis (length n, plane size P): forward FFT of the nc input
-// fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1)
+// fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1).
+// mode 1 (one scalar input F): outputs i k~_o g F^ for o < dim, then g F^, g = alpha sc/(c2 sigma - c0);
+// mode 2 (two Stokes components): output o = sum_c conj(m(fk[o], c)) F^_c, the transpose of the
+// forward Stokes multiplier m(kind, component).
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw,
                     hipStream_t s);
@@ -78,6 +82,7 @@ struct SpreadArgs {
   int mode;
   int nf;             // output fields
   int mass;           // SP_FDDIV / SP_SCALAR_VEC: include the mass term
+  int raw;            // SP_PLAIN: coef_c = f[i][c] (no ds_i h^-D): the transpose of S*
   double eta;
   const int* tile_off;
   const int* list;
@@ -113,6 +118,21 @@ struct InterpArgs {
 };
 template <typename T> void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, hipStream_t st);
 
+// Kernel-derivative gather: out[i][e] = sum_x F_i(x) d/dX_ie prod_d phi((x_d - X_id)/h), with
+// F_i(x) = sum_k coef[i][k] field_k(x) (field_k of the grid type; at most 8 fields).
+struct GatherArgs {
+  MarkerGeom g;
+  int kernel;
+  int64_t n_ib;
+  const int* s;
+  const double* f;
+  int nfield;
+  const void* field[8];
+  const double* coef;   // [n_ib][nfield]
+  double* out;          // [n_ib][dim]
+};
+template <typename T> void gather_dx(const GatherArgs& a, hipStream_t st);
+
 // ------------------------------------------------------------------ grid elementwise
 template <typename T> void grid_axpby(T* y, double a, const T* x, double b, int64_t n, hipStream_t st);
 template <typename T> void grid_add_const(T* y, const double* c_dev, int ncomp, int64_t n, hipStream_t st);
@@ -130,5 +150,14 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
                double* partial, int nblk, hipStream_t st);
 void kr_add(double* dst, const double* a, const double* b, int n, hipStream_t st);
 int kr_nblk(int64_t n);
+
+// ------------------------------------------------------------------ adjoint, marker side
+// y = h^-D ds (.) (combination of the interpolated adjoint fields G [n_ib][ng]) + b p + eta ds pu
+void adj_combine(int stokes, int dim, int64_t n_ib, int ng, double hDinv, double eta, const double* G,
+                 const double* nrm, const double* ds, const double* p, double b, const double* pu, double* y,
+                 hipStream_t st);
+// per-marker weights coef [n_ib][nc] of the fields gathered with kernel derivatives for dL/dX
+void adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hDinv, double eta, const double* mu,
+               const double* q, const double* nrm, const double* ds, double* coef, hipStream_t st);
 
 }  // namespace ibdl

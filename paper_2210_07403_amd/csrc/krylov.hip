@@ -72,7 +72,7 @@ __global__ void k_add_small(double* __restrict__ dst, const double* __restrict__
   for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = a[e] + b[e];
 }
 
-// partial sums of eta * ds_i * q[i][c] over markers, per component c
+// partial sums of eta * ds_i * q[i][c] over markers, per component c (ds = NULL: unit weights)
 __global__ __launch_bounds__(kB) void k_border_partial(const double* __restrict__ q, const double* __restrict__ ds,
                                                        int64_t n_ib, int nq, int nblk, double* __restrict__ partial) {
   __shared__ double red[kB];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kB) void k_border_partial(const double* __restrict_
   const int64_t beg = (int64_t)blockIdx.x * kElemsPerBlock;
   const int64_t end = beg + kElemsPerBlock < n_ib ? beg + kElemsPerBlock : n_ib;
   double s = 0.0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += kB) s += ds[i] * q[i * nq + c];
+  for (int64_t i = beg + threadIdx.x; i < end; i += kB) s += (ds ? ds[i] : 1.0) * q[i * nq + c];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int st = kB / 2; st > 0; st >>= 1) {
@@ -96,6 +96,79 @@ __global__ void k_border_final(const double* __restrict__ partial, int nblk, dou
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += partial[c * nblk + b];
     out[c] = eta * s;
+  }
+}
+
+// Marker side of the transposed operator.  G holds, per marker, the interpolated adjoint grid
+// fields (scalar: D_d w for d < D, then w when eta > 0; Stokes: the fields dual to A11, A12, A22
+// (and eta Q1, eta Q2)); the result is
+//   scalar  y_i = h^-D ds_i (sum_d n_id G_i,d - eta G_i,D) + b p_i + eta ds_i pu
+//   Stokes  y_ic = h^-D ds_i sum_f (d c_f / d Q_c) G_i,f + b p_ic + eta ds_i pu_c
+// with c_f the per-marker spread coefficients 2 Q1 n1, Q1 n2 + Q2 n1, 2 Q2 n2, eta Q1, eta Q2.
+__global__ void k_adj_combine(int stokes, int dim, int64_t n_ib, int ng, double hDinv, double eta,
+                              const double* __restrict__ G, const double* __restrict__ nrm,
+                              const double* __restrict__ ds, const double* __restrict__ p, double b,
+                              const double* __restrict__ pu, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_ib) return;
+  const double* Gi = G + i * ng;
+  const double w = hDinv * ds[i];
+  if (!stokes) {
+    double s = 0.0;
+    for (int d = 0; d < dim; ++d) s += nrm[i * dim + d] * Gi[d];
+    if (ng > dim) s -= eta * Gi[dim];
+    double v = w * s;
+    if (p) v += b * p[i];
+    if (pu) v += eta * ds[i] * pu[0];
+    y[i] = v;
+    return;
+  }
+  const double n1 = nrm[2 * i], n2 = nrm[2 * i + 1];
+  double s1 = 2.0 * n1 * Gi[0] + n2 * Gi[1];
+  double s2 = n1 * Gi[1] + 2.0 * n2 * Gi[2];
+  if (ng > 3) {
+    s1 += eta * Gi[3];
+    s2 += eta * Gi[4];
+  }
+  double v1 = w * s1, v2 = w * s2;
+  if (p) {
+    v1 += b * p[2 * i];
+    v2 += b * p[2 * i + 1];
+  }
+  if (pu) {
+    v1 += eta * ds[i] * pu[0];
+    v2 += eta * ds[i] * pu[1];
+  }
+  y[2 * i] = v1;
+  y[2 * i + 1] = v2;
+}
+
+// Per-marker weights of the grid fields whose kernel-derivative gathers make up dL/dX:
+//   scalar  [u: -mu_i] [D_d r: -h^-D ds_i Q_i n_id] [r: eta h^-D ds_i Q_i (eta > 0)]
+//   Stokes  [u_c: -mu_ic] [Z_f: h^-D ds_i c_f,i for the nf spread fields]
+__global__ void k_adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hDinv, double eta,
+                            const double* __restrict__ mu, const double* __restrict__ q,
+                            const double* __restrict__ nrm, const double* __restrict__ ds,
+                            double* __restrict__ coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_ib) return;
+  double* c = coef + i * nc;
+  const double w = hDinv * ds[i];
+  if (!stokes) {
+    c[0] = -mu[i];
+    for (int d = 0; d < dim; ++d) c[1 + d] = -w * q[i] * nrm[i * dim + d];
+    if (nc > dim + 1) c[dim + 1] = eta * w * q[i];
+    return;
+  }
+  const double q1 = q[2 * i], q2 = q[2 * i + 1], n1 = nrm[2 * i], n2 = nrm[2 * i + 1];
+  c[0] = -mu[2 * i];
+  c[1] = -mu[2 * i + 1];
+  c[2] = w * 2.0 * q1 * n1;
+  c[3] = w * (q1 * n2 + q2 * n1);
+  c[4] = w * 2.0 * q2 * n2;
+  if (nc > 5) {
+    c[5] = w * eta * q1;
+    c[6] = w * eta * q2;
   }
 }
 
@@ -146,6 +219,21 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
   hipLaunchKernelGGL(k_border_partial, dim3(nblk, nq), dim3(kB), 0, st, q, ds, n_ib, nq, nblk, partial);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_border_final, dim3(nq), dim3(64), 0, st, partial, nblk, eta, out);
+  IBDL_LAUNCH_CHECK();
+}
+
+void adj_combine(int stokes, int dim, int64_t n_ib, int ng, double hDinv, double eta, const double* G,
+                 const double* nrm, const double* ds, const double* p, double b, const double* pu, double* y,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, stokes, dim, n_ib, ng,
+                     hDinv, eta, G, nrm, ds, p, b, pu, y);
+  IBDL_LAUNCH_CHECK();
+}
+
+void adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hDinv, double eta, const double* mu,
+               const double* q, const double* nrm, const double* ds, double* coef, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_coefs, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, stokes, dim, n_ib, nc,
+                     hDinv, eta, mu, q, nrm, ds, coef);
   IBDL_LAUNCH_CHECK();
 }
 
