@@ -152,6 +152,45 @@ ibdl_status_t ibdl_apply_transpose(ibdl_t h, const double* p, double* y);
 ibdl_status_t ibdl_backward(ibdl_t h, const double* q, const void* u_grid, const void* dL_du, double tol,
                             int32_t maxit, double* dL_dX, double* dL_ddata, ibdl_info_t* info);
 
+/* ---------------------------------------------------------------- batches of problems
+ * Many independent plain scalar Dirichlet problems (Sec. 5.3.2: screened Poisson or Poisson,
+ * eta = 0, finite-difference symbols, a 4-point kernel), of any grid sizes and marker counts,
+ * solved together.  Problems with the same grid (sizes, box, origin, kappa) share one launch per
+ * stage; the batched operator is replayed from a HIP graph every GMRES iteration; the FFT
+ * passes' launch shapes are chosen by timing per (dim, grid, precision, problem count).  All
+ * problems share dim, precision and kernel. */
+typedef struct ibdl_batch_s* ibdl_batch_t;
+
+/* cfgs[p], n_ib[p]: host arrays of nprob configurations and marker counts; X[p], nrm[p], ds[p]:
+ * host arrays of device pointers to each problem's markers (layouts as in ibdl_create; copied).
+ * The batch works on its own stream, ordered after cfgs[0].stream at every call. */
+ibdl_status_t ibdl_batch_create(int32_t nprob, const ibdl_config_t* cfgs, const int64_t* n_ib,
+                                const double* const* X, const double* const* nrm, const double* const* ds,
+                                ibdl_batch_t* out);
+ibdl_status_t ibdl_batch_destroy(ibdl_batch_t b);
+
+/* y[p] = A_p q[p] for every problem (host arrays of device pointers to double [n_ib[p]]). */
+ibdl_status_t ibdl_batch_apply(ibdl_batch_t b, const double* const* q, double* const* y);
+
+/* Solve every problem with boundary data data[p] (device double [n_ib[p]]) and g~ = 0 to
+ * ||b - A q|| / ||b|| <= tol (GMRES as in ibdl_solve, per problem), q[p] the densities, u[p] the
+ * grid solutions ([grid] of the grid type, or NULL entries / u = NULL to skip), infos[p] per
+ * problem (or NULL).  Returns IBDL_NOT_CONVERGED if any problem did not converge.  Synchronises. */
+ibdl_status_t ibdl_batch_solve(ibdl_batch_t b, const double* const* data, double tol, int32_t maxit,
+                               double* const* q, void* const* u, ibdl_info_t* infos);
+
+/* Replay the batched apply from a captured HIP graph (1, the default) or launch it directly (0). */
+ibdl_status_t ibdl_batch_set_graph(ibdl_batch_t b, int32_t enable);
+
+/* Number of grid groups; for group >= 0 also its problem count, grid sizes n[3] and the launch
+ * shapes chosen for its FFT passes (rows per block of the x passes, lines per block of the fused
+ * pass).  Any output pointer may be NULL. */
+ibdl_status_t ibdl_batch_query(ibdl_batch_t b, int32_t group, int32_t* ngroups, int32_t* nprob_in_group,
+                               int32_t* n, int32_t* rows_per_block, int32_t* lines_per_block);
+
+/* Message of the last failure on the batch (or of the last failed ibdl_batch_create for NULL). */
+const char* ibdl_batch_last_error(ibdl_batch_t b);
+
 /* Sizes of the handle: n_aug (unknowns), grid points per component, grid components of the
  * solution (nq).  Any output pointer may be NULL. */
 ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq);

@@ -15,7 +15,7 @@ import torch
 
 from . import _binding as B
 
-__all__ = ["Problem", "SolveInfo", "IBDLError", "IBDLSolve", "ibdl_solve"]
+__all__ = ["Problem", "Batch", "SolveInfo", "IBDLError", "IBDLSolve", "ibdl_solve"]
 
 IBDLError = B.IBDLError
 
@@ -198,6 +198,111 @@ class Problem:
         if u is not None and self.nq == 1:
             u = u[0]
         return q, u, res
+
+
+class Batch:
+    """Many independent plain scalar Dirichlet problems solved together (ibdl_batch_*).
+
+    problems: sequence of dicts with keys dim, n, L, origin, X, nrm, ds, pde ("screened" or
+    "poisson"), kappa and optionally kernel ("peskin4" / "cos4"); all share dim, kernel and the
+    precision given here.  Finite-difference symbols, eta = 0."""
+
+    def __init__(self, problems, precision="mixed", device="cuda"):
+        lib = B.load()
+        self.device = torch.device(device)
+        self.precision = precision
+        self.grid_dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.nprob = len(problems)
+        cfgs = (B.Config * self.nprob)()
+        self.stream = torch.cuda.current_stream(self.device)
+        keep = []
+        self.n_ib, self.grid_shapes = [], []
+        for k, pb in enumerate(problems):
+            c = cfgs[k]
+            dim = int(pb["dim"])
+            c.dim = dim
+            for d in range(3):
+                c.n[d] = int(pb["n"][d]) if d < dim else 1
+                c.L[d] = float(pb["L"][d]) if d < dim else 1.0
+                c.origin[d] = float(pb["origin"][d]) if d < dim else 0.0
+            c.pde = B.PDE[pb.get("pde", "poisson")]
+            c.kappa = float(pb.get("kappa", 0.0))
+            c.mu = 1.0
+            c.bc = B.BC["dirichlet"]
+            c.eta = 0.0
+            c.kernel = B.KERNEL[pb.get("kernel", "peskin4")]
+            c.disc = B.DISC["fd2"]
+            c.precision = B.PRECISION[precision]
+            c.stream = ctypes.c_void_p(self.stream.cuda_stream)
+            Xd, Nd, Dd = (_dev_f64(pb["X"], self.device), _dev_f64(pb["nrm"], self.device),
+                          _dev_f64(pb["ds"], self.device))
+            keep += [Xd, Nd, Dd]
+            self.n_ib.append(int(Dd.shape[0]))
+            self.grid_shapes.append(tuple(reversed([int(v) for v in pb["n"]][:dim])))
+        ptr = lambda ts: (ctypes.c_void_p * self.nprob)(*[t.data_ptr() for t in ts])
+        nib = (ctypes.c_int64 * self.nprob)(*self.n_ib)
+        self._h = ctypes.c_void_p()
+        B.check_batch(lib.ibdl_batch_create(self.nprob, cfgs, nib, ptr(keep[0::3]), ptr(keep[1::3]),
+                                            ptr(keep[2::3]), ctypes.byref(self._h)), None)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            B.load().ibdl_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vecs(self, vs):
+        ts = [_dev_f64(v, self.device).reshape(-1) for v in vs]
+        for t, n in zip(ts, self.n_ib):
+            if t.numel() != n:
+                raise ValueError("each vector must have n_ib entries of its problem")
+        return ts
+
+    def set_graph(self, enable=True):
+        B.check_batch(B.load().ibdl_batch_set_graph(self._h, 1 if enable else 0), self._h)
+
+    def groups(self):
+        """[{nprob, n, rows_per_block, lines_per_block}] of the grid groups."""
+        lib = B.load()
+        ng = ctypes.c_int32()
+        B.check_batch(lib.ibdl_batch_query(self._h, -1, ctypes.byref(ng), None, None, None, None), self._h)
+        out = []
+        for g in range(ng.value):
+            npg, rpb, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            n = (ctypes.c_int32 * 3)()
+            B.check_batch(lib.ibdl_batch_query(self._h, g, None, ctypes.byref(npg), n, ctypes.byref(rpb),
+                                               ctypes.byref(w)), self._h)
+            out.append(dict(nprob=npg.value, n=tuple(n), rows_per_block=rpb.value, lines_per_block=w.value))
+        return out
+
+    def apply(self, qs):
+        qt = self._vecs(qs)
+        ys = [torch.empty_like(t) for t in qt]
+        P = lambda ts: (ctypes.c_void_p * self.nprob)(*[t.data_ptr() for t in ts])
+        B.check_batch(B.load().ibdl_batch_apply(self._h, P(qt), P(ys)), self._h)
+        return ys
+
+    def solve(self, data, tol=1e-8, maxit=100, want_u=True):
+        """Returns (q list, u list or None, [SolveInfo])."""
+        dt = self._vecs(data)
+        qs = [torch.empty(n, dtype=torch.float64, device=self.device) for n in self.n_ib]
+        us = [torch.empty(s, dtype=self.grid_dtype, device=self.device) for s in self.grid_shapes] if want_u else None
+        infos = (B.Info * self.nprob)()
+        hists = [(ctypes.c_double * 256)() for _ in range(self.nprob)]
+        for k in range(self.nprob):
+            infos[k].history = ctypes.cast(hists[k], ctypes.POINTER(ctypes.c_double))
+            infos[k].history_cap = 256
+        P = lambda ts: (ctypes.c_void_p * self.nprob)(*[t.data_ptr() for t in ts])
+        st = B.load().ibdl_batch_solve(self._h, P(dt), float(tol), int(maxit), P(qs), P(us) if us else None, infos)
+        B.check_batch(st, self._h)
+        res = [SolveInfo(infos[k].iters, infos[k].status, infos[k].krylov_relres, infos[k].true_relres_fp64,
+                         [hists[k][i] for i in range(min(infos[k].iters, 256))]) for k in range(self.nprob)]
+        return qs, us, res
 
 
 class IBDLSolve(torch.autograd.Function):

@@ -46,6 +46,15 @@ _SIGS = {
     "ibdl_apply_transpose": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                 ctypes.POINTER(Info)]),
+    "ibdl_batch_create": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    ctypes.POINTER(c_void_p)]),
+    "ibdl_batch_destroy": (c_int32, [c_void_p]),
+    "ibdl_batch_apply": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ibdl_batch_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ibdl_batch_set_graph": (c_int32, [c_void_p, c_int32]),
+    "ibdl_batch_query": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                   ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "ibdl_batch_last_error": (ctypes.c_char_p, [c_void_p]),
     "ibdl_query": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64), ctypes.POINTER(c_int32)]),
     "ibdl_last_error": (ctypes.c_char_p, [c_void_p]),
     "ibdl_set_timing": (c_int32, [c_void_p, c_int32]),
@@ -82,6 +91,13 @@ class IBDLError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+def check_batch(status, handle=None):
+    if status < 0:
+        msg = load().ibdl_batch_last_error(handle)
+        raise IBDLError(status, msg.decode() if msg else "")
+    return status
 
 
 def check(status, handle=None):

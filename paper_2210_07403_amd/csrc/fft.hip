@@ -163,32 +163,33 @@ template <typename TR, int M> struct RowCfg {
 // ------------------------------------------------------------------ x axis, forward R2C
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                  int64_t nrows, const cplx<T>* __restrict__ tw) {
+                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * RC::RPB;
-  const int nvalid = (int)((nrows - row0) < RC::RPB ? (nrows - row0) : RC::RPB);
+  const int NT = RPB * RC::T;
+  const int64_t row0 = (int64_t)blockIdx.x * RPB;
+  const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   const C* src = reinterpret_cast<const C*>(in) + row0 * M;
-  for (int e = tid; e < RC::RPB * M; e += RC::NT) {
+  for (int e = tid; e < RPB * M; e += NT) {
     const int r = e / M, c = e - r * M;
     lds[r * RC::LS + c] = (r < nvalid) ? src[e] : mk<C>(0, 0);
   }
   __syncthreads();
   const int row = tid / RC::T, i = tid - row * RC::T;
   C v[Plan<M>::RMAX];
-  if (row < RC::RPB) line_load<M>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, false>(v, i, lds + (row < RC::RPB ? row : 0) * RC::LS, 1, tw, 2);
+  if (row < RPB) line_load<M>(v, i, lds + row * RC::LS, 1);
+  fft_line<M, false>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
-  if (row < RC::RPB) {
+  if (row < RPB) {
 #pragma unroll
     for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
   C* dst = out + row0 * (M + 1);
-  for (int e = tid; e < nvalid * (M + 1); e += RC::NT) {
+  for (int e = tid; e < nvalid * (M + 1); e += NT) {
     const int r = e / (M + 1), k = e - r * (M + 1);
     const C zk = lds[r * RC::LS + (k == M ? 0 : k)];
     const C zm = lds[r * RC::LS + (k == 0 ? 0 : M - k)];
@@ -201,23 +202,24 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
 // ------------------------------------------------------------------ x axis, inverse C2R
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
-                                                  int64_t nrows, const cplx<T>* __restrict__ tw) {
+                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * RC::RPB;
-  const int nvalid = (int)((nrows - row0) < RC::RPB ? (nrows - row0) : RC::RPB);
+  const int NT = RPB * RC::T;
+  const int64_t row0 = (int64_t)blockIdx.x * RPB;
+  const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   const C* src = in + row0 * (M + 1);
-  for (int e = tid; e < RC::RPB * (M + 1); e += RC::NT) {
+  for (int e = tid; e < RPB * (M + 1); e += NT) {
     const int r = e / (M + 1);
     lds[e] = (r < nvalid) ? src[e] : mk<C>(0, 0);
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{M-k}) + i conj(W^k) (X_k - conj X_{M-k}); each thread owns a pair (k, M-k)
   constexpr int HP = M / 2 + 1;
-  for (int e = tid; e < nvalid * HP; e += RC::NT) {
+  for (int e = tid; e < nvalid * HP; e += NT) {
     const int r = e / HP, k = e - r * HP;
     C* rowp = lds + r * RC::LS;
     const C a = rowp[k], b = rowp[M - k];
@@ -232,16 +234,16 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   __syncthreads();
   const int row = tid / RC::T, i = tid - row * RC::T;
   C v[Plan<M>::RMAX];
-  if (row < RC::RPB) line_load<M>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, true>(v, i, lds + (row < RC::RPB ? row : 0) * RC::LS, 1, tw, 2);
+  if (row < RPB) line_load<M>(v, i, lds + row * RC::LS, 1);
+  fft_line<M, true>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
-  if (row < RC::RPB) {
+  if (row < RPB) {
 #pragma unroll
     for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
   C* dst = reinterpret_cast<C*>(out) + row0 * M;
-  for (int e = tid; e < nvalid * M; e += RC::NT) {
+  for (int e = tid; e < nvalid * M; e += NT) {
     const int r = e / M, c = e - r * M;
     dst[e] = lds[r * RC::LS + c];
   }
@@ -259,21 +261,22 @@ template <typename T, int N> struct TileCfg {
 // ------------------------------------------------------------------ strided in-place C2C
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
-                                                    int64_t outer, int64_t es, const cplx<T>* __restrict__ tw) {
+                                                    int64_t outer, int64_t es, const cplx<T>* __restrict__ tw,
+                                                    int W) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
-  const int c = tid % TC::W, i = tid / TC::W;
-  const int64_t l = (int64_t)blockIdx.x * TC::W + c;
+  const int c = tid & (W - 1), i = tid / W;
+  const int64_t l = (int64_t)blockIdx.x * W + c;
   const bool valid = l < nlines;
   const int64_t base = valid ? (l / inner) * outer + (l % inner) : 0;
   C v[Plan<N>::RMAX];
 #pragma unroll
   for (int s = 0; s < Plan<N>::RMAX; ++s)
     v[s] = valid ? data[base + (int64_t)(i + s * Plan<N>::T) * es] : mk<C>(0, 0);
-  fft_line<N, INV>(v, i, lds + c, TC::W, tw, 1);
+  fft_line<N, INV>(v, i, lds + c, W, tw, 1);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < Plan<N>::RMAX; ++s) data[base + (int64_t)(i + s * Plan<N>::T) * es] = v[s];
@@ -315,15 +318,16 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
 
 template <typename T, int N, int NO, bool STOKES>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                  const cplx<T>* __restrict__ tw) {
+                                                  const cplx<T>* __restrict__ tw, int W, int64_t bstride) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
+  data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
-  const int c = tid % TC::W, i = tid / TC::W;
-  const int64_t l = (int64_t)blockIdx.x * TC::W + c;
+  const int c = tid & (W - 1), i = tid / W;
+  const int64_t l = (int64_t)blockIdx.x * W + c;
   const bool valid = l < P;
   const int64_t FS = P * N;
   // mode indices of this line: 2-D l = jx, e = jy; 3-D l = jy*nxh + jx, e = jz
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
     C v[RM];
 #pragma unroll
     for (int s = 0; s < RM; ++s) v[s] = valid ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
-    fft_line<N, false>(v, i, lds + c, TC::W, tw, 1);
+    fft_line<N, false>(v, i, lds + c, W, tw, 1);
     const int fk = md.fk[f];
     if constexpr (!STOKES) {
       if (fk == FK_MASS) {
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   }
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    fft_line<N, true>(acc[o], i, lds + c, TC::W, tw, 1);
+    fft_line<N, true>(acc[o], i, lds + c, W, tw, 1);
     if (valid) {
 #pragma unroll
       for (int s = 0; s < RM; ++s) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[o][s];
@@ -400,15 +404,16 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
 template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                   const cplx<T>* __restrict__ tw) {
+                                                   const cplx<T>* __restrict__ tw, int W, int64_t bstride) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
+  data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
-  const int c = tid % TC::W, i = tid / TC::W;
-  const int64_t l = (int64_t)blockIdx.x * TC::W + c;
+  const int c = tid & (W - 1), i = tid / W;
+  const int64_t l = (int64_t)blockIdx.x * W + c;
   const bool valid = l < P;
   const int jx = (int)(valid ? l % md.nxh : 0);
   const int jy2 = (int)(valid ? l / md.nxh : 0);
@@ -419,14 +424,14 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   C v[RM];
 #pragma unroll
   for (int s = 0; s < RM; ++s) v[s] = valid ? data[l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
-  fft_line<N, false>(v, i, lds + c, TC::W, tw, 1);
+  fft_line<N, false>(v, i, lds + c, W, tw, 1);
   const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
 #pragma unroll
   for (int s = 0; s < RM; ++s) {
     const T den = c2 * (sig_l + sgl[i + s * TT]) - c0;
     v[s] = cscale(v[s], den == (T)0 ? (T)0 : num / den);
   }
-  fft_line<N, true>(v, i, lds + c, TC::W, tw, 1);
+  fft_line<N, true>(v, i, lds + c, W, tw, 1);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) data[l + (int64_t)(i + s * TT) * P] = v[s];
@@ -438,15 +443,16 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
 // all read before the first store, and each workgroup owns its lines in every field).
 template <typename T, int N, int NI, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data, int64_t P, int no, MultDesc md,
-                                                      const cplx<T>* __restrict__ tw) {
+                                                      const cplx<T>* __restrict__ tw, int W, int64_t bstride) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
+  data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
-  const int c = tid % TC::W, i = tid / TC::W;
-  const int64_t l = (int64_t)blockIdx.x * TC::W + c;
+  const int c = tid & (W - 1), i = tid / W;
+  const int64_t l = (int64_t)blockIdx.x * W + c;
   const bool valid = l < P;
   const int64_t FS = P * N;
   const int jx = (int)(valid ? l % md.nxh : 0);
@@ -469,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   for (int f = 0; f < NI; ++f) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) v[f][s] = valid ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
-    fft_line<N, false>(v[f], i, lds + c, TC::W, tw, 1);
+    fft_line<N, false>(v[f], i, lds + c, W, tw, 1);
   }
   for (int o = 0; o < no; ++o) {
     C acc[RM];
@@ -490,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
         for (int f = 0; f < NI; ++f) acc[s] = cadd(acc[s], cmul(cconj(mult_coef<T>(md, md.fk[o], f, sig, kt)), v[f][s]));
       }
     }
-    fft_line<N, true>(acc, i, lds + c, TC::W, tw, 1);
+    fft_line<N, true>(acc, i, lds + c, W, tw, 1);
     if (valid) {
 #pragma unroll
       for (int s = 0; s < RM; ++s) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[s];
@@ -518,66 +524,97 @@ template <typename F> void dispatch_n(int n, F&& f) {
 int fft_supported(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
 
 template <typename T>
-void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s) {
+int fft_x_rpb_max(int nx) {
+  int r = 0;
+  dispatch_n(nx / 2, [&](auto Mc) { r = RowCfg<T, decltype(Mc)::value>::RPB; });
+  return r;
+}
+
+template <typename T>
+int fft_line_w_max(int n) {
+  int r = 0;
+  dispatch_n(n, [&](auto Nc) { r = TileCfg<T, decltype(Nc)::value>::W; });
+  return r;
+}
+
+namespace {
+int pick(int want, int max) {
+  if (want <= 0 || want > max) return max;
+  int v = 1;
+  while (2 * v <= want) v *= 2;
+  return v;
+}
+}  // namespace
+
+template <typename T>
+void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb) {
   dispatch_n(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
-    const int64_t nb = (nrows + RC::RPB - 1) / RC::RPB;
-    const size_t lds = sizeof(cplx<T>) * RC::RPB * RC::LS;
-    hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(RC::NT), lds, s, in, out, nrows, tw_x);
+    const int R = pick(rpb, RC::RPB);
+    const int64_t nb = (nrows + R - 1) / R;
+    const size_t lds = sizeof(cplx<T>) * R * RC::LS;
+    hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
-void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s) {
+void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb) {
   dispatch_n(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
-    const int64_t nb = (nrows + RC::RPB - 1) / RC::RPB;
-    const size_t lds = sizeof(cplx<T>) * RC::RPB * RC::LS;
-    hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(RC::NT), lds, s, in, out, nrows, tw_x);
+    const int R = pick(rpb, RC::RPB);
+    const int64_t nb = (nrows + R - 1) / R;
+    const size_t lds = sizeof(cplx<T>) * R * RC::LS;
+    hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es, bool inverse,
-                 const cplx<T>* tw, hipStream_t s) {
+                 const cplx<T>* tw, hipStream_t s, int w) {
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     using TC = TileCfg<T, N>;
-    const int64_t nb = (nlines + TC::W - 1) / TC::W;
-    const size_t lds = sizeof(cplx<T>) * N * TC::W;
+    const int W = pick(w, TC::W);
+    const int64_t nb = (nlines + W - 1) / W;
+    const size_t lds = sizeof(cplx<T>) * N * W;
+    const dim3 blk(W * TC::T_);
     if (inverse)
-      hipLaunchKernelGGL((k_strided<T, N, true>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, nlines, inner,
-                         outer, es, tw);
+      hipLaunchKernelGGL((k_strided<T, N, true>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
+                         tw, W);
     else
-      hipLaunchKernelGGL((k_strided<T, N, false>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, nlines, inner,
-                         outer, es, tw);
+      hipLaunchKernelGGL((k_strided<T, N, false>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
+                         tw, W);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
-void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw, hipStream_t s) {
+void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw, hipStream_t s,
+                    int batch, int64_t bstride, int w) {
+  if (batch < 1) return;
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     using TC = TileCfg<T, N>;
-    const int64_t nb = (P + TC::W - 1) / TC::W;
-    const size_t lds = sizeof(cplx<T>) * N * TC::W;
+    const int W = pick(w, TC::W);
+    const int64_t nb = (P + W - 1) / W;
+    const size_t lds = sizeof(cplx<T>) * N * W;
+    const dim3 grid((unsigned)nb, (unsigned)batch), blk(W * TC::T_);
     if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1)
-      hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, no, md, tw);
+      hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride);
     else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5)
-      hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, no, md, tw);
+      hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), grid, blk, lds, s, data, P, no, md, tw, W, bstride);
     else if (md.mode != 0)
       throw Error(-2, "fused pass: unsupported transposed multiplier");
     else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)
-      hipLaunchKernelGGL((k_fused1<T, N>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
+      hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride);
     else if (!md.stokes && no == 1)
-      hipLaunchKernelGGL((k_fused<T, N, 1, false>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
+      hipLaunchKernelGGL((k_fused<T, N, 1, false>), grid, blk, lds, s, data, P, md, tw, W, bstride);
     else if (md.stokes && no == 2)
-      hipLaunchKernelGGL((k_fused<T, N, 2, true>), dim3((unsigned)nb), dim3(TC::NT), lds, s, data, P, md, tw);
+      hipLaunchKernelGGL((k_fused<T, N, 2, true>), grid, blk, lds, s, data, P, md, tw, W, bstride);
     else
       throw Error(-2, "fused pass: unsupported multiplier / output count");
   });
@@ -585,11 +622,14 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
 }
 
 #define IBDL_FFT_INST(T)                                                                                   \
-  template void fft_x_r2c<T>(const T*, cplx<T>*, int, int64_t, const cplx<T>*, hipStream_t);              \
-  template void fft_x_c2r<T>(const cplx<T>*, T*, int, int64_t, const cplx<T>*, hipStream_t);              \
+  template void fft_x_r2c<T>(const T*, cplx<T>*, int, int64_t, const cplx<T>*, hipStream_t, int);         \
+  template void fft_x_c2r<T>(const cplx<T>*, T*, int, int64_t, const cplx<T>*, hipStream_t, int);         \
   template void fft_strided<T>(cplx<T>*, int, int64_t, int64_t, int64_t, int64_t, bool, const cplx<T>*,   \
-                               hipStream_t);                                                               \
-  template void fft_fused_last<T>(cplx<T>*, int, int64_t, int, const MultDesc&, const cplx<T>*, hipStream_t);
+                               hipStream_t, int);                                                          \
+  template void fft_fused_last<T>(cplx<T>*, int, int64_t, int, const MultDesc&, const cplx<T>*, hipStream_t, \
+                                  int, int64_t, int);                                                      \
+  template int fft_x_rpb_max<T>(int);                                                                      \
+  template int fft_line_w_max<T>(int);
 IBDL_FFT_INST(float)
 IBDL_FFT_INST(double)
 

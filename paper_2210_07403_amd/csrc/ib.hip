@@ -71,7 +71,7 @@ __device__ __forceinline__ int tile_id(const MarkerGeom& g, const int (&j0)[3], 
 
 __global__ void k_marker_setup(MarkerGeom g, int kernel, int64_t n_ib, const double* __restrict__ X,
                                int* __restrict__ s, double* __restrict__ f, double* __restrict__ wt,
-                               int* __restrict__ tile_count) {
+                               int* __restrict__ tile_count, const int* __restrict__ pid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_ib) return;
   int si[3] = {0, 0, 0};
@@ -106,22 +106,24 @@ __global__ void k_marker_setup(MarkerGeom g, int kernel, int64_t n_ib, const dou
   }
   int j0[3], nt[3];
   marker_tiles(g, si, j0, nt);
+  const int toff = pid ? pid[i] * g.ntile[0] * g.ntile[1] * g.ntile[2] : 0;   // tiles of problem pid[i]
   for (int a = 0; a < nt[2]; ++a)
     for (int b = 0; b < nt[1]; ++b)
-      for (int c = 0; c < nt[0]; ++c) atomicAdd(&tile_count[tile_id(g, j0, a, b, c)], 1);
+      for (int c = 0; c < nt[0]; ++c) atomicAdd(&tile_count[toff + tile_id(g, j0, a, b, c)], 1);
 }
 
 __global__ void k_fill(MarkerGeom g, int64_t n_ib, const int* __restrict__ s, const int* __restrict__ off,
-                       int* __restrict__ cur, int* __restrict__ list) {
+                       int* __restrict__ cur, int* __restrict__ list, const int* __restrict__ pid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_ib) return;
   int si[3] = {s[i * 3], s[i * 3 + 1], s[i * 3 + 2]};
   int j0[3], nt[3];
   marker_tiles(g, si, j0, nt);
+  const int toff = pid ? pid[i] * g.ntile[0] * g.ntile[1] * g.ntile[2] : 0;
   for (int a = 0; a < nt[2]; ++a)
     for (int b = 0; b < nt[1]; ++b)
       for (int c = 0; c < nt[0]; ++c) {
-        const int id = tile_id(g, j0, a, b, c);
+        const int id = toff + tile_id(g, j0, a, b, c);
         const int pos = off[id] + atomicAdd(&cur[id], 1);
         list[pos] = (int)i;
       }
@@ -251,9 +253,11 @@ __global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, const cplx<T>* __
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tile = a.busy[blockIdx.x];
-  const int tx = tile % g.ntile[0];
-  const int ty = (tile / g.ntile[0]) % g.ntile[1];
-  const int tz = tile / (g.ntile[0] * g.ntile[1]);
+  const int ntl = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  const int prob = tile / ntl, tl = tile - prob * ntl;   // problem of a batch, tile within it
+  const int tx = tl % g.ntile[0];
+  const int ty = (tl / g.ntile[0]) % g.ntile[1];
+  const int tz = tl / (g.ntile[0] * g.ntile[1]);
   const int x0 = tx * kT3X, y0 = ty * kT3Y, z0 = tz * kT3Z;
   const int lx = lane % kT3X, ly = lane / kT3X;
   const int mx = g.n[0] - 1, my = g.n[1] - 1, mz = g.n[2] - 1;
@@ -320,6 +324,7 @@ __global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, const cplx<T>* __
   // fixed-order reduction of the four waves' partial sums, one field at a time
   T* red = reinterpret_cast<T*>(&s_r[0][0][0][0]);   // needs 4 * 8 * 64 values
   const int64_t ntot = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  out += (int64_t)prob * a.nf * ntot;
 #pragma unroll
   for (int c = 0; c < NF; ++c) {
     if (c >= a.nf) break;
@@ -349,8 +354,10 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tile = a.busy[blockIdx.x];
-  const int tx = tile % g.ntile[0];
-  const int ty = tile / g.ntile[0];
+  const int ntl = g.ntile[0] * g.ntile[1];
+  const int prob = tile / ntl, tl = tile - prob * ntl;
+  const int tx = tl % g.ntile[0];
+  const int ty = tl / g.ntile[0];
   const int x0 = tx * kT2X, y0 = ty * kT2Y;
   const int lx = lane % kT2X, yg = lane / kT2X;
   const int mx = g.n[0] - 1, my = g.n[1] - 1;
@@ -410,6 +417,7 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
   }
   T* red = reinterpret_cast<T*>(&s_y[0][0][0]);   // needs 4 * 4 * 64 values
   const int64_t ntot = (int64_t)g.n[0] * g.n[1];
+  out += (int64_t)prob * a.nf * ntot;
 #pragma unroll
   for (int c = 0; c < NF; ++c) {
     if (c >= a.nf) break;
@@ -448,6 +456,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a, const T* __restric
     }
   }
   const int64_t ntot = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+  if (a.pid) u += (int64_t)a.pid[i] * a.nf * ntot;
   for (int c = 0; c < a.nf; ++c) {
     const T* uc = u + c * ntot;
     T acc = 0;
@@ -497,6 +506,7 @@ __global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __
     wx[t] = row[1 + t].x;
   }
   const int64_t ntot = (int64_t)g.n[0] * g.n[1] * (D == 3 ? g.n[2] : 1);
+  if (a.pid) u += (int64_t)a.pid[im] * a.nf * ntot;
   for (int c = 0; c < a.nf; ++c) {
     const T* uc = u + c * ntot + base;
     T v = ((uc[ix[0]] * wx[0] + uc[ix[1]] * wx[1]) + uc[ix[2]] * wx[2] + uc[ix[3]] * wx[3]) * wyz;
@@ -610,18 +620,19 @@ inline unsigned grid_blocks(int64_t n) {
 }  // namespace
 
 void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* X, int* s, double* f, double* wt,
-                   int* tile_count, hipStream_t st) {
-  const int64_t ntile = (int64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
+                   int* tile_count, hipStream_t st, const int* pid, int nprob) {
+  const int64_t ntile = (int64_t)g.ntile[0] * g.ntile[1] * g.ntile[2] * nprob;
   IBDL_HIP(hipMemsetAsync(tile_count, 0, sizeof(int) * ntile, st));
   if (n_ib > 0)
     hipLaunchKernelGGL(k_marker_setup, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, g, kernel, n_ib, X,
-                       s, f, wt, tile_count);
+                       s, f, wt, tile_count, pid);
   IBDL_LAUNCH_CHECK();
 }
 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count, int* tile_off,
-                 int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off, hipStream_t st) {
-  const int ntile = g.ntile[0] * g.ntile[1] * g.ntile[2];
+                 int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off, hipStream_t st, const int* pid,
+                 int nprob) {
+  const int ntile = g.ntile[0] * g.ntile[1] * g.ntile[2] * nprob;
   hipLaunchKernelGGL(k_busy_flags, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, tile_cur, ntile);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_cur, busy_off, ntile);
@@ -633,7 +644,7 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
   IBDL_HIP(hipMemsetAsync(tile_cur, 0, sizeof(int) * ntile, st));
   if (n_ib > 0)
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, g, n_ib, s, tile_off,
-                       tile_cur, list_tmp);
+                       tile_cur, list_tmp, pid);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_sort_tiles, dim3(ntile), dim3(256), 0, st, tile_off, list_tmp, list);
   IBDL_LAUNCH_CHECK();

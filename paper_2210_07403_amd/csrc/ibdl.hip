@@ -11,6 +11,7 @@
 
 #include "../../include/ibdl.h"
 #include "kernels.h"
+#include "tables.h"
 
 using namespace ibdl;
 
@@ -179,39 +180,16 @@ template <typename T> GridWork<T>& ensure_work(ibdl_s* h) {
   W.spec = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->nspec * nf);
   W.wtab = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->n_ib * 24);
   weight_table<T>(h->wt, h->n_ib, W.wtab, h->st);
-  for (int d = 0; d < h->dim; ++d) {
-    const int n = h->n[d];
-    std::vector<cplx<T>> tw(n);
-    for (int m = 0; m < n; ++m) {
-      const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
-      tw[m].x = (T)cosl(a);
-      tw[m].y = (T)(-sinl(a));
-    }
-    W.tw[d] = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * n);
-    IBDL_HIP(hipMemcpy(W.tw[d], tw.data(), sizeof(cplx<T>) * n, hipMemcpyHostToDevice));
-    const int len = (d == 0) ? (int)h->nxh : n;
-    std::vector<T> sg(len), kt(len);
-    for (int j = 0; j < len; ++j) {
-      const long double th = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
-      if (h->fd()) {
-        sg[j] = (T)((2.0L * cosl(th) - 2.0L) / ((long double)h->h * h->h));
-        kt[j] = (T)(sinl(th) / (long double)h->h);
-      } else {
-        const int m = (j < n / 2) ? j : j - n;
-        const long double k = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)h->cfg.L[d];
-        sg[j] = (T)(-k * k);
-        kt[j] = (j == n / 2) ? (T)0 : (T)k;
-      }
-    }
-    W.sig[d] = (T*)h->dalloc<T>(sizeof(T) * len);
-    W.kt[d] = (T*)h->dalloc<T>(sizeof(T) * len);
-    IBDL_HIP(hipMemcpy(W.sig[d], sg.data(), sizeof(T) * len, hipMemcpyHostToDevice));
-    IBDL_HIP(hipMemcpy(W.kt[d], kt.data(), sizeof(T) * len, hipMemcpyHostToDevice));
+  GridTables<T> G = make_grid_tables<T>(h->dim, h->n, h->cfg.L, h->h, h->fd(),
+                                        [&](size_t bytes) { return h->dalloc<T>(bytes); });
+  for (int d = 0; d < 3; ++d) {
+    W.tw[d] = G.tw[d];
+    W.sig[d] = G.sig[d];
+    W.kt[d] = G.kt[d];
   }
   return W;
 }
 
-// grow the real and spectral work arrays to nf fields (contents are not kept)
 template <typename T> GridWork<T>& ensure_fields(ibdl_s* h, int nf) {
   GridWork<T>& W = ensure_work<T>(h);
   if (W.nfields >= nf) return W;

@@ -29,22 +29,28 @@ struct MultDesc {
   const void* kt[3];   // per-axis derivative symbols k~ (grid type)
 };
 
+// Tunable launch shapes: rpb = rows per block of the x passes, w = lines per block of the strided
+// and fused passes (powers of two; 0 or anything above the maximum means the maximum that fits
+// 256 threads and 64 KiB of LDS).
+template <typename T> int fft_x_rpb_max(int nx);
+template <typename T> int fft_line_w_max(int n);
 template <typename T>
-void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s);
+void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0);
 template <typename T>
-void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s);
+void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0);
 // in-place strided C2C pass: line l starts at (l / inner) * outer + (l % inner), element stride es
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es,
-                 bool inverse, const cplx<T>* tw, hipStream_t s);
+                 bool inverse, const cplx<T>* tw, hipStream_t s, int w = 0);
 // in-place fused pass along the last axis (length n, plane size P): forward FFT of the nc input
 // fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1).
 // mode 1 (one scalar input F): outputs i k~_o g F^ for o < dim, then g F^, g = alpha sc/(c2 sigma - c0);
 // mode 2 (two Stokes components): output o = sum_c conj(m(fk[o], c)) F^_c, the transpose of the
 // forward Stokes multiplier m(kind, component).
+// batch problems with the same multiplier: problem b's fields start bstride elements after b-1's.
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw,
-                    hipStream_t s);
+                    hipStream_t s, int batch = 1, int64_t bstride = 0, int w = 0);
 int fft_supported(int n);
 
 // ------------------------------------------------------------------ markers, spread, interp
@@ -61,13 +67,14 @@ struct MarkerGeom {
 
 // marker setup: window start s[i][3] (wrapped), fractional offset f[i][3], weight table
 // wt[i][3][12] (kernel weights W[0..5] and centred differences G[0..5] on the window), tile counts
+// Batches: pid[i] is marker i's problem and tiles are numbered problem-major (nprob * ntile).
 void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* X, int* s, double* f,
-                   double* wt, int* tile_count, hipStream_t st);
+                   double* wt, int* tile_count, hipStream_t st, const int* pid = nullptr, int nprob = 1);
 // bin markers by tile (sorted candidate lists) and list the non-empty tiles: busy[0..nbusy) with
 // nbusy = busy_off[ntile]
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
                  int* tile_off, int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off,
-                 hipStream_t st);
+                 hipStream_t st, const int* pid = nullptr, int nprob = 1);
 
 enum SpreadMode {
   SP_PLAIN = 0,     // nf fields: coef_c = f[i][c] ds_i h^-D
@@ -97,7 +104,8 @@ struct SpreadArgs {
   const double* ds;   // [n_ib]
 };
 // Spread over the non-empty tiles only: nodes of empty tiles are left untouched, so the caller
-// clears the nf output fields first (grid_fill_zero).  wtab: per-precision weight table
+// clears the nf output fields first (grid_fill_zero).  A batch tile id p * ntile + t writes problem
+// p's fields at out + p * nf * (grid points).  wtab: per-precision weight table
 // [n_ib][3][8] of (W, G) pairs (weight_table).
 template <typename T> void grid_fill_zero(T* y, int64_t n, hipStream_t st);
 template <typename T> void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st);
@@ -115,6 +123,7 @@ struct InterpArgs {
   double b;
   const double* x;     // [n_ib][nf] or null
   const double* ub;    // [nf] or null
+  const int* pid;      // batch: marker i reads fields at u + pid[i] * nf * (grid points); or null
 };
 template <typename T> void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, hipStream_t st);
 
@@ -150,6 +159,27 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
                double* partial, int nblk, hipStream_t st);
 void kr_add(double* dst, const double* a, const double* b, int n, hipStream_t st);
 int kr_nblk(int64_t n);
+
+// ------------------------------------------------------------------ batched Krylov vectors
+// Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product
+// block b covers [beg[b], end[b]) of one problem, whose blocks are pb0[p] .. pb0[p+1]-1.
+struct KrylovSegments {
+  int nprob = 0;
+  int64_t n = 0;
+  int nblk = 0;
+  const int* seg = nullptr;
+  const int64_t* beg = nullptr;
+  const int64_t* end = nullptr;
+  const int* pb0 = nullptr;
+};
+// out[p * ostride + j] = <V_j, w> over problem p's segment, j < k
+void kb_multidot(const double* V, int64_t ldv, int k, const double* w, const KrylovSegments& sg, double* partial,
+                 int ostride, double* out, hipStream_t st);
+void kb_gemv_sub(const double* V, int64_t ldv, int k, const double* H, int hs, const KrylovSegments& sg, double* w,
+                 hipStream_t st);
+void kb_lincomb(const double* V, int64_t ldv, int k, const double* Y, int ys, const KrylovSegments& sg, double* x,
+                hipStream_t st);
+void kb_scale(const double* src, const double* sc, const KrylovSegments& sg, double* dst, hipStream_t st);
 
 // ------------------------------------------------------------------ adjoint, marker side
 // y = h^-D ds (.) (combination of the interpolated adjoint fields G [n_ib][ng]) + b p + eta ds pu

@@ -172,6 +172,70 @@ __global__ void k_adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hD
   }
 }
 
+// ------------------------------------------------------------------ batched (segmented) vectors
+// A batch vector is the concatenation of the problems' vectors; block b of a segmented dot covers
+// [beg[b], end[b]) inside one problem's segment, and problem p owns blocks pb0[p] .. pb0[p+1]-1.
+__global__ __launch_bounds__(kB) void k_bmultidot(const double* __restrict__ V, int64_t ldv, int k,
+                                                  const double* __restrict__ w, const int64_t* __restrict__ beg,
+                                                  const int64_t* __restrict__ end, int nblk,
+                                                  double* __restrict__ partial) {
+  __shared__ double red[kB];
+  const int64_t b0 = beg[blockIdx.x], b1 = end[blockIdx.x];
+  for (int j = 0; j < k; ++j) {
+    const double* vj = V + j * ldv;
+    double s = 0.0;
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kB) s += vj[e] * w[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kB / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[j * nblk + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[p * ostride + j] = sum of problem p's partial sums of dot j (grid: k x nprob)
+__global__ void k_breduce(const double* __restrict__ partial, int nblk, const int* __restrict__ pb0, int ostride,
+                          double* __restrict__ out) {
+  const int j = blockIdx.x, p = blockIdx.y;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = pb0[p]; b < pb0[p + 1]; ++b) s += partial[j * nblk + b];
+    out[p * ostride + j] = s;
+  }
+}
+
+// w[e] -= sum_j V_j[e] H[seg(e)][j]
+__global__ void k_bgemv_sub(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ H,
+                            int hs, const int* __restrict__ seg, double* __restrict__ w, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double* hp = H + (int64_t)seg[e] * hs;
+    double s = w[e];
+    for (int j = 0; j < k; ++j) s -= V[j * ldv + e] * hp[j];
+    w[e] = s;
+  }
+}
+
+// x[e] = sum_j V_j[e] Y[seg(e)][j]
+__global__ void k_blincomb(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ Y, int ys,
+                           const int* __restrict__ seg, double* __restrict__ x, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double* yp = Y + (int64_t)seg[e] * ys;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += V[j * ldv + e] * yp[j];
+    x[e] = s;
+  }
+}
+
+// dst[e] = src[e] * sc[seg(e)]
+__global__ void k_bscale(const double* __restrict__ src, const double* __restrict__ sc, const int* __restrict__ seg,
+                         double* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e] * sc[seg[e]];
+}
+
 inline unsigned blocks_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
@@ -219,6 +283,31 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
   hipLaunchKernelGGL(k_border_partial, dim3(nblk, nq), dim3(kB), 0, st, q, ds, n_ib, nq, nblk, partial);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_border_final, dim3(nq), dim3(64), 0, st, partial, nblk, eta, out);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_multidot(const double* V, int64_t ldv, int k, const double* w, const KrylovSegments& sg, double* partial,
+                 int ostride, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_bmultidot, dim3(sg.nblk), dim3(kB), 0, st, V, ldv, k, w, sg.beg, sg.end, sg.nblk, partial);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_breduce, dim3(k, sg.nprob), dim3(64), 0, st, partial, sg.nblk, sg.pb0, ostride, out);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_gemv_sub(const double* V, int64_t ldv, int k, const double* H, int hs, const KrylovSegments& sg, double* w,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_bgemv_sub, dim3(blocks_for(sg.n)), dim3(256), 0, st, V, ldv, k, H, hs, sg.seg, w, sg.n);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_lincomb(const double* V, int64_t ldv, int k, const double* Y, int ys, const KrylovSegments& sg, double* x,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_blincomb, dim3(blocks_for(sg.n)), dim3(256), 0, st, V, ldv, k, Y, ys, sg.seg, x, sg.n);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_scale(const double* src, const double* sc, const KrylovSegments& sg, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_bscale, dim3(blocks_for(sg.n)), dim3(256), 0, st, src, sc, sg.seg, dst, sg.n);
   IBDL_LAUNCH_CHECK();
 }
 
