@@ -49,26 +49,32 @@ def workload(name):
 
 def stage_cost(spec, prec, pr):
     """Algorithmic cost per launch of each stage of one operator apply: HBM bytes for the
-    memory-bound passes, floating-point operations for the spread (bound by vector ALU issue)."""
+    memory-bound passes (the x passes and the zero fill touch only the rows the markers' windows
+    meet; the forward y pass reads only those rows, the inverse writes only those), floating-point
+    operations for the spread (bound by vector ALU issue)."""
     t = 4 if prec == "mixed" else 8
     ntot = pr.grid_points
     nxh = spec.n[0] // 2 + 1
     nspec = ntot // spec.n[0] * nxh
-    R, C = ntot * t, nspec * 2 * t
+    C = nspec * 2 * t
+    nact, _ = pr.active_rows()
+    Ra, Ca = nact * spec.n[0] * t, nact * nxh * 2 * t
     scalar_fd = spec.pde != "stokes" and spec.disc == "fd2"
     c = 1 if scalar_fd else (5 if spec.pde == "stokes" else spec.dim + (1 if spec.eta > 0 else 0))
     o = pr.nq
     taps = 4 ** spec.dim
     b = {
-        "fill": ("hbm", c * R),
-        "fft_x_fwd": ("hbm", c * (R + C)),
-        "fused_last_axis": ("hbm", (c + o) * C),
-        "fft_x_inv": ("hbm", o * (C + R)),
+        "fill": ("hbm", c * Ra),
+        "fft_x_fwd": ("hbm", c * (Ra + Ca)),
+        "fft_x_inv": ("hbm", o * (Ca + Ra)),
         "interp": ("hbm", spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2)),
     }
     if spec.dim == 3:
-        b["fft_y_fwd"] = ("hbm", 2 * c * C)
-        b["fft_y_inv"] = ("hbm", 2 * o * C)
+        b["fft_y_fwd"] = ("hbm", c * (Ca + C))
+        b["fused_last_axis"] = ("hbm", (c + o) * C)
+        b["fft_y_inv"] = ("hbm", o * (C + Ca))
+    else:
+        b["fused_last_axis"] = ("hbm", (c + o) * Ca)
     # spread: per marker and window node, D-1 products per term and one add per term; the
     # finite-difference dipole spread has D derivative terms (+ mass), other modes c fields
     if scalar_fd:
@@ -117,6 +123,75 @@ def load_traffic(workload, kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def _timed(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
+    """The other rows of the path on this workload and the batched workload: FP64 at the accuracy
+    the mixed path reaches, the adjoint solve, and 64 problems batched vs one after another."""
+    import numpy as np
+    import torch
+    import paper_2210_07403_amd as ibdl
+    from workloads import problems as P
+    out = {}
+    m = spec.markers
+    print("# extras: mixed vs FP64 at equal accuracy", file=sys.stderr, flush=True)
+    if prec == "mixed":
+        t_mix, (_, _, im) = _timed(lambda: pr.solve(data, g, tol=tol, maxit=100), 3)
+        p64 = ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, m.nrm, m.ds, pde=spec.pde, kappa=spec.kappa,
+                           mu=spec.mu, bc=spec.bc, eta=spec.eta, kernel=spec.kernel, disc=spec.disc,
+                           precision="fp64", device=dev)
+        g64 = g.double() if g is not None else None
+        tol64 = max(im.true_relres_fp64, 1e-14)
+        t64, (_, _, i64) = _timed(lambda: p64.solve(data, g64, tol=tol64, maxit=100), 3)
+        out["mixed_vs_fp64"] = {"mixed_ms": round(1e3 * t_mix, 3), "mixed_true_relres": im.true_relres_fp64,
+                                "mixed_iters": im.iters, "fp64_ms": round(1e3 * t64, 3),
+                                "fp64_true_relres": i64.true_relres_fp64, "fp64_iters": i64.iters,
+                                "fp64_tol": tol64, "speedup": round(t64 / t_mix, 3)}
+        p64.close()
+    print("# extras: adjoint", file=sys.stderr, flush=True)
+    q, u, _ = pr.solve(data, g, tol=tol, maxit=100)
+    psi = torch.randn(u.shape, dtype=u.dtype, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+    t_fw, _ = _timed(lambda: pr.solve(data, g, tol=tol, maxit=100), 2)
+    t_bw, (_, _, ib) = _timed(lambda: pr.backward(q, u, psi, tol=tol, maxit=100), 2)
+    out["adjoint"] = {"forward_solve_ms": round(1e3 * t_fw, 3), "backward_ms": round(1e3 * t_bw, 3),
+                      "adjoint_iters": ib.iters, "adjoint_true_relres": ib.true_relres_fp64}
+    print("# extras: batch of 64", file=sys.stderr, flush=True)
+    specs = P.cfg4_batch()
+    dicts = [dict(dim=s.dim, n=s.n, L=s.L, origin=s.origin, X=s.markers.X, nrm=s.markers.nrm, ds=s.markers.ds,
+                  pde=s.pde, kappa=s.kappa, kernel=s.kernel) for s in specs]
+    bdata = [torch.as_tensor(np.asarray(s.data, dtype=np.float64), device=dev) for s in specs]
+    res = {}
+    for bp in ("mixed", "fp64"):
+        bt = ibdl.Batch(dicts, precision=bp, device=dev)
+        bt.solve(bdata, tol=1e-8, maxit=100, want_u=False)
+        tb, (_, _, binfo) = _timed(lambda: bt.solve(bdata, tol=1e-8, maxit=100, want_u=False), 3)
+        res[bp] = {"ms": round(1e3 * tb, 3), "solves_per_sec": round(len(specs) / tb, 1),
+                   "max_iters": max(i.iters for i in binfo),
+                   "max_true_relres": max(i.true_relres_fp64 for i in binfo), "groups": bt.groups()}
+        bt.close()
+    probs = [ibdl.Problem(s.dim, s.n, s.L, s.origin, s.markers.X, s.markers.nrm, s.markers.ds, pde=s.pde,
+                          kappa=s.kappa, kernel=s.kernel, precision="fp64", device=dev) for s in specs]
+    for p_, d_ in zip(probs, bdata):
+        p_.solve(d_, None, tol=1e-8, maxit=100, want_u=False)
+    tseq, _ = _timed(lambda: [p_.solve(d_, None, tol=1e-8, maxit=100, want_u=False) for p_, d_ in zip(probs, bdata)], 2)
+    for p_ in probs:
+        p_.close()
+    out["batch64"] = {"workload": "64 2-D Poisson Dirichlet problems, grids 128/256/512, 256-2048 markers, tol 1e-8",
+                      "batched_mixed": res["mixed"], "batched_fp64": res["fp64"],
+                      "sequential_fp64_ms": round(1e3 * tseq, 3),
+                      "speedup_batched_mixed_vs_sequential_fp64": round(tseq / (res["mixed"]["ms"] * 1e-3), 2),
+                      "speedup_batched_fp64_vs_sequential_fp64": round(tseq / (res["fp64"]["ms"] * 1e-3), 2)}
+    return out
+
+
 def cpu_baseline(spec, budget_s=20.0):
     """Time the FP64 numpy oracle's operator apply on this host (bounded sample)."""
     import numpy as np
@@ -152,6 +227,8 @@ def main():
     ap.add_argument("--workload", default="sphere256", choices=["sphere256", "star1024", "circle64"])
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-vs-FP64, adjoint and batched measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (counter calibration runs)")
     args = ap.parse_args()
@@ -240,6 +317,7 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
+    extras = {} if args.no_extras else measure_extras(spec, prec, pr, data, g, tol, max(relres), dev)
     total_applies = int(sum(iters))
     out = {
         "metric": METRIC,
@@ -267,8 +345,10 @@ def main():
         "model_U_effective_GB_s": round(mu / (apply_ms * 1e-3) / 1e9, 1),
         "model_U_frac_hbm_peak": round(mu / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "model_F_effective_GB_s": round(mf / (apply_ms * 1e-3) / 1e9, 1),
+        "active_rows": list(pr.active_rows()),
         "stages": stage_report,
         "roofline": roof,
+        **extras,
     }
     pr.close()
     if not args.no_cpu_baseline:

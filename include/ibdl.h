@@ -195,6 +195,11 @@ const char* ibdl_batch_last_error(ibdl_batch_t b);
  * solution (nq).  Any output pointer may be NULL. */
 ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq);
 
+/* Rows (x-lines) that the markers' 6-node windows meet, nact, out of rows_total = grid points / nx.
+ * The operator apply runs its x passes over those rows only: the spread field is zero on the
+ * others and the interpolation does not read them.  Either pointer may be NULL. */
+ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total);
+
 /* Profiling: enable (1) or disable (0) per-stage timing with HIP events recorded on the handle's
  * stream around every kernel stage (resets the accumulated times).  Costs a few microseconds per
  * stage; leave it off outside profiling. */

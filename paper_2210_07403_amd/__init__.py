@@ -167,6 +167,12 @@ class Problem:
         B.check(st, self._h)
         return dX, dd, SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64, [])
 
+    def active_rows(self):
+        """(rows the markers' windows meet, all rows) of one grid field."""
+        a, t = ctypes.c_int64(), ctypes.c_int64()
+        B.check(B.load().ibdl_active_rows(self._h, ctypes.byref(a), ctypes.byref(t)), self._h)
+        return int(a.value), int(t.value)
+
     def set_timing(self, enable=True):
         B.check(B.load().ibdl_set_timing(self._h, 1 if enable else 0), self._h)
 

@@ -163,7 +163,8 @@ template <typename TR, int M> struct RowCfg {
 // ------------------------------------------------------------------ x axis, forward R2C
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB) {
+                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB,
+                                                  RowList rl) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -172,10 +173,13 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   const int NT = RPB * RC::T;
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
-  const C* src = reinterpret_cast<const C*>(in) + row0 * M;
+  __shared__ int64_t rbase[kBlock];   // row index of each block row (active-row list or contiguous)
+  for (int r = tid; r < RPB; r += NT) rbase[r] = r < nvalid ? rl.row(row0 + r) : 0;
+  __syncthreads();
+  const C* src = reinterpret_cast<const C*>(in);
   for (int e = tid; e < RPB * M; e += NT) {
     const int r = e / M, c = e - r * M;
-    lds[r * RC::LS + c] = (r < nvalid) ? src[e] : mk<C>(0, 0);
+    lds[r * RC::LS + c] = (r < nvalid) ? src[rbase[r] * M + c] : mk<C>(0, 0);
   }
   __syncthreads();
   const int row = tid / RC::T, i = tid - row * RC::T;
@@ -188,21 +192,21 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
     for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
-  C* dst = out + row0 * (M + 1);
   for (int e = tid; e < nvalid * (M + 1); e += NT) {
     const int r = e / (M + 1), k = e - r * (M + 1);
     const C zk = lds[r * RC::LS + (k == M ? 0 : k)];
     const C zm = lds[r * RC::LS + (k == 0 ? 0 : M - k)];
     const C E = mk<C>((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
     const C O = mk<C>((zk.y + zm.y) * (T)0.5, -(zk.x - zm.x) * (T)0.5);
-    dst[e] = cadd(E, cmul(tw[k], O));
+    out[rbase[r] * (M + 1) + k] = cadd(E, cmul(tw[k], O));
   }
 }
 
 // ------------------------------------------------------------------ x axis, inverse C2R
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
-                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB) {
+                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB,
+                                                  RowList rl) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -211,10 +215,12 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   const int NT = RPB * RC::T;
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
-  const C* src = in + row0 * (M + 1);
+  __shared__ int64_t rbase[kBlock];
+  for (int r = tid; r < RPB; r += NT) rbase[r] = r < nvalid ? rl.row(row0 + r) : 0;
+  __syncthreads();
   for (int e = tid; e < RPB * (M + 1); e += NT) {
-    const int r = e / (M + 1);
-    lds[e] = (r < nvalid) ? src[e] : mk<C>(0, 0);
+    const int r = e / (M + 1), k = e - r * (M + 1);
+    lds[e] = (r < nvalid) ? in[rbase[r] * (M + 1) + k] : mk<C>(0, 0);
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{M-k}) + i conj(W^k) (X_k - conj X_{M-k}); each thread owns a pair (k, M-k)
@@ -242,10 +248,10 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
     for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
-  C* dst = reinterpret_cast<C*>(out) + row0 * M;
+  C* dst = reinterpret_cast<C*>(out);
   for (int e = tid; e < nvalid * M; e += NT) {
     const int r = e / M, c = e - r * M;
-    dst[e] = lds[r * RC::LS + c];
+    dst[rbase[r] * M + c] = lds[r * RC::LS + c];
   }
 }
 
@@ -262,7 +268,7 @@ template <typename T, int N> struct TileCfg {
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
                                                     int64_t outer, int64_t es, const cplx<T>* __restrict__ tw,
-                                                    int W) {
+                                                    int W, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -272,14 +278,20 @@ __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, 
   const int64_t l = (int64_t)blockIdx.x * W + c;
   const bool valid = l < nlines;
   const int64_t base = valid ? (l / inner) * outer + (l % inner) : 0;
+  const RowMask pm = rm.plane(valid ? (l / inner) : 0);   // rows of this line's plane that matter
   C v[Plan<N>::RMAX];
 #pragma unroll
-  for (int s = 0; s < Plan<N>::RMAX; ++s)
-    v[s] = valid ? data[base + (int64_t)(i + s * Plan<N>::T) * es] : mk<C>(0, 0);
+  for (int s = 0; s < Plan<N>::RMAX; ++s) {
+    const int y = i + s * Plan<N>::T;
+    v[s] = (valid && pm.keep(y)) ? data[base + (int64_t)y * es] : mk<C>(0, 0);
+  }
   fft_line<N, INV>(v, i, lds + c, W, tw, 1);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < Plan<N>::RMAX; ++s) data[base + (int64_t)(i + s * Plan<N>::T) * es] = v[s];
+    for (int s = 0; s < Plan<N>::RMAX; ++s) {
+      const int y = i + s * Plan<N>::T;
+      if (pm.keep_out(y)) data[base + (int64_t)y * es] = v[s];
+    }
   }
 }
 
@@ -318,7 +330,7 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
 
 template <typename T, int N, int NO, bool STOKES>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                  const cplx<T>* __restrict__ tw, int W, int64_t bstride) {
+                                                  const cplx<T>* __restrict__ tw, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
@@ -363,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   for (int f = 0; f < md.nc; ++f) {
     C v[RM];
 #pragma unroll
-    for (int s = 0; s < RM; ++s) v[s] = valid ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+    for (int s = 0; s < RM; ++s)
+      v[s] = (valid && rm.keep(i + s * TT)) ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
     fft_line<N, false>(v, i, lds + c, W, tw, 1);
     const int fk = md.fk[f];
     if constexpr (!STOKES) {
@@ -395,7 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
     fft_line<N, true>(acc[o], i, lds + c, W, tw, 1);
     if (valid) {
 #pragma unroll
-      for (int s = 0; s < RM; ++s) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[o][s];
+      for (int s = 0; s < RM; ++s)
+        if (rm.keep_out(i + s * TT)) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[o][s];
     }
   }
 }
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
 template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                   const cplx<T>* __restrict__ tw, int W, int64_t bstride) {
+                                                   const cplx<T>* __restrict__ tw, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
@@ -423,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   if (d3) sig_l += static_cast<const T*>(md.sig[1])[jy2];
   C v[RM];
 #pragma unroll
-  for (int s = 0; s < RM; ++s) v[s] = valid ? data[l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+  for (int s = 0; s < RM; ++s) v[s] = (valid && rm.keep(i + s * TT)) ? data[l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
   fft_line<N, false>(v, i, lds + c, W, tw, 1);
   const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
 #pragma unroll
@@ -434,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   fft_line<N, true>(v, i, lds + c, W, tw, 1);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < RM; ++s) data[l + (int64_t)(i + s * TT) * P] = v[s];
+    for (int s = 0; s < RM; ++s)
+      if (rm.keep_out(i + s * TT)) data[l + (int64_t)(i + s * TT) * P] = v[s];
   }
 }
 
@@ -443,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
 // all read before the first store, and each workgroup owns its lines in every field).
 template <typename T, int N, int NI, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data, int64_t P, int no, MultDesc md,
-                                                      const cplx<T>* __restrict__ tw, int W, int64_t bstride) {
+                                                      const cplx<T>* __restrict__ tw, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
@@ -474,7 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
 #pragma unroll
   for (int f = 0; f < NI; ++f) {
 #pragma unroll
-    for (int s = 0; s < RM; ++s) v[f][s] = valid ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+    for (int s = 0; s < RM; ++s)
+      v[f][s] = (valid && rm.keep(i + s * TT)) ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
     fft_line<N, false>(v[f], i, lds + c, W, tw, 1);
   }
   for (int o = 0; o < no; ++o) {
@@ -499,7 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
     fft_line<N, true>(acc, i, lds + c, W, tw, 1);
     if (valid) {
 #pragma unroll
-      for (int s = 0; s < RM; ++s) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[s];
+      for (int s = 0; s < RM; ++s)
+        if (rm.keep_out(i + s * TT)) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[s];
     }
   }
 }
@@ -547,34 +564,38 @@ int pick(int want, int max) {
 }  // namespace
 
 template <typename T>
-void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb) {
+void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
+               const RowList& rl) {
   dispatch_n(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
     const int R = pick(rpb, RC::RPB);
     const int64_t nb = (nrows + R - 1) / R;
     const size_t lds = sizeof(cplx<T>) * R * RC::LS;
-    hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R);
+    if (nb > 0)
+      hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
-void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb) {
+void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
+               const RowList& rl) {
   dispatch_n(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
     const int R = pick(rpb, RC::RPB);
     const int64_t nb = (nrows + R - 1) / R;
     const size_t lds = sizeof(cplx<T>) * R * RC::LS;
-    hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R);
+    if (nb > 0)
+      hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es, bool inverse,
-                 const cplx<T>* tw, hipStream_t s, int w) {
+                 const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm) {
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     using TC = TileCfg<T, N>;
@@ -584,17 +605,17 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
     const dim3 blk(W * TC::T_);
     if (inverse)
       hipLaunchKernelGGL((k_strided<T, N, true>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
-                         tw, W);
+                         tw, W, rm);
     else
       hipLaunchKernelGGL((k_strided<T, N, false>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
-                         tw, W);
+                         tw, W, rm);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw, hipStream_t s,
-                    int batch, int64_t bstride, int w) {
+                    int batch, int64_t bstride, int w, const RowMask& rm) {
   if (batch < 1) return;
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
@@ -604,17 +625,17 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
     const size_t lds = sizeof(cplx<T>) * N * W;
     const dim3 grid((unsigned)nb, (unsigned)batch), blk(W * TC::T_);
     if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1)
-      hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride);
+      hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
     else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5)
-      hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), grid, blk, lds, s, data, P, no, md, tw, W, bstride);
+      hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
     else if (md.mode != 0)
       throw Error(-2, "fused pass: unsupported transposed multiplier");
     else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)
-      hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride);
+      hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
     else if (!md.stokes && no == 1)
-      hipLaunchKernelGGL((k_fused<T, N, 1, false>), grid, blk, lds, s, data, P, md, tw, W, bstride);
+      hipLaunchKernelGGL((k_fused<T, N, 1, false>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
     else if (md.stokes && no == 2)
-      hipLaunchKernelGGL((k_fused<T, N, 2, true>), grid, blk, lds, s, data, P, md, tw, W, bstride);
+      hipLaunchKernelGGL((k_fused<T, N, 2, true>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
     else
       throw Error(-2, "fused pass: unsupported multiplier / output count");
   });
@@ -622,12 +643,14 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
 }
 
 #define IBDL_FFT_INST(T)                                                                                   \
-  template void fft_x_r2c<T>(const T*, cplx<T>*, int, int64_t, const cplx<T>*, hipStream_t, int);         \
-  template void fft_x_c2r<T>(const cplx<T>*, T*, int, int64_t, const cplx<T>*, hipStream_t, int);         \
+  template void fft_x_r2c<T>(const T*, cplx<T>*, int, int64_t, const cplx<T>*, hipStream_t, int,         \
+                             const RowList&);                                                              \
+  template void fft_x_c2r<T>(const cplx<T>*, T*, int, int64_t, const cplx<T>*, hipStream_t, int,         \
+                             const RowList&);                                                              \
   template void fft_strided<T>(cplx<T>*, int, int64_t, int64_t, int64_t, int64_t, bool, const cplx<T>*,   \
-                               hipStream_t, int);                                                          \
+                               hipStream_t, int, const RowMask&);                                          \
   template void fft_fused_last<T>(cplx<T>*, int, int64_t, int, const MultDesc&, const cplx<T>*, hipStream_t, \
-                                  int, int64_t, int);                                                      \
+                                  int, int64_t, int, const RowMask&);                                      \
   template int fft_x_rpb_max<T>(int);                                                                      \
   template int fft_line_w_max<T>(int);
 IBDL_FFT_INST(float)

@@ -521,6 +521,62 @@ __global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __
   }
 }
 
+// ------------------------------------------------------------------ active rows
+// Rows y of plane z that a marker's 6-node window meets: [s_y, s_y + 5] for z in [s_z, s_z + 5]
+// (mod n); a window that wraps around y marks the whole plane.
+__global__ void k_rows_init(int* __restrict__ lo, int* __restrict__ hi, int nplanes, int ny) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < nplanes) {
+    lo[z] = ny;
+    hi[z] = -1;
+  }
+}
+
+__global__ void k_rows_mark(MarkerGeom g, int64_t n_ib, const int* __restrict__ s, int* __restrict__ lo,
+                            int* __restrict__ hi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_ib) return;
+  const int ny = g.n[1];
+  const int sy = s[i * 3 + 1];
+  const int ylo = sy + 5 < ny ? sy : 0;
+  const int yhi = sy + 5 < ny ? sy + 5 : ny - 1;
+  const int nz = g.dim == 3 ? g.n[2] : 1;
+  const int nw = g.dim == 3 ? 6 : 1;
+  for (int t = 0; t < nw; ++t) {
+    const int z = g.dim == 3 ? (s[i * 3 + 2] + t) & (nz - 1) : 0;
+    atomicMin(&lo[z], ylo);
+    atomicMax(&hi[z], yhi);
+  }
+}
+
+// per-plane row counts, the (lo, hi) pairs used by the y-pass masks, and then the row list
+__global__ void k_rows_count(const int* __restrict__ lo, const int* __restrict__ hi, int nplanes,
+                             int* __restrict__ cnt, int2* __restrict__ lim) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nplanes) return;
+  const bool any = hi[z] >= lo[z];
+  cnt[z] = any ? hi[z] - lo[z] + 1 : 0;
+  lim[z] = any ? make_int2(lo[z], hi[z]) : make_int2(1, 0);
+}
+
+__global__ void k_rows_list(const int* __restrict__ lo, const int* __restrict__ cnt, const int* __restrict__ off,
+                            int nplanes, int ny, int* __restrict__ rows) {
+  const int z = blockIdx.x;
+  if (z >= nplanes) return;
+  for (int k = threadIdx.x; k < cnt[z]; k += blockDim.x) rows[off[z] + k] = z * ny + lo[z] + k;
+}
+
+template <typename T>
+__global__ void k_fill_rows(T* __restrict__ y, const int* __restrict__ rows, int64_t nact, int nx, int nfields,
+                            int64_t rpf) {
+  const int64_t n = nact * nfields * nx;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / nx, c = e - r * nx;
+    const int64_t row = rows[r % nact] + (r / nact) * rpf;
+    y[row * nx + c] = (T)0;
+  }
+}
+
 // ------------------------------------------------------------------ kernel-derivative gather
 // One thread per marker over its K^D window (K = 4: taps 1..4 of the 6-node window; K = 6: all),
 // in double: out[i][e] = sum_x F_i(x) (-phi'(r_e)/h) prod_{d != e} phi(r_d), r_d = (x_d - X_id)/h.
@@ -650,6 +706,30 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
   IBDL_LAUNCH_CHECK();
 }
 
+void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int* hi, int* cnt, int* off, int2* lim,
+                  int* rows, hipStream_t st) {
+  const int nplanes = g.dim == 3 ? g.n[2] : 1;
+  hipLaunchKernelGGL(k_rows_init, dim3((nplanes + 255) / 256), dim3(256), 0, st, lo, hi, nplanes, g.n[1]);
+  IBDL_LAUNCH_CHECK();
+  if (n_ib > 0)
+    hipLaunchKernelGGL(k_rows_mark, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, g, n_ib, s, lo, hi);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_rows_count, dim3((nplanes + 255) / 256), dim3(256), 0, st, lo, hi, nplanes, cnt, lim);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, off, nplanes);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_rows_list, dim3(nplanes), dim3(256), 0, st, lo, cnt, off, nplanes, g.n[1], rows);
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
+void grid_fill_rows(T* y, const int* rows, int64_t nact, int nx, int nfields, int64_t rpf, hipStream_t st) {
+  const int64_t n = nact * nfields * nx;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_fill_rows<T>), dim3(grid_blocks(n)), dim3(256), 0, st, y, rows, nact, nx, nfields, rpf);
+  IBDL_LAUNCH_CHECK();
+}
+
 template <typename T>
 void grid_fill_zero(T* y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_fill<T>), dim3(grid_blocks(n)), dim3(256), 0, st, y, n);
@@ -735,6 +815,7 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
   template void spread<T>(const SpreadArgs&, const cplx<T>*, T*, hipStream_t);            \
   template void weight_table<T>(const double*, int64_t, cplx<T>*, hipStream_t);           \
   template void grid_fill_zero<T>(T*, int64_t, hipStream_t);                              \
+  template void grid_fill_rows<T>(T*, const int*, int64_t, int, int, int64_t, hipStream_t); \
   template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
   template void gather_dx<T>(const GatherArgs&, hipStream_t);                             \

@@ -49,6 +49,11 @@ struct ibdl_s {
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
   int *busy = nullptr, *busy_off = nullptr;
   int nbusy = 0;
+  // active rows (rows of the markers' windows): list for the x passes, per-plane limits for y
+  int *row_lo = nullptr, *row_hi = nullptr, *row_cnt = nullptr, *row_off = nullptr, *rows = nullptr;
+  int2* row_lim = nullptr;
+  int64_t nact = 0;
+  int lim2d[2] = {0, -1};     // 2-D: the one plane's limits, on the host
   MarkerGeom geom{};
   std::unique_ptr<GridWork<float>> w32;
   std::unique_ptr<GridWork<double>> w64;
@@ -223,34 +228,63 @@ template <typename T> MultDesc base_desc(ibdl_s* h, GridWork<T>& W) {
   return md;
 }
 
-// real fields src[0..nin) -> spectra -> fused multiplier -> real fields dst[0..nout)
+// real fields src[0..nin) -> spectra -> fused multiplier -> real fields dst[0..nout).
+// sparse: src is zero outside the active rows and only the active rows of dst are needed (the
+// operator apply), so the x passes run over the row list and the y passes mask the other rows.
 template <typename T>
-void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md) {
+void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md,
+              bool sparse = false) {
   const int64_t rows_per_field = h->ntot / h->n[0];
+  RowList rl;
+  RowMask fwd, inv, fused;
+  if (sparse) {
+    rl.rows = h->rows;
+    rl.nact = h->nact;
+    rl.rpf = rows_per_field;
+    if (h->dim == 3) {
+      fwd.lim = inv.lim = h->row_lim;
+      fwd.nplanes = inv.nplanes = h->n[2];
+      fwd.load = 1;
+      inv.store = 1;
+    } else {
+      fused.load = fused.store = 1;
+      fused.lo = h->lim2d[0];
+      fused.hi = h->lim2d[1];
+    }
+  }
+  const int64_t rin = sparse ? h->nact * nin : rows_per_field * nin;
+  const int64_t rout = sparse ? h->nact * nout : rows_per_field * nout;
   {
     StageTimer t(h, ST_FFT_X_FWD);
-    fft_x_r2c<T>(src, W.spec, h->n[0], rows_per_field * nin, W.tw[0], h->st);
+    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, 0, rl);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, false,
-                   W.tw[1], h->st);
+                   W.tw[1], h->st, 0, fwd);
   }
   const int last = h->dim - 1;
   const int64_t P = h->nspec / h->n[last];
   {
     StageTimer t(h, ST_FUSED);
-    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st);
+    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, 0, fused);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_INV);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, true,
-                   W.tw[1], h->st);
+                   W.tw[1], h->st, 0, inv);
   }
   {
     StageTimer t(h, ST_FFT_X_INV);
-    fft_x_c2r<T>(W.spec, dst, h->n[0], rows_per_field * nout, W.tw[0], h->st);
+    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, 0, rl);
   }
+}
+
+// zero nf spread fields: the active rows only when the pipeline runs sparse
+template <typename T> void clear_fields(ibdl_s* h, T* y, int nf, bool sparse) {
+  StageTimer t(h, ST_FILL);
+  if (sparse) grid_fill_rows<T>(y, h->rows, h->nact, h->n[0], nf, h->ntot / h->n[0], h->st);
+  else grid_fill_zero<T>(y, h->ntot * nf, h->st);
 }
 
 SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
@@ -298,16 +332,13 @@ void ensure_partial(ibdl_s* h, int need) {
 // Density q (device, [n_ib][nq]) -> grid field u[q] induced by it (plus optional mass values m and
 // forcing g as in the grid recovery), written to dst (nq fields).
 template <typename T>
-void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T* dst) {
+void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T* dst, bool sparse = false) {
   GridWork<T>& W = ensure_work<T>(h);
   MultDesc md = base_desc<T>(h, W);
   if (h->stokes()) {
     const int nf = (h->cfg.eta > 0 || g) ? 5 : 3;
     SpreadArgs a = spread_args(h, SP_STOKES, nf, q);
-    {
-      StageTimer t(h, ST_FILL);
-      grid_fill_zero<T>(W.real, h->ntot * a.nf, h->st);
-    }
+    clear_fields<T>(h, W.real, a.nf, sparse);
     {
       StageTimer t(h, ST_SPREAD);
       spread<T>(a, W.wtab, W.real, h->st);
@@ -317,7 +348,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     const int kinds[5] = {FK_A11, FK_A12, FK_A22, FK_G1, FK_G2};
     for (int i = 0; i < nf; ++i) md.fk[i] = kinds[i];
     md.alpha = 1.0;
-    pipeline<T>(h, W, W.real, nf, dst, 2, md);
+    pipeline<T>(h, W, W.real, nf, dst, 2, md, sparse);
     return;
   }
   const bool mass = h->cfg.eta > 0 || m != nullptr || g != nullptr;
@@ -325,10 +356,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     SpreadArgs a = spread_args(h, SP_FDDIV, 1, q);
     a.mass = (h->cfg.eta > 0 || m != nullptr) ? 1 : 0;
     a.m = m;
-    {
-      StageTimer t(h, ST_FILL);
-      grid_fill_zero<T>(W.real, h->ntot * a.nf, h->st);
-    }
+    clear_fields<T>(h, W.real, a.nf, sparse);
     {
       StageTimer t(h, ST_SPREAD);
       spread<T>(a, W.wtab, W.real, h->st);
@@ -341,10 +369,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     SpreadArgs a = spread_args(h, SP_SCALAR_VEC, nf, q);
     a.mass = mass ? 1 : 0;
     a.m = m;
-    {
-      StageTimer t(h, ST_FILL);
-      grid_fill_zero<T>(W.real, h->ntot * a.nf, h->st);
-    }
+    clear_fields<T>(h, W.real, a.nf, sparse);
     {
       StageTimer t(h, ST_SPREAD);
       spread<T>(a, W.wtab, W.real, h->st);
@@ -355,13 +380,13 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     if (mass) md.fk[h->dim] = FK_MASS;
   }
   md.alpha = -1.0;
-  pipeline<T>(h, W, W.real, md.nc, dst, 1, md);
+  pipeline<T>(h, W, W.real, md.nc, dst, 1, md, sparse);
 }
 
 // y = A q
 template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
   GridWork<T>& W = ensure_work<T>(h);
-  density_to_grid<T>(h, q, nullptr, nullptr, W.real);
+  density_to_grid<T>(h, q, nullptr, nullptr, W.real, true);
   const double half = h->neumann() ? -0.5 : 0.5;
   const double* ub = h->has_ubar ? q + h->n_ib * h->nq : nullptr;
   InterpArgs ia = interp_args(h, h->nq, 1.0, half, q, ub);
@@ -443,7 +468,7 @@ int adj_nout(ibdl_s* h) {
   return h->dim + (h->cfg.eta > 0 ? 1 : 0);
 }
 
-template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst) {
+template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst, bool sparse = false) {
   MultDesc md = base_desc<T>(h, W);
   const int nout = adj_nout(h);
   md.alpha = 1.0;
@@ -457,7 +482,7 @@ template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* 
     md.nc = 1;
     md.fk[0] = FK_MASS;
   }
-  pipeline<T>(h, W, src, md.nc, dst, nout, md);
+  pipeline<T>(h, W, src, md.nc, dst, nout, md, sparse);
 }
 
 void ensure_adj(ibdl_s* h) {
@@ -486,15 +511,12 @@ template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
   ensure_adj(h);
   SpreadArgs a = spread_args(h, SP_PLAIN, h->nq, p);
   a.raw = 1;
-  {
-    StageTimer t(h, ST_FILL);
-    grid_fill_zero<T>(W.real, h->ntot * h->nq, h->st);
-  }
+  clear_fields<T>(h, W.real, h->nq, true);
   {
     StageTimer t(h, ST_SPREAD);
     spread<T>(a, W.wtab, W.real, h->st);
   }
-  adj_grid<T>(h, W, W.real, W.real);
+  adj_grid<T>(h, W, W.real, W.real, true);
   const double half = h->neumann() ? -0.5 : 0.5;
   const double* pu = h->has_ubar ? p + h->n_ib * h->nq : nullptr;
   adj_markers<T>(h, W, p, half, pu, y);
@@ -711,11 +733,19 @@ void build_markers(ibdl_s* h) {
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
               h->busy_off, h->st);
+  markers_rows(h->geom, h->n_ib, h->s, h->row_lo, h->row_hi, h->row_cnt, h->row_off, h->row_lim, h->rows, h->st);
   const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
-  int nb = 0;
+  const int nplanes = h->dim == 3 ? h->n[2] : 1;
+  int nb = 0, na = 0;
+  int2 l2 = make_int2(1, 0);
   IBDL_HIP(hipMemcpyAsync(&nb, h->busy_off + ntile, sizeof(int), hipMemcpyDeviceToHost, h->st));
+  IBDL_HIP(hipMemcpyAsync(&na, h->row_off + nplanes, sizeof(int), hipMemcpyDeviceToHost, h->st));
+  IBDL_HIP(hipMemcpyAsync(&l2, h->row_lim, sizeof(int2), hipMemcpyDeviceToHost, h->st));
   IBDL_HIP(hipStreamSynchronize(h->st));
   h->nbusy = nb;
+  h->nact = na;
+  h->lim2d[0] = l2.x;
+  h->lim2d[1] = l2.y;
   if (h->w32 && h->w32->wtab) weight_table<float>(h->wt, h->n_ib, h->w32->wtab, h->st);
   if (h->w64 && h->w64->wtab) weight_table<double>(h->wt, h->n_ib, h->w64->wtab, h->st);
 }
@@ -785,6 +815,13 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->busy_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);
+    const int nplanes = h->dim == 3 ? h->n[2] : 1;
+    h->row_lo = (int*)h->dalloc<int>(sizeof(int) * nplanes);
+    h->row_hi = (int*)h->dalloc<int>(sizeof(int) * nplanes);
+    h->row_cnt = (int*)h->dalloc<int>(sizeof(int) * (nplanes + 1));
+    h->row_off = (int*)h->dalloc<int>(sizeof(int) * (nplanes + 1));
+    h->row_lim = (int2*)h->dalloc<int>(sizeof(int2) * nplanes);
+    h->rows = (int*)h->dalloc<int>(sizeof(int) * (int64_t)h->n[1] * nplanes);
     h->small = (double*)h->dalloc<double>(sizeof(double) * 1024);
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
@@ -949,6 +986,13 @@ ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t
   if (n_aug) *n_aug = h->n_aug;
   if (grid_points) *grid_points = h->ntot;
   if (nq) *nq = h->nq;
+  return IBDL_OK;
+}
+
+ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total) {
+  if (!h) return IBDL_ERR_ARG;
+  if (nact) *nact = h->nact;
+  if (rows_total) *rows_total = h->ntot / h->n[0];
   return IBDL_OK;
 }
 

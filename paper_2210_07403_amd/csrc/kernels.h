@@ -14,6 +14,34 @@ enum FieldKind {
   FK_G1 = 7, FK_G2 = 8               // Stokes single-layer / forcing components
 };
 
+// Rows (x-lines, index z * ny + y within a field) that carry data.  A spread field is zero outside
+// the rows its markers' windows meet, and the interpolation reads only those rows, so the x passes
+// can run over a list of them and the y passes can skip the loads / stores of the others.
+struct RowList {
+  const int* rows = nullptr;   // active rows of one field, increasing (NULL: every row)
+  int64_t nact = 0;            // active rows per field
+  int64_t rpf = 0;             // rows per field
+  __device__ int64_t row(int64_t r) const { return rows ? (int64_t)rows[r % nact] + (r / nact) * rpf : r; }
+};
+struct RowMask {
+  const int2* lim = nullptr;   // per plane z: rows y in [lim.x, lim.y] matter (NULL: all)
+  int nplanes = 1;
+  int load = 0;                // read only those rows (others are zero)
+  int store = 0;               // write only those rows
+  int lo = 0, hi = 1 << 30;    // limits of the current plane (2-D: set by the host; else plane())
+  __device__ RowMask plane(int64_t line_plane) const {
+    RowMask m = *this;
+    if (lim) {
+      const int2 v = lim[line_plane % nplanes];
+      m.lo = v.x;
+      m.hi = v.y;
+    }
+    return m;
+  }
+  __device__ bool keep(int y) const { return !load || (y >= lo && y <= hi); }
+  __device__ bool keep_out(int y) const { return !store || (y >= lo && y <= hi); }
+};
+
 struct MultDesc {
   int mode;         // 0: forward multiplier; 1: scalar gradient outputs; 2: transposed Stokes
   int dim;          // 2 or 3
@@ -34,14 +62,17 @@ struct MultDesc {
 // 256 threads and 64 KiB of LDS).
 template <typename T> int fft_x_rpb_max(int nx);
 template <typename T> int fft_line_w_max(int n);
+// x passes over nrows rows (with a row list: nrows = active rows per field x fields)
 template <typename T>
-void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0);
+void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0,
+               const RowList& rl = RowList());
 template <typename T>
-void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0);
+void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0,
+               const RowList& rl = RowList());
 // in-place strided C2C pass: line l starts at (l / inner) * outer + (l % inner), element stride es
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es,
-                 bool inverse, const cplx<T>* tw, hipStream_t s, int w = 0);
+                 bool inverse, const cplx<T>* tw, hipStream_t s, int w = 0, const RowMask& rm = RowMask());
 // in-place fused pass along the last axis (length n, plane size P): forward FFT of the nc input
 // fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1).
 // mode 1 (one scalar input F): outputs i k~_o g F^ for o < dim, then g F^, g = alpha sc/(c2 sigma - c0);
@@ -50,7 +81,8 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
 // batch problems with the same multiplier: problem b's fields start bstride elements after b-1's.
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw,
-                    hipStream_t s, int batch = 1, int64_t bstride = 0, int w = 0);
+                    hipStream_t s, int batch = 1, int64_t bstride = 0, int w = 0,
+                    const RowMask& rm = RowMask());
 int fft_supported(int n);
 
 // ------------------------------------------------------------------ markers, spread, interp
@@ -75,6 +107,15 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
                  int* tile_off, int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off,
                  hipStream_t st, const int* pid = nullptr, int nprob = 1);
+
+// Active rows of the markers' windows: lo/hi [planes] (scratch), cnt/off [planes + 1] (scratch),
+// lim [planes] = (lo, hi) per plane, rows = the row list (up to ny * planes entries), increasing;
+// the count is off[planes].  planes = nz in 3-D, 1 in 2-D.
+void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int* hi, int* cnt, int* off, int2* lim,
+                  int* rows, hipStream_t st);
+// zero the listed rows of nfields fields (rpf rows per field, nx values per row)
+template <typename T>
+void grid_fill_rows(T* y, const int* rows, int64_t nact, int nx, int nfields, int64_t rpf, hipStream_t st);
 
 enum SpreadMode {
   SP_PLAIN = 0,     // nf fields: coef_c = f[i][c] ds_i h^-D
