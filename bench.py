@@ -346,6 +346,7 @@ def main():
         "model_U_frac_hbm_peak": round(mu / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "model_F_effective_GB_s": round(mf / (apply_ms * 1e-3) / 1e9, 1),
         "active_rows": list(pr.active_rows()),
+        "launch_shape": dict(zip(("rows_per_block", "lines_y", "lines_last"), pr.launch_shape())),
         "stages": stage_report,
         "roofline": roof,
         **extras,

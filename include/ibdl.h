@@ -200,6 +200,11 @@ ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t
  * others and the interpolation does not read them.  Either pointer may be NULL. */
 ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total);
 
+/* Launch shapes of the operator apply's FFT passes in the working precision, chosen by timing at
+ * the first apply (rows per block of the x passes, lines per block of the y passes and of the fused
+ * last-axis pass; 0 = not measured yet, the largest shape is used).  Any pointer may be NULL. */
+ibdl_status_t ibdl_launch_shape(ibdl_t h, int32_t* rows_per_block, int32_t* lines_y, int32_t* lines_last);
+
 /* Profiling: enable (1) or disable (0) per-stage timing with HIP events recorded on the handle's
  * stream around every kernel stage (resets the accumulated times).  Costs a few microseconds per
  * stage; leave it off outside profiling. */

@@ -173,6 +173,12 @@ class Problem:
         B.check(B.load().ibdl_active_rows(self._h, ctypes.byref(a), ctypes.byref(t)), self._h)
         return int(a.value), int(t.value)
 
+    def launch_shape(self):
+        """Measured launch shapes of the apply's FFT passes: (rows per block, y lines, last-axis lines)."""
+        r, y, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        B.check(B.load().ibdl_launch_shape(self._h, ctypes.byref(r), ctypes.byref(y), ctypes.byref(z)), self._h)
+        return int(r.value), int(y.value), int(z.value)
+
     def set_timing(self, enable=True):
         B.check(B.load().ibdl_set_timing(self._h, 1 if enable else 0), self._h)
 

@@ -25,6 +25,7 @@
 #include "../../include/ibdl.h"
 #include "kernels.h"
 #include "tables.h"
+#include "tune.h"
 
 using namespace ibdl;
 
@@ -32,13 +33,7 @@ namespace {
 
 std::string g_batch_create_error;
 
-struct Tuned {
-  int rpb = 0;   // rows per block of the x passes (0: maximum)
-  int w = 0;     // lines per block of the fused last-axis pass (0: maximum)
-};
-using TuneKey = std::tuple<int, int, int, int, int, int>;   // dim, n0, n1, n2, precision, problems bucket
-std::mutex g_tune_mu;
-std::map<TuneKey, Tuned> g_tune;
+using Tuned = LaunchShape;
 
 template <typename T> struct GroupWork {
   GridTables<T> tab;
@@ -155,7 +150,7 @@ template <typename T> void group_pipeline(ibdl_batch_s* B, Group& G, GroupWork<T
     fft_strided<T>(W.spec, G.n[1], (int64_t)np * G.n[2] * G.nxh, G.nxh, G.nxh * G.n[1], G.nxh, false, W.tab.tw[1],
                    B->st);
   const int last = B->dim - 1;
-  fft_fused_last<T>(W.spec, G.n[last], G.nspec / G.n[last], 1, md, W.tab.tw[last], B->st, np, G.nspec, tn.w);
+  fft_fused_last<T>(W.spec, G.n[last], G.nspec / G.n[last], 1, md, W.tab.tw[last], B->st, np, G.nspec, tn.wz);
   if (B->dim == 3)
     fft_strided<T>(W.spec, G.n[1], (int64_t)np * G.n[2] * G.nxh, G.nxh, G.nxh * G.n[1], G.nxh, true, W.tab.tw[1],
                    B->st);
@@ -208,17 +203,8 @@ template <typename T> GroupWork<T>& group_work(ibdl_batch_s* B, Group& G) {
 // down to an eighth of it, two warm-up and three timed runs of the group's FFT passes each.
 template <typename T> void tune_group(ibdl_batch_s* B, Group& G, GroupWork<T>& W) {
   const int np = (int)G.probs.size();
-  int bucket = 1;
-  while (bucket < np) bucket *= 2;
-  const TuneKey key{B->dim, G.n[0], G.n[1], G.n[2], (int)sizeof(T), bucket};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
-      W.tune = it->second;
-      return;
-    }
-  }
+  const TuneKey key{1, B->dim, G.n[0], G.n[1], G.n[2], (int)sizeof(T), 1, pow2_bucket(np)};
+  if (tune_get(key, &W.tune)) return;
   const int rmax = fft_x_rpb_max<T>(G.n[0]);
   const int wmax = fft_line_w_max<T>(G.n[B->dim - 1]);
   hipEvent_t e0, e1;
@@ -230,7 +216,7 @@ template <typename T> void tune_group(ibdl_batch_s* B, Group& G, GroupWork<T>& W
     for (int w = wmax; w >= 1 && w * 8 >= wmax; w /= 2) {
       Tuned c;
       c.rpb = r;
-      c.w = w;
+      c.wz = w;
       for (int k = 0; k < 2; ++k) group_pipeline<T>(B, G, W, c);
       IBDL_HIP(hipEventRecord(e0, B->st));
       for (int k = 0; k < 3; ++k) group_pipeline<T>(B, G, W, c);
@@ -246,8 +232,7 @@ template <typename T> void tune_group(ibdl_batch_s* B, Group& G, GroupWork<T>& W
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   W.tune = best;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = best;
+  tune_put(key, best);
 }
 
 // y = A x for every problem of the batch (Dirichlet: y = S* u[x] + x/2)
@@ -771,7 +756,7 @@ ibdl_status_t ibdl_batch_query(ibdl_batch_t b, int32_t group, int32_t* ngroups, 
     if (n)
       for (int d = 0; d < 3; ++d) n[d] = G.n[d];
     if (rows_per_block) *rows_per_block = t.rpb;
-    if (lines_per_block) *lines_per_block = t.w;
+    if (lines_per_block) *lines_per_block = t.wz;
     return IBDL_OK;
   });
 }

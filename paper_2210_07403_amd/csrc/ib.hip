@@ -240,103 +240,147 @@ template <typename T> __device__ __forceinline__ T bcast(T v, int lane) {
   }
 }
 
-// Each wave takes the candidates c0 + 4*l + wave (l < LW) of the tile's sorted list, one per lane:
-// the lane keeps the candidate's uniform data (window start, the tile-aligned z column of (W, G),
-// field coefficients) in registers, and the accumulation loop broadcasts them with readlane; only
-// the lane-varying x / y weights come from LDS rows written by the owning lane.
-template <typename T, int NF>
-__global__ __launch_bounds__(256) void k_spread3(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
+// ------------------------------------------------------------------ 3-D spread on the matrix cores
+// A tile's spread is a sum of rank-1 tensor products, i.e. a matrix product
+//   out[(y,z), x] = sum_k P[(y,z), k] Q[k, x],   k = (candidate, term),
+// with Q a kernel row along x and P the matching (y,z) factor.  Finite-difference dipole field:
+//   term 0: P = c_x W_y W_z,                          Q = G_x
+//   term 1: P = c_y G_y W_z + c_z W_y G_z + c_m W_y W_z,  Q = W_x
+// other modes (field c): P = cf_c W_y W_z, Q = W_x.  The 16 x 4 x 8 tile is two 16 x 16 blocks of
+// (y,z) rows against 16 x columns; v_mfma_{f32,f64}_16x16x4 adds four k per instruction.  Operand
+// layout (both precisions): lane l supplies P[l % 16][l / 16] and Q[l / 16][l % 16]; result row
+// 4 (l / 16) + v (f32) or l / 16 + 4 v (f64), column l % 16.  The four waves take K-steps round
+// robin and their partial tiles are added in wave order, so the result is deterministic.
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+constexpr int kSC = 64;   // candidates staged in LDS per pass (a multiple of 4)
+
+template <typename T, int NF, bool FD>
+__global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
   using T2 = cplx<T>;
-  constexpr int LW = spread_lanes<T>();
-  __shared__ T2 s_r[4][LW][2][8];          // x and y window rows (W, G), zero at taps 6 and 7
+  using M = Mfma<T>;
+  constexpr int NC = FD ? 4 : NF;                    // coefficients per candidate
+  constexpr int STAGE = kSC * 24 * (int)sizeof(T2) + kSC * NC * (int)sizeof(T) + kSC * 4 * (int)sizeof(int);
+  constexpr int RED = 4 * 512 * (int)sizeof(T);      // one field's wave partials
+  __shared__ __align__(16) unsigned char smem[STAGE > RED ? STAGE : RED];
+  T2(*s_w)[24] = reinterpret_cast<T2(*)[24]>(smem);                       // marker weight rows
+  T(*s_c)[NC] = reinterpret_cast<T(*)[NC]>(smem + kSC * 24 * sizeof(T2));  // coefficients
+  int(*s_o)[4] = reinterpret_cast<int(*)[4]>(smem + kSC * 24 * sizeof(T2) + kSC * NC * sizeof(T));
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tile = a.busy[blockIdx.x];
   const int ntl = g.ntile[0] * g.ntile[1] * g.ntile[2];
-  const int prob = tile / ntl, tl = tile - prob * ntl;   // problem of a batch, tile within it
+  const int prob = tile / ntl, tl = tile - prob * ntl;
   const int tx = tl % g.ntile[0];
   const int ty = (tl / g.ntile[0]) % g.ntile[1];
   const int tz = tl / (g.ntile[0] * g.ntile[1]);
   const int x0 = tx * kT3X, y0 = ty * kT3Y, z0 = tz * kT3Z;
-  const int lx = lane % kT3X, ly = lane / kT3X;
   const int mx = g.n[0] - 1, my = g.n[1] - 1, mz = g.n[2] - 1;
-  const bool fddiv = NF == 1 && a.mode == SP_FDDIV;
-  T acc[kT3Z][NF];
+  typename M::v4 acc[NF][2];
 #pragma unroll
-  for (int z = 0; z < kT3Z; ++z)
-#pragma unroll
-    for (int c = 0; c < NF; ++c) acc[z][c] = 0;
+  for (int c = 0; c < NF; ++c) acc[c][0] = acc[c][1] = typename M::v4{0, 0, 0, 0};
   const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
   const double hD = g.h * g.h * g.h;
-  for (int c0 = beg; c0 < end; c0 += 4 * LW) {
-    // candidates of this wave in this pass
-    const int left = end - c0 - wave;
-    const int cnt = left <= 0 ? 0 : ((left + 3) / 4 < LW ? (left + 3) / 4 : LW);
-    int sx = 0, sy = 0;
-    T2 zr[kT3Z];
-    T cf[5];
-#pragma unroll
-    for (int z = 0; z < kT3Z; ++z) zr[z] = mk<T2>((T)0, (T)0);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) cf[c] = 0;
-    if (lane < cnt) {
-      const int m = a.list[c0 + 4 * lane + wave];
-      const T2* row = wtab + (int64_t)m * 24;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        s_r[wave][lane][0][t] = row[t];
-        s_r[wave][lane][1][t] = row[8 + t];
-      }
-      sx = a.s[m * 3 + 0];
-      sy = a.s[m * 3 + 1];
-      const int sz = a.s[m * 3 + 2];
-#pragma unroll
-      for (int z = 0; z < kT3Z; ++z) zr[z] = row[16 + min((z0 + z - sz) & mz, 6)];
+  constexpr int NT = FD ? 2 : 1, CPS = 4 / NT;       // terms per candidate, candidates per K-step
+  const int kk = lane >> 4, i16 = lane & 15;
+  const int yy = i16 & 3, zz = i16 >> 2;
+  for (int c0 = beg; c0 < end; c0 += kSC) {
+    const int cnt = end - c0 < kSC ? end - c0 : kSC;
+    // one lane per candidate: marker id, window offsets relative to the tile, coefficients
+    if (tid < kSC) {
       double c8[8];
-      spread_coefs(a, m, 3, a.raw ? 1.0 : a.ds[m] / hD, c8);
+      int m = -1, ox = 6, oy = 6, oz = 6;
+      if (tid < cnt) {
+        m = a.list[c0 + tid];
+        ox = a.s[m * 3 + 0];
+        oy = a.s[m * 3 + 1];
+        oz = a.s[m * 3 + 2];
+        spread_coefs(a, m, 3, a.raw ? 1.0 : a.ds[m] / hD, c8);
+      } else {
+        for (int c = 0; c < 8; ++c) c8[c] = 0.0;
+      }
+      s_o[tid][0] = m;
+      s_o[tid][1] = ox;
+      s_o[tid][2] = oy;
+      s_o[tid][3] = oz;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) cf[c] = (T)c8[c];
+      for (int c = 0; c < NC; ++c) s_c[tid][c] = (T)c8[c];
     }
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const int bx = bcast(sx, j), by = bcast(sy, j);
-      const T2 xv = s_r[wave][j][0][min((x0 + lx - bx) & mx, 6)];
-      const T2 yv = s_r[wave][j][1][min((y0 + ly - by) & my, 6)];
-      if (fddiv) {
-        const T A = bcast(cf[0], j) * xv.y * yv.x + bcast(cf[1], j) * xv.x * yv.y + bcast(cf[3], j) * xv.x * yv.x;
-        const T B = bcast(cf[2], j) * xv.x * yv.x;
-#pragma unroll
-        for (int z = 0; z < kT3Z; ++z) acc[z][0] += A * bcast(zr[z].x, j) + B * bcast(zr[z].y, j);
+    // the candidates' 24-entry weight rows, contiguous per marker (zero for padding candidates)
+    for (int e = tid; e < kSC * 24; e += 256) {
+      const int cand = e / 24, k = e - cand * 24;
+      const int m = s_o[cand][0];
+      s_w[cand][k] = m >= 0 ? wtab[(int64_t)m * 24 + k] : mk<T2>((T)0, (T)0);
+    }
+    __syncthreads();
+    const int nsteps = (cnt + CPS - 1) / CPS;
+    for (int st = wave; st < nsteps; st += 4) {
+      const int cand = st * CPS + kk / NT;
+      // tile node -> window tap (6 and 7 hold zeros)
+      const int tx_ = min((x0 + i16 - s_o[cand][1]) & mx, 6);
+      const int ty_ = min((y0 + yy - s_o[cand][2]) & my, 6);
+      const int tza = min((z0 + zz - s_o[cand][3]) & mz, 6);
+      const int tzb = min((z0 + zz + 4 - s_o[cand][3]) & mz, 6);
+      const T2 xv = s_w[cand][tx_], yv = s_w[cand][8 + ty_];
+      const T2 za = s_w[cand][16 + tza], zb = s_w[cand][16 + tzb];
+      if constexpr (FD) {
+        const bool t0 = (kk & 1) == 0;
+        const T cx = s_c[cand][0], cy = s_c[cand][1], cz = s_c[cand][2], cm = s_c[cand][3];
+        const T q = t0 ? xv.y : xv.x;
+        const T pyz = cy * yv.y + cm * yv.x, wy = yv.x;
+        const T pa = t0 ? cx * wy * za.x : pyz * za.x + cz * wy * za.y;
+        const T pb = t0 ? cx * wy * zb.x : pyz * zb.x + cz * wy * zb.y;
+        acc[0][0] = M::mma(pa, q, acc[0][0]);
+        acc[0][1] = M::mma(pb, q, acc[0][1]);
       } else {
-        const T w2 = xv.x * yv.x;
+        const T q = xv.x, wa = yv.x * za.x, wb = yv.x * zb.x;
 #pragma unroll
-        for (int z = 0; z < kT3Z; ++z) {
-          const T wz = w2 * bcast(zr[z].x, j);
-#pragma unroll
-          for (int c = 0; c < NF; ++c)
-            if (c < a.nf) acc[z][c] += bcast(cf[c], j) * wz;
+        for (int c = 0; c < NF; ++c) {
+          if (c < a.nf) {
+            const T cf = s_c[cand][c];
+            acc[c][0] = M::mma(cf * wa, q, acc[c][0]);
+            acc[c][1] = M::mma(cf * wb, q, acc[c][1]);
+          }
         }
       }
     }
     __syncthreads();
   }
-  // fixed-order reduction of the four waves' partial sums, one field at a time
-  T* red = reinterpret_cast<T*>(&s_r[0][0][0][0]);   // needs 4 * 8 * 64 values
+  // fixed-order sum of the four waves' partial tiles, field by field
+  T* red = reinterpret_cast<T*>(smem);   // [wave][block][v][lane]
   const int64_t ntot = (int64_t)g.n[0] * g.n[1] * g.n[2];
   out += (int64_t)prob * a.nf * ntot;
 #pragma unroll
   for (int c = 0; c < NF; ++c) {
     if (c >= a.nf) break;
 #pragma unroll
-    for (int z = 0; z < kT3Z; ++z) red[(wave * kT3Z + z) * 64 + lane] = acc[z][c];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[((wave * 2 + b) * 4 + v) * 64 + lane] = acc[c][b][v];
     __syncthreads();
-    for (int o = tid; o < kT3Z * 64; o += 256) {
-      const int z = o >> 6, l = o & 63;
-      const T v = ((red[(0 * kT3Z + z) * 64 + l] + red[(1 * kT3Z + z) * 64 + l]) + red[(2 * kT3Z + z) * 64 + l]) +
-                  red[(3 * kT3Z + z) * 64 + l];
-      const int64_t idx = ((int64_t)(z0 + z) * g.n[1] + (y0 + l / kT3X)) * g.n[0] + x0 + l % kT3X;
-      out[c * ntot + idx] = v;
+    for (int o = tid; o < 512; o += 256) {
+      const int b = o >> 8, v = (o >> 6) & 3, l = o & 63;
+      const T val = ((red[((0 * 2 + b) * 4 + v) * 64 + l] + red[((1 * 2 + b) * 4 + v) * 64 + l]) +
+                     red[((2 * 2 + b) * 4 + v) * 64 + l]) + red[((3 * 2 + b) * 4 + v) * 64 + l];
+      const int i = M::row(l, v);          // (y, z) row within the block
+      const int x = l & 15, y = i & 3, z = (i >> 2) + 4 * b;
+      out[c * ntot + ((int64_t)(z0 + z) * g.n[1] + (y0 + y)) * g.n[0] + x0 + x] = val;
     }
     __syncthreads();
   }
@@ -566,15 +610,15 @@ __global__ void k_rows_list(const int* __restrict__ lo, const int* __restrict__ 
   for (int k = threadIdx.x; k < cnt[z]; k += blockDim.x) rows[off[z] + k] = z * ny + lo[z] + k;
 }
 
+// one wave per listed row, 16-byte stores
 template <typename T>
-__global__ void k_fill_rows(T* __restrict__ y, const int* __restrict__ rows, int64_t nact, int nx, int nfields,
-                            int64_t rpf) {
-  const int64_t n = nact * nfields * nx;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / nx, c = e - r * nx;
-    const int64_t row = rows[r % nact] + (r / nact) * rpf;
-    y[row * nx + c] = (T)0;
-  }
+__global__ __launch_bounds__(64) void k_fill_rows(T* __restrict__ y, const int* __restrict__ rows, int64_t nact,
+                                                  int nx, int64_t rpf) {
+  const int64_t r = blockIdx.x;
+  const int64_t row = rows[r % nact] + (r / nact) * rpf;
+  float4* dst = reinterpret_cast<float4*>(y + row * nx);
+  const int nv = nx * (int)sizeof(T) / 16;
+  for (int v = threadIdx.x; v < nv; v += 64) dst[v] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // ------------------------------------------------------------------ kernel-derivative gather
@@ -724,9 +768,10 @@ void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int*
 
 template <typename T>
 void grid_fill_rows(T* y, const int* rows, int64_t nact, int nx, int nfields, int64_t rpf, hipStream_t st) {
-  const int64_t n = nact * nfields * nx;
-  if (n == 0) return;
-  hipLaunchKernelGGL((k_fill_rows<T>), dim3(grid_blocks(n)), dim3(256), 0, st, y, rows, nact, nx, nfields, rpf);
+  const int64_t nb = nact * nfields;
+  if (nb == 0) return;
+  if ((nx * (int)sizeof(T)) % 16 != 0) throw Error(-2, "grid_fill_rows: rows must be a multiple of 16 bytes");
+  hipLaunchKernelGGL((k_fill_rows<T>), dim3((unsigned)nb), dim3(64), 0, st, y, rows, nact, nx, rpf);
   IBDL_LAUNCH_CHECK();
 }
 
@@ -745,8 +790,12 @@ void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
     if (one) hipLaunchKernelGGL((k_spread2<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
     else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   } else {
-    if (one) hipLaunchKernelGGL((k_spread3<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
-    else hipLaunchKernelGGL((k_spread3<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+    if (one && a.mode == SP_FDDIV)
+      hipLaunchKernelGGL((k_spread3m<T, 1, true>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+    else if (one)
+      hipLaunchKernelGGL((k_spread3m<T, 1, false>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+    else
+      hipLaunchKernelGGL((k_spread3m<T, 5, false>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   }
   IBDL_LAUNCH_CHECK();
 }

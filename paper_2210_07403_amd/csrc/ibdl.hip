@@ -12,6 +12,7 @@
 #include "../../include/ibdl.h"
 #include "kernels.h"
 #include "tables.h"
+#include "tune.h"
 
 using namespace ibdl;
 
@@ -25,6 +26,8 @@ template <typename T> struct GridWork {
   cplx<T>* spec = nullptr;
   cplx<T>* wtab = nullptr;   // marker weight table in this precision
   int nfields = 0;
+  LaunchShape shape;         // launch shapes of the operator apply's FFT passes (measured)
+  bool tuned = false;
 };
 
 std::string g_create_error;
@@ -256,27 +259,27 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   const int64_t rout = sparse ? h->nact * nout : rows_per_field * nout;
   {
     StageTimer t(h, ST_FFT_X_FWD);
-    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, 0, rl);
+    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, false,
-                   W.tw[1], h->st, 0, fwd);
+                   W.tw[1], h->st, sparse ? W.shape.wy : 0, fwd);
   }
   const int last = h->dim - 1;
   const int64_t P = h->nspec / h->n[last];
   {
     StageTimer t(h, ST_FUSED);
-    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, 0, fused);
+    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, sparse ? W.shape.wz : 0, fused);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_INV);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, true,
-                   W.tw[1], h->st, 0, inv);
+                   W.tw[1], h->st, sparse ? W.shape.wy : 0, inv);
   }
   {
     StageTimer t(h, ST_FFT_X_INV);
-    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, 0, rl);
+    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl);
   }
 }
 
@@ -329,63 +332,142 @@ void ensure_partial(ibdl_s* h, int need) {
   h->pcap = need;
 }
 
+// The spread fields and Fourier multiplier of the density-to-grid map: Stokes A11, A12, A22 (and
+// eta Q1, eta Q2 or the forcing); FD scalar one fused divergence field (plus the mass term);
+// spectral scalar the D components of q n (plus the mass field).
+struct DensityPlan {
+  int mode = SP_FDDIV;
+  int nf = 1;       // spread fields = multiplier inputs
+  int nout = 1;
+  MultDesc md{};
+};
+
+template <typename T> DensityPlan density_plan(ibdl_s* h, GridWork<T>& W, bool mass) {
+  DensityPlan p;
+  p.md = base_desc<T>(h, W);
+  MultDesc& md = p.md;
+  if (h->stokes()) {
+    p.mode = SP_STOKES;
+    p.nf = mass ? 5 : 3;
+    p.nout = 2;
+    const int kinds[5] = {FK_A11, FK_A12, FK_A22, FK_G1, FK_G2};
+    for (int i = 0; i < p.nf; ++i) md.fk[i] = kinds[i];
+    md.alpha = 1.0;
+  } else if (h->fd()) {
+    p.mode = SP_FDDIV;
+    p.nf = 1;
+    md.fk[0] = FK_MASS;
+    md.alpha = -1.0;
+  } else {
+    p.mode = SP_SCALAR_VEC;
+    p.nf = h->dim + (mass ? 1 : 0);
+    for (int d = 0; d < h->dim; ++d) md.fk[d] = FK_DX + d;
+    if (mass) md.fk[h->dim] = FK_MASS;
+    md.alpha = -1.0;
+  }
+  md.nc = p.nf;
+  return p;
+}
+
 // Density q (device, [n_ib][nq]) -> grid field u[q] induced by it (plus optional mass values m and
 // forcing g as in the grid recovery), written to dst (nq fields).
 template <typename T>
 void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T* dst, bool sparse = false) {
   GridWork<T>& W = ensure_work<T>(h);
-  MultDesc md = base_desc<T>(h, W);
-  if (h->stokes()) {
-    const int nf = (h->cfg.eta > 0 || g) ? 5 : 3;
-    SpreadArgs a = spread_args(h, SP_STOKES, nf, q);
-    clear_fields<T>(h, W.real, a.nf, sparse);
-    {
-      StageTimer t(h, ST_SPREAD);
-      spread<T>(a, W.wtab, W.real, h->st);
-    }
-    if (g) grid_axpby<T>(W.real + 3 * h->ntot, -1.0, g, 1.0, 2 * h->ntot, h->st);
-    md.nc = nf;
-    const int kinds[5] = {FK_A11, FK_A12, FK_A22, FK_G1, FK_G2};
-    for (int i = 0; i < nf; ++i) md.fk[i] = kinds[i];
-    md.alpha = 1.0;
-    pipeline<T>(h, W, W.real, nf, dst, 2, md, sparse);
-    return;
-  }
   const bool mass = h->cfg.eta > 0 || m != nullptr || g != nullptr;
-  if (h->fd()) {
-    SpreadArgs a = spread_args(h, SP_FDDIV, 1, q);
-    a.mass = (h->cfg.eta > 0 || m != nullptr) ? 1 : 0;
-    a.m = m;
-    clear_fields<T>(h, W.real, a.nf, sparse);
-    {
-      StageTimer t(h, ST_SPREAD);
-      spread<T>(a, W.wtab, W.real, h->st);
-    }
-    if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
-    md.nc = 1;
-    md.fk[0] = FK_MASS;
-  } else {
-    const int nf = h->dim + (mass ? 1 : 0);
-    SpreadArgs a = spread_args(h, SP_SCALAR_VEC, nf, q);
-    a.mass = mass ? 1 : 0;
-    a.m = m;
-    clear_fields<T>(h, W.real, a.nf, sparse);
-    {
-      StageTimer t(h, ST_SPREAD);
-      spread<T>(a, W.wtab, W.real, h->st);
-    }
-    if (g) grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
-    md.nc = nf;
-    for (int d = 0; d < h->dim; ++d) md.fk[d] = FK_DX + d;
-    if (mass) md.fk[h->dim] = FK_MASS;
+  const DensityPlan pl = density_plan<T>(h, W, mass);
+  SpreadArgs a = spread_args(h, pl.mode, pl.nf, q);
+  // FD: the mass term of the fused field carries eta q and m; a forcing is subtracted afterwards
+  a.mass = pl.mode == SP_FDDIV ? ((h->cfg.eta > 0 || m != nullptr) ? 1 : 0) : (mass ? 1 : 0);
+  a.m = m;
+  clear_fields<T>(h, W.real, pl.nf, sparse);
+  {
+    StageTimer t(h, ST_SPREAD);
+    spread<T>(a, W.wtab, W.real, h->st);
   }
-  md.alpha = -1.0;
-  pipeline<T>(h, W, W.real, md.nc, dst, 1, md, sparse);
+  if (g) {
+    if (pl.mode == SP_STOKES) grid_axpby<T>(W.real + 3 * h->ntot, -1.0, g, 1.0, 2 * h->ntot, h->st);
+    else if (pl.mode == SP_FDDIV) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
+    else grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
+  }
+  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse);
+}
+
+// Launch shapes of the apply's FFT passes by measurement: rows per block of the x passes, lines
+// per block of the y passes and of the fused pass, each from the largest that fits down to an
+// eighth of it, two warm-up and three timed runs per candidate on the handle's own arrays.
+template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
+  const DensityPlan pl = density_plan<T>(h, W, h->cfg.eta > 0);
+  const TuneKey key{0, h->dim, h->n[0], h->n[1], h->n[2], (int)sizeof(T), pl.nf, pow2_bucket(h->nact)};
+  if (tune_get(key, &W.shape)) return;
+  grid_fill_zero<T>(W.real, h->ntot * W.nfields, h->st);
+  grid_fill_zero<T>(reinterpret_cast<T*>(W.spec), h->nspec * 2 * W.nfields, h->st);
+  const int64_t rpf = h->ntot / h->n[0];
+  RowList rl;
+  rl.rows = h->rows;
+  rl.nact = h->nact;
+  rl.rpf = rpf;
+  RowMask fwd, inv, fused;
+  if (h->dim == 3) {
+    fwd.lim = inv.lim = h->row_lim;
+    fwd.nplanes = inv.nplanes = h->n[2];
+    fwd.load = 1;
+    inv.store = 1;
+  } else {
+    fused.load = fused.store = 1;
+    fused.lo = h->lim2d[0];
+    fused.hi = h->lim2d[1];
+  }
+  hipEvent_t e0, e1;
+  IBDL_HIP(hipEventCreate(&e0));
+  IBDL_HIP(hipEventCreate(&e1));
+  auto best_of = [&](int wmax, auto&& run) {
+    int best = wmax;
+    float best_ms = 1e30f;
+    for (int w = wmax; w >= 1 && w * 8 >= wmax; w /= 2) {
+      for (int k = 0; k < 2; ++k) run(w);
+      IBDL_HIP(hipEventRecord(e0, h->st));
+      for (int k = 0; k < 3; ++k) run(w);
+      IBDL_HIP(hipEventRecord(e1, h->st));
+      IBDL_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      IBDL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = w;
+      }
+    }
+    return best;
+  };
+  LaunchShape sh;
+  sh.rpb = best_of(fft_x_rpb_max<T>(h->n[0]), [&](int r) {
+    fft_x_r2c<T>(W.real, W.spec, h->n[0], h->nact * pl.nf, W.tw[0], h->st, r, rl);
+    fft_x_c2r<T>(W.spec, W.real, h->n[0], h->nact * pl.nout, W.tw[0], h->st, r, rl);
+  });
+  if (h->dim == 3)
+    sh.wy = best_of(fft_line_w_max<T>(h->n[1]), [&](int w) {
+      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nf * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, false,
+                     W.tw[1], h->st, w, fwd);
+      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nout * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, true,
+                     W.tw[1], h->st, w, inv);
+    });
+  const int last = h->dim - 1;
+  sh.wz = best_of(fft_line_w_max<T>(h->n[last]), [&](int w) {
+    fft_fused_last<T>(W.spec, h->n[last], h->nspec / h->n[last], pl.nout, pl.md, W.tw[last], h->st, 1, 0, w, fused);
+  });
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  W.shape = sh;
+  tune_put(key, sh);
 }
 
 // y = A q
 template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
   GridWork<T>& W = ensure_work<T>(h);
+  if (!W.tuned) {
+    tune_apply<T>(h, W);
+    W.tuned = true;
+  }
   density_to_grid<T>(h, q, nullptr, nullptr, W.real, true);
   const double half = h->neumann() ? -0.5 : 0.5;
   const double* ub = h->has_ubar ? q + h->n_ib * h->nq : nullptr;
@@ -993,6 +1075,17 @@ ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total) {
   if (!h) return IBDL_ERR_ARG;
   if (nact) *nact = h->nact;
   if (rows_total) *rows_total = h->ntot / h->n[0];
+  return IBDL_OK;
+}
+
+ibdl_status_t ibdl_launch_shape(ibdl_t h, int32_t* rows_per_block, int32_t* lines_y, int32_t* lines_last) {
+  if (!h) return IBDL_ERR_ARG;
+  LaunchShape sh;
+  if (h->mixed() && h->w32) sh = h->w32->shape;
+  else if (!h->mixed() && h->w64) sh = h->w64->shape;
+  if (rows_per_block) *rows_per_block = sh.rpb;
+  if (lines_y) *lines_y = sh.wy;
+  if (lines_last) *lines_last = sh.wz;
   return IBDL_OK;
 }
 
