@@ -125,6 +125,7 @@ template <typename T> MultDesc group_desc(const Group& G, const GroupWork<T>& W,
   md.mode = 0;
   md.dim = dim;
   md.nxh = (int)G.nxh;
+  md.nxp = (int)G.nxh;
   md.stokes = 0;
   md.nc = 1;
   md.fk[0] = FK_MASS;

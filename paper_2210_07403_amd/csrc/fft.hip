@@ -164,7 +164,7 @@ template <typename TR, int M> struct RowCfg {
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
                                                   int64_t nrows, const cplx<T>* __restrict__ tw, int RPB,
-                                                  RowList rl) {
+                                                  RowList rl, int64_t pitch) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
     const C zm = lds[r * RC::LS + (k == 0 ? 0 : M - k)];
     const C E = mk<C>((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
     const C O = mk<C>((zk.y + zm.y) * (T)0.5, -(zk.x - zm.x) * (T)0.5);
-    out[rbase[r] * (M + 1) + k] = cadd(E, cmul(tw[k], O));
+    out[rbase[r] * pitch + k] = cadd(E, cmul(tw[k], O));
   }
 }
 
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                   int64_t nrows, const cplx<T>* __restrict__ tw, int RPB,
-                                                  RowList rl) {
+                                                  RowList rl, int64_t pitch) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   __syncthreads();
   for (int e = tid; e < RPB * (M + 1); e += NT) {
     const int r = e / (M + 1), k = e - r * (M + 1);
-    lds[e] = (r < nvalid) ? in[rbase[r] * (M + 1) + k] : mk<C>(0, 0);
+    lds[e] = (r < nvalid) ? in[rbase[r] * pitch + k] : mk<C>(0, 0);
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{M-k}) + i conj(W^k) (X_k - conj X_{M-k}); each thread owns a pair (k, M-k)
@@ -268,7 +268,7 @@ template <typename T, int N> struct TileCfg {
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
                                                     int64_t outer, int64_t es, const cplx<T>* __restrict__ tw,
-                                                    int W, RowMask rm) {
+                                                    int W, RowMask rm, int64_t vinner) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, 
   const int tid = threadIdx.x;
   const int c = tid & (W - 1), i = tid / W;
   const int64_t l = (int64_t)blockIdx.x * W + c;
-  const bool valid = l < nlines;
+  const bool valid = l < nlines && (l % inner) < vinner;
   const int64_t base = valid ? (l / inner) * outer + (l % inner) : 0;
   const RowMask pm = rm.plane(valid ? (l / inner) : 0);   // rows of this line's plane that matter
   C v[Plan<N>::RMAX];
@@ -340,11 +340,11 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   const int tid = threadIdx.x;
   const int c = tid & (W - 1), i = tid / W;
   const int64_t l = (int64_t)blockIdx.x * W + c;
-  const bool valid = l < P;
+  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
   // mode indices of this line: 2-D l = jx, e = jy; 3-D l = jy*nxh + jx, e = jz
-  const int jx = (int)(valid ? l % md.nxh : 0);
-  const int jy2 = (int)(valid ? l / md.nxh : 0);
+  const int jx = (int)(valid ? l % md.nxp : 0);
+  const int jy2 = (int)(valid ? l / md.nxp : 0);
   const bool d3 = md.dim == 3;
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);   // symbols along the line
   const T* ktl_ = static_cast<const T*>(md.kt[d3 ? 2 : 1]);
@@ -428,9 +428,9 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   const int tid = threadIdx.x;
   const int c = tid & (W - 1), i = tid / W;
   const int64_t l = (int64_t)blockIdx.x * W + c;
-  const bool valid = l < P;
-  const int jx = (int)(valid ? l % md.nxh : 0);
-  const int jy2 = (int)(valid ? l / md.nxh : 0);
+  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
+  const int jx = (int)(valid ? l % md.nxp : 0);
+  const int jy2 = (int)(valid ? l / md.nxp : 0);
   const bool d3 = md.dim == 3;
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
@@ -468,10 +468,10 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   const int tid = threadIdx.x;
   const int c = tid & (W - 1), i = tid / W;
   const int64_t l = (int64_t)blockIdx.x * W + c;
-  const bool valid = l < P;
+  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
-  const int jx = (int)(valid ? l % md.nxh : 0);
-  const int jy2 = (int)(valid ? l / md.nxh : 0);
+  const int jx = (int)(valid ? l % md.nxp : 0);
+  const int jy2 = (int)(valid ? l / md.nxp : 0);
   const bool d3 = md.dim == 3;
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
   const T* ktl_ = static_cast<const T*>(md.kt[d3 ? 2 : 1]);
@@ -565,7 +565,8 @@ int pick(int want, int max) {
 
 template <typename T>
 void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
-               const RowList& rl) {
+               const RowList& rl, int64_t pitch) {
+  if (pitch <= 0) pitch = nx / 2 + 1;
   dispatch_n(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
@@ -573,14 +574,16 @@ void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* 
     const int64_t nb = (nrows + R - 1) / R;
     const size_t lds = sizeof(cplx<T>) * R * RC::LS;
     if (nb > 0)
-      hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl);
+      hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
+                         pitch);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
-               const RowList& rl) {
+               const RowList& rl, int64_t pitch) {
+  if (pitch <= 0) pitch = nx / 2 + 1;
   dispatch_n(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
@@ -588,14 +591,16 @@ void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* 
     const int64_t nb = (nrows + R - 1) / R;
     const size_t lds = sizeof(cplx<T>) * R * RC::LS;
     if (nb > 0)
-      hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl);
+      hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
+                         pitch);
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es, bool inverse,
-                 const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm) {
+                 const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm, int64_t vinner) {
+  if (vinner <= 0) vinner = inner;
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     using TC = TileCfg<T, N>;
@@ -605,10 +610,10 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
     const dim3 blk(W * TC::T_);
     if (inverse)
       hipLaunchKernelGGL((k_strided<T, N, true>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
-                         tw, W, rm);
+                         tw, W, rm, vinner);
     else
       hipLaunchKernelGGL((k_strided<T, N, false>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
-                         tw, W, rm);
+                         tw, W, rm, vinner);
   });
   IBDL_LAUNCH_CHECK();
 }
@@ -644,11 +649,11 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
 
 #define IBDL_FFT_INST(T)                                                                                   \
   template void fft_x_r2c<T>(const T*, cplx<T>*, int, int64_t, const cplx<T>*, hipStream_t, int,         \
-                             const RowList&);                                                              \
+                             const RowList&, int64_t);                                                     \
   template void fft_x_c2r<T>(const cplx<T>*, T*, int, int64_t, const cplx<T>*, hipStream_t, int,         \
-                             const RowList&);                                                              \
+                             const RowList&, int64_t);                                                     \
   template void fft_strided<T>(cplx<T>*, int, int64_t, int64_t, int64_t, int64_t, bool, const cplx<T>*,   \
-                               hipStream_t, int, const RowMask&);                                          \
+                               hipStream_t, int, const RowMask&, int64_t);                                 \
   template void fft_fused_last<T>(cplx<T>*, int, int64_t, int, const MultDesc&, const cplx<T>*, hipStream_t, \
                                   int, int64_t, int, const RowMask&);                                      \
   template int fft_x_rpb_max<T>(int);                                                                      \

@@ -576,20 +576,37 @@ __global__ void k_rows_init(int* __restrict__ lo, int* __restrict__ hi, int npla
   }
 }
 
-__global__ void k_rows_mark(MarkerGeom g, int64_t n_ib, const int* __restrict__ s, int* __restrict__ lo,
-                            int* __restrict__ hi) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_ib) return;
+// per-block limits in LDS first (many markers share a plane), then one global update per touched plane
+__global__ __launch_bounds__(256) void k_rows_mark(MarkerGeom g, int64_t n_ib, const int* __restrict__ s,
+                                                   int* __restrict__ lo, int* __restrict__ hi) {
+  extern __shared__ int sm[];
   const int ny = g.n[1];
-  const int sy = s[i * 3 + 1];
-  const int ylo = sy + 5 < ny ? sy : 0;
-  const int yhi = sy + 5 < ny ? sy + 5 : ny - 1;
   const int nz = g.dim == 3 ? g.n[2] : 1;
-  const int nw = g.dim == 3 ? 6 : 1;
-  for (int t = 0; t < nw; ++t) {
-    const int z = g.dim == 3 ? (s[i * 3 + 2] + t) & (nz - 1) : 0;
-    atomicMin(&lo[z], ylo);
-    atomicMax(&hi[z], yhi);
+  int* slo = sm;
+  int* shi = sm + nz;
+  for (int z = threadIdx.x; z < nz; z += blockDim.x) {
+    slo[z] = ny;
+    shi[z] = -1;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_ib) {
+    const int sy = s[i * 3 + 1];
+    const int ylo = sy + 5 < ny ? sy : 0;
+    const int yhi = sy + 5 < ny ? sy + 5 : ny - 1;
+    const int nw = g.dim == 3 ? 6 : 1;
+    for (int t = 0; t < nw; ++t) {
+      const int z = g.dim == 3 ? (s[i * 3 + 2] + t) & (nz - 1) : 0;
+      atomicMin(&slo[z], ylo);
+      atomicMax(&shi[z], yhi);
+    }
+  }
+  __syncthreads();
+  for (int z = threadIdx.x; z < nz; z += blockDim.x) {
+    if (shi[z] >= 0) {
+      atomicMin(&lo[z], slo[z]);
+      atomicMax(&hi[z], shi[z]);
+    }
   }
 }
 
@@ -756,7 +773,8 @@ void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int*
   hipLaunchKernelGGL(k_rows_init, dim3((nplanes + 255) / 256), dim3(256), 0, st, lo, hi, nplanes, g.n[1]);
   IBDL_LAUNCH_CHECK();
   if (n_ib > 0)
-    hipLaunchKernelGGL(k_rows_mark, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, g, n_ib, s, lo, hi);
+    hipLaunchKernelGGL(k_rows_mark, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), sizeof(int) * 2 * nplanes, st,
+                       g, n_ib, s, lo, hi);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_rows_count, dim3((nplanes + 255) / 256), dim3(256), 0, st, lo, hi, nplanes, cnt, lim);
   IBDL_LAUNCH_CHECK();

@@ -39,7 +39,7 @@ struct ibdl_s {
   int dim = 2;
   int n[3] = {1, 1, 1};
   double h = 0;
-  int64_t ntot = 0, nxh = 0, nspec = 0;
+  int64_t ntot = 0, nxh = 0, nxp = 0, nspec = 0;   // nxp: half-spectrum row pitch (128-byte rows)
   int64_t n_ib = 0;
   int nq = 1;
   bool has_ubar = false;
@@ -213,6 +213,7 @@ template <typename T> MultDesc base_desc(ibdl_s* h, GridWork<T>& W) {
   MultDesc md{};
   md.dim = h->dim;
   md.nxh = (int)h->nxh;
+  md.nxp = (int)h->nxp;
   md.sc = 1.0 / (double)h->ntot;
   md.mu = h->cfg.mu;
   for (int d = 0; d < 3; ++d) {
@@ -259,12 +260,12 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   const int64_t rout = sparse ? h->nact * nout : rows_per_field * nout;
   {
     StageTimer t(h, ST_FFT_X_FWD);
-    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl);
+    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl, h->nxp);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
-    fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, false,
-                   W.tw[1], h->st, sparse ? W.shape.wy : 0, fwd);
+    fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
+                   W.tw[1], h->st, sparse ? W.shape.wy : 0, fwd, h->nxh);
   }
   const int last = h->dim - 1;
   const int64_t P = h->nspec / h->n[last];
@@ -274,12 +275,12 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_INV);
-    fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, true,
-                   W.tw[1], h->st, sparse ? W.shape.wy : 0, inv);
+    fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
+                   W.tw[1], h->st, sparse ? W.shape.wy : 0, inv, h->nxh);
   }
   {
     StageTimer t(h, ST_FFT_X_INV);
-    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl);
+    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl, h->nxp);
   }
 }
 
@@ -441,15 +442,15 @@ template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
   };
   LaunchShape sh;
   sh.rpb = best_of(fft_x_rpb_max<T>(h->n[0]), [&](int r) {
-    fft_x_r2c<T>(W.real, W.spec, h->n[0], h->nact * pl.nf, W.tw[0], h->st, r, rl);
-    fft_x_c2r<T>(W.spec, W.real, h->n[0], h->nact * pl.nout, W.tw[0], h->st, r, rl);
+    fft_x_r2c<T>(W.real, W.spec, h->n[0], h->nact * pl.nf, W.tw[0], h->st, r, rl, h->nxp);
+    fft_x_c2r<T>(W.spec, W.real, h->n[0], h->nact * pl.nout, W.tw[0], h->st, r, rl, h->nxp);
   });
   if (h->dim == 3)
     sh.wy = best_of(fft_line_w_max<T>(h->n[1]), [&](int w) {
-      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nf * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, false,
-                     W.tw[1], h->st, w, fwd);
-      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nout * h->n[2] * h->nxh, h->nxh, h->nxh * h->n[1], h->nxh, true,
-                     W.tw[1], h->st, w, inv);
+      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nf * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
+                     W.tw[1], h->st, w, fwd, h->nxh);
+      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
+                     W.tw[1], h->st, w, inv, h->nxh);
     });
   const int last = h->dim - 1;
   sh.wz = best_of(fft_line_w_max<T>(h->n[last]), [&](int w) {
@@ -867,7 +868,8 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->h = cfg->L[0] / (double)cfg->n[0];
     h->ntot = (int64_t)h->n[0] * h->n[1] * h->n[2];
     h->nxh = h->n[0] / 2 + 1;
-    h->nspec = h->nxh * h->n[1] * h->n[2];
+    h->nxp = (h->nxh + 15) / 16 * 16;
+    h->nspec = h->nxp * h->n[1] * h->n[2];
     h->n_ib = n_ib;
     h->nq = h->stokes() ? h->dim : 1;
     h->has_ubar = cfg->eta > 0 && h->kappa() == 0.0;

@@ -45,7 +45,8 @@ struct RowMask {
 struct MultDesc {
   int mode;         // 0: forward multiplier; 1: scalar gradient outputs; 2: transposed Stokes
   int dim;          // 2 or 3
-  int nxh;          // nx/2 + 1
+  int nxh;          // nx/2 + 1 modes along x
+  int nxp;          // row pitch of the half spectrum (>= nxh; lines with x index >= nxh are padding)
   int stokes;       // 0: scalar multiplier, 1: Stokes multiplier
   int nc;           // input fields
   int fk[8];        // kind of each input field
@@ -63,16 +64,19 @@ struct MultDesc {
 template <typename T> int fft_x_rpb_max(int nx);
 template <typename T> int fft_line_w_max(int n);
 // x passes over nrows rows (with a row list: nrows = active rows per field x fields)
+// pitch: spectrum row pitch in complex values (0: nx/2 + 1)
 template <typename T>
 void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0,
-               const RowList& rl = RowList());
+               const RowList& rl = RowList(), int64_t pitch = 0);
 template <typename T>
 void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0,
-               const RowList& rl = RowList());
-// in-place strided C2C pass: line l starts at (l / inner) * outer + (l % inner), element stride es
+               const RowList& rl = RowList(), int64_t pitch = 0);
+// in-place strided C2C pass: line l starts at (l / inner) * outer + (l % inner), element stride es;
+// lines with l % inner >= vinner are padding and skipped (vinner 0: none)
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es,
-                 bool inverse, const cplx<T>* tw, hipStream_t s, int w = 0, const RowMask& rm = RowMask());
+                 bool inverse, const cplx<T>* tw, hipStream_t s, int w = 0, const RowMask& rm = RowMask(),
+                 int64_t vinner = 0);
 // in-place fused pass along the last axis (length n, plane size P): forward FFT of the nc input
 // fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1).
 // mode 1 (one scalar input F): outputs i k~_o g F^ for o < dim, then g F^, g = alpha sc/(c2 sigma - c0);
