@@ -130,6 +130,16 @@ ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y);
 ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, double tol,
                          int32_t maxit, double* q, void* u_grid, ibdl_info_t* info);
 
+/* Solve A q = b to a double-precision true residual ||b - A q|| / ||b|| <= tol by iterative
+ * refinement: b and every residual are formed with double-precision applies, and each round adds
+ * the GMRES solution (working precision: float grid work on a mixed handle) of A d = r to
+ * inner_tol (0 < inner_tol < 1).  At most max_rounds rounds of at most maxit iterations.
+ * Arguments as in ibdl_solve; info->iters is the total of inner iterations, info->krylov_relres
+ * the last round's Krylov residual, info->true_relres_fp64 the final true residual.
+ * IBDL_NOT_CONVERGED if tol is not met within max_rounds. */
+ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_grid, double tol, int32_t maxit,
+                                 double inner_tol, int32_t max_rounds, double* q, void* u_grid, ibdl_info_t* info);
+
 /* y = A^T p, the transpose of the operator of ibdl_apply (same layout and precision rules).
  * With Phi the interpolation matrix (S* = Phi, Sec. 2.2.2), S = h^-D Phi^T diag(ds) and the grid
  * operators' transposes (L^-1 symmetric, D_d^T = -D_d with the Nyquist reading of the spectral

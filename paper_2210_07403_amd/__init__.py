@@ -143,6 +143,25 @@ class Problem:
         B.check(B.load().ibdl_apply(self._h, qt.data_ptr(), y.data_ptr()), self._h)
         return y
 
+    def solve_refined(self, data, g=None, tol=1e-8, maxit=100, inner_tol=1e-4, max_rounds=10, want_u=True):
+        """Iterative refinement to a double-precision true residual <= tol (working-precision
+        GMRES corrections, double residuals); returns (q, u or None, SolveInfo)."""
+        dt = _dev_f64(data, self.device).reshape(-1)
+        if dt.numel() != self.n_ib * self.nq:
+            raise ValueError("data must have n_ib * nq entries")
+        gt = self._as_grid(g, self.nq) if g is not None else None
+        q = torch.empty(self.n_aug, dtype=torch.float64, device=self.device)
+        u = self._grid(self.nq) if want_u else None
+        info = B.Info()
+        st = B.load().ibdl_solve_refined(self._h, dt.data_ptr(), gt.data_ptr() if gt is not None else None,
+                                         float(tol), int(maxit), float(inner_tol), int(max_rounds), q.data_ptr(),
+                                         u.data_ptr() if u is not None else None, ctypes.byref(info))
+        B.check(st, self._h)
+        res = SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64, [])
+        if u is not None and self.nq == 1:
+            u = u[0]
+        return q, u, res
+
     def apply_transpose(self, p):
         pt = _dev_f64(p, self.device).reshape(-1)
         if pt.numel() != self.n_aug:

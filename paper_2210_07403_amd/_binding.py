@@ -43,6 +43,8 @@ _SIGS = {
     "ibdl_apply": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                              ctypes.POINTER(Info)]),
+    "ibdl_solve_refined": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_double, c_int32,
+                                     c_void_p, c_void_p, ctypes.POINTER(Info)]),
     "ibdl_apply_transpose": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                 ctypes.POINTER(Info)]),

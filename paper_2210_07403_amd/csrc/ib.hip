@@ -691,6 +691,12 @@ __global__ void k_axpby(T* __restrict__ y, double a, const T* __restrict__ x, do
     y[e] = (T)(a * (double)x[e] + b * (double)y[e]);
 }
 
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ x, D* __restrict__ y, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = (D)x[e];
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ y, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
@@ -855,6 +861,12 @@ void gather_dx(const GatherArgs& a, hipStream_t st) {
     if (six) hipLaunchKernelGGL((k_gather_dx<T, 3, 6>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_gather_dx<T, 3, 4>), grid, dim3(256), 0, st, a);
   }
+  IBDL_LAUNCH_CHECK();
+}
+
+void grid_widen(const float* x, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_blocks(n)), dim3(256), 0, st, x, y, n);
   IBDL_LAUNCH_CHECK();
 }
 

@@ -172,6 +172,53 @@ __global__ void k_adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hD
   }
 }
 
+// One Arnoldi step's vector work in three launches.  MODE 0: d_j = V_j . w (j < k); MODE 1:
+// w -= V h, then d_j = V_j . w; MODE 2: w -= V h, then d_0 = w . w.  Each block handles a chunk of
+// 2048 elements (a thread updates and then reads the same elements, so no barrier is needed between
+// the update and the dots); the last block to finish adds the per-block partials in block order, so
+// the sums do not depend on scheduling.
+template <int MODE>
+__global__ __launch_bounds__(kB) void k_arnoldi(const double* __restrict__ V, int64_t ldv, int k, double* w,
+                                                const double* __restrict__ h, int64_t n, int nblk,
+                                                double* partial, unsigned* counter, double* __restrict__ out) {
+  __shared__ double red[kB];
+  __shared__ int is_last;
+  const int64_t beg = (int64_t)blockIdx.x * kElemsPerBlock;
+  const int64_t end = beg + kElemsPerBlock < n ? beg + kElemsPerBlock : n;
+  if (MODE > 0) {
+    for (int64_t e = beg + threadIdx.x; e < end; e += kB) {
+      double s = w[e];
+      for (int j = 0; j < k; ++j) s -= V[j * ldv + e] * h[j];
+      w[e] = s;
+    }
+  }
+  const int nd = MODE == 2 ? 1 : k;
+  for (int d = 0; d < nd; ++d) {
+    double s = 0.0;
+    for (int64_t e = beg + threadIdx.x; e < end; e += kB) s += (MODE == 2 ? w[e] : V[d * ldv + e]) * w[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kB / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[d * nblk + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+  __threadfence();
+  if (threadIdx.x == 0) is_last = atomicAdd(counter, 1u) == (unsigned)(nblk - 1);
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    for (int d = threadIdx.x; d < nd; d += kB) {
+      double s = 0.0;
+      for (int b = 0; b < nblk; ++b) s += partial[d * nblk + b];
+      out[d] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
 // ------------------------------------------------------------------ batched (segmented) vectors
 // A batch vector is the concatenation of the problems' vectors; block b of a segmented dot covers
 // [beg[b], end[b]) inside one problem's segment, and problem p owns blocks pb0[p] .. pb0[p+1]-1.
@@ -283,6 +330,17 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
   hipLaunchKernelGGL(k_border_partial, dim3(nblk, nq), dim3(kB), 0, st, q, ds, n_ib, nq, nblk, partial);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_border_final, dim3(nq), dim3(64), 0, st, partial, nblk, eta, out);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const double* h, int64_t n, double* partial,
+                int nblk, unsigned* counter, double* out, hipStream_t st) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_arnoldi<0>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial, counter, out);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_arnoldi<1>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial, counter, out);
+  else
+    hipLaunchKernelGGL(k_arnoldi<2>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial, counter, out);
   IBDL_LAUNCH_CHECK();
 }
 

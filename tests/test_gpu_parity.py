@@ -195,3 +195,21 @@ def test_invalid_arguments_raise():
     with pytest.raises(ibdl.IBDLError):
         pr.solve(spec.data, None, tol=1e-8, maxit=0)
     pr.close()
+
+
+@pytest.mark.parametrize("name", ["helmholtz_fd", "completed_poisson", "neumann", "stokes_exterior", "sphere_3d"])
+def test_solve_refined_mixed_reaches_fp64_accuracy(name):
+    """Iterative refinement on a mixed handle: float-grid GMRES corrections, double residuals,
+    down to a double-precision true residual far below what the float operator resolves.  Both
+    sides are solved to 1e-13, as in the FP64 solve test; the solution error is bounded by the
+    condition number times the residual (the completed operator's is the largest here)."""
+    spec = OPERATORS[name]()
+    pr = make_problem(spec, "mixed")
+    o = make_oracle(spec)
+    # a mixed handle receives g~ in float: the oracle solves with the same rounded forcing
+    g32 = None if spec.g is None else np.asarray(spec.g, dtype=np.float32).astype(np.float64)
+    xo, _, _ = gmres(o.apply, o.rhs(spec.data, g32), 1e-13, 300)
+    q, u, info = pr.solve_refined(spec.data, spec.g, tol=1e-13, maxit=100, inner_tol=1e-4, max_rounds=30)
+    assert info.status == 0 and info.true_relres_fp64 <= 1e-13, info
+    assert relerr(to_np(q), xo) < 1e-9, relerr(to_np(q), xo)
+    pr.close()
