@@ -45,6 +45,8 @@ struct ibdl_s {
   bool has_ubar = false;
   int64_t n_aug = 0;
   hipStream_t st = nullptr;
+  hipStream_t aux = nullptr;    // second stream: the double-precision residual beside the recovery
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double *X = nullptr, *nrm = nullptr, *ds = nullptr;
   int* s = nullptr;
   double* f = nullptr;
@@ -133,6 +135,10 @@ struct ibdl_s {
       (void)hipEventDestroy(p.second.second);
     }
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamSynchronize(aux);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
   }
   bool mixed() const { return cfg.precision == IBDL_MIXED; }
   bool stokes() const { return cfg.pde == IBDL_PDE_STOKES; }
@@ -236,54 +242,62 @@ template <typename T> MultDesc base_desc(ibdl_s* h, GridWork<T>& W) {
 }
 
 // real fields src[0..nin) -> spectra -> fused multiplier -> real fields dst[0..nout).
-// sparse: src is zero outside the active rows and only the active rows of dst are needed (the
-// operator apply), so the x passes run over the row list and the y passes mask the other rows.
+// Row modes: ROWS_DENSE every row; ROWS_SPARSE src is zero outside the active rows and only the
+// active rows of dst are needed (the operator apply), so the x passes run over the row list and the
+// y passes mask the other rows; ROWS_OUT a dense src whose result is needed on the active rows only
+// (a right-hand side that is interpolated next).
+enum RowsMode { ROWS_DENSE = 0, ROWS_SPARSE = 1, ROWS_OUT = 2 };
+
 template <typename T>
 void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md,
-              bool sparse = false) {
+              int rows = ROWS_DENSE) {
   const int64_t rows_per_field = h->ntot / h->n[0];
-  RowList rl;
+  const bool sin = rows == ROWS_SPARSE, sout = rows != ROWS_DENSE;
+  RowList rl_in, rl_out;
   RowMask fwd, inv, fused;
-  if (sparse) {
-    rl.rows = h->rows;
-    rl.nact = h->nact;
-    rl.rpf = rows_per_field;
+  if (sout) {
+    rl_out.rows = h->rows;
+    rl_out.nact = h->nact;
+    rl_out.rpf = rows_per_field;
+    if (sin) rl_in = rl_out;
     if (h->dim == 3) {
       fwd.lim = inv.lim = h->row_lim;
       fwd.nplanes = inv.nplanes = h->n[2];
-      fwd.load = 1;
+      fwd.load = sin ? 1 : 0;
       inv.store = 1;
     } else {
-      fused.load = fused.store = 1;
+      fused.load = sin ? 1 : 0;
+      fused.store = 1;
       fused.lo = h->lim2d[0];
       fused.hi = h->lim2d[1];
     }
   }
-  const int64_t rin = sparse ? h->nact * nin : rows_per_field * nin;
-  const int64_t rout = sparse ? h->nact * nout : rows_per_field * nout;
+  const bool tuned = rows == ROWS_SPARSE;   // the measured shapes are those of the apply
+  const int64_t rin = sin ? h->nact * nin : rows_per_field * nin;
+  const int64_t rout = sout ? h->nact * nout : rows_per_field * nout;
   {
     StageTimer t(h, ST_FFT_X_FWD);
-    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl, h->nxp);
+    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, tuned ? W.shape.rpb : 0, rl_in, h->nxp);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
-                   W.tw[1], h->st, sparse ? W.shape.wy : 0, fwd, h->nxh);
+                   W.tw[1], h->st, tuned ? W.shape.wy : 0, fwd, h->nxh);
   }
   const int last = h->dim - 1;
   const int64_t P = h->nspec / h->n[last];
   {
     StageTimer t(h, ST_FUSED);
-    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, sparse ? W.shape.wz : 0, fused);
+    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, tuned ? W.shape.wz : 0, fused);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_INV);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
-                   W.tw[1], h->st, sparse ? W.shape.wy : 0, inv, h->nxh);
+                   W.tw[1], h->st, tuned ? W.shape.wy : 0, inv, h->nxh);
   }
   {
     StageTimer t(h, ST_FFT_X_INV);
-    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, sparse ? W.shape.rpb : 0, rl, h->nxp);
+    fft_x_c2r<T>(W.spec, dst, h->n[0], rout, W.tw[0], h->st, tuned ? W.shape.rpb : 0, rl_out, h->nxp);
   }
 }
 
@@ -394,7 +408,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     else if (pl.mode == SP_FDDIV) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
     else grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
   }
-  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse);
+  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse ? ROWS_SPARSE : ROWS_DENSE);
 }
 
 // Launch shapes of the apply's FFT passes by measurement: rows per block of the x passes, lines
@@ -491,7 +505,7 @@ template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
 }
 
 // u = L^-1 rhs (scalar) or L^-1 P rhs (Stokes)
-template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u) {
+template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u, int rows = ROWS_DENSE) {
   GridWork<T>& W = ensure_work<T>(h);
   MultDesc md = base_desc<T>(h, W);
   if (h->stokes()) {
@@ -499,12 +513,12 @@ template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u) {
     md.fk[0] = FK_G1;
     md.fk[1] = FK_G2;
     md.alpha = -1.0;
-    pipeline<T>(h, W, rhs, 2, u, 2, md);
+    pipeline<T>(h, W, rhs, 2, u, 2, md, rows);
   } else {
     md.nc = 1;
     md.fk[0] = FK_MASS;
     md.alpha = 1.0;
-    pipeline<T>(h, W, rhs, 1, u, 1, md);
+    pipeline<T>(h, W, rhs, 1, u, 1, md, rows);
   }
 }
 
@@ -516,11 +530,11 @@ template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, doub
     grid_fill_zero<T>(W.real, h->ntot, h->st);
     spread<T>(a, W.wtab, W.real, h->st);
     if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
-    grid_solve_t<T>(h, W.real, W.real);
+    grid_solve_t<T>(h, W.real, W.real, ROWS_OUT);   // only the rows the interpolation reads
     InterpArgs ia = interp_args(h, 1, 1.0, 0.0, nullptr, nullptr);
     interp<T>(ia, W.wtab, W.real, b, h->st);
   } else if (g) {
-    grid_solve_t<T>(h, g, W.real);
+    grid_solve_t<T>(h, g, W.real, ROWS_OUT);
     InterpArgs ia = interp_args(h, h->nq, -1.0, 1.0, data, nullptr);
     interp<T>(ia, W.wtab, W.real, b, h->st);
   } else {
@@ -571,7 +585,7 @@ template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* 
     md.nc = 1;
     md.fk[0] = FK_MASS;
   }
-  pipeline<T>(h, W, src, md.nc, dst, nout, md, sparse);
+  pipeline<T>(h, W, src, md.nc, dst, nout, md, sparse ? ROWS_SPARSE : ROWS_DENSE);
 }
 
 void ensure_adj(ibdl_s* h) {
@@ -916,6 +930,9 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     IBDL_HIP(hipHostMalloc((void**)&h->hostbuf, sizeof(double) * 1024, hipHostMallocDefault));
+    IBDL_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    IBDL_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    IBDL_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * n_ib, hipMemcpyDeviceToDevice, h->st));
@@ -1006,15 +1023,39 @@ ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, doubl
     int iters = 0;
     double relres = 0;
     const int status = gmres(h, h->vb, tol, maxit, q, info, &iters, &relres);
-    // true residual ||b - A q|| / ||b|| with a double-precision apply
-    apply_any(h, q, h->vr, true);
-    kr_axpby(h->vr, 1.0, h->vb, -1.0, h->n_aug, h->st);
-    const double rn = host_norm(h, h->vr, h->n_aug);
-    const double bn = host_norm(h, h->vb, h->n_aug);
+    // True residual ||b - A q|| / ||b|| with a double-precision apply.  On a mixed handle it uses
+    // the double work arrays and the recovery the float ones, so it runs on the second stream
+    // beside the recovery.
+    const bool overlap = h->mixed() && u_grid;
+    hipStream_t main = h->st;
+    if (overlap) {
+      IBDL_HIP(hipEventRecord(h->ev_fork, main));
+      IBDL_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+      h->st = h->aux;
+    }
+    try {
+      apply_any(h, q, h->vr, true);
+      kr_axpby(h->vr, 1.0, h->vb, -1.0, h->n_aug, h->st);
+      const int nblk = kr_nblk(h->n_aug);
+      ensure_partial(h, nblk);
+      kr_multidot(h->vr, h->n_aug, 1, h->vr, h->n_aug, h->partial, nblk, h->small + 600, h->st);
+      kr_multidot(h->vb, h->n_aug, 1, h->vb, h->n_aug, h->partial, nblk, h->small + 601, h->st);
+      IBDL_HIP(hipMemcpyAsync(h->hostbuf + 600, h->small + 600, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    } catch (...) {
+      h->st = main;
+      throw;
+    }
+    if (overlap) {
+      IBDL_HIP(hipEventRecord(h->ev_join, h->aux));
+      h->st = main;
+    }
     if (u_grid) {
       if (h->mixed()) recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
       else recover_t<double>(h, q, data, (const double*)g_grid, (double*)u_grid);
     }
+    if (overlap) IBDL_HIP(hipStreamWaitEvent(main, h->ev_join, 0));
+    IBDL_HIP(hipStreamSynchronize(main));
+    const double rn = sqrt(std::max(h->hostbuf[600], 0.0)), bn = sqrt(std::max(h->hostbuf[601], 0.0));
     if (info) {
       info->iters = iters;
       info->status = status;
