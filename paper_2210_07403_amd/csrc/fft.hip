@@ -131,6 +131,54 @@ __device__ __forceinline__ void line_load(C* v, int i, const C* lds, int es) {
   for (int s = 0; s < Plan<N>::RMAX; ++s) v[s] = lds[(i + s * Plan<N>::T) * es];
 }
 
+// Global loads / stores of a line's register elements i + s*T (element stride es from base, 32-bit
+// offsets: a field never holds 2^31 values here).  One validity branch per line; the row mask is
+// uniform across the launch, so its test is a scalar branch around the masked form.
+template <int N, typename C>
+__device__ __forceinline__ void line_gload(C* v, const C* __restrict__ base, int i, int es, bool valid,
+                                           const RowMask& m) {
+  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  if (!valid) {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) v[s] = mk<C>(0, 0);
+    return;
+  }
+  const C* p = base + i * es;
+  if (m.load) {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) {
+      const int y = i + s * TT;
+      v[s] = (y >= m.lo && y <= m.hi) ? p[s * TT * es] : mk<C>(0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) v[s] = p[s * TT * es];
+  }
+}
+
+template <int N, typename C>
+__device__ __forceinline__ void line_gstore(const C* v, C* __restrict__ base, int i, int es, bool valid,
+                                            const RowMask& m) {
+  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  if (!valid) return;
+  C* p = base + i * es;
+  if (m.store) {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) {
+      const int y = i + s * TT;
+      if (y >= m.lo && y <= m.hi) p[s * TT * es] = v[s];
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) p[s * TT * es] = v[s];
+  }
+}
+
+// 1/x: the hardware reciprocal in single precision (about one ulp, well inside what the float
+// path resolves), an exact division in double
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Full line transform on registers v (pattern i + s*T).  All threads of the block must call it
 // (it contains block barriers when N needs more than one stage).  lds: this line's exchange
 // buffer with element stride es; the caller must not rely on its contents afterwards.
@@ -280,19 +328,9 @@ __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, 
   const int64_t base = valid ? (l / inner) * outer + (l % inner) : 0;
   const RowMask pm = rm.plane(valid ? (l / inner) : 0);   // rows of this line's plane that matter
   C v[Plan<N>::RMAX];
-#pragma unroll
-  for (int s = 0; s < Plan<N>::RMAX; ++s) {
-    const int y = i + s * Plan<N>::T;
-    v[s] = (valid && pm.keep(y)) ? data[base + (int64_t)y * es] : mk<C>(0, 0);
-  }
+  line_gload<N>(v, data + base, i, (int)es, valid, pm);
   fft_line<N, INV>(v, i, lds + c, W, tw, 1);
-  if (valid) {
-#pragma unroll
-    for (int s = 0; s < Plan<N>::RMAX; ++s) {
-      const int y = i + s * Plan<N>::T;
-      if (pm.keep_out(y)) data[base + (int64_t)y * es] = v[s];
-    }
-  }
+  line_gstore<N>(v, data + base, i, (int)es, valid, pm);
 }
 
 // ------------------------------------------------------------------ Fourier multiplier
@@ -307,14 +345,14 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
   using C = cplx<T>;
   if (!md.stokes) {
     const T den = (T)md.c2 * sig - (T)md.c0;
-    const T g = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) / den;
+    const T g = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) * recip(den);
     if (fk == FK_MASS) return mk<C>(g, 0);
     return mk<C>(0, g * kt[fk]);
   }
   const T ell = -sig;
-  const T il = ell == (T)0 ? (T)0 : (T)1 / ell;
+  const T il = ell == (T)0 ? (T)0 : recip(ell);
   const T lam = (T)md.c2 * ell + (T)md.c0;
-  const T is = lam == (T)0 ? (T)0 : (T)1 / lam;
+  const T is = lam == (T)0 ? (T)0 : recip(lam);
   const T ko = kt[o];
   const T P0 = (o == 0 ? (T)1 : (T)0) - ko * kt[0] * il;
   const T P1 = (o == 1 ? (T)1 : (T)0) - ko * kt[1] * il;
@@ -368,15 +406,13 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
       const T den = (T)md.c2 * (sig_l + sgl[i + s * TT]) - (T)md.c0;
-      gfac[s] = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) / den;
+      gfac[s] = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) * recip(den);
     }
   }
 
   for (int f = 0; f < md.nc; ++f) {
     C v[RM];
-#pragma unroll
-    for (int s = 0; s < RM; ++s)
-      v[s] = (valid && rm.keep(i + s * TT)) ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+    line_gload<N>(v, data + f * FS + l, i, (int)P, valid, rm);
     fft_line<N, false>(v, i, lds + c, W, tw, 1);
     const int fk = md.fk[f];
     if constexpr (!STOKES) {
@@ -406,11 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     fft_line<N, true>(acc[o], i, lds + c, W, tw, 1);
-    if (valid) {
-#pragma unroll
-      for (int s = 0; s < RM; ++s)
-        if (rm.keep_out(i + s * TT)) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[o][s];
-    }
+    line_gstore<N>(acc[o], data + o * FS + l, i, (int)P, valid, rm);
   }
 }
 
@@ -436,21 +468,16 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
   if (d3) sig_l += static_cast<const T*>(md.sig[1])[jy2];
   C v[RM];
-#pragma unroll
-  for (int s = 0; s < RM; ++s) v[s] = (valid && rm.keep(i + s * TT)) ? data[l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+  line_gload<N>(v, data + l, i, (int)P, valid, rm);
   fft_line<N, false>(v, i, lds + c, W, tw, 1);
   const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
 #pragma unroll
   for (int s = 0; s < RM; ++s) {
     const T den = c2 * (sig_l + sgl[i + s * TT]) - c0;
-    v[s] = cscale(v[s], den == (T)0 ? (T)0 : num / den);
+    v[s] = cscale(v[s], den == (T)0 ? (T)0 : num * recip(den));
   }
   fft_line<N, true>(v, i, lds + c, W, tw, 1);
-  if (valid) {
-#pragma unroll
-    for (int s = 0; s < RM; ++s)
-      if (rm.keep_out(i + s * TT)) data[l + (int64_t)(i + s * TT) * P] = v[s];
-  }
+  line_gstore<N>(v, data + l, i, (int)P, valid, rm);
 }
 
 // Transposed / multi-output pass: the NI input spectra stay in registers after their forward
@@ -488,9 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   C v[NI][RM];
 #pragma unroll
   for (int f = 0; f < NI; ++f) {
-#pragma unroll
-    for (int s = 0; s < RM; ++s)
-      v[f][s] = (valid && rm.keep(i + s * TT)) ? data[f * FS + l + (int64_t)(i + s * TT) * P] : mk<C>(0, 0);
+    line_gload<N>(v[f], data + f * FS + l, i, (int)P, valid, rm);
     fft_line<N, false>(v[f], i, lds + c, W, tw, 1);
   }
   for (int o = 0; o < no; ++o) {
@@ -503,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
       const T sig = sig_l + sgl[e];
       if constexpr (MODE == 1) {
         const T den = (T)md.c2 * sig - (T)md.c0;
-        const T g = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) / den;
+        const T g = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) * recip(den);
         const T ko = o == 0 ? kt[0] : (o == 1 ? kt[1] : kt[2]);
         acc[s] = o < md.dim ? mul_ir(v[0][s], g * ko) : cscale(v[0][s], g);
       } else {
@@ -513,11 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
       }
     }
     fft_line<N, true>(acc, i, lds + c, W, tw, 1);
-    if (valid) {
-#pragma unroll
-      for (int s = 0; s < RM; ++s)
-        if (rm.keep_out(i + s * TT)) data[o * FS + l + (int64_t)(i + s * TT) * P] = acc[s];
-    }
+    line_gstore<N>(acc, data + o * FS + l, i, (int)P, valid, rm);
   }
 }
 
