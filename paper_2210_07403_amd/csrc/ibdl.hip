@@ -65,7 +65,6 @@ struct ibdl_s {
   double* V = nullptr;
   int vcap = 0;
   double* small = nullptr;    // 1024 doubles of small device scratch
-  unsigned* counter = nullptr;  // completion counter of the fused Arnoldi reductions (0 between calls)
   double* partial = nullptr;  // partial sums
   int pcap = 0;
   double* vb = nullptr;       // right-hand side
@@ -705,7 +704,8 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     h->vcap = maxit + 1;
   }
   const int nblk = kr_nblk(n);
-  ensure_partial(h, nblk * (maxit + 2));
+  const int anblk = kr_arnoldi_nblk(n);
+  ensure_partial(h, std::max(nblk, anblk) * (maxit + 2));
   const double beta = host_norm(h, b, n);
   *iters = 0;
   *relres = 0.0;
@@ -725,9 +725,9 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   for (int j = 0; j < maxit; ++j) {
     double* w = h->V + (int64_t)(j + 1) * n;
     apply_any(h, h->V + (int64_t)j * n, w, false, trans);
-    kr_arnoldi(0, h->V, n, j + 1, w, nullptr, n, h->partial, nblk, h->counter, h1, h->st);
-    kr_arnoldi(1, h->V, n, j + 1, w, h1, n, h->partial, nblk, h->counter, h2, h->st);
-    kr_arnoldi(2, h->V, n, j + 1, w, h2, n, h->partial, nblk, h->counter, hn, h->st);
+    kr_arnoldi(0, h->V, n, j + 1, w, nullptr, n, h->partial, anblk, h1, h->st);
+    kr_arnoldi(1, h->V, n, j + 1, w, h1, n, h->partial, anblk, h2, h->st);
+    kr_arnoldi(2, h->V, n, j + 1, w, h2, n, h->partial, anblk, hn, h->st);
     IBDL_HIP(hipMemcpyAsync(h->hostbuf, h->small, sizeof(double) * 513, hipMemcpyDeviceToHost, h->st));
     IBDL_HIP(hipStreamSynchronize(h->st));
     double* Hj = &H[(size_t)j * (maxit + 1)];
@@ -925,8 +925,6 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->row_lim = (int2*)h->dalloc<int>(sizeof(int2) * nplanes);
     h->rows = (int*)h->dalloc<int>(sizeof(int) * (int64_t)h->n[1] * nplanes);
     h->small = (double*)h->dalloc<double>(sizeof(double) * 1024);
-    h->counter = (unsigned*)h->dalloc<unsigned>(sizeof(unsigned) * 4);
-    IBDL_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 4, h->st));
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     IBDL_HIP(hipHostMalloc((void**)&h->hostbuf, sizeof(double) * 1024, hipHostMallocDefault));

@@ -205,11 +205,12 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
                double* partial, int nblk, hipStream_t st);
 void kr_add(double* dst, const double* a, const double* b, int n, hipStream_t st);
 int kr_nblk(int64_t n);
-// Arnoldi vector work (one launch each): mode 0 out_j = V_j . w; mode 1 w -= V h then out_j = V_j . w;
-// mode 2 w -= V h then out_0 = w . w; j < k.  partial: k * nblk doubles; counter: a device word that
-// is 0 between calls (the last block resets it).
+// Arnoldi vector work (a partial-sum kernel and a fixed-order reduction each): mode 0 out_j = V_j . w;
+// mode 1 w -= V h then out_j = V_j . w; mode 2 w -= V h then out_0 = w . w; j < k.  partial: k * nblk
+// doubles with nblk = kr_arnoldi_nblk(n).
 void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const double* h, int64_t n, double* partial,
-                int nblk, unsigned* counter, double* out, hipStream_t st);
+                int nblk, double* out, hipStream_t st);
+int kr_arnoldi_nblk(int64_t n);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

@@ -172,51 +172,65 @@ __global__ void k_adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hD
   }
 }
 
-// One Arnoldi step's vector work in three launches.  MODE 0: d_j = V_j . w (j < k); MODE 1:
-// w -= V h, then d_j = V_j . w; MODE 2: w -= V h, then d_0 = w . w.  Each block handles a chunk of
-// 2048 elements (a thread updates and then reads the same elements, so no barrier is needed between
-// the update and the dots); the last block to finish adds the per-block partials in block order, so
-// the sums do not depend on scheduling.
+// One Arnoldi step's vector work.  MODE 0: d_j = V_j . w (j < k); MODE 1: w -= V h, then
+// d_j = V_j . w; MODE 2: w -= V h, then d_0 = w . w.  A block handles 256 elements, one per thread
+// (the thread updates its element and then reads it, so no barrier is needed between the update and
+// the dots); dot products are taken eight at a time, each thread keeping eight partial products and
+// the block adding them in a fixed tree.  The per-block partials are added by k_arnoldi_reduce, one
+// block per dot product, in a fixed order, so the sums do not depend on scheduling.  (A last-block
+// reduction inside the first kernel would need device-wide fences, which write back the per-XCD L2
+// caches and cost more than the second launch.)
+constexpr int kArnChunk = 256;
+constexpr int kArnGroup = 8;
+
 template <int MODE>
 __global__ __launch_bounds__(kB) void k_arnoldi(const double* __restrict__ V, int64_t ldv, int k, double* w,
                                                 const double* __restrict__ h, int64_t n, int nblk,
-                                                double* partial, unsigned* counter, double* __restrict__ out) {
-  __shared__ double red[kB];
-  __shared__ int is_last;
-  const int64_t beg = (int64_t)blockIdx.x * kElemsPerBlock;
-  const int64_t end = beg + kElemsPerBlock < n ? beg + kElemsPerBlock : n;
-  if (MODE > 0) {
-    for (int64_t e = beg + threadIdx.x; e < end; e += kB) {
-      double s = w[e];
-      for (int j = 0; j < k; ++j) s -= V[j * ldv + e] * h[j];
-      w[e] = s;
-    }
+                                                double* __restrict__ partial) {
+  __shared__ double red[kArnGroup][kB];
+  const int64_t e = (int64_t)blockIdx.x * kArnChunk + threadIdx.x;
+  const bool in = e < n;
+  double we = in ? w[e] : 0.0;
+  if (MODE > 0 && in) {
+    for (int j = 0; j < k; ++j) we -= V[j * ldv + e] * h[j];
+    w[e] = we;
   }
   const int nd = MODE == 2 ? 1 : k;
-  for (int d = 0; d < nd; ++d) {
-    double s = 0.0;
-    for (int64_t e = beg + threadIdx.x; e < end; e += kB) s += (MODE == 2 ? w[e] : V[d * ldv + e]) * w[e];
-    red[threadIdx.x] = s;
+  for (int d0 = 0; d0 < nd; d0 += kArnGroup) {
+#pragma unroll
+    for (int g = 0; g < kArnGroup; ++g) {
+      const int d = d0 + g;
+      double p = 0.0;
+      if (in && d < nd) p = (MODE == 2 ? we : V[d * ldv + e]) * we;
+      red[g][threadIdx.x] = p;
+    }
     __syncthreads();
     for (int st = kB / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      if (threadIdx.x < st) {
+#pragma unroll
+        for (int g = 0; g < kArnGroup; ++g) red[g][threadIdx.x] += red[g][threadIdx.x + st];
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) partial[d * nblk + blockIdx.x] = red[0];
+    if (threadIdx.x < kArnGroup && d0 + threadIdx.x < nd) partial[(d0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
     __syncthreads();
   }
-  __threadfence();
-  if (threadIdx.x == 0) is_last = atomicAdd(counter, 1u) == (unsigned)(nblk - 1);
+}
+
+// out[d] = sum over blocks of partial[d][b]: strided per-thread sums, then a fixed tree
+__global__ __launch_bounds__(kB) void k_arnoldi_reduce(const double* __restrict__ partial, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double red[kB];
+  const int d = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kB) s += partial[d * nblk + b];
+  red[threadIdx.x] = s;
   __syncthreads();
-  if (is_last) {
-    __threadfence();
-    for (int d = threadIdx.x; d < nd; d += kB) {
-      double s = 0.0;
-      for (int b = 0; b < nblk; ++b) s += partial[d * nblk + b];
-      out[d] = s;
-    }
-    if (threadIdx.x == 0) *counter = 0u;
+  for (int st = kB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[d] = red[0];
 }
 
 // ------------------------------------------------------------------ batched (segmented) vectors
@@ -333,14 +347,15 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
   IBDL_LAUNCH_CHECK();
 }
 
+int kr_arnoldi_nblk(int64_t n) { return (int)((n + kArnChunk - 1) / kArnChunk) > 0 ? (int)((n + kArnChunk - 1) / kArnChunk) : 1; }
+
 void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const double* h, int64_t n, double* partial,
-                int nblk, unsigned* counter, double* out, hipStream_t st) {
-  if (mode == 0)
-    hipLaunchKernelGGL(k_arnoldi<0>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial, counter, out);
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_arnoldi<1>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial, counter, out);
-  else
-    hipLaunchKernelGGL(k_arnoldi<2>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial, counter, out);
+                int nblk, double* out, hipStream_t st) {
+  if (mode == 0) hipLaunchKernelGGL(k_arnoldi<0>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
+  else if (mode == 1) hipLaunchKernelGGL(k_arnoldi<1>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
+  else hipLaunchKernelGGL(k_arnoldi<2>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_arnoldi_reduce, dim3(mode == 2 ? 1 : k), dim3(kB), 0, st, partial, nblk, out);
   IBDL_LAUNCH_CHECK();
 }
 
