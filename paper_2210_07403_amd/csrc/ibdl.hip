@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <memory>
 #include <string>
 #include <vector>
@@ -70,6 +72,27 @@ struct ibdl_s {
   double* vb = nullptr;       // right-hand side
   double* vr = nullptr;       // residual scratch
   double* hostbuf = nullptr;  // pinned host scratch (1024 doubles)
+  // host-mapped coherent memory for the per-iteration Arnoldi values: the GPU writes them and a
+  // sequence tag, the host polls the tag (no copy-engine transfer, no stream-sync wake-up)
+  double* hmap = nullptr;
+  double* hmap_dev = nullptr;
+  volatile unsigned* htag = nullptr;
+  unsigned* htag_dev = nullptr;
+  unsigned seq = 0;
+  // the working-precision operator apply (and its transpose) captured in HIP graphs, replayed from
+  // the fixed vectors gx -> gy inside GMRES (rebuilt when the markers change)
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  double *gx = nullptr, *gy = nullptr;
+  bool use_graph = true;
+  void drop_graphs() {
+    for (int k = 0; k < 2; ++k) {
+      if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+      gexec[k] = nullptr;
+      graph[k] = nullptr;
+    }
+  }
   double* g64 = nullptr;      // refinement: the forcing widened to double ([nq][grid])
   double* vx = nullptr;       // refinement: correction of one round [n_aug]
   double* adj_m = nullptr;    // adjoint: interpolated fields / gather weights [n_ib][8]
@@ -128,7 +151,9 @@ struct ibdl_s {
       else (void)hipDeviceSynchronize();
     }
     for (void* p : allocs) (void)hipFree(p);
+    drop_graphs();
     if (hostbuf) (void)hipHostFree(hostbuf);
+    if (hmap) (void)hipHostFree(hmap);
     for (auto& p : pending) {
       (void)hipEventDestroy(p.second.first);
       (void)hipEventDestroy(p.second.second);
@@ -695,6 +720,64 @@ double host_norm(ibdl_s* h, const double* v, int64_t n) {
   return sqrt(h->hostbuf[0]);
 }
 
+// Publish n device doubles to the host-mapped buffer and wait for them: poll the tag for up to
+// 2 ms (an iteration's GPU work is well below that), then fall back to a stream synchronisation,
+// after which the tag must be there.
+const volatile double* wait_published(ibdl_s* h, const double* src, int n) {
+  const unsigned seq = ++h->seq;
+  kr_publish(src, n, h->hmap_dev, h->htag_dev, seq, h->st);
+  const auto t0 = std::chrono::steady_clock::now();
+  while (*h->htag != seq) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+      IBDL_HIP(hipStreamSynchronize(h->st));
+      if (*h->htag != seq) throw Error(IBDL_ERR_HIP, "Arnoldi values did not reach the host");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return h->hmap;
+}
+
+// One operator apply inside GMRES: the captured graph of the working-precision apply (transposed
+// with trans) replayed from gx into gy, or, while stage timing is on, direct launches into
+// eager_dst.  Returns where the result is.
+double* apply_step(ibdl_s* h, const double* x, bool trans, double* eager_dst) {
+  if (h->timing || !h->use_graph) {
+    apply_any(h, x, eager_dst, false, trans);
+    return eager_dst;
+  }
+  const int64_t n = h->n_aug;
+  const int k = trans ? 1 : 0;
+  if (!h->gexec[k]) {
+    if (!h->gx) {
+      h->gx = (double*)h->dalloc<double>(sizeof(double) * n);
+      h->gy = (double*)h->dalloc<double>(sizeof(double) * n);
+    }
+    // a direct run first allocates every workspace and measures the launch shapes
+    IBDL_HIP(hipMemcpyAsync(h->gx, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+    apply_any(h, h->gx, h->gy, false, trans);
+    IBDL_HIP(hipStreamSynchronize(h->st));
+    hipStream_t main = h->st;
+    h->st = h->aux;
+    IBDL_HIP(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
+    try {
+      apply_any(h, h->gx, h->gy, false, trans);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(h->aux, &g);
+      if (g) (void)hipGraphDestroy(g);
+      h->st = main;
+      throw;
+    }
+    h->st = main;
+    IBDL_HIP(hipStreamEndCapture(h->aux, &h->graph[k]));
+    IBDL_HIP(hipGraphInstantiate(&h->gexec[k], h->graph[k], nullptr, nullptr, 0));
+  }
+  IBDL_HIP(hipMemcpyAsync(h->gx, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+  IBDL_HIP(hipGraphLaunch(h->gexec[k], h->st));
+  return h->gy;
+}
+
 // GMRES, x0 = 0, no restart; classical Gram-Schmidt twice on the device; Givens on the host.
 int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
           double* relres, bool trans = false) {
@@ -723,20 +806,19 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   double* h2 = h->small + 256;      // [maxit+1]
   double* hn = h->small + 512;      // norm^2
   for (int j = 0; j < maxit; ++j) {
-    double* w = h->V + (int64_t)(j + 1) * n;
-    apply_any(h, h->V + (int64_t)j * n, w, false, trans);
+    double* vnext = h->V + (int64_t)(j + 1) * n;
+    double* w = apply_step(h, h->V + (int64_t)j * n, trans, vnext);
     kr_arnoldi(0, h->V, n, j + 1, w, nullptr, n, h->partial, anblk, h1, h->st);
     kr_arnoldi(1, h->V, n, j + 1, w, h1, n, h->partial, anblk, h2, h->st);
     kr_arnoldi(2, h->V, n, j + 1, w, h2, n, h->partial, anblk, hn, h->st);
-    IBDL_HIP(hipMemcpyAsync(h->hostbuf, h->small, sizeof(double) * 513, hipMemcpyDeviceToHost, h->st));
-    IBDL_HIP(hipStreamSynchronize(h->st));
+    const volatile double* hv = wait_published(h, h->small, 513);
     double* Hj = &H[(size_t)j * (maxit + 1)];
-    for (int i = 0; i <= j; ++i) Hj[i] = h->hostbuf[i] + h->hostbuf[256 + i];
-    const double hnext = sqrt(std::max(h->hostbuf[512], 0.0));
+    for (int i = 0; i <= j; ++i) Hj[i] = hv[i] + hv[256 + i];
+    const double hnext = sqrt(std::max((double)hv[512], 0.0));
     if (!std::isfinite(hnext)) throw Error(IBDL_ERR_NONFINITE, "non-finite value in the Arnoldi process");
     Hj[j + 1] = hnext;
     const bool breakdown = !(hnext > 1e-300 * beta);
-    if (!breakdown) kr_scale(w, 1.0 / hnext, w, n, h->st);
+    if (!breakdown) kr_scale(w, 1.0 / hnext, vnext, n, h->st);
     for (int i = 0; i < j; ++i) {
       const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
       Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
@@ -831,6 +913,7 @@ void validate(const ibdl_config_t* c, int64_t n_ib) {
 }
 
 void build_markers(ibdl_s* h) {
+  h->drop_graphs();
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
               h->busy_off, h->st);
@@ -928,6 +1011,11 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     IBDL_HIP(hipHostMalloc((void**)&h->hostbuf, sizeof(double) * 1024, hipHostMallocDefault));
+    IBDL_HIP(hipHostMalloc((void**)&h->hmap, sizeof(double) * 1024 + 64, hipHostMallocMapped | hipHostMallocCoherent));
+    IBDL_HIP(hipHostGetDevicePointer((void**)&h->hmap_dev, h->hmap, 0));
+    h->htag = reinterpret_cast<volatile unsigned*>(h->hmap + 1024);
+    h->htag_dev = reinterpret_cast<unsigned*>(h->hmap_dev + 1024);
+    *h->htag = 0;
     IBDL_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
     IBDL_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     IBDL_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));

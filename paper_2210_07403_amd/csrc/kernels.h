@@ -211,6 +211,9 @@ int kr_nblk(int64_t n);
 void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const double* h, int64_t n, double* partial,
                 int nblk, double* out, hipStream_t st);
 int kr_arnoldi_nblk(int64_t n);
+// host_dst / host_tag: device addresses of host-mapped, coherent pinned memory; the tag is written
+// last, after a system-scope fence
+void kr_publish(const double* src, int n, double* host_dst, unsigned* host_tag, unsigned seq, hipStream_t st);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

@@ -297,6 +297,18 @@ __global__ void k_bscale(const double* __restrict__ src, const double* __restric
     dst[e] = src[e] * sc[seg[e]];
 }
 
+// Copy n doubles into host-mapped memory, then (after a system-scope fence) the sequence tag, so a
+// host that sees the tag sees the values.
+__global__ __launch_bounds__(kB) void k_publish(const double* __restrict__ src, int n, double* dst,
+                                                unsigned* tag, unsigned seq) {
+  for (int i = threadIdx.x; i < n; i += kB) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned*>(tag) = seq;
+  }
+}
+
 inline unsigned blocks_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
@@ -356,6 +368,11 @@ void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const 
   else hipLaunchKernelGGL(k_arnoldi<2>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_arnoldi_reduce, dim3(mode == 2 ? 1 : k), dim3(kB), 0, st, partial, nblk, out);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kr_publish(const double* src, int n, double* host_dst, unsigned* host_tag, unsigned seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kB), 0, st, src, n, host_dst, host_tag, seq);
   IBDL_LAUNCH_CHECK();
 }
 
