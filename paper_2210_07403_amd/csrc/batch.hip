@@ -40,6 +40,7 @@ template <typename T> struct GroupWork {
   T* real = nullptr;          // [problem][grid]
   cplx<T>* spec = nullptr;    // [problem][half spectrum]
   cplx<T>* wtab = nullptr;    // weight table in this precision
+  T* crec = nullptr;          // per-marker spread coefficients (scratch of the 3-D spread)
   Tuned tune;
   bool ready = false;
 };
@@ -179,6 +180,8 @@ template <typename T> void group_density_to_grid(ibdl_batch_s* B, Group& G, Grou
   a.q = q;
   a.nrm = G.nrm;
   a.ds = G.ds;
+  a.nmark = G.nib;
+  a.crec = W.crec;
   spread<T>(a, W.wtab, W.real, B->st);
   group_pipeline<T>(B, G, W, W.tune);
 }
@@ -193,6 +196,7 @@ template <typename T> GroupWork<T>& group_work(ibdl_batch_s* B, Group& G) {
   W.real = (T*)B->dalloc(sizeof(T) * G.ntot * np);
   W.spec = (cplx<T>*)B->dalloc(sizeof(cplx<T>) * G.nspec * np);
   W.wtab = (cplx<T>*)B->dalloc(sizeof(cplx<T>) * G.nib * 24);
+  W.crec = (T*)B->dalloc(sizeof(T) * G.nib * 8);
   weight_table<T>(G.wt, G.nib, W.wtab, B->st);
   grid_fill_zero<T>(W.real, G.ntot * np, B->st);
   W.ready = true;

@@ -269,6 +269,19 @@ template <> struct Mfma<double> {
 
 constexpr int kSC = 64;   // candidates staged in LDS per pass (a multiple of 4)
 
+// per-marker field coefficients (times ds h^-D unless raw), once per spread: a tile's staging then
+// reads one record per candidate instead of the density, normal and weight
+template <typename T>
+__global__ void k_marker_coefs(SpreadArgs a, T* __restrict__ rec, int64_t n_ib) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_ib) return;
+  const double hD = a.g.h * a.g.h * (a.g.dim == 3 ? a.g.h : 1.0);
+  double c8[8];
+  spread_coefs(a, (int)m, a.g.dim, a.raw ? 1.0 : a.ds[m] / hD, c8);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) rec[m * 8 + c] = (T)c8[c];
+}
+
 template <typename T, int NF, bool FD>
 __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
   using T2 = cplx<T>;
@@ -295,7 +308,6 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
 #pragma unroll
   for (int c = 0; c < NF; ++c) acc[c][0] = acc[c][1] = typename M::v4{0, 0, 0, 0};
   const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
-  const double hD = g.h * g.h * g.h;
   constexpr int NT = FD ? 2 : 1, CPS = 4 / NT;       // terms per candidate, candidates per K-step
   const int kk = lane >> 4, i16 = lane & 15;
   const int yy = i16 & 3, zz = i16 >> 2;
@@ -303,23 +315,25 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
     const int cnt = end - c0 < kSC ? end - c0 : kSC;
     // one lane per candidate: marker id, window offsets relative to the tile, coefficients
     if (tid < kSC) {
-      double c8[8];
       int m = -1, ox = 6, oy = 6, oz = 6;
+      T cv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) cv[c] = (T)0;
       if (tid < cnt) {
         m = a.list[c0 + tid];
         ox = a.s[m * 3 + 0];
         oy = a.s[m * 3 + 1];
         oz = a.s[m * 3 + 2];
-        spread_coefs(a, m, 3, a.raw ? 1.0 : a.ds[m] / hD, c8);
-      } else {
-        for (int c = 0; c < 8; ++c) c8[c] = 0.0;
+        const T* rec = static_cast<const T*>(a.crec) + (int64_t)m * 8;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cv[c] = rec[c];
       }
       s_o[tid][0] = m;
       s_o[tid][1] = ox;
       s_o[tid][2] = oy;
       s_o[tid][3] = oz;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) s_c[tid][c] = (T)c8[c];
+      for (int c = 0; c < NC; ++c) s_c[tid][c] = cv[c];
     }
     __syncthreads();
     // the candidates' 24-entry weight rows, contiguous per marker (zero for padding candidates)
@@ -814,6 +828,11 @@ void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
     if (one) hipLaunchKernelGGL((k_spread2<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
     else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   } else {
+    if (!a.crec) throw Error(-1, "3-D spread: coefficient scratch missing");
+    const int64_t n_ib = a.nmark;
+    if (n_ib > 0)
+      hipLaunchKernelGGL((k_marker_coefs<T>), dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, a,
+                         static_cast<T*>(a.crec), n_ib);
     if (one && a.mode == SP_FDDIV)
       hipLaunchKernelGGL((k_spread3m<T, 1, true>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
     else if (one)

@@ -27,6 +27,7 @@ template <typename T> struct GridWork {
   T* real = nullptr;
   cplx<T>* spec = nullptr;
   cplx<T>* wtab = nullptr;   // marker weight table in this precision
+  T* crec = nullptr;         // per-marker spread coefficients [n_ib][8] (scratch of the 3-D spread)
   int nfields = 0;
   LaunchShape shape;         // launch shapes of the operator apply's FFT passes (measured)
   bool tuned = false;
@@ -220,6 +221,7 @@ template <typename T> GridWork<T>& ensure_work(ibdl_s* h) {
   W.real = (T*)h->dalloc<T>(sizeof(T) * h->ntot * nf);
   W.spec = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->nspec * nf);
   W.wtab = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->n_ib * 24);
+  W.crec = (T*)h->dalloc<T>(sizeof(T) * h->n_ib * 8);
   weight_table<T>(h->wt, h->n_ib, W.wtab, h->st);
   GridTables<T> G = make_grid_tables<T>(h->dim, h->n, h->cfg.L, h->h, h->fd(),
                                         [&](size_t bytes) { return h->dalloc<T>(bytes); });
@@ -352,6 +354,13 @@ SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
   return a;
 }
 
+// the spread with this precision's tables and coefficient scratch
+template <typename T> void spread_w(ibdl_s* h, SpreadArgs a, GridWork<T>& W, T* out) {
+  a.nmark = h->n_ib;
+  a.crec = W.crec;
+  spread<T>(a, W.wtab, out, h->st);
+}
+
 InterpArgs interp_args(ibdl_s* h, int nf, double a, double b, const double* x, const double* ub) {
   InterpArgs ia{};
   ia.g = h->geom;
@@ -425,7 +434,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
   clear_fields<T>(h, W.real, pl.nf, sparse);
   {
     StageTimer t(h, ST_SPREAD);
-    spread<T>(a, W.wtab, W.real, h->st);
+    spread_w<T>(h, a, W, W.real);
   }
   if (g) {
     if (pl.mode == SP_STOKES) grid_axpby<T>(W.real + 3 * h->ntot, -1.0, g, 1.0, 2 * h->ntot, h->st);
@@ -552,7 +561,7 @@ template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, doub
   if (h->neumann()) {
     SpreadArgs a = spread_args(h, SP_PLAIN, 1, data);
     grid_fill_zero<T>(W.real, h->ntot, h->st);
-    spread<T>(a, W.wtab, W.real, h->st);
+    spread_w<T>(h, a, W, W.real);
     if (g) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
     grid_solve_t<T>(h, W.real, W.real, ROWS_OUT);   // only the rows the interpolation reads
     InterpArgs ia = interp_args(h, 1, 1.0, 0.0, nullptr, nullptr);
@@ -641,7 +650,7 @@ template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
   clear_fields<T>(h, W.real, h->nq, true);
   {
     StageTimer t(h, ST_SPREAD);
-    spread<T>(a, W.wtab, W.real, h->st);
+    spread_w<T>(h, a, W, W.real);
   }
   adj_grid<T>(h, W, W.real, W.real, true);
   const double half = h->neumann() ? -0.5 : 0.5;
@@ -678,7 +687,7 @@ template <typename T> void grad_X_t(ibdl_s* h, const double* q, const T* u, cons
   SpreadArgs a = spread_args(h, SP_PLAIN, h->nq, h->adj_mu);
   a.raw = 1;
   grid_fill_zero<T>(W.real, h->ntot * h->nq, h->st);
-  spread<T>(a, W.wtab, W.real, h->st);
+  spread_w<T>(h, a, W, W.real);
   if (h->stokes()) grid_axpby<T>(W.real, 1.0, psi, -1.0, h->ntot * h->nq, h->st);
   else grid_axpby<T>(W.real, -1.0, psi, 1.0, h->ntot, h->st);
   adj_grid<T>(h, W, W.real, W.real);
@@ -1060,10 +1069,10 @@ ibdl_status_t ibdl_spread(ibdl_t h, const double* f, int32_t nc, void* grid) {
     SpreadArgs a = spread_args(h, SP_PLAIN, nc, f);
     if (h->mixed()) {
       grid_fill_zero<float>((float*)grid, h->ntot * nc, h->st);
-      spread<float>(a, ensure_work<float>(h).wtab, (float*)grid, h->st);
+      spread_w<float>(h, a, ensure_work<float>(h), (float*)grid);
     } else {
       grid_fill_zero<double>((double*)grid, h->ntot * nc, h->st);
-      spread<double>(a, ensure_work<double>(h).wtab, (double*)grid, h->st);
+      spread_w<double>(h, a, ensure_work<double>(h), (double*)grid);
     }
     return IBDL_OK;
   });

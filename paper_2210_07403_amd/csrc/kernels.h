@@ -147,6 +147,9 @@ struct SpreadArgs {
   const double* m;    // optional extra mass values [n_ib] (Neumann V_b), may be null
   const double* nrm;  // [n_ib][dim]
   const double* ds;   // [n_ib]
+  int64_t nmark;      // markers (records to prepare)
+  void* crec;         // 3-D: scratch of n_ib * 8 values of the grid type for the per-marker field
+                      // coefficients (written by the spread launcher, then staged by the tiles)
 };
 // Spread over the non-empty tiles only: nodes of empty tiles are left untouched, so the caller
 // clears the nf output fields first (grid_fill_zero).  A batch tile id p * ntile + t writes problem
