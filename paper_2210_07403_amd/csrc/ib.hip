@@ -267,7 +267,7 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-constexpr int kSC = 64;   // candidates staged in LDS per pass (a multiple of 4)
+constexpr int kSC = 64;   // candidates staged in LDS per pass (4 lanes each: a 256-thread block)
 
 // per-marker field coefficients (times ds h^-D unless raw), once per spread: a tile's staging then
 // reads one record per candidate instead of the density, normal and weight
@@ -311,46 +311,43 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
   constexpr int NT = FD ? 2 : 1, CPS = 4 / NT;       // terms per candidate, candidates per K-step
   const int kk = lane >> 4, i16 = lane & 15;
   const int yy = i16 & 3, zz = i16 >> 2;
+  // staging: four lanes per candidate (lane quarter p loads window offset p < 3, coefficients
+  // p, p + 4, ... and entries 6p .. 6p + 5 of the weight row), all loads of a pass issued at once;
+  // the next pass's marker ids are fetched while the current pass accumulates
+  const int scand = tid >> 2, part = tid & 3;
+  int m_next = scand < end - beg ? a.list[beg + scand] : -1;
   for (int c0 = beg; c0 < end; c0 += kSC) {
     const int cnt = end - c0 < kSC ? end - c0 : kSC;
-    // one lane per candidate: marker id, window offsets relative to the tile, coefficients
-    if (tid < kSC) {
-      int m = -1, ox = 6, oy = 6, oz = 6;
-      T cv[NC];
+    {
+      const int m = m_next;
+      const bool live = m >= 0;
+      const int mm = live ? m : 0;   // padding candidates read marker 0 and store zeros
+      const T2* wrow = wtab + (int64_t)mm * 24 + 6 * part;
+      T2 w6[6];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) cv[c] = (T)0;
-      if (tid < cnt) {
-        m = a.list[c0 + tid];
-        ox = a.s[m * 3 + 0];
-        oy = a.s[m * 3 + 1];
-        oz = a.s[m * 3 + 2];
-        const T* rec = static_cast<const T*>(a.crec) + (int64_t)m * 8;
+      for (int i = 0; i < 6; ++i) w6[i] = wrow[i];
+      const int o = a.s[mm * 3 + (part < 3 ? part : 0)];
+      const T* rec = static_cast<const T*>(a.crec) + (int64_t)mm * 8;
+      T cv[(NC + 3) / 4];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) cv[c] = rec[c];
-      }
-      s_o[tid][0] = m;
-      s_o[tid][1] = ox;
-      s_o[tid][2] = oy;
-      s_o[tid][3] = oz;
+      for (int j = 0; j < (NC + 3) / 4; ++j) cv[j] = (part + 4 * j < NC) ? rec[part + 4 * j] : (T)0;
+      m_next = (c0 + kSC + scand < end) ? a.list[c0 + kSC + scand] : -1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) s_c[tid][c] = cv[c];
-    }
-    __syncthreads();
-    // the candidates' 24-entry weight rows, contiguous per marker (zero for padding candidates)
-    for (int e = tid; e < kSC * 24; e += 256) {
-      const int cand = e / 24, k = e - cand * 24;
-      const int m = s_o[cand][0];
-      s_w[cand][k] = m >= 0 ? wtab[(int64_t)m * 24 + k] : mk<T2>((T)0, (T)0);
+      for (int i = 0; i < 6; ++i) s_w[scand][6 * part + i] = live ? w6[i] : mk<T2>((T)0, (T)0);
+      if (part < 3) s_o[scand][part] = live ? o : 6;
+#pragma unroll
+      for (int j = 0; j < (NC + 3) / 4; ++j)
+        if (part + 4 * j < NC) s_c[scand][part + 4 * j] = live ? cv[j] : (T)0;
     }
     __syncthreads();
     const int nsteps = (cnt + CPS - 1) / CPS;
     for (int st = wave; st < nsteps; st += 4) {
       const int cand = st * CPS + kk / NT;
       // tile node -> window tap (6 and 7 hold zeros)
-      const int tx_ = min((x0 + i16 - s_o[cand][1]) & mx, 6);
-      const int ty_ = min((y0 + yy - s_o[cand][2]) & my, 6);
-      const int tza = min((z0 + zz - s_o[cand][3]) & mz, 6);
-      const int tzb = min((z0 + zz + 4 - s_o[cand][3]) & mz, 6);
+      const int tx_ = min((x0 + i16 - s_o[cand][0]) & mx, 6);
+      const int ty_ = min((y0 + yy - s_o[cand][1]) & my, 6);
+      const int tza = min((z0 + zz - s_o[cand][2]) & mz, 6);
+      const int tzb = min((z0 + zz + 4 - s_o[cand][2]) & mz, 6);
       const T2 xv = s_w[cand][tx_], yv = s_w[cand][8 + ty_];
       const T2 za = s_w[cand][16 + tza], zb = s_w[cand][16 + tzb];
       if constexpr (FD) {
