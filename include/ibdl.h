@@ -215,6 +215,11 @@ ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total);
  * last-axis pass; 0 = not measured yet, the largest shape is used).  Any pointer may be NULL. */
 ibdl_status_t ibdl_launch_shape(ibdl_t h, int32_t* rows_per_block, int32_t* lines_y, int32_t* lines_last);
 
+/* GMRES in ibdl_solve, ibdl_solve_refined and ibdl_backward replays each operator apply from a
+ * HIP graph captured at the first apply (1, the default) or launches its kernels directly (0).
+ * Both give the same bits.  Disabling drops the captured graphs. */
+ibdl_status_t ibdl_set_graph(ibdl_t h, int32_t enable);
+
 /* Profiling: enable (1) or disable (0) per-stage timing with HIP events recorded on the handle's
  * stream around every kernel stage (resets the accumulated times).  Costs a few microseconds per
  * stage; leave it off outside profiling. */

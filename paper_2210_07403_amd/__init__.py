@@ -198,6 +198,10 @@ class Problem:
         B.check(B.load().ibdl_launch_shape(self._h, ctypes.byref(r), ctypes.byref(y), ctypes.byref(z)), self._h)
         return int(r.value), int(y.value), int(z.value)
 
+    def set_graph(self, enable=True):
+        """Replay GMRES's operator applies from a captured HIP graph (default) or launch directly."""
+        B.check(B.load().ibdl_set_graph(self._h, 1 if enable else 0), self._h)
+
     def set_timing(self, enable=True):
         B.check(B.load().ibdl_set_timing(self._h, 1 if enable else 0), self._h)
 

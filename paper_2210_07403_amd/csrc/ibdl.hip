@@ -1241,6 +1241,15 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
   });
 }
 
+ibdl_status_t ibdl_set_graph(ibdl_t h, int32_t enable) {
+  return guarded(h, [&]() {
+    IBDL_HIP(hipStreamSynchronize(h->st));
+    h->use_graph = enable != 0;
+    if (!h->use_graph) h->drop_graphs();
+    return IBDL_OK;
+  });
+}
+
 ibdl_status_t ibdl_set_timing(ibdl_t h, int32_t enable) {
   return guarded(h, [&]() {
     h->collect();
