@@ -91,21 +91,30 @@ template <int N, int S, bool INV, typename C>
 __device__ __forceinline__ void stage_compute(C* v, int i, const C* __restrict__ tw, int tws) {
   using P = Plan<N>;
   constexpr int R = P::radix(S), PP = P::pw(S), NB = P::RMAX / R, TT = P::T;
+  if constexpr (PP > 1) {
+    // all twiddles of the stage are loaded before the first is used, so that their loads are in
+    // flight together rather than one latency each
+    C w[NB][R];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+      const int k = (i + m * TT) & (PP - 1);
+#pragma unroll
+      for (int j = 1; j < R; ++j) w[m][j] = tw[(j * k * (N / (PP * R))) * tws];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        if (INV) w[m][j].y = -w[m][j].y;
+        v[m + j * NB] = cmul(v[m + j * NB], w[m][j]);
+      }
+  }
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
     C x[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) x[j] = v[m + j * NB];
-    if constexpr (PP > 1) {
-      const int b = i + m * TT;
-      const int k = b & (PP - 1);
-#pragma unroll
-      for (int j = 1; j < R; ++j) {
-        C w = tw[(j * k * (N / (PP * R))) * tws];
-        if (INV) w.y = -w.y;
-        x[j] = cmul(x[j], w);
-      }
-    }
     dft<R, INV>(x);
 #pragma unroll
     for (int j = 0; j < R; ++j) v[m + j * NB] = x[j];
@@ -222,12 +231,26 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   __shared__ int64_t rbase[kBlock];   // row index of each block row (active-row list or contiguous)
-  for (int r = tid; r < RPB; r += NT) rbase[r] = r < nvalid ? rl.row(row0 + r) : 0;
+  __shared__ unsigned long long rseg[kBlock];   // busy x-segments of each block row
+  for (int r = tid; r < RPB; r += NT) {
+    rbase[r] = r < nvalid ? rl.row(row0 + r) : 0;
+    rseg[r] = r < nvalid ? rl.segmask(row0 + r) : 0ull;
+  }
   __syncthreads();
   const C* src = reinterpret_cast<const C*>(in);
-  for (int e = tid; e < RPB * M; e += NT) {
-    const int r = e / M, c = e - r * M;
-    lds[r * RC::LS + c] = (r < nvalid) ? src[rbase[r] * M + c] : mk<C>(0, 0);
+  // every load of a thread is issued before the first LDS write (RPB * M values, M / T per thread)
+  constexpr int K = M / RC::T;
+  C ld[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int e = tid + j * NT, r = e / M, c = e - r * M;
+    ld[j] = mk<C>(0, 0);
+    if ((rseg[r] >> (c >> rl.seg_log2)) & 1ull) ld[j] = src[rbase[r] * M + c];
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int e = tid + j * NT, r = e / M, c = e - r * M;
+    lds[r * RC::LS + c] = ld[j];
   }
   __syncthreads();
   const int row = tid / RC::T, i = tid - row * RC::T;
@@ -240,13 +263,21 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
     for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
-  for (int e = tid; e < nvalid * (M + 1); e += NT) {
-    const int r = e / (M + 1), k = e - r * (M + 1);
-    const C zk = lds[r * RC::LS + (k == M ? 0 : k)];
-    const C zm = lds[r * RC::LS + (k == 0 ? 0 : M - k)];
-    const C E = mk<C>((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
-    const C O = mk<C>((zk.y + zm.y) * (T)0.5, -(zk.x - zm.x) * (T)0.5);
-    out[rbase[r] * pitch + k] = cadd(E, cmul(tw[k], O));
+  constexpr int KO = (M + 1 + RC::T - 1) / RC::T;   // M + 1 outputs per row
+  C wk_[KO];
+#pragma unroll
+  for (int j = 0; j < KO; ++j) wk_[j] = tw[(tid + j * NT) % (M + 1)];   // twiddles first, loads together
+#pragma unroll
+  for (int j = 0; j < KO; ++j) {
+    const int e = tid + j * NT;
+    if (e < nvalid * (M + 1)) {
+      const int r = e / (M + 1), k = e - r * (M + 1);
+      const C zk = lds[r * RC::LS + (k == M ? 0 : k)];
+      const C zm = lds[r * RC::LS + (k == 0 ? 0 : M - k)];
+      const C E = mk<C>((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
+      const C O = mk<C>((zk.y + zm.y) * (T)0.5, -(zk.x - zm.x) * (T)0.5);
+      out[rbase[r] * pitch + k] = cadd(E, cmul(wk_[j], O));
+    }
   }
 }
 
@@ -266,23 +297,44 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   __shared__ int64_t rbase[kBlock];
   for (int r = tid; r < RPB; r += NT) rbase[r] = r < nvalid ? rl.row(row0 + r) : 0;
   __syncthreads();
-  for (int e = tid; e < RPB * (M + 1); e += NT) {
-    const int r = e / (M + 1), k = e - r * (M + 1);
-    lds[e] = (r < nvalid) ? in[rbase[r] * pitch + k] : mk<C>(0, 0);
+  // every load of a thread is issued before the first LDS write
+  constexpr int KI = (M + 1 + RC::T - 1) / RC::T;
+  C ld[KI];
+#pragma unroll
+  for (int j = 0; j < KI; ++j) {
+    const int e = tid + j * NT, r = e / (M + 1), k = e - r * (M + 1);
+    ld[j] = mk<C>(0, 0);
+    if (e < RPB * (M + 1) && r < nvalid) ld[j] = in[rbase[r] * pitch + k];
+  }
+#pragma unroll
+  for (int j = 0; j < KI; ++j) {
+    const int e = tid + j * NT;
+    if (e < RPB * (M + 1)) lds[e] = ld[j];
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{M-k}) + i conj(W^k) (X_k - conj X_{M-k}); each thread owns a pair (k, M-k)
-  constexpr int HP = M / 2 + 1;
-  for (int e = tid; e < nvalid * HP; e += NT) {
-    const int r = e / HP, k = e - r * HP;
-    C* rowp = lds + r * RC::LS;
-    const C a = rowp[k], b = rowp[M - k];
-    const C wk = cconj(tw[k]), wm = cconj(tw[M - k]);
-    const C za = cadd(mk<C>(a.x + b.x, a.y - b.y), cmul(mk<C>(-wk.y, wk.x), mk<C>(a.x - b.x, a.y + b.y)));
-    rowp[k] = za;
-    if (k != 0 && 2 * k != M) {
-      const C zb = cadd(mk<C>(b.x + a.x, b.y - a.y), cmul(mk<C>(-wm.y, wm.x), mk<C>(b.x - a.x, b.y + a.y)));
-      rowp[M - k] = zb;
+  constexpr int HP = M / 2 + 1, KP = (HP + RC::T - 1) / RC::T;
+  C wk_[KP], wm_[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {   // twiddles first: their loads are issued together
+    const int k = (tid + j * NT) % HP;
+    wk_[j] = cconj(tw[k]);
+    wm_[j] = cconj(tw[M - k]);
+  }
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int e = tid + j * NT;
+    if (e < nvalid * HP) {
+      const int r = e / HP, k = e - r * HP;
+      C* rowp = lds + r * RC::LS;
+      const C a = rowp[k], b = rowp[M - k];
+      const C wk = wk_[j], wm = wm_[j];
+      const C za = cadd(mk<C>(a.x + b.x, a.y - b.y), cmul(mk<C>(-wk.y, wk.x), mk<C>(a.x - b.x, a.y + b.y)));
+      rowp[k] = za;
+      if (k != 0 && 2 * k != M) {
+        const C zb = cadd(mk<C>(b.x + a.x, b.y - a.y), cmul(mk<C>(-wm.y, wm.x), mk<C>(b.x - a.x, b.y + a.y)));
+        rowp[M - k] = zb;
+      }
     }
   }
   __syncthreads();
@@ -297,9 +349,13 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   }
   __syncthreads();
   C* dst = reinterpret_cast<C*>(out);
-  for (int e = tid; e < nvalid * M; e += NT) {
-    const int r = e / M, c = e - r * M;
-    dst[rbase[r] * M + c] = lds[r * RC::LS + c];
+#pragma unroll
+  for (int j = 0; j < M / RC::T; ++j) {
+    const int e = tid + j * NT;
+    if (e < nvalid * M) {
+      const int r = e / M, c = e - r * M;
+      dst[rbase[r] * M + c] = lds[r * RC::LS + c];
+    }
   }
 }
 

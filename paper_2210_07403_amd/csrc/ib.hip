@@ -164,6 +164,18 @@ __global__ void k_wtab(const double* __restrict__ wt, int64_t n_ib, cplx<T>* __r
   tab[e] = t < 6 ? mk<cplx<T>>((T)wt[r * 12 + t], (T)wt[r * 12 + 6 + t]) : mk<cplx<T>>((T)0, (T)0);
 }
 
+// busy tiles along x of each tile strip as a bit mask (strip s holds tiles s * ntx + t, t < ntx)
+__global__ void k_segments(const int* __restrict__ tile_off, int ntx, int64_t nstrips, unsigned long long* seg) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nstrips) return;
+  unsigned long long m = 0;
+  for (int t = 0; t < ntx; ++t) {
+    const int64_t id = s * ntx + t;
+    if (tile_off[id + 1] > tile_off[id]) m |= 1ull << t;
+  }
+  seg[s] = m;
+}
+
 // ids of the tiles with at least one candidate, in increasing order (off is the exclusive scan of
 // the 0/1 flags computed by k_busy_flags)
 __global__ void k_busy_flags(const int* __restrict__ cnt, int* __restrict__ flag, int n) {
@@ -781,6 +793,14 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
                        tile_cur, list_tmp, pid);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_sort_tiles, dim3(ntile), dim3(256), 0, st, tile_off, list_tmp, list);
+  IBDL_LAUNCH_CHECK();
+}
+
+void markers_segments(const MarkerGeom& g, const int* tile_off, unsigned long long* seg, hipStream_t st) {
+  if (g.ntile[0] > 64) throw Error(-2, "markers_segments: more than 64 tiles along x");
+  const int64_t nstrips = (int64_t)g.ntile[1] * (g.dim == 3 ? g.ntile[2] : 1);
+  hipLaunchKernelGGL(k_segments, dim3((unsigned)((nstrips + 255) / 256)), dim3(256), 0, st, tile_off, g.ntile[0],
+                     nstrips, seg);
   IBDL_LAUNCH_CHECK();
 }
 

@@ -57,6 +57,7 @@ struct ibdl_s {
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
   int *busy = nullptr, *busy_off = nullptr;
   int nbusy = 0;
+  unsigned long long* seg = nullptr;   // busy x-segments of each tile strip (RowList::seg)
   // active rows (rows of the markers' windows): list for the x passes, per-plane limits for y
   int *row_lo = nullptr, *row_hi = nullptr, *row_cnt = nullptr, *row_off = nullptr, *rows = nullptr;
   int2* row_lim = nullptr;
@@ -276,7 +277,7 @@ enum RowsMode { ROWS_DENSE = 0, ROWS_SPARSE = 1, ROWS_OUT = 2 };
 
 template <typename T>
 void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md,
-              int rows = ROWS_DENSE) {
+              int rows = ROWS_DENSE, bool busy_only = false) {
   const int64_t rows_per_field = h->ntot / h->n[0];
   const bool sin = rows == ROWS_SPARSE, sout = rows != ROWS_DENSE;
   RowList rl_in, rl_out;
@@ -286,6 +287,14 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
     rl_out.nact = h->nact;
     rl_out.rpf = rows_per_field;
     if (sin) rl_in = rl_out;
+    if (sin && busy_only) {   // src holds a spread's output: only its busy tiles were written
+      rl_in.seg = h->seg;
+      rl_in.seg_ny = h->n[1];
+      rl_in.seg_ty = h->geom.tile[1];
+      rl_in.seg_tz = h->dim == 3 ? h->geom.tile[2] : 1;
+      rl_in.seg_nsy = h->geom.ntile[1];
+      rl_in.seg_log2 = __builtin_ctz((unsigned)h->geom.tile[0] / 2);
+    }
     if (h->dim == 3) {
       fwd.lim = inv.lim = h->row_lim;
       fwd.nplanes = inv.nplanes = h->n[2];
@@ -431,7 +440,9 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
   // FD: the mass term of the fused field carries eta q and m; a forcing is subtracted afterwards
   a.mass = pl.mode == SP_FDDIV ? ((h->cfg.eta > 0 || m != nullptr) ? 1 : 0) : (mass ? 1 : 0);
   a.m = m;
-  clear_fields<T>(h, W.real, pl.nf, sparse);
+  // sparse without forcing: the x pass reads the spread's busy tiles only, nothing to clear
+  const bool busy_only = sparse && g == nullptr;
+  if (!busy_only) clear_fields<T>(h, W.real, pl.nf, sparse);
   {
     StageTimer t(h, ST_SPREAD);
     spread_w<T>(h, a, W, W.real);
@@ -441,7 +452,7 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
     else if (pl.mode == SP_FDDIV) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
     else grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
   }
-  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse ? ROWS_SPARSE : ROWS_DENSE);
+  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse ? ROWS_SPARSE : ROWS_DENSE, busy_only);
 }
 
 // Launch shapes of the apply's FFT passes by measurement: rows per block of the x passes, lines
@@ -604,7 +615,8 @@ int adj_nout(ibdl_s* h) {
   return h->dim + (h->cfg.eta > 0 ? 1 : 0);
 }
 
-template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst, bool sparse = false) {
+template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst, bool sparse = false,
+                                    bool busy_only = false) {
   MultDesc md = base_desc<T>(h, W);
   const int nout = adj_nout(h);
   md.alpha = 1.0;
@@ -618,7 +630,7 @@ template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* 
     md.nc = 1;
     md.fk[0] = FK_MASS;
   }
-  pipeline<T>(h, W, src, md.nc, dst, nout, md, sparse ? ROWS_SPARSE : ROWS_DENSE);
+  pipeline<T>(h, W, src, md.nc, dst, nout, md, sparse ? ROWS_SPARSE : ROWS_DENSE, busy_only);
 }
 
 void ensure_adj(ibdl_s* h) {
@@ -647,12 +659,11 @@ template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
   ensure_adj(h);
   SpreadArgs a = spread_args(h, SP_PLAIN, h->nq, p);
   a.raw = 1;
-  clear_fields<T>(h, W.real, h->nq, true);
   {
     StageTimer t(h, ST_SPREAD);
     spread_w<T>(h, a, W, W.real);
   }
-  adj_grid<T>(h, W, W.real, W.real, true);
+  adj_grid<T>(h, W, W.real, W.real, true, true);
   const double half = h->neumann() ? -0.5 : 0.5;
   const double* pu = h->has_ubar ? p + h->n_ib * h->nq : nullptr;
   adj_markers<T>(h, W, p, half, pu, y);
@@ -926,6 +937,7 @@ void build_markers(ibdl_s* h) {
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
               h->busy_off, h->st);
+  markers_segments(h->geom, h->tile_off, h->seg, h->st);
   markers_rows(h->geom, h->n_ib, h->s, h->row_lo, h->row_hi, h->row_cnt, h->row_off, h->row_lim, h->rows, h->st);
   const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
   const int nplanes = h->dim == 3 ? h->n[2] : 1;
@@ -1007,6 +1019,7 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->tile_cur = (int*)h->dalloc<int>(sizeof(int) * ntile);
     h->busy = (int*)h->dalloc<int>(sizeof(int) * ntile);
     h->busy_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
+    h->seg = (unsigned long long*)h->dalloc<unsigned long long>(sizeof(unsigned long long) * (ntile / g.ntile[0]));
     h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     const int nplanes = h->dim == 3 ? h->n[2] : 1;

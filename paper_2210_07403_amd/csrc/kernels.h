@@ -17,11 +17,23 @@ enum FieldKind {
 // Rows (x-lines, index z * ny + y within a field) that carry data.  A spread field is zero outside
 // the rows its markers' windows meet, and the interpolation reads only those rows, so the x passes
 // can run over a list of them and the y passes can skip the loads / stores of the others.
+// A spread also writes every node of each tile that a marker window meets (its busy tiles) and
+// nothing else, so with seg set the forward x pass reads only the busy x-segments of a row and takes
+// the others as zero: seg[strip] has bit t set when x-segment t (2^seg_log2 complex values, one
+// tile wide) of the tile strip (y / seg_ty, z / seg_tz) is busy.  The fields need no clearing then.
 struct RowList {
   const int* rows = nullptr;   // active rows of one field, increasing (NULL: every row)
   int64_t nact = 0;            // active rows per field
   int64_t rpf = 0;             // rows per field
+  const unsigned long long* seg = nullptr;   // busy x-segments per tile strip (NULL: read everything)
+  int seg_ny = 1, seg_ty = 1, seg_tz = 1, seg_nsy = 1, seg_log2 = 3;
   __device__ int64_t row(int64_t r) const { return rows ? (int64_t)rows[r % nact] + (r / nact) * rpf : r; }
+  __device__ unsigned long long segmask(int64_t r) const {
+    if (!seg) return ~0ull;
+    const int w = rows ? rows[r % nact] : (int)(r % rpf);   // row z * ny + y within its field
+    const int y = w % seg_ny, z = w / seg_ny;
+    return seg[y / seg_ty + (int64_t)seg_nsy * (z / seg_tz)];
+  }
 };
 struct RowMask {
   const int2* lim = nullptr;   // per plane z: rows y in [lim.x, lim.y] matter (NULL: all)
@@ -111,6 +123,9 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
                  int* tile_off, int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off,
                  hipStream_t st, const int* pid = nullptr, int nprob = 1);
+
+// seg[strip] = bit mask of the busy tiles along x of each tile strip (ntile[0] <= 64)
+void markers_segments(const MarkerGeom& g, const int* tile_off, unsigned long long* seg, hipStream_t st);
 
 // Active rows of the markers' windows: lo/hi [planes] (scratch), cnt/off [planes + 1] (scratch),
 // lim [planes] = (lo, hi) per plane, rows = the row list (up to ny * planes entries), increasing;
