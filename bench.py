@@ -49,9 +49,10 @@ def workload(name):
 
 def stage_cost(spec, prec, pr):
     """Algorithmic cost per launch of each stage of one operator apply: HBM bytes for the
-    memory-bound passes (the x passes and the zero fill touch only the rows the markers' windows
-    meet; the forward y pass reads only those rows, the inverse writes only those), floating-point
-    operations for the spread (a per-tile contraction on the matrix cores)."""
+    memory-bound passes (the x passes touch only the rows the markers' windows meet, the forward
+    one only their busy tile segments; the forward y pass reads only those rows, the inverse
+    writes only those), floating-point operations for the spread (a per-tile contraction on the
+    matrix cores)."""
     t = 4 if prec == "mixed" else 8
     ntot = pr.grid_points
     nxh = spec.n[0] // 2 + 1
@@ -63,9 +64,12 @@ def stage_cost(spec, prec, pr):
     c = 1 if scalar_fd else (5 if spec.pde == "stokes" else spec.dim + (1 if spec.eta > 0 else 0))
     o = pr.nq
     taps = 4 ** spec.dim
+    # the forward x pass reads only the busy tile segments of the active rows (the rest is zero)
+    _, nseg, tile = pr.spread_tiles()
+    Rb = nseg * tile[0] * t
     b = {
         "fill": ("hbm", c * Ra),
-        "fft_x_fwd": ("hbm", c * (Ra + Ca)),
+        "fft_x_fwd": ("hbm", c * (Rb + Ca)),
         "fft_x_inv": ("hbm", o * (Ca + Ra)),
         "interp": ("hbm", spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2)),
     }

@@ -210,6 +210,12 @@ ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t
  * others and the interpolation does not read them.  Either pointer may be NULL. */
 ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total);
 
+/* Tiling of the spread: nbusy = tiles (tile[0] x tile[1] (x tile[2]) nodes) that a marker window
+ * meets, which the spread writes whole; segments_read = (active row, busy tile) pairs, i.e. the
+ * tile[0]-node row segments the operator apply's forward x pass reads per spread field (it takes
+ * every other value of an active row as zero).  Any pointer may be NULL. */
+ibdl_status_t ibdl_spread_tiles(ibdl_t h, int64_t* nbusy, int64_t* segments_read, int32_t* tile);
+
 /* Launch shapes of the operator apply's FFT passes in the working precision, chosen by timing at
  * the first apply (rows per block of the x passes, lines per block of the y passes and of the fused
  * last-axis pass; 0 = not measured yet, the largest shape is used).  Any pointer may be NULL. */

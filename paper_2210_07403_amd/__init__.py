@@ -192,6 +192,13 @@ class Problem:
         B.check(B.load().ibdl_active_rows(self._h, ctypes.byref(a), ctypes.byref(t)), self._h)
         return int(a.value), int(t.value)
 
+    def spread_tiles(self):
+        """(busy tiles, busy row segments the apply's forward x pass reads per field, tile shape)."""
+        nb, ns = ctypes.c_int64(), ctypes.c_int64()
+        t = (ctypes.c_int32 * 3)()
+        B.check(B.load().ibdl_spread_tiles(self._h, ctypes.byref(nb), ctypes.byref(ns), t), self._h)
+        return int(nb.value), int(ns.value), tuple(int(v) for v in t)
+
     def launch_shape(self):
         """Measured launch shapes of the apply's FFT passes: (rows per block, y lines, last-axis lines)."""
         r, y, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

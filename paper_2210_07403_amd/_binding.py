@@ -64,6 +64,7 @@ _SIGS = {
     "ibdl_last_error": (ctypes.c_char_p, [c_void_p]),
     "ibdl_set_timing": (c_int32, [c_void_p, c_int32]),
     "ibdl_set_graph": (c_int32, [c_void_p, c_int32]),
+    "ibdl_spread_tiles": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ibdl_get_timing": (c_int32, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int64), c_int32]),
 }
 

@@ -62,6 +62,7 @@ struct ibdl_s {
   int *row_lo = nullptr, *row_hi = nullptr, *row_cnt = nullptr, *row_off = nullptr, *rows = nullptr;
   int2* row_lim = nullptr;
   int64_t nact = 0;
+  int64_t seg_read = 0;       // (active row, busy x-segment) pairs the apply's forward x pass reads
   int lim2d[2] = {0, -1};     // 2-D: the one plane's limits, on the host
   MarkerGeom geom{};
   std::unique_ptr<GridWork<float>> w32;
@@ -951,6 +952,20 @@ void build_markers(ibdl_s* h) {
   h->nact = na;
   h->lim2d[0] = l2.x;
   h->lim2d[1] = l2.y;
+  {   // count the busy x-segments of the active rows (reported by ibdl_spread_tiles)
+    const int64_t nstrips = ntile / h->geom.ntile[0];
+    std::vector<int> rows(na);
+    std::vector<unsigned long long> seg(nstrips);
+    if (na > 0) IBDL_HIP(hipMemcpy(rows.data(), h->rows, sizeof(int) * na, hipMemcpyDeviceToHost));
+    IBDL_HIP(hipMemcpy(seg.data(), h->seg, sizeof(unsigned long long) * nstrips, hipMemcpyDeviceToHost));
+    int64_t cnt = 0;
+    for (int w : rows) {
+      const int y = w % h->n[1], z = w / h->n[1];
+      const int64_t strip = y / h->geom.tile[1] + (int64_t)h->geom.ntile[1] * (h->dim == 3 ? z / h->geom.tile[2] : 0);
+      cnt += __builtin_popcountll(seg[strip]);
+    }
+    h->seg_read = cnt;
+  }
   if (h->w32 && h->w32->wtab) weight_table<float>(h->wt, h->n_ib, h->w32->wtab, h->st);
   if (h->w64 && h->w64->wtab) weight_table<double>(h->wt, h->n_ib, h->w64->wtab, h->st);
 }
@@ -1299,6 +1314,15 @@ ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total) {
   if (!h) return IBDL_ERR_ARG;
   if (nact) *nact = h->nact;
   if (rows_total) *rows_total = h->ntot / h->n[0];
+  return IBDL_OK;
+}
+
+ibdl_status_t ibdl_spread_tiles(ibdl_t h, int64_t* nbusy, int64_t* segments_read, int32_t* tile) {
+  if (!h) return IBDL_ERR_ARG;
+  if (nbusy) *nbusy = h->nbusy;
+  if (segments_read) *segments_read = h->seg_read;
+  if (tile)
+    for (int d = 0; d < 3; ++d) tile[d] = h->geom.tile[d];
   return IBDL_OK;
 }
 

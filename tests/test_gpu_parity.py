@@ -249,3 +249,63 @@ def test_gmres_graph_replays_match_direct_launches(name, precision):
             assert np.array_equal(to_np(dX1), dX0), rep
             assert np.array_equal(to_np(dd1), dd0), rep
     pr.close()
+
+
+def _tiles_reference(spec):
+    """Busy tiles, active rows and busy row segments from the markers' 6-node windows (node
+    s = floor((x - origin) / h) - 2 and the five after it on each axis, periodic)."""
+    n = spec.n
+    dim = spec.dim
+    h = spec.L[0] / n[0]
+    X = np.asarray(spec.markers.X, dtype=np.float64)
+    xi = (X - np.asarray(spec.origin)) / h
+    xi = xi - np.asarray(n) * np.floor(xi / np.asarray(n))
+    s = (np.floor(xi).astype(np.int64) - 2) % np.asarray(n)
+    tile = (16, 4, 8) if dim == 3 else (16, 16)
+    nt = [n[d] // tile[d] for d in range(dim)]
+    busy = np.zeros(tuple(reversed(nt)), dtype=bool)     # [tz][ty][tx] or [ty][tx]
+    nplanes = n[2] if dim == 3 else 1
+    lo = np.full(nplanes, n[1], dtype=np.int64)
+    hi = np.full(nplanes, -1, dtype=np.int64)
+    off = np.arange(6)
+    for m in range(len(X)):
+        nodes = [(s[m, d] + off) % n[d] for d in range(dim)]
+        tiles = [np.unique(nodes[d] // tile[d]) for d in range(dim)]
+        if dim == 3:
+            busy[np.ix_(tiles[2], tiles[1], tiles[0])] = True
+            for z in nodes[2]:
+                lo[z] = min(lo[z], nodes[1].min())
+                hi[z] = max(hi[z], nodes[1].max())
+        else:
+            busy[np.ix_(tiles[1], tiles[0])] = True
+            lo[0] = min(lo[0], nodes[1].min())
+            hi[0] = max(hi[0], nodes[1].max())
+    nact, nseg = 0, 0
+    for z in range(nplanes):
+        for y in range(lo[z], hi[z] + 1):
+            nact += 1
+            nseg += int(busy[z // tile[2], y // tile[1]].sum()) if dim == 3 else int(busy[y // tile[1]].sum())
+    return int(busy.sum()), nact, nseg, tile
+
+
+@pytest.mark.parametrize("name", ["sphere_3d", "helmholtz_fd", "stokes_exterior"])
+def test_spread_tiles_and_active_rows(name):
+    """The tile binning and the row bookkeeping the apply's x passes rely on, recounted on the host."""
+    spec = OPERATORS[name]()
+    pr = make_problem(spec, "mixed")
+    nbusy, nact, nseg, tile = _tiles_reference(spec)
+    got_busy, got_seg, got_tile = pr.spread_tiles()
+    assert got_tile[:spec.dim] == tile
+    assert (got_busy, pr.active_rows()[0], got_seg) == (nbusy, nact, nseg)
+    pr.close()
+
+
+def test_spread_tiles_seam_crossing():
+    """Markers on and across the periodic seams (windows that wrap) in 3-D."""
+    X, nrm, ds = _markers(3, (32, 16, 16), (2.0, 1.0, 1.0), (0.0, -0.5, 0.0), 517, 5)
+    spec = _spec_like(3, (32, 16, 16), (2.0, 1.0, 1.0), (0.0, -0.5, 0.0), X, nrm, ds)
+    pr = make_problem(spec, "fp64")
+    nbusy, nact, nseg, _ = _tiles_reference(spec)
+    got_busy, got_seg, _ = pr.spread_tiles()
+    assert (got_busy, pr.active_rows()[0], got_seg) == (nbusy, nact, nseg)
+    pr.close()
