@@ -87,13 +87,14 @@ __device__ __forceinline__ void dft(C* x) {
   }
 }
 
-template <int N, int S, bool INV, typename C>
+// BATCH (a table in global memory): all twiddles of the stage are loaded before the first is used,
+// so that their loads are in flight together rather than one latency each; a table staged in LDS
+// is read as it is used.
+template <int N, int S, bool INV, bool BATCH, typename C>
 __device__ __forceinline__ void stage_compute(C* v, int i, const C* __restrict__ tw, int tws) {
   using P = Plan<N>;
   constexpr int R = P::radix(S), PP = P::pw(S), NB = P::RMAX / R, TT = P::T;
   if constexpr (PP > 1) {
-    // all twiddles of the stage are loaded before the first is used, so that their loads are in
-    // flight together rather than one latency each
     C w[NB][R];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -101,7 +102,7 @@ __device__ __forceinline__ void stage_compute(C* v, int i, const C* __restrict__
 #pragma unroll
       for (int j = 1; j < R; ++j) w[m][j] = tw[(j * k * (N / (PP * R))) * tws];
     }
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (BATCH) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 0; m < NB; ++m)
 #pragma unroll
@@ -140,46 +141,55 @@ __device__ __forceinline__ void line_load(C* v, int i, const C* lds, int es) {
   for (int s = 0; s < Plan<N>::RMAX; ++s) v[s] = lds[(i + s * Plan<N>::T) * es];
 }
 
-// Global loads / stores of a line's register elements i + s*T (element stride es from base, 32-bit
-// offsets: a field never holds 2^31 values here).  One validity branch per line; the row mask is
-// uniform across the launch, so its test is a scalar branch around the masked form.
+// Global loads / stores of a line's register elements i + s*T: element o0 + (i + s*T) * es of the
+// launch-uniform array base.  Addresses are base plus a 32-bit byte offset (the launchers check
+// that no launch spans 4 GiB), i.e. a scalar base and one 32-bit register per access.  One
+// validity branch per line; the row mask is uniform across the launch, so its test is a scalar
+// branch around the masked form.
+template <typename C> __device__ __forceinline__ const C& at(const C* base, unsigned byte) {
+  return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(base) + (size_t)byte);
+}
+template <typename C> __device__ __forceinline__ C& at(C* base, unsigned byte) {
+  return *reinterpret_cast<C*>(reinterpret_cast<char*>(base) + (size_t)byte);
+}
+
 template <int N, typename C>
-__device__ __forceinline__ void line_gload(C* v, const C* __restrict__ base, int i, int es, bool valid,
-                                           const RowMask& m) {
+__device__ __forceinline__ void line_gload(C* v, const C* __restrict__ base, unsigned o0, unsigned es, int i,
+                                           bool valid, const RowMask& m) {
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
   if (!valid) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) v[s] = mk<C>(0, 0);
     return;
   }
-  const C* p = base + i * es;
+  const unsigned b0 = (o0 + (unsigned)i * es) * (unsigned)sizeof(C), step = TT * es * (unsigned)sizeof(C);
   if (m.load) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
       const int y = i + s * TT;
-      v[s] = (y >= m.lo && y <= m.hi) ? p[s * TT * es] : mk<C>(0, 0);
+      v[s] = (y >= m.lo && y <= m.hi) ? at(base, b0 + s * step) : mk<C>(0, 0);
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < RM; ++s) v[s] = p[s * TT * es];
+    for (int s = 0; s < RM; ++s) v[s] = at(base, b0 + s * step);
   }
 }
 
 template <int N, typename C>
-__device__ __forceinline__ void line_gstore(const C* v, C* __restrict__ base, int i, int es, bool valid,
-                                            const RowMask& m) {
+__device__ __forceinline__ void line_gstore(const C* v, C* __restrict__ base, unsigned o0, unsigned es, int i,
+                                            bool valid, const RowMask& m) {
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
   if (!valid) return;
-  C* p = base + i * es;
+  const unsigned b0 = (o0 + (unsigned)i * es) * (unsigned)sizeof(C), step = TT * es * (unsigned)sizeof(C);
   if (m.store) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
       const int y = i + s * TT;
-      if (y >= m.lo && y <= m.hi) p[s * TT * es] = v[s];
+      if (y >= m.lo && y <= m.hi) at(base, b0 + s * step) = v[s];
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < RM; ++s) p[s * TT * es] = v[s];
+    for (int s = 0; s < RM; ++s) at(base, b0 + s * step) = v[s];
   }
 }
 
@@ -191,36 +201,45 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // Full line transform on registers v (pattern i + s*T).  All threads of the block must call it
 // (it contains block barriers when N needs more than one stage).  lds: this line's exchange
 // buffer with element stride es; the caller must not rely on its contents afterwards.
-template <int N, bool INV, int S = 0, typename C>
+template <int N, bool INV, bool BATCH = false, int S = 0, typename C>
 __device__ __forceinline__ void fft_line(C* v, int i, C* lds, int es, const C* __restrict__ tw, int tws) {
   if constexpr (S < Plan<N>::NST) {
-    stage_compute<N, S, INV>(v, i, tw, tws);
+    stage_compute<N, S, INV, BATCH>(v, i, tw, tws);
     if constexpr (S + 1 < Plan<N>::NST) {
       __syncthreads();
       stage_store<N, S>(v, i, lds, es);
       __syncthreads();
       line_load<N>(v, i, lds, es);
     }
-    fft_line<N, INV, S + 1>(v, i, lds, es, tw, tws);
+    fft_line<N, INV, BATCH, S + 1>(v, i, lds, es, tw, tws);
   }
+}
+
+// copy the twiddle table (n entries) into LDS at dst; the first read follows a block barrier
+template <typename C>
+__device__ __forceinline__ const C* stage_table(C* dst, const C* __restrict__ tw, int n, int tid, int nthr) {
+  for (int e = tid; e < n; e += nthr) dst[e] = tw[e];
+  return dst;
 }
 
 constexpr int pow2floor(int v) { return v >= 2 ? 2 * pow2floor(v / 2) : 1; }
 
-// rows per block of the x-axis passes: as many as fit 256 threads and 64 KiB of LDS
+// rows per block of the x-axis passes: as many as fit 256 threads and 64 KiB of LDS beside the
+// twiddle table
 template <typename TR, int M> struct RowCfg {
   static constexpr int T = Plan<M>::T;
   static constexpr int LS = M + 1;  // LDS row stride (complex elements)
   static constexpr int R0 = kBlock / T;
-  static constexpr int RL = pow2floor(kLdsBytes / (LS * (int)sizeof(cplx<TR>)));
+  static constexpr int RL = pow2floor((kLdsBytes - 2 * M * (int)sizeof(cplx<TR>)) / (LS * (int)sizeof(cplx<TR>)));
   static constexpr int RPB = (R0 < RL ? R0 : RL) > 0 ? (R0 < RL ? R0 : RL) : 1;
   static constexpr int NT = RPB * T;  // threads per block
+  static_assert((RPB * LS + 2 * M) * (int)sizeof(cplx<TR>) <= 65536, "x pass: LDS over 64 KiB");
 };
 
 // ------------------------------------------------------------------ x axis, forward R2C
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB,
+                                                  int64_t nrows, const cplx<T>* __restrict__ twg, int RPB,
                                                   RowList rl, int64_t pitch) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
@@ -228,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
   const int NT = RPB * RC::T;
+  const C* tw = stage_table(lds + RPB * RC::LS, twg, 2 * M, tid, NT);
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   __shared__ int64_t rbase[kBlock];   // row index of each block row (active-row list or contiguous)
@@ -284,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
 // ------------------------------------------------------------------ x axis, inverse C2R
 template <typename T, int M>
 __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
-                                                  int64_t nrows, const cplx<T>* __restrict__ tw, int RPB,
+                                                  int64_t nrows, const cplx<T>* __restrict__ twg, int RPB,
                                                   RowList rl, int64_t pitch) {
   using C = cplx<T>;
   using RC = RowCfg<T, M>;
@@ -292,6 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
   const int NT = RPB * RC::T;
+  const C* tw = stage_table(lds + RPB * RC::LS, twg, 2 * M, tid, NT);
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   __shared__ int64_t rbase[kBlock];
@@ -366,27 +387,31 @@ template <typename T, int N> struct TileCfg {
   static constexpr int WL = kLdsBytes / (N * (int)sizeof(cplx<T>));
   static constexpr int W = (W0 < WL ? W0 : WL) > 0 ? (W0 < WL ? W0 : WL) : 1;
   static constexpr int NT = W * T_;  // threads per block
+  // twiddles staged in LDS when the table fits beside the widest tile (all but 1024 in double)
+  static constexpr bool TWL = (W * N + N) * (int)sizeof(cplx<T>) <= 65536;
 };
 
 // ------------------------------------------------------------------ strided in-place C2C
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
-                                                    int64_t outer, int64_t es, const cplx<T>* __restrict__ tw,
+                                                    int64_t outer, int64_t es, const cplx<T>* __restrict__ twg,
                                                     int W, RowMask rm, int64_t vinner) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
   const int c = tid & (W - 1), i = tid / W;
-  const int64_t l = (int64_t)blockIdx.x * W + c;
-  const bool valid = l < nlines && (l % inner) < vinner;
-  const int64_t base = valid ? (l / inner) * outer + (l % inner) : 0;
-  const RowMask pm = rm.plane(valid ? (l / inner) : 0);   // rows of this line's plane that matter
+  const unsigned l = blockIdx.x * (unsigned)W + c;
+  const unsigned lp = l / (unsigned)inner, li = l - lp * (unsigned)inner;
+  const bool valid = l < nlines && li < vinner;
+  const unsigned base = valid ? lp * (unsigned)outer + li : 0u;
+  const RowMask pm = rm.plane(valid ? lp : 0);   // rows of this line's plane that matter
   C v[Plan<N>::RMAX];
-  line_gload<N>(v, data + base, i, (int)es, valid, pm);
-  fft_line<N, INV>(v, i, lds + c, W, tw, 1);
-  line_gstore<N>(v, data + base, i, (int)es, valid, pm);
+  line_gload<N>(v, data, base, (unsigned)es, i, valid, pm);
+  fft_line<N, INV, !TC::TWL>(v, i, lds + c, W, tw, 1);
+  line_gstore<N>(v, data, base, (unsigned)es, i, valid, pm);
 }
 
 // ------------------------------------------------------------------ Fourier multiplier
@@ -424,7 +449,7 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
 
 template <typename T, int N, int NO, bool STOKES>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                  const cplx<T>* __restrict__ tw, int W, int64_t bstride, RowMask rm) {
+                                                  const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
@@ -432,8 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
   const int c = tid & (W - 1), i = tid / W;
-  const int64_t l = (int64_t)blockIdx.x * W + c;
+  const int l = blockIdx.x * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
   // mode indices of this line: 2-D l = jx, e = jy; 3-D l = jy*nxh + jx, e = jz
@@ -468,8 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 
   for (int f = 0; f < md.nc; ++f) {
     C v[RM];
-    line_gload<N>(v, data + f * FS + l, i, (int)P, valid, rm);
-    fft_line<N, false>(v, i, lds + c, W, tw, 1);
+    line_gload<N>(v, data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, false, !TC::TWL>(v, i, lds + c, W, tw, 1);
     const int fk = md.fk[f];
     if constexpr (!STOKES) {
       if (fk == FK_MASS) {
@@ -497,8 +523,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   }
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    fft_line<N, true>(acc[o], i, lds + c, W, tw, 1);
-    line_gstore<N>(acc[o], data + o * FS + l, i, (int)P, valid, rm);
+    fft_line<N, true, !TC::TWL>(acc[o], i, lds + c, W, tw, 1);
+    line_gstore<N>(acc[o], data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
   }
 }
 
@@ -506,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
 template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                   const cplx<T>* __restrict__ tw, int W, int64_t bstride, RowMask rm) {
+                                                   const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
@@ -514,8 +540,9 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
   const int c = tid & (W - 1), i = tid / W;
-  const int64_t l = (int64_t)blockIdx.x * W + c;
+  const int l = blockIdx.x * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int jx = (int)(valid ? l % md.nxp : 0);
   const int jy2 = (int)(valid ? l / md.nxp : 0);
@@ -524,16 +551,16 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
   if (d3) sig_l += static_cast<const T*>(md.sig[1])[jy2];
   C v[RM];
-  line_gload<N>(v, data + l, i, (int)P, valid, rm);
-  fft_line<N, false>(v, i, lds + c, W, tw, 1);
+  line_gload<N>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
+  fft_line<N, false, !TC::TWL>(v, i, lds + c, W, tw, 1);
   const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
 #pragma unroll
   for (int s = 0; s < RM; ++s) {
     const T den = c2 * (sig_l + sgl[i + s * TT]) - c0;
     v[s] = cscale(v[s], den == (T)0 ? (T)0 : num * recip(den));
   }
-  fft_line<N, true>(v, i, lds + c, W, tw, 1);
-  line_gstore<N>(v, data + l, i, (int)P, valid, rm);
+  fft_line<N, true, !TC::TWL>(v, i, lds + c, W, tw, 1);
+  line_gstore<N>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
 }
 
 // Transposed / multi-output pass: the NI input spectra stay in registers after their forward
@@ -541,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
 // all read before the first store, and each workgroup owns its lines in every field).
 template <typename T, int N, int NI, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data, int64_t P, int no, MultDesc md,
-                                                      const cplx<T>* __restrict__ tw, int W, int64_t bstride, RowMask rm) {
+                                                      const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
   constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
@@ -549,8 +576,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
   const int c = tid & (W - 1), i = tid / W;
-  const int64_t l = (int64_t)blockIdx.x * W + c;
+  const int l = blockIdx.x * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
   const int jx = (int)(valid ? l % md.nxp : 0);
@@ -571,8 +599,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   C v[NI][RM];
 #pragma unroll
   for (int f = 0; f < NI; ++f) {
-    line_gload<N>(v[f], data + f * FS + l, i, (int)P, valid, rm);
-    fft_line<N, false>(v[f], i, lds + c, W, tw, 1);
+    line_gload<N>(v[f], data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, false, !TC::TWL>(v[f], i, lds + c, W, tw, 1);
   }
   for (int o = 0; o < no; ++o) {
     C acc[RM];
@@ -593,8 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
         for (int f = 0; f < NI; ++f) acc[s] = cadd(acc[s], cmul(cconj(mult_coef<T>(md, md.fk[o], f, sig, kt)), v[f][s]));
       }
     }
-    fft_line<N, true>(acc, i, lds + c, W, tw, 1);
-    line_gstore<N>(acc, data + o * FS + l, i, (int)P, valid, rm);
+    fft_line<N, true, !TC::TWL>(acc, i, lds + c, W, tw, 1);
+    line_gstore<N>(acc, data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
   }
 }
 
@@ -649,7 +677,7 @@ void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* 
     using RC = RowCfg<T, M>;
     const int R = pick(rpb, RC::RPB);
     const int64_t nb = (nrows + R - 1) / R;
-    const size_t lds = sizeof(cplx<T>) * R * RC::LS;
+    const size_t lds = sizeof(cplx<T>) * (R * RC::LS + 2 * M);
     if (nb > 0)
       hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
                          pitch);
@@ -666,7 +694,7 @@ void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* 
     using RC = RowCfg<T, M>;
     const int R = pick(rpb, RC::RPB);
     const int64_t nb = (nrows + R - 1) / R;
-    const size_t lds = sizeof(cplx<T>) * R * RC::LS;
+    const size_t lds = sizeof(cplx<T>) * (R * RC::LS + 2 * M);
     if (nb > 0)
       hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
                          pitch);
@@ -678,12 +706,16 @@ template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es, bool inverse,
                  const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm, int64_t vinner) {
   if (vinner <= 0) vinner = inner;
+  if (nlines <= 0) return;
+  const int64_t span = ((nlines - 1) / inner) * outer + (inner - 1) + (int64_t)(n - 1) * es + 1;
+  if (span * (int64_t)sizeof(cplx<T>) > (int64_t)UINT32_MAX || nlines > INT32_MAX)
+    throw Error(-2, "strided FFT pass: one launch may not span 4 GiB");
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     using TC = TileCfg<T, N>;
     const int W = pick(w, TC::W);
     const int64_t nb = (nlines + W - 1) / W;
-    const size_t lds = sizeof(cplx<T>) * N * W;
+    const size_t lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
     const dim3 blk(W * TC::T_);
     if (inverse)
       hipLaunchKernelGGL((k_strided<T, N, true>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
@@ -699,12 +731,15 @@ template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw, hipStream_t s,
                     int batch, int64_t bstride, int w, const RowMask& rm) {
   if (batch < 1) return;
+  const int64_t nf = std::max<int64_t>(std::max(md.nc, no), 1);
+  if (nf * P * n * (int64_t)sizeof(cplx<T>) > (int64_t)UINT32_MAX || P > INT32_MAX)
+    throw Error(-2, "fused FFT pass: one problem's fields may not span 4 GiB");
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     using TC = TileCfg<T, N>;
     const int W = pick(w, TC::W);
     const int64_t nb = (P + W - 1) / W;
-    const size_t lds = sizeof(cplx<T>) * N * W;
+    const size_t lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
     const dim3 grid((unsigned)nb, (unsigned)batch), blk(W * TC::T_);
     if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1)
       hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
