@@ -40,7 +40,6 @@ template <typename T> struct GroupWork {
   T* real = nullptr;          // [problem][grid]
   cplx<T>* spec = nullptr;    // [problem][half spectrum]
   cplx<T>* wtab = nullptr;    // weight table in this precision
-  T* crec = nullptr;          // per-marker spread coefficients (scratch of the 3-D spread)
   Tuned tune;
   bool ready = false;
 };
@@ -58,7 +57,8 @@ struct Group {
   double *X = nullptr, *nrm = nullptr, *ds = nullptr, *f = nullptr, *wt = nullptr;
   int *s = nullptr, *pid = nullptr;
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
-  int *busy = nullptr, *busy_off = nullptr;
+  int4* busy = nullptr;
+  int* busy_off = nullptr;
   int nbusy = 0;
   GroupWork<float> w32;
   GroupWork<double> w64;
@@ -180,8 +180,6 @@ template <typename T> void group_density_to_grid(ibdl_batch_s* B, Group& G, Grou
   a.q = q;
   a.nrm = G.nrm;
   a.ds = G.ds;
-  a.nmark = G.nib;
-  a.crec = W.crec;
   spread<T>(a, W.wtab, W.real, B->st);
   group_pipeline<T>(B, G, W, W.tune);
 }
@@ -196,7 +194,6 @@ template <typename T> GroupWork<T>& group_work(ibdl_batch_s* B, Group& G) {
   W.real = (T*)B->dalloc(sizeof(T) * G.ntot * np);
   W.spec = (cplx<T>*)B->dalloc(sizeof(cplx<T>) * G.nspec * np);
   W.wtab = (cplx<T>*)B->dalloc(sizeof(cplx<T>) * G.nib * 24);
-  W.crec = (T*)B->dalloc(sizeof(T) * G.nib * 8);
   weight_table<T>(G.wt, G.nib, W.wtab, B->st);
   grid_fill_zero<T>(W.real, G.ntot * np, B->st);
   W.ready = true;
@@ -584,7 +581,7 @@ ibdl_status_t ibdl_batch_create(int32_t nprob, const ibdl_config_t* cfgs, const 
       G.tile_count = (int*)B->dalloc(sizeof(int) * ntile);
       G.tile_off = (int*)B->dalloc(sizeof(int) * (ntile + 1));
       G.tile_cur = (int*)B->dalloc(sizeof(int) * ntile);
-      G.busy = (int*)B->dalloc(sizeof(int) * ntile);
+      G.busy = (int4*)B->dalloc(sizeof(int4) * ntile);
       G.busy_off = (int*)B->dalloc(sizeof(int) * (ntile + 1));
       G.list = (int*)B->dalloc(sizeof(int) * maxlist);
       G.list_tmp = (int*)B->dalloc(sizeof(int) * maxlist);

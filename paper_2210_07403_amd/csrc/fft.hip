@@ -22,8 +22,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kLdsBytes = 65536;
 
-template <int N> struct Plan {
-  static constexpr int RMAX = (N <= 16) ? N : ((N == 32 || N == 64 || N == 512) ? 8 : 16);
+// Stockham plan of a length-N line: RMAX elements per thread (the radix of every stage but the last),
+// T = N / RMAX threads per line
+constexpr int plan_rmax(int N) { return (N <= 16) ? N : ((N == 32 || N == 64 || N == 512) ? 8 : 16); }
+template <int N, int RMX = plan_rmax(N)> struct Plan {
+  static constexpr int RMAX = RMX;
   static constexpr int T = N / RMAX;
   static constexpr int LR = ilog2c(RMAX);
   static constexpr int NFULL = ilog2c(N) / LR;
@@ -90,9 +93,9 @@ __device__ __forceinline__ void dft(C* x) {
 // BATCH (a table in global memory): all twiddles of the stage are loaded before the first is used,
 // so that their loads are in flight together rather than one latency each; a table staged in LDS
 // is read as it is used.
-template <int N, int S, bool INV, bool BATCH, typename C>
+template <int N, int S, bool INV, bool BATCH, int RMX, typename C>
 __device__ __forceinline__ void stage_compute(C* v, int i, const C* __restrict__ tw, int tws) {
-  using P = Plan<N>;
+  using P = Plan<N, RMX>;
   constexpr int R = P::radix(S), PP = P::pw(S), NB = P::RMAX / R, TT = P::T;
   if constexpr (PP > 1) {
     C w[NB][R];
@@ -122,9 +125,9 @@ __device__ __forceinline__ void stage_compute(C* v, int i, const C* __restrict__
   }
 }
 
-template <int N, int S, typename C>
+template <int N, int S, int RMX, typename C>
 __device__ __forceinline__ void stage_store(const C* v, int i, C* lds, int es) {
-  using P = Plan<N>;
+  using P = Plan<N, RMX>;
   constexpr int R = P::radix(S), PP = P::pw(S), NB = P::RMAX / R, TT = P::T;
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
@@ -135,10 +138,10 @@ __device__ __forceinline__ void stage_store(const C* v, int i, C* lds, int es) {
   }
 }
 
-template <int N, typename C>
+template <int N, int RMX, typename C>
 __device__ __forceinline__ void line_load(C* v, int i, const C* lds, int es) {
 #pragma unroll
-  for (int s = 0; s < Plan<N>::RMAX; ++s) v[s] = lds[(i + s * Plan<N>::T) * es];
+  for (int s = 0; s < RMX; ++s) v[s] = lds[(i + s * Plan<N, RMX>::T) * es];
 }
 
 // Global loads / stores of a line's register elements i + s*T: element o0 + (i + s*T) * es of the
@@ -201,17 +204,17 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // Full line transform on registers v (pattern i + s*T).  All threads of the block must call it
 // (it contains block barriers when N needs more than one stage).  lds: this line's exchange
 // buffer with element stride es; the caller must not rely on its contents afterwards.
-template <int N, bool INV, bool BATCH = false, int S = 0, typename C>
+template <int N, bool INV, bool BATCH = false, int RMX = plan_rmax(N), int S = 0, typename C>
 __device__ __forceinline__ void fft_line(C* v, int i, C* lds, int es, const C* __restrict__ tw, int tws) {
-  if constexpr (S < Plan<N>::NST) {
-    stage_compute<N, S, INV, BATCH>(v, i, tw, tws);
-    if constexpr (S + 1 < Plan<N>::NST) {
+  if constexpr (S < Plan<N, RMX>::NST) {
+    stage_compute<N, S, INV, BATCH, RMX>(v, i, tw, tws);
+    if constexpr (S + 1 < Plan<N, RMX>::NST) {
       __syncthreads();
-      stage_store<N, S>(v, i, lds, es);
+      stage_store<N, S, RMX>(v, i, lds, es);
       __syncthreads();
-      line_load<N>(v, i, lds, es);
+      line_load<N, RMX>(v, i, lds, es);
     }
-    fft_line<N, INV, BATCH, S + 1>(v, i, lds, es, tw, tws);
+    fft_line<N, INV, BATCH, RMX, S + 1>(v, i, lds, es, tw, tws);
   }
 }
 
@@ -226,8 +229,10 @@ constexpr int pow2floor(int v) { return v >= 2 ? 2 * pow2floor(v / 2) : 1; }
 
 // rows per block of the x-axis passes: as many as fit 256 threads and 64 KiB of LDS beside the
 // twiddle table
+constexpr int xrmax(int M) { return plan_rmax(M) < 8 ? plan_rmax(M) : 8; }   // elements per thread, x passes
 template <typename TR, int M> struct RowCfg {
-  static constexpr int T = Plan<M>::T;
+  static constexpr int RMX = xrmax(M);
+  static constexpr int T = Plan<M, RMX>::T;
   static constexpr int LS = M + 1;  // LDS row stride (complex elements)
   static constexpr int R0 = kBlock / T;
   static constexpr int RL = pow2floor((kLdsBytes - 2 * M * (int)sizeof(cplx<TR>)) / (LS * (int)sizeof(cplx<TR>)));
@@ -274,13 +279,13 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   }
   __syncthreads();
   const int row = tid / RC::T, i = tid - row * RC::T;
-  C v[Plan<M>::RMAX];
-  if (row < RPB) line_load<M>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, false>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
+  C v[RC::RMX];
+  if (row < RPB) line_load<M, RC::RMX>(v, i, lds + row * RC::LS, 1);
+  fft_line<M, false, false, RC::RMX>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
   if (row < RPB) {
 #pragma unroll
-    for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
+    for (int s = 0; s < RC::RMX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
   constexpr int KO = (M + 1 + RC::T - 1) / RC::T;   // M + 1 outputs per row
@@ -360,13 +365,13 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   }
   __syncthreads();
   const int row = tid / RC::T, i = tid - row * RC::T;
-  C v[Plan<M>::RMAX];
-  if (row < RPB) line_load<M>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, true>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
+  C v[RC::RMX];
+  if (row < RPB) line_load<M, RC::RMX>(v, i, lds + row * RC::LS, 1);
+  fft_line<M, true, false, RC::RMX>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
   if (row < RPB) {
 #pragma unroll
-    for (int s = 0; s < Plan<M>::RMAX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
+    for (int s = 0; s < RC::RMX; ++s) lds[row * RC::LS + i + s * RC::T] = v[s];
   }
   __syncthreads();
   C* dst = reinterpret_cast<C*>(out);

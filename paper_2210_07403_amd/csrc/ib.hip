@@ -164,16 +164,19 @@ __global__ void k_wtab(const double* __restrict__ wt, int64_t n_ib, cplx<T>* __r
   tab[e] = t < 6 ? mk<cplx<T>>((T)wt[r * 12 + t], (T)wt[r * 12 + 6 + t]) : mk<cplx<T>>((T)0, (T)0);
 }
 
-// busy tiles along x of each tile strip as a bit mask (strip s holds tiles s * ntx + t, t < ntx)
-__global__ void k_segments(const int* __restrict__ tile_off, int ntx, int64_t nstrips, unsigned long long* seg) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nstrips) return;
+// busy tiles along x of each listed row as a bit mask (tile (t, strip of the row) for t < ntx)
+__global__ void k_row_segments(MarkerGeom g, const int* __restrict__ tile_off, const int* __restrict__ rows,
+                               int64_t nact, unsigned long long* __restrict__ seg) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nact) return;
+  const int w = rows[r], y = w % g.n[1], z = w / g.n[1];
+  const int64_t strip = y / g.tile[1] + (int64_t)g.ntile[1] * (g.dim == 3 ? z / g.tile[2] : 0);
   unsigned long long m = 0;
-  for (int t = 0; t < ntx; ++t) {
-    const int64_t id = s * ntx + t;
+  for (int t = 0; t < g.ntile[0]; ++t) {
+    const int64_t id = strip * g.ntile[0] + t;
     if (tile_off[id + 1] > tile_off[id]) m |= 1ull << t;
   }
-  seg[s] = m;
+  seg[r] = m;
 }
 
 // ids of the tiles with at least one candidate, in increasing order (off is the exclusive scan of
@@ -182,9 +185,10 @@ __global__ void k_busy_flags(const int* __restrict__ cnt, int* __restrict__ flag
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flag[i] = cnt[i] > 0 ? 1 : 0;
 }
-__global__ void k_busy_ids(const int* __restrict__ cnt, const int* __restrict__ foff, int* __restrict__ busy, int n) {
+__global__ void k_busy_ids(const int* __restrict__ cnt, const int* __restrict__ foff, const int* __restrict__ off,
+                           int4* __restrict__ busy, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && cnt[i] > 0) busy[foff[i]] = i;
+  if (i < n && cnt[i] > 0) busy[foff[i]] = make_int4(i, off[i], off[i + 1], 0);
 }
 
 // sort each tile's marker list ascending (rank sort; marker indices in a tile are unique)
@@ -237,6 +241,24 @@ __device__ __forceinline__ void spread_coefs(const SpreadArgs& a, int m, int D, 
   }
 }
 
+// coefficient c of marker m: the value spread_coefs leaves in cf[c] (3-D modes)
+__device__ __forceinline__ double spread_coef(const SpreadArgs& a, int m, int D, double base, int c) {
+  if (a.mode == SP_PLAIN) return c < a.nf ? a.q[(int64_t)m * a.nf + c] * base : 0.0;
+  const double qm = a.q[m];
+  if (c < D) return qm * a.nrm[(int64_t)m * D + c] * base;
+  if (c == (a.mode == SP_FDDIV ? 3 : D)) return a.mass ? (a.eta * qm + (a.m ? a.m[m] : 0.0)) * base : 0.0;
+  return 0.0;
+}
+
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b to XCD b mod 8).  This renumbers them
+// so that each XCD takes a contiguous range of [0, n): neighbouring tiles, which share markers, then
+// share an L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_chunk(int b, int n) {
+  constexpr int X = 8;
+  const int x = b % X, j = b / X, q = n / X, r = n % X;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // Lanes used per wave for candidates in one pass (LDS budget: 32 KiB / 48 KiB per block).
 template <typename T> constexpr int spread_lanes() { return sizeof(T) == 4 ? 64 : 32; }
 
@@ -281,19 +303,6 @@ template <> struct Mfma<double> {
 
 constexpr int kSC = 64;   // candidates staged in LDS per pass (4 lanes each: a 256-thread block)
 
-// per-marker field coefficients (times ds h^-D unless raw), once per spread: a tile's staging then
-// reads one record per candidate instead of the density, normal and weight
-template <typename T>
-__global__ void k_marker_coefs(SpreadArgs a, T* __restrict__ rec, int64_t n_ib) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_ib) return;
-  const double hD = a.g.h * a.g.h * (a.g.dim == 3 ? a.g.h : 1.0);
-  double c8[8];
-  spread_coefs(a, (int)m, a.g.dim, a.raw ? 1.0 : a.ds[m] / hD, c8);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) rec[m * 8 + c] = (T)c8[c];
-}
-
 template <typename T, int NF, bool FD>
 __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
   using T2 = cplx<T>;
@@ -308,23 +317,26 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int tile = a.busy[blockIdx.x];
+  const int4 bt = a.busy[xcd_chunk(blockIdx.x, gridDim.x)];
+  const int tile = bt.x;
   const int ntl = g.ntile[0] * g.ntile[1] * g.ntile[2];
   const int prob = tile / ntl, tl = tile - prob * ntl;
   const int tx = tl % g.ntile[0];
   const int ty = (tl / g.ntile[0]) % g.ntile[1];
   const int tz = tl / (g.ntile[0] * g.ntile[1]);
   const int x0 = tx * kT3X, y0 = ty * kT3Y, z0 = tz * kT3Z;
+  const double hD = g.h * g.h * g.h;
   const int mx = g.n[0] - 1, my = g.n[1] - 1, mz = g.n[2] - 1;
   typename M::v4 acc[NF][2];
 #pragma unroll
   for (int c = 0; c < NF; ++c) acc[c][0] = acc[c][1] = typename M::v4{0, 0, 0, 0};
-  const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
+  const int beg = bt.y, end = bt.z;
   constexpr int NT = FD ? 2 : 1, CPS = 4 / NT;       // terms per candidate, candidates per K-step
   const int kk = lane >> 4, i16 = lane & 15;
   const int yy = i16 & 3, zz = i16 >> 2;
-  // staging: four lanes per candidate (lane quarter p loads window offset p < 3, coefficients
-  // p, p + 4, ... and entries 6p .. 6p + 5 of the weight row), all loads of a pass issued at once;
+  // staging: four lanes per candidate (lane quarter p loads window offset p < 3, forms the field
+  // coefficients p, p + 4, ... and loads entries 6p .. 6p + 5 of the weight row), all loads of a
+  // pass issued at once;
   // the next pass's marker ids are fetched while the current pass accumulates
   const int scand = tid >> 2, part = tid & 3;
   int m_next = scand < end - beg ? a.list[beg + scand] : -1;
@@ -339,10 +351,11 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
 #pragma unroll
       for (int i = 0; i < 6; ++i) w6[i] = wrow[i];
       const int o = a.s[mm * 3 + (part < 3 ? part : 0)];
-      const T* rec = static_cast<const T*>(a.crec) + (int64_t)mm * 8;
+      const double base = a.raw ? 1.0 : a.ds[mm] / hD;
       T cv[(NC + 3) / 4];
 #pragma unroll
-      for (int j = 0; j < (NC + 3) / 4; ++j) cv[j] = (part + 4 * j < NC) ? rec[part + 4 * j] : (T)0;
+      for (int j = 0; j < (NC + 3) / 4; ++j)
+        cv[j] = (part + 4 * j < NC) ? (T)spread_coef(a, mm, 3, base, part + 4 * j) : (T)0;
       m_next = (c0 + kSC + scand < end) ? a.list[c0 + kSC + scand] : -1;
 #pragma unroll
       for (int i = 0; i < 6; ++i) s_w[scand][6 * part + i] = live ? w6[i] : mk<T2>((T)0, (T)0);
@@ -420,7 +433,8 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int tile = a.busy[blockIdx.x];
+  const int4 bt = a.busy[xcd_chunk(blockIdx.x, gridDim.x)];
+  const int tile = bt.x;
   const int ntl = g.ntile[0] * g.ntile[1];
   const int prob = tile / ntl, tl = tile - prob * ntl;
   const int tx = tl % g.ntile[0];
@@ -434,7 +448,7 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int c = 0; c < NF; ++c) acc[j][c] = 0;
-  const int beg = a.tile_off[tile], end = a.tile_off[tile + 1];
+  const int beg = bt.y, end = bt.z;
   const double hD = g.h * g.h;
   for (int c0 = beg; c0 < end; c0 += 4 * LW) {
     const int left = end - c0 - wave;
@@ -553,7 +567,8 @@ template <typename T, int D>
 __global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __restrict__ wtab, const T* __restrict__ u,
                                                  double* __restrict__ out) {
   constexpr int RL = (D == 3) ? 16 : 4;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-contiguous marker ranges: markers close in index share grid lines, so they share an L2
+  const int64_t gid = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t i = gid / RL;
   const int r = (int)(gid % RL);
   const bool valid = i < a.n_ib;
@@ -776,16 +791,17 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
 }
 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count, int* tile_off,
-                 int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off, hipStream_t st, const int* pid,
+                 int* tile_cur, int* list, int* list_tmp, int4* busy, int* busy_off, hipStream_t st, const int* pid,
                  int nprob) {
   const int ntile = g.ntile[0] * g.ntile[1] * g.ntile[2] * nprob;
   hipLaunchKernelGGL(k_busy_flags, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, tile_cur, ntile);
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_cur, busy_off, ntile);
   IBDL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_busy_ids, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, busy_off, busy, ntile);
-  IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_count, tile_off, ntile);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_busy_ids, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, busy_off, tile_off, busy,
+                     ntile);
   IBDL_LAUNCH_CHECK();
   IBDL_HIP(hipMemsetAsync(tile_cur, 0, sizeof(int) * ntile, st));
   if (n_ib > 0)
@@ -796,11 +812,12 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
   IBDL_LAUNCH_CHECK();
 }
 
-void markers_segments(const MarkerGeom& g, const int* tile_off, unsigned long long* seg, hipStream_t st) {
-  if (g.ntile[0] > 64) throw Error(-2, "markers_segments: more than 64 tiles along x");
-  const int64_t nstrips = (int64_t)g.ntile[1] * (g.dim == 3 ? g.ntile[2] : 1);
-  hipLaunchKernelGGL(k_segments, dim3((unsigned)((nstrips + 255) / 256)), dim3(256), 0, st, tile_off, g.ntile[0],
-                     nstrips, seg);
+void markers_row_segments(const MarkerGeom& g, const int* tile_off, const int* rows, int64_t nact,
+                          unsigned long long* seg, hipStream_t st) {
+  if (g.ntile[0] > 64) throw Error(-2, "markers_row_segments: more than 64 tiles along x");
+  if (nact <= 0) return;
+  hipLaunchKernelGGL(k_row_segments, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, st, g, tile_off, rows, nact,
+                     seg);
   IBDL_LAUNCH_CHECK();
 }
 
@@ -845,11 +862,7 @@ void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
     if (one) hipLaunchKernelGGL((k_spread2<T, 1>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
     else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   } else {
-    if (!a.crec) throw Error(-1, "3-D spread: coefficient scratch missing");
-    const int64_t n_ib = a.nmark;
-    if (n_ib > 0)
-      hipLaunchKernelGGL((k_marker_coefs<T>), dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, a,
-                         static_cast<T*>(a.crec), n_ib);
+    if (a.mode == SP_STOKES) throw Error(-1, "3-D spread: the Stokes mode is two-dimensional");
     if (one && a.mode == SP_FDDIV)
       hipLaunchKernelGGL((k_spread3m<T, 1, true>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
     else if (one)

@@ -27,7 +27,6 @@ template <typename T> struct GridWork {
   T* real = nullptr;
   cplx<T>* spec = nullptr;
   cplx<T>* wtab = nullptr;   // marker weight table in this precision
-  T* crec = nullptr;         // per-marker spread coefficients [n_ib][8] (scratch of the 3-D spread)
   int nfields = 0;
   LaunchShape shape;         // launch shapes of the operator apply's FFT passes (measured)
   bool tuned = false;
@@ -55,9 +54,10 @@ struct ibdl_s {
   double* f = nullptr;
   double* wt = nullptr;   // per-marker kernel weight table [n_ib][3][12]
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
-  int *busy = nullptr, *busy_off = nullptr;
+  int4* busy = nullptr;
+  int* busy_off = nullptr;
   int nbusy = 0;
-  unsigned long long* seg = nullptr;   // busy x-segments of each tile strip (RowList::seg)
+  unsigned long long* seg = nullptr;   // busy x-segments of each active row (RowList::seg)
   // active rows (rows of the markers' windows): list for the x passes, per-plane limits for y
   int *row_lo = nullptr, *row_hi = nullptr, *row_cnt = nullptr, *row_off = nullptr, *rows = nullptr;
   int2* row_lim = nullptr;
@@ -223,7 +223,6 @@ template <typename T> GridWork<T>& ensure_work(ibdl_s* h) {
   W.real = (T*)h->dalloc<T>(sizeof(T) * h->ntot * nf);
   W.spec = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->nspec * nf);
   W.wtab = (cplx<T>*)h->dalloc<T>(sizeof(cplx<T>) * h->n_ib * 24);
-  W.crec = (T*)h->dalloc<T>(sizeof(T) * h->n_ib * 8);
   weight_table<T>(h->wt, h->n_ib, W.wtab, h->st);
   GridTables<T> G = make_grid_tables<T>(h->dim, h->n, h->cfg.L, h->h, h->fd(),
                                         [&](size_t bytes) { return h->dalloc<T>(bytes); });
@@ -290,10 +289,6 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
     if (sin) rl_in = rl_out;
     if (sin && busy_only) {   // src holds a spread's output: only its busy tiles were written
       rl_in.seg = h->seg;
-      rl_in.seg_ny = h->n[1];
-      rl_in.seg_ty = h->geom.tile[1];
-      rl_in.seg_tz = h->dim == 3 ? h->geom.tile[2] : 1;
-      rl_in.seg_nsy = h->geom.ntile[1];
       rl_in.seg_log2 = __builtin_ctz((unsigned)h->geom.tile[0] / 2);
     }
     if (h->dim == 3) {
@@ -366,8 +361,6 @@ SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
 
 // the spread with this precision's tables and coefficient scratch
 template <typename T> void spread_w(ibdl_s* h, SpreadArgs a, GridWork<T>& W, T* out) {
-  a.nmark = h->n_ib;
-  a.crec = W.crec;
   spread<T>(a, W.wtab, out, h->st);
 }
 
@@ -938,7 +931,6 @@ void build_markers(ibdl_s* h) {
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
               h->busy_off, h->st);
-  markers_segments(h->geom, h->tile_off, h->seg, h->st);
   markers_rows(h->geom, h->n_ib, h->s, h->row_lo, h->row_hi, h->row_cnt, h->row_off, h->row_lim, h->rows, h->st);
   const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
   const int nplanes = h->dim == 3 ? h->n[2] : 1;
@@ -952,18 +944,14 @@ void build_markers(ibdl_s* h) {
   h->nact = na;
   h->lim2d[0] = l2.x;
   h->lim2d[1] = l2.y;
-  {   // count the busy x-segments of the active rows (reported by ibdl_spread_tiles)
-    const int64_t nstrips = ntile / h->geom.ntile[0];
-    std::vector<int> rows(na);
-    std::vector<unsigned long long> seg(nstrips);
-    if (na > 0) IBDL_HIP(hipMemcpy(rows.data(), h->rows, sizeof(int) * na, hipMemcpyDeviceToHost));
-    IBDL_HIP(hipMemcpy(seg.data(), h->seg, sizeof(unsigned long long) * nstrips, hipMemcpyDeviceToHost));
+  {   // busy x-segments of the active rows; their count is reported by ibdl_spread_tiles
+    markers_row_segments(h->geom, h->tile_off, h->rows, na, h->seg, h->st);
+    std::vector<unsigned long long> seg(na);
+    if (na > 0)
+      IBDL_HIP(hipMemcpyAsync(seg.data(), h->seg, sizeof(unsigned long long) * na, hipMemcpyDeviceToHost, h->st));
+    IBDL_HIP(hipStreamSynchronize(h->st));
     int64_t cnt = 0;
-    for (int w : rows) {
-      const int y = w % h->n[1], z = w / h->n[1];
-      const int64_t strip = y / h->geom.tile[1] + (int64_t)h->geom.ntile[1] * (h->dim == 3 ? z / h->geom.tile[2] : 0);
-      cnt += __builtin_popcountll(seg[strip]);
-    }
+    for (unsigned long long m : seg) cnt += __builtin_popcountll(m);
     h->seg_read = cnt;
   }
   if (h->w32 && h->w32->wtab) weight_table<float>(h->wt, h->n_ib, h->w32->wtab, h->st);
@@ -1032,9 +1020,8 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->tile_count = (int*)h->dalloc<int>(sizeof(int) * ntile);
     h->tile_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->tile_cur = (int*)h->dalloc<int>(sizeof(int) * ntile);
-    h->busy = (int*)h->dalloc<int>(sizeof(int) * ntile);
+    h->busy = (int4*)h->dalloc<int4>(sizeof(int4) * ntile);
     h->busy_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
-    h->seg = (unsigned long long*)h->dalloc<unsigned long long>(sizeof(unsigned long long) * (ntile / g.ntile[0]));
     h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     const int nplanes = h->dim == 3 ? h->n[2] : 1;
@@ -1044,6 +1031,7 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->row_off = (int*)h->dalloc<int>(sizeof(int) * (nplanes + 1));
     h->row_lim = (int2*)h->dalloc<int>(sizeof(int2) * nplanes);
     h->rows = (int*)h->dalloc<int>(sizeof(int) * (int64_t)h->n[1] * nplanes);
+    h->seg = (unsigned long long*)h->dalloc<unsigned long long>(sizeof(unsigned long long) * (int64_t)h->n[1] * nplanes);
     h->small = (double*)h->dalloc<double>(sizeof(double) * 1024);
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);

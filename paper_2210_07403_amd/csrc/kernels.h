@@ -19,21 +19,16 @@ enum FieldKind {
 // can run over a list of them and the y passes can skip the loads / stores of the others.
 // A spread also writes every node of each tile that a marker window meets (its busy tiles) and
 // nothing else, so with seg set the forward x pass reads only the busy x-segments of a row and takes
-// the others as zero: seg[strip] has bit t set when x-segment t (2^seg_log2 complex values, one
-// tile wide) of the tile strip (y / seg_ty, z / seg_tz) is busy.  The fields need no clearing then.
+// the others as zero: seg[r] has bit t set when x-segment t (2^seg_log2 complex values, one tile
+// wide) of listed row r is in a busy tile.  The fields need no clearing then.
 struct RowList {
   const int* rows = nullptr;   // active rows of one field, increasing (NULL: every row)
   int64_t nact = 0;            // active rows per field
   int64_t rpf = 0;             // rows per field
-  const unsigned long long* seg = nullptr;   // busy x-segments per tile strip (NULL: read everything)
-  int seg_ny = 1, seg_ty = 1, seg_tz = 1, seg_nsy = 1, seg_log2 = 3;
+  const unsigned long long* seg = nullptr;   // busy x-segments per listed row (NULL: read everything)
+  int seg_log2 = 3;
   __device__ int64_t row(int64_t r) const { return rows ? (int64_t)rows[r % nact] + (r / nact) * rpf : r; }
-  __device__ unsigned long long segmask(int64_t r) const {
-    if (!seg) return ~0ull;
-    const int w = rows ? rows[r % nact] : (int)(r % rpf);   // row z * ny + y within its field
-    const int y = w % seg_ny, z = w / seg_ny;
-    return seg[y / seg_ty + (int64_t)seg_nsy * (z / seg_tz)];
-  }
+  __device__ unsigned long long segmask(int64_t r) const { return seg ? seg[r % nact] : ~0ull; }
 };
 struct RowMask {
   const int2* lim = nullptr;   // per plane z: rows y in [lim.x, lim.y] matter (NULL: all)
@@ -119,19 +114,21 @@ struct MarkerGeom {
 void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* X, int* s, double* f,
                    double* wt, int* tile_count, hipStream_t st, const int* pid = nullptr, int nprob = 1);
 // bin markers by tile (sorted candidate lists) and list the non-empty tiles: busy[0..nbusy) with
-// nbusy = busy_off[ntile]
+// nbusy = busy_off[ntile], each (tile id, tile_off[tile], tile_off[tile + 1], 0)
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
-                 int* tile_off, int* tile_cur, int* list, int* list_tmp, int* busy, int* busy_off,
+                 int* tile_off, int* tile_cur, int* list, int* list_tmp, int4* busy, int* busy_off,
                  hipStream_t st, const int* pid = nullptr, int nprob = 1);
 
-// seg[strip] = bit mask of the busy tiles along x of each tile strip (ntile[0] <= 64)
-void markers_segments(const MarkerGeom& g, const int* tile_off, unsigned long long* seg, hipStream_t st);
 
 // Active rows of the markers' windows: lo/hi [planes] (scratch), cnt/off [planes + 1] (scratch),
 // lim [planes] = (lo, hi) per plane, rows = the row list (up to ny * planes entries), increasing;
 // the count is off[planes].  planes = nz in 3-D, 1 in 2-D.
 void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int* hi, int* cnt, int* off, int2* lim,
                   int* rows, hipStream_t st);
+// seg[r] = bit mask of the busy tiles along x that listed row r (rows[r], r < nact) passes through
+// (ntile[0] <= 64)
+void markers_row_segments(const MarkerGeom& g, const int* tile_off, const int* rows, int64_t nact,
+                          unsigned long long* seg, hipStream_t st);
 // zero the listed rows of nfields fields (rpf rows per field, nx values per row)
 template <typename T>
 void grid_fill_rows(T* y, const int* rows, int64_t nact, int nx, int nfields, int64_t rpf, hipStream_t st);
@@ -153,7 +150,7 @@ struct SpreadArgs {
   double eta;
   const int* tile_off;
   const int* list;
-  const int* busy;    // non-empty tile ids
+  const int4* busy;   // non-empty tiles: (tile id, list begin, list end, 0)
   int nbusy;
   const int* s;
   const double* f;
@@ -162,9 +159,6 @@ struct SpreadArgs {
   const double* m;    // optional extra mass values [n_ib] (Neumann V_b), may be null
   const double* nrm;  // [n_ib][dim]
   const double* ds;   // [n_ib]
-  int64_t nmark;      // markers (records to prepare)
-  void* crec;         // 3-D: scratch of n_ib * 8 values of the grid type for the per-marker field
-                      // coefficients (written by the spread launcher, then staged by the tiles)
 };
 // Spread over the non-empty tiles only: nodes of empty tiles are left untouched, so the caller
 // clears the nf output fields first (grid_fill_zero).  A batch tile id p * ntile + t writes problem
