@@ -58,6 +58,7 @@ struct Group {
   int *s = nullptr, *pid = nullptr;
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
   int4* busy = nullptr;
+  int4* busy_tmp = nullptr;
   int* busy_off = nullptr;
   int nbusy = 0;
   GroupWork<float> w32;
@@ -582,6 +583,7 @@ ibdl_status_t ibdl_batch_create(int32_t nprob, const ibdl_config_t* cfgs, const 
       G.tile_off = (int*)B->dalloc(sizeof(int) * (ntile + 1));
       G.tile_cur = (int*)B->dalloc(sizeof(int) * ntile);
       G.busy = (int4*)B->dalloc(sizeof(int4) * ntile);
+      G.busy_tmp = (int4*)B->dalloc(sizeof(int4) * ntile);
       G.busy_off = (int*)B->dalloc(sizeof(int) * (ntile + 1));
       G.list = (int*)B->dalloc(sizeof(int) * maxlist);
       G.list_tmp = (int*)B->dalloc(sizeof(int) * maxlist);
@@ -598,8 +600,8 @@ ibdl_status_t ibdl_batch_create(int32_t nprob, const ibdl_config_t* cfgs, const 
       }
       IBDL_HIP(hipMemcpyAsync(G.pid, pid.data(), sizeof(int) * G.nib, hipMemcpyHostToDevice, B->st));
       markers_setup(g, B->kernel, G.nib, G.X, G.s, G.f, G.wt, G.tile_count, B->st, G.pid, np);
-      markers_bin(g, G.nib, G.s, G.tile_count, G.tile_off, G.tile_cur, G.list, G.list_tmp, G.busy, G.busy_off, B->st,
-                  G.pid, np);
+      markers_bin(g, G.nib, G.s, G.tile_count, G.tile_off, G.tile_cur, G.list, G.list_tmp, G.busy, G.busy_tmp,
+                  G.busy_off, B->st, G.pid, np);
       int nb = 0;
       IBDL_HIP(hipMemcpyAsync(&nb, G.busy_off + ntile, sizeof(int), hipMemcpyDeviceToHost, B->st));
       IBDL_HIP(hipStreamSynchronize(B->st));

@@ -191,6 +191,33 @@ __global__ void k_busy_ids(const int* __restrict__ cnt, const int* __restrict__ 
   if (i < n && cnt[i] > 0) busy[foff[i]] = make_int4(i, off[i], off[i + 1], 0);
 }
 
+// The busy tiles in decreasing order of their candidate count (ties by tile id): the spread's
+// workgroups then start with the longest tiles and end with the shortest, which evens out the
+// CUs' finishing times.  Rank sort; *nptr = number of busy tiles.
+__global__ __launch_bounds__(256) void k_busy_order(const int4* __restrict__ in, const int* __restrict__ nptr,
+                                                    int4* __restrict__ out) {
+  __shared__ int sc[256];
+  const int n = *nptr;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int4 v = i < n ? in[i] : make_int4(0, 0, 0, 0);
+  const int c = v.z - v.y;
+  int r = 0;
+  for (int k0 = 0; k0 < n; k0 += 256) {
+    __syncthreads();
+    if (k0 + (int)threadIdx.x < n) {
+      const int4 u = in[k0 + threadIdx.x];
+      sc[threadIdx.x] = u.z - u.y;
+    }
+    __syncthreads();
+    const int kn = n - k0 < 256 ? n - k0 : 256;
+    for (int k = 0; k < kn; ++k) {
+      const int ck = sc[k];
+      r += (ck > c) || (ck == c && k0 + k < i);
+    }
+  }
+  if (i < n) out[r] = v;
+}
+
 // sort each tile's marker list ascending (rank sort; marker indices in a tile are unique)
 __global__ __launch_bounds__(256) void k_sort_tiles(const int* __restrict__ off, const int* __restrict__ tmp,
                                                     int* __restrict__ list) {
@@ -301,15 +328,20 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-constexpr int kSC = 64;   // candidates staged in LDS per pass (4 lanes each: a 256-thread block)
+constexpr int kSpreadWaves = 4, kSpreadCands = 64;   // launch shape of the 3-D spread
+// NW waves per tile (64 NW threads) share the K-steps; SC candidates are staged per pass, four
+// lanes each
 
-template <typename T, int NF, bool FD>
-__global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
+template <typename T, int NF, bool FD, int NW, int SC>
+__global__ __launch_bounds__(64 * NW) void k_spread3m(SpreadArgs a, const cplx<T>* __restrict__ wtab,
+                                                      T* __restrict__ out) {
   using T2 = cplx<T>;
   using M = Mfma<T>;
+  constexpr int kSC = SC, NTH = 64 * NW;
+  constexpr int PER = (kSC * 4 + NTH - 1) / NTH;     // staging items (candidate, quarter) per thread
   constexpr int NC = FD ? 4 : NF;                    // coefficients per candidate
   constexpr int STAGE = kSC * 24 * (int)sizeof(T2) + kSC * NC * (int)sizeof(T) + kSC * 4 * (int)sizeof(int);
-  constexpr int RED = 4 * 512 * (int)sizeof(T);      // one field's wave partials
+  constexpr int RED = NW * 512 * (int)sizeof(T);     // one field's wave partials
   __shared__ __align__(16) unsigned char smem[STAGE > RED ? STAGE : RED];
   T2(*s_w)[24] = reinterpret_cast<T2(*)[24]>(smem);                       // marker weight rows
   T(*s_c)[NC] = reinterpret_cast<T(*)[NC]>(smem + kSC * 24 * sizeof(T2));  // coefficients
@@ -317,7 +349,7 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 bt = a.busy[xcd_chunk(blockIdx.x, gridDim.x)];
+  const int4 bt = a.busy[blockIdx.x];
   const int tile = bt.x;
   const int ntl = g.ntile[0] * g.ntile[1] * g.ntile[2];
   const int prob = tile / ntl, tl = tile - prob * ntl;
@@ -338,12 +370,19 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
   // coefficients p, p + 4, ... and loads entries 6p .. 6p + 5 of the weight row), all loads of a
   // pass issued at once;
   // the next pass's marker ids are fetched while the current pass accumulates
-  const int scand = tid >> 2, part = tid & 3;
-  int m_next = scand < end - beg ? a.list[beg + scand] : -1;
+  int m_next[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int scand = (tid + p * NTH) >> 2;
+    m_next[p] = (scand < kSC && scand < end - beg) ? a.list[beg + scand] : -1;
+  }
   for (int c0 = beg; c0 < end; c0 += kSC) {
     const int cnt = end - c0 < kSC ? end - c0 : kSC;
-    {
-      const int m = m_next;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int it = tid + p * NTH, scand = it >> 2, part = it & 3;
+      if (scand >= kSC) break;
+      const int m = m_next[p];
       const bool live = m >= 0;
       const int mm = live ? m : 0;   // padding candidates read marker 0 and store zeros
       const T2* wrow = wtab + (int64_t)mm * 24 + 6 * part;
@@ -356,7 +395,7 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
 #pragma unroll
       for (int j = 0; j < (NC + 3) / 4; ++j)
         cv[j] = (part + 4 * j < NC) ? (T)spread_coef(a, mm, 3, base, part + 4 * j) : (T)0;
-      m_next = (c0 + kSC + scand < end) ? a.list[c0 + kSC + scand] : -1;
+      m_next[p] = (c0 + kSC + scand < end) ? a.list[c0 + kSC + scand] : -1;
 #pragma unroll
       for (int i = 0; i < 6; ++i) s_w[scand][6 * part + i] = live ? w6[i] : mk<T2>((T)0, (T)0);
       if (part < 3) s_o[scand][part] = live ? o : 6;
@@ -366,7 +405,7 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
     }
     __syncthreads();
     const int nsteps = (cnt + CPS - 1) / CPS;
-    for (int st = wave; st < nsteps; st += 4) {
+    for (int st = wave; st < nsteps; st += NW) {
       const int cand = st * CPS + kk / NT;
       // tile node -> window tap (6 and 7 hold zeros)
       const int tx_ = min((x0 + i16 - s_o[cand][0]) & mx, 6);
@@ -398,7 +437,7 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
     }
     __syncthreads();
   }
-  // fixed-order sum of the four waves' partial tiles, field by field
+  // fixed-order sum of the waves' partial tiles, field by field
   T* red = reinterpret_cast<T*>(smem);   // [wave][block][v][lane]
   const int64_t ntot = (int64_t)g.n[0] * g.n[1] * g.n[2];
   out += (int64_t)prob * a.nf * ntot;
@@ -410,10 +449,11 @@ __global__ __launch_bounds__(256) void k_spread3m(SpreadArgs a, const cplx<T>* _
 #pragma unroll
       for (int v = 0; v < 4; ++v) red[((wave * 2 + b) * 4 + v) * 64 + lane] = acc[c][b][v];
     __syncthreads();
-    for (int o = tid; o < 512; o += 256) {
+    for (int o = tid; o < 512; o += NTH) {
       const int b = o >> 8, v = (o >> 6) & 3, l = o & 63;
-      const T val = ((red[((0 * 2 + b) * 4 + v) * 64 + l] + red[((1 * 2 + b) * 4 + v) * 64 + l]) +
-                     red[((2 * 2 + b) * 4 + v) * 64 + l]) + red[((3 * 2 + b) * 4 + v) * 64 + l];
+      T val = red[(b * 4 + v) * 64 + l];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) val += red[((w * 2 + b) * 4 + v) * 64 + l];
       const int i = M::row(l, v);          // (y, z) row within the block
       const int x = l & 15, y = i & 3, z = (i >> 2) + 4 * b;
       out[c * ntot + ((int64_t)(z0 + z) * g.n[1] + (y0 + y)) * g.n[0] + x0 + x] = val;
@@ -433,7 +473,7 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 bt = a.busy[xcd_chunk(blockIdx.x, gridDim.x)];
+  const int4 bt = a.busy[blockIdx.x];
   const int tile = bt.x;
   const int ntl = g.ntile[0] * g.ntile[1];
   const int prob = tile / ntl, tl = tile - prob * ntl;
@@ -791,8 +831,8 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
 }
 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count, int* tile_off,
-                 int* tile_cur, int* list, int* list_tmp, int4* busy, int* busy_off, hipStream_t st, const int* pid,
-                 int nprob) {
+                 int* tile_cur, int* list, int* list_tmp, int4* busy, int4* busy_tmp, int* busy_off, hipStream_t st,
+                 const int* pid, int nprob) {
   const int ntile = g.ntile[0] * g.ntile[1] * g.ntile[2] * nprob;
   hipLaunchKernelGGL(k_busy_flags, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, tile_cur, ntile);
   IBDL_LAUNCH_CHECK();
@@ -800,8 +840,10 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
   IBDL_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_count, tile_off, ntile);
   IBDL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_busy_ids, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, busy_off, tile_off, busy,
-                     ntile);
+  hipLaunchKernelGGL(k_busy_ids, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, busy_off, tile_off,
+                     busy_tmp, ntile);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_busy_order, dim3((ntile + 255) / 256), dim3(256), 0, st, busy_tmp, busy_off + ntile, busy);
   IBDL_LAUNCH_CHECK();
   IBDL_HIP(hipMemsetAsync(tile_cur, 0, sizeof(int) * ntile, st));
   if (n_ib > 0)
@@ -863,12 +905,13 @@ void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
     else hipLaunchKernelGGL((k_spread2<T, 5>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
   } else {
     if (a.mode == SP_STOKES) throw Error(-1, "3-D spread: the Stokes mode is two-dimensional");
+    constexpr int NW = kSpreadWaves, SC = kSpreadCands;
     if (one && a.mode == SP_FDDIV)
-      hipLaunchKernelGGL((k_spread3m<T, 1, true>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+      hipLaunchKernelGGL((k_spread3m<T, 1, true, NW, SC>), dim3(a.nbusy), dim3(64 * NW), 0, st, a, wtab, out);
     else if (one)
-      hipLaunchKernelGGL((k_spread3m<T, 1, false>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+      hipLaunchKernelGGL((k_spread3m<T, 1, false, NW, SC>), dim3(a.nbusy), dim3(64 * NW), 0, st, a, wtab, out);
     else
-      hipLaunchKernelGGL((k_spread3m<T, 5, false>), dim3(a.nbusy), dim3(256), 0, st, a, wtab, out);
+      hipLaunchKernelGGL((k_spread3m<T, 5, false, NW, SC>), dim3(a.nbusy), dim3(64 * NW), 0, st, a, wtab, out);
   }
   IBDL_LAUNCH_CHECK();
 }

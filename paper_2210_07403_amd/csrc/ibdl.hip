@@ -55,6 +55,7 @@ struct ibdl_s {
   double* wt = nullptr;   // per-marker kernel weight table [n_ib][3][12]
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
   int4* busy = nullptr;
+  int4* busy_tmp = nullptr;
   int* busy_off = nullptr;
   int nbusy = 0;
   unsigned long long* seg = nullptr;   // busy x-segments of each active row (RowList::seg)
@@ -930,7 +931,7 @@ void build_markers(ibdl_s* h) {
   h->drop_graphs();
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
-              h->busy_off, h->st);
+              h->busy_tmp, h->busy_off, h->st);
   markers_rows(h->geom, h->n_ib, h->s, h->row_lo, h->row_hi, h->row_cnt, h->row_off, h->row_lim, h->rows, h->st);
   const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
   const int nplanes = h->dim == 3 ? h->n[2] : 1;
@@ -1021,6 +1022,7 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->tile_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->tile_cur = (int*)h->dalloc<int>(sizeof(int) * ntile);
     h->busy = (int4*)h->dalloc<int4>(sizeof(int4) * ntile);
+    h->busy_tmp = (int4*)h->dalloc<int4>(sizeof(int4) * ntile);
     h->busy_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);

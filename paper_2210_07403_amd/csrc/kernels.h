@@ -114,9 +114,10 @@ struct MarkerGeom {
 void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* X, int* s, double* f,
                    double* wt, int* tile_count, hipStream_t st, const int* pid = nullptr, int nprob = 1);
 // bin markers by tile (sorted candidate lists) and list the non-empty tiles: busy[0..nbusy) with
-// nbusy = busy_off[ntile], each (tile id, tile_off[tile], tile_off[tile + 1], 0)
+// nbusy = busy_off[ntile], each (tile id, tile_off[tile], tile_off[tile + 1], 0), in decreasing
+// order of candidate count (ties by tile id); busy_tmp: scratch of the same size
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
-                 int* tile_off, int* tile_cur, int* list, int* list_tmp, int4* busy, int* busy_off,
+                 int* tile_off, int* tile_cur, int* list, int* list_tmp, int4* busy, int4* busy_tmp, int* busy_off,
                  hipStream_t st, const int* pid = nullptr, int nprob = 1);
 
 
