@@ -20,6 +20,8 @@ using namespace ibdl;
 
 namespace {
 
+constexpr int kSlot = 1024;   // doubles per host-mapped Arnoldi slot (h1, h2 and the norm)
+
 template <typename T> struct GridWork {
   cplx<T>* tw[3] = {nullptr, nullptr, nullptr};
   T* sig[3] = {nullptr, nullptr, nullptr};
@@ -78,6 +80,7 @@ struct ibdl_s {
   double* hostbuf = nullptr;  // pinned host scratch (1024 doubles)
   // host-mapped coherent memory for the per-iteration Arnoldi values: the GPU writes them and a
   // sequence tag, the host polls the tag (no copy-engine transfer, no stream-sync wake-up)
+  // host-mapped Arnoldi values: two slots of kSlot doubles, then one 64-byte tag per slot
   double* hmap = nullptr;
   double* hmap_dev = nullptr;
   volatile unsigned* htag = nullptr;
@@ -735,68 +738,73 @@ double host_norm(ibdl_s* h, const double* v, int64_t n) {
   return sqrt(h->hostbuf[0]);
 }
 
-// Publish n device doubles to the host-mapped buffer and wait for them: poll the tag for up to
-// 2 ms (an iteration's GPU work is well below that), then fall back to a stream synchronisation,
-// after which the tag must be there.
-const volatile double* wait_published(ibdl_s* h, const double* src, int n) {
+// Publish n device doubles to slot `slot` of the host-mapped buffer (stream-ordered); returns the
+// sequence number its tag will carry.
+unsigned publish(ibdl_s* h, const double* src, int n, int slot) {
   const unsigned seq = ++h->seq;
-  kr_publish(src, n, h->hmap_dev, h->htag_dev, seq, h->st);
+  kr_publish(src, n, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq, h->st);
+  return seq;
+}
+
+// Wait for a publication: poll its tag for up to 2 ms (an iteration's GPU work is well below that),
+// then fall back to a stream synchronisation, after which the tag must be there.
+const volatile double* wait_published(ibdl_s* h, int slot, unsigned seq) {
+  volatile unsigned* tag = h->htag + 16 * slot;
   const auto t0 = std::chrono::steady_clock::now();
-  while (*h->htag != seq) {
+  while (*tag != seq) {
     if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
       IBDL_HIP(hipStreamSynchronize(h->st));
-      if (*h->htag != seq) throw Error(IBDL_ERR_HIP, "Arnoldi values did not reach the host");
+      if (*tag != seq) throw Error(IBDL_ERR_HIP, "Arnoldi values did not reach the host");
       break;
     }
   }
   std::atomic_thread_fence(std::memory_order_acquire);
-  return h->hmap;
+  return h->hmap + slot * kSlot;
 }
 
-// One operator apply inside GMRES: the captured graph of the working-precision apply (transposed
-// with trans) replayed from gx into gy, or, while stage timing is on, direct launches into
-// eager_dst.  Returns where the result is.
-double* apply_step(ibdl_s* h, const double* x, bool trans, double* eager_dst) {
-  if (h->timing || !h->use_graph) {
-    apply_any(h, x, eager_dst, false, trans);
-    return eager_dst;
-  }
+// GMRES applies the working-precision operator (transposed with trans) by replaying a HIP graph
+// captured from direct launches, reading gx and writing gy.  Captures it on first use; returns
+// false when applies are launched directly instead (stage timing on, or graphs disabled).
+bool ensure_graph(ibdl_s* h, bool trans) {
+  if (h->timing || !h->use_graph) return false;
   const int64_t n = h->n_aug;
   const int k = trans ? 1 : 0;
-  if (!h->gexec[k]) {
-    if (!h->gx) {
-      h->gx = (double*)h->dalloc<double>(sizeof(double) * n);
-      h->gy = (double*)h->dalloc<double>(sizeof(double) * n);
-    }
-    // a direct run first allocates every workspace and measures the launch shapes
-    IBDL_HIP(hipMemcpyAsync(h->gx, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
-    apply_any(h, h->gx, h->gy, false, trans);
-    IBDL_HIP(hipStreamSynchronize(h->st));
-    hipStream_t main = h->st;
-    h->st = h->aux;
-    IBDL_HIP(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
-    try {
-      apply_any(h, h->gx, h->gy, false, trans);
-    } catch (...) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(h->aux, &g);
-      if (g) (void)hipGraphDestroy(g);
-      h->st = main;
-      throw;
-    }
-    h->st = main;
-    IBDL_HIP(hipStreamEndCapture(h->aux, &h->graph[k]));
-    IBDL_HIP(hipGraphInstantiate(&h->gexec[k], h->graph[k], nullptr, nullptr, 0));
+  if (h->gexec[k]) return true;
+  if (!h->gx) {
+    h->gx = (double*)h->dalloc<double>(sizeof(double) * n);
+    h->gy = (double*)h->dalloc<double>(sizeof(double) * n);
   }
-  IBDL_HIP(hipMemcpyAsync(h->gx, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
-  IBDL_HIP(hipGraphLaunch(h->gexec[k], h->st));
-  return h->gy;
+  // a direct run first allocates every workspace and measures the launch shapes
+  IBDL_HIP(hipMemsetAsync(h->gx, 0, sizeof(double) * n, h->st));
+  apply_any(h, h->gx, h->gy, false, trans);
+  IBDL_HIP(hipStreamSynchronize(h->st));
+  hipStream_t main = h->st;
+  h->st = h->aux;
+  IBDL_HIP(hipStreamBeginCapture(h->aux, hipStreamCaptureModeThreadLocal));
+  try {
+    apply_any(h, h->gx, h->gy, false, trans);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h->aux, &g);
+    if (g) (void)hipGraphDestroy(g);
+    h->st = main;
+    throw;
+  }
+  h->st = main;
+  IBDL_HIP(hipStreamEndCapture(h->aux, &h->graph[k]));
+  IBDL_HIP(hipGraphInstantiate(&h->gexec[k], h->graph[k], nullptr, nullptr, 0));
+  return true;
 }
 
 // GMRES, x0 = 0, no restart; classical Gram-Schmidt twice on the device; Givens on the host.
+// The device runs one Arnoldi step ahead of the host: step j + 1 (normalise w_j into V[j+1] with
+// the norm the device computed, apply, orthogonalise, publish) is queued before the host waits for
+// step j's values, so the GPU does not idle on the host's Givens update and convergence test.  A
+// step queued after the last one the host uses only writes V[j+1] and scratch.
 int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
           double* relres, bool trans = false) {
   const int64_t n = h->n_aug;
+  if (maxit > 255) throw Error(IBDL_ERR_ARG, "maxit must be at most 255");
   if (h->vcap < maxit + 1) {
     h->V = (double*)h->dalloc<double>(sizeof(double) * n * (maxit + 1));
     h->vcap = maxit + 1;
@@ -812,7 +820,10 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
     return IBDL_OK;
   }
+  const bool graph = ensure_graph(h, trans);
+  double* gin = graph ? h->gx : nullptr;
   kr_scale(b, 1.0 / beta, h->V, n, h->st);
+  if (graph) IBDL_HIP(hipMemcpyAsync(h->gx, h->V, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
   std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0);
   gv[0] = beta;
   int k = 0;
@@ -820,20 +831,44 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   double* h1 = h->small;            // [maxit+1]
   double* h2 = h->small + 256;      // [maxit+1]
   double* hn = h->small + 512;      // norm^2
-  for (int j = 0; j < maxit; ++j) {
-    double* vnext = h->V + (int64_t)(j + 1) * n;
-    double* w = apply_step(h, h->V + (int64_t)j * n, trans, vnext);
+  const double tiny = 1e-300 * beta;
+  unsigned seq[2] = {0, 0};
+  // queue Arnoldi step j (V[j] is in place, and in gx for the graph); returns where w is
+  auto step = [&](int j) -> double* {
+    double* w;
+    if (graph) {
+      IBDL_HIP(hipGraphLaunch(h->gexec[trans ? 1 : 0], h->st));
+      w = h->gy;
+    } else {
+      w = h->V + (int64_t)(j + 1) * n;
+      apply_any(h, h->V + (int64_t)j * n, w, false, trans);
+    }
     kr_arnoldi(0, h->V, n, j + 1, w, nullptr, n, h->partial, anblk, h1, h->st);
     kr_arnoldi(1, h->V, n, j + 1, w, h1, n, h->partial, anblk, h2, h->st);
     kr_arnoldi(2, h->V, n, j + 1, w, h2, n, h->partial, anblk, hn, h->st);
-    const volatile double* hv = wait_published(h, h->small, 513);
+    seq[j & 1] = publish(h, h->small, 513, j & 1);
+    return w;
+  };
+  double* w = step(0);
+  auto next = [&](int j) {   // queue step j + 1 behind step j
+    kr_scale_norm(w, hn, tiny, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
+    w = step(j + 1);
+  };
+  std::vector<double> rs(maxit, 1.0);   // residual estimates of the steps the host has finished
+  for (int j = 0; j < maxit; ++j) {
+    // Step j + 1 is queued ahead unless step j is predicted to converge: the residual ratio of the
+    // last two steps, applied once more, brings it to tol.  A step queued after convergence would
+    // delay whatever follows on the stream by a whole apply.
+    bool ahead = j + 1 < maxit;
+    if (ahead && j >= 2) ahead = rs[j - 1] * (rs[j - 1] / rs[j - 2]) > tol;
+    if (ahead) next(j);
+    const volatile double* hv = wait_published(h, j & 1, seq[j & 1]);
     double* Hj = &H[(size_t)j * (maxit + 1)];
     for (int i = 0; i <= j; ++i) Hj[i] = hv[i] + hv[256 + i];
     const double hnext = sqrt(std::max((double)hv[512], 0.0));
     if (!std::isfinite(hnext)) throw Error(IBDL_ERR_NONFINITE, "non-finite value in the Arnoldi process");
     Hj[j + 1] = hnext;
-    const bool breakdown = !(hnext > 1e-300 * beta);
-    if (!breakdown) kr_scale(w, 1.0 / hnext, vnext, n, h->st);
+    const bool breakdown = !(hnext > tiny);
     for (int i = 0; i < j; ++i) {
       const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
       Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
@@ -848,8 +883,10 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     gv[j] = cs[j] * gv[j];
     k = j + 1;
     res = fabs(gv[j + 1]) / beta;
+    rs[j] = res;
     if (info && info->history && j < info->history_cap) info->history[j] = res;
     if (res <= tol || breakdown) break;
+    if (!ahead && j + 1 < maxit) next(j);
   }
   std::vector<double> y(k);
   for (int i = k - 1; i >= 0; --i) {
@@ -1038,11 +1075,13 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     IBDL_HIP(hipHostMalloc((void**)&h->hostbuf, sizeof(double) * 1024, hipHostMallocDefault));
-    IBDL_HIP(hipHostMalloc((void**)&h->hmap, sizeof(double) * 1024 + 64, hipHostMallocMapped | hipHostMallocCoherent));
+    IBDL_HIP(hipHostMalloc((void**)&h->hmap, sizeof(double) * 2 * kSlot + 128,
+                           hipHostMallocMapped | hipHostMallocCoherent));
     IBDL_HIP(hipHostGetDevicePointer((void**)&h->hmap_dev, h->hmap, 0));
-    h->htag = reinterpret_cast<volatile unsigned*>(h->hmap + 1024);
-    h->htag_dev = reinterpret_cast<unsigned*>(h->hmap_dev + 1024);
-    *h->htag = 0;
+    h->htag = reinterpret_cast<volatile unsigned*>(h->hmap + 2 * kSlot);
+    h->htag_dev = reinterpret_cast<unsigned*>(h->hmap_dev + 2 * kSlot);
+    h->htag[0] = 0;
+    h->htag[16] = 0;
     IBDL_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
     IBDL_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     IBDL_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));

@@ -213,6 +213,10 @@ void kr_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n
 void kr_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n, hipStream_t st);
 void kr_lincomb(const double* V, int64_t ldv, int k, const double* y, double* x, int64_t n, hipStream_t st);
 void kr_scale(const double* src, double s, double* dst, int64_t n, hipStream_t st);
+// dst (and dst2 unless NULL) = src / sqrt(max(*nrm2, 0)) with the norm read on the device; zero
+// when the norm is not above floor
+void kr_scale_norm(const double* src, const double* nrm2, double floor, double* dst, double* dst2, int64_t n,
+                   hipStream_t st);
 void kr_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t st);
 void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double eta, double* out,
                double* partial, int nblk, hipStream_t st);

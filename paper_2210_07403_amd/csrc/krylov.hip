@@ -63,6 +63,20 @@ __global__ void k_scale(const double* __restrict__ src, double s, double* __rest
     dst[e] = src[e] * s;
 }
 
+// dst (and dst2 if set) = src / sqrt(max(*nrm2, 0)); 0 where that norm is not above floor (the
+// Arnoldi breakdown, which the host detects from the same value)
+__global__ void k_scale_norm(const double* src, const double* __restrict__ nrm2, double floor, double* dst,
+                             double* dst2, int64_t n) {
+  const double v = *nrm2;
+  const double h = sqrt(v > 0.0 ? v : 0.0);
+  const double s = h > floor ? 1.0 / h : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = src[e] * s;
+    dst[e] = x;
+    if (dst2) dst2[e] = x;
+  }
+}
+
 __global__ void k_axpby_d(double* __restrict__ y, double a, const double* __restrict__ x, double b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     y[e] = a * x[e] + b * y[e];
@@ -338,6 +352,12 @@ void kr_lincomb(const double* V, int64_t ldv, int k, const double* y, double* x,
 
 void kr_scale(const double* src, double s, double* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(256), 0, st, src, s, dst, n);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kr_scale_norm(const double* src, const double* nrm2, double floor, double* dst, double* dst2, int64_t n,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_norm, dim3(blocks_for(n)), dim3(256), 0, st, src, nrm2, floor, dst, dst2, n);
   IBDL_LAUNCH_CHECK();
 }
 
