@@ -156,10 +156,10 @@ template <typename C> __device__ __forceinline__ C& at(C* base, unsigned byte) {
   return *reinterpret_cast<C*>(reinterpret_cast<char*>(base) + (size_t)byte);
 }
 
-template <int N, typename C>
+template <int N, int RMX, typename C>
 __device__ __forceinline__ void line_gload(C* v, const C* __restrict__ base, unsigned o0, unsigned es, int i,
                                            bool valid, const RowMask& m) {
-  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  constexpr int RM = RMX, TT = Plan<N, RMX>::T;
   if (!valid) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) v[s] = mk<C>(0, 0);
@@ -178,10 +178,10 @@ __device__ __forceinline__ void line_gload(C* v, const C* __restrict__ base, uns
   }
 }
 
-template <int N, typename C>
+template <int N, int RMX, typename C>
 __device__ __forceinline__ void line_gstore(const C* v, C* __restrict__ base, unsigned o0, unsigned es, int i,
                                             bool valid, const RowMask& m) {
-  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  constexpr int RM = RMX, TT = Plan<N, RMX>::T;
   if (!valid) return;
   const unsigned b0 = (o0 + (unsigned)i * es) * (unsigned)sizeof(C), step = TT * es * (unsigned)sizeof(C);
   if (m.store) {
@@ -386,8 +386,15 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
 }
 
 // tile width (lines per block) for strided and fused passes
+// elements per thread of the strided and fused passes: at most 8 in double precision up to N = 256,
+// whose 16-element lines need more registers than leave room for a second wave per SIMD (longer
+// lines keep 16, or their tiles would narrow below 64-byte segments)
+template <typename T> constexpr int rmax_t(int N) {
+  return sizeof(T) == 8 && N <= 256 && plan_rmax(N) > 8 ? 8 : plan_rmax(N);
+}
 template <typename T, int N> struct TileCfg {
-  static constexpr int T_ = Plan<N>::T;
+  static constexpr int RMX = rmax_t<T>(N);
+  static constexpr int T_ = Plan<N, RMX>::T;
   static constexpr int W0 = kBlock / T_;
   static constexpr int WL = kLdsBytes / (N * (int)sizeof(cplx<T>));
   static constexpr int W = (W0 < WL ? W0 : WL) > 0 ? (W0 < WL ? W0 : WL) : 1;
@@ -413,10 +420,10 @@ __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, 
   const bool valid = l < nlines && li < vinner;
   const unsigned base = valid ? lp * (unsigned)outer + li : 0u;
   const RowMask pm = rm.plane(valid ? lp : 0);   // rows of this line's plane that matter
-  C v[Plan<N>::RMAX];
-  line_gload<N>(v, data, base, (unsigned)es, i, valid, pm);
-  fft_line<N, INV, !TC::TWL>(v, i, lds + c, W, tw, 1);
-  line_gstore<N>(v, data, base, (unsigned)es, i, valid, pm);
+  C v[TC::RMX];
+  line_gload<N, TC::RMX>(v, data, base, (unsigned)es, i, valid, pm);
+  fft_line<N, INV, !TC::TWL, TC::RMX>(v, i, lds + c, W, tw, 1);
+  line_gstore<N, TC::RMX>(v, data, base, (unsigned)es, i, valid, pm);
 }
 
 // ------------------------------------------------------------------ Fourier multiplier
@@ -457,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
                                                   const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
-  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
@@ -499,8 +506,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 
   for (int f = 0; f < md.nc; ++f) {
     C v[RM];
-    line_gload<N>(v, data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
-    fft_line<N, false, !TC::TWL>(v, i, lds + c, W, tw, 1);
+    line_gload<N, RM>(v, data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, false, !TC::TWL, RM>(v, i, lds + c, W, tw, 1);
     const int fk = md.fk[f];
     if constexpr (!STOKES) {
       if (fk == FK_MASS) {
@@ -528,8 +535,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   }
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    fft_line<N, true, !TC::TWL>(acc[o], i, lds + c, W, tw, 1);
-    line_gstore<N>(acc[o], data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, true, !TC::TWL, RM>(acc[o], i, lds + c, W, tw, 1);
+    line_gstore<N, RM>(acc[o], data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
   }
 }
 
@@ -540,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
                                                    const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
-  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
@@ -556,16 +563,16 @@ __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, i
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
   if (d3) sig_l += static_cast<const T*>(md.sig[1])[jy2];
   C v[RM];
-  line_gload<N>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
-  fft_line<N, false, !TC::TWL>(v, i, lds + c, W, tw, 1);
+  line_gload<N, RM>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
+  fft_line<N, false, !TC::TWL, RM>(v, i, lds + c, W, tw, 1);
   const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
 #pragma unroll
   for (int s = 0; s < RM; ++s) {
     const T den = c2 * (sig_l + sgl[i + s * TT]) - c0;
     v[s] = cscale(v[s], den == (T)0 ? (T)0 : num * recip(den));
   }
-  fft_line<N, true, !TC::TWL>(v, i, lds + c, W, tw, 1);
-  line_gstore<N>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
+  fft_line<N, true, !TC::TWL, RM>(v, i, lds + c, W, tw, 1);
+  line_gstore<N, RM>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
 }
 
 // Transposed / multi-output pass: the NI input spectra stay in registers after their forward
@@ -576,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
                                                       const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
   using TC = TileCfg<T, N>;
-  constexpr int RM = Plan<N>::RMAX, TT = Plan<N>::T;
+  constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
@@ -604,8 +611,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   C v[NI][RM];
 #pragma unroll
   for (int f = 0; f < NI; ++f) {
-    line_gload<N>(v[f], data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
-    fft_line<N, false, !TC::TWL>(v[f], i, lds + c, W, tw, 1);
+    line_gload<N, RM>(v[f], data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, false, !TC::TWL, RM>(v[f], i, lds + c, W, tw, 1);
   }
   for (int o = 0; o < no; ++o) {
     C acc[RM];
@@ -626,8 +633,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
         for (int f = 0; f < NI; ++f) acc[s] = cadd(acc[s], cmul(cconj(mult_coef<T>(md, md.fk[o], f, sig, kt)), v[f][s]));
       }
     }
-    fft_line<N, true, !TC::TWL>(acc, i, lds + c, W, tw, 1);
-    line_gstore<N>(acc, data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, true, !TC::TWL, RM>(acc, i, lds + c, W, tw, 1);
+    line_gstore<N, RM>(acc, data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
   }
 }
 
