@@ -738,11 +738,11 @@ double host_norm(ibdl_s* h, const double* v, int64_t n) {
   return sqrt(h->hostbuf[0]);
 }
 
-// Publish n device doubles to slot `slot` of the host-mapped buffer (stream-ordered); returns the
-// sequence number its tag will carry.
-unsigned publish(ibdl_s* h, const double* src, int n, int slot) {
+// Publish n device doubles (the last one first reduced from pnorm, see kr_publish) to slot `slot`
+// of the host-mapped buffer (stream-ordered); returns the sequence number its tag will carry.
+unsigned publish(ibdl_s* h, double* src, int n, const double* pnorm, int nblk, int slot) {
   const unsigned seq = ++h->seq;
-  kr_publish(src, n, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq, h->st);
+  kr_publish(src, n, pnorm, nblk, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq, h->st);
   return seq;
 }
 
@@ -811,7 +811,7 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   }
   const int nblk = kr_nblk(n);
   const int anblk = kr_arnoldi_nblk(n);
-  ensure_partial(h, std::max(nblk, anblk) * (maxit + 2));
+  ensure_partial(h, std::max(nblk * (maxit + 2), anblk * (2 * maxit + 3)));
   const double beta = host_norm(h, b, n);
   *iters = 0;
   *relres = 0.0;
@@ -828,9 +828,8 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   gv[0] = beta;
   int k = 0;
   double res = 1.0;
-  double* h1 = h->small;            // [maxit+1]
-  double* h2 = h->small + 256;      // [maxit+1]
-  double* hn = h->small + 512;      // norm^2
+  // h->small: first Gram-Schmidt coefficients [0, 256), second [256, 512), |w|^2 at 512
+  double* hn = h->small + 512;
   const double tiny = 1e-300 * beta;
   unsigned seq[2] = {0, 0};
   // queue Arnoldi step j (V[j] is in place, and in gx for the graph); returns where w is
@@ -843,10 +842,8 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
       w = h->V + (int64_t)(j + 1) * n;
       apply_any(h, h->V + (int64_t)j * n, w, false, trans);
     }
-    kr_arnoldi(0, h->V, n, j + 1, w, nullptr, n, h->partial, anblk, h1, h->st);
-    kr_arnoldi(1, h->V, n, j + 1, w, h1, n, h->partial, anblk, h2, h->st);
-    kr_arnoldi(2, h->V, n, j + 1, w, h2, n, h->partial, anblk, hn, h->st);
-    seq[j & 1] = publish(h, h->small, 513, j & 1);
+    kr_arnoldi_step(h->V, n, j + 1, w, n, h->partial, anblk, h->small, h->st);
+    seq[j & 1] = publish(h, h->small, 513, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, j & 1);
     return w;
   };
   double* w = step(0);

@@ -222,15 +222,19 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
                double* partial, int nblk, hipStream_t st);
 void kr_add(double* dst, const double* a, const double* b, int n, hipStream_t st);
 int kr_nblk(int64_t n);
-// Arnoldi vector work (a partial-sum kernel and a fixed-order reduction each): mode 0 out_j = V_j . w;
-// mode 1 w -= V h then out_j = V_j . w; mode 2 w -= V h then out_0 = w . w; j < k.  partial: k * nblk
-// doubles with nblk = kr_arnoldi_nblk(n).
-void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const double* h, int64_t n, double* partial,
-                int nblk, double* out, hipStream_t st);
+// One Arnoldi step's vector work, classical Gram-Schmidt twice on w against V_0..V_{k-1}
+// (three launches; each reduces the previous one's block partial sums itself, in a fixed order):
+// h[j] = V_j . w, w -= V h; h[256 + j] = V_j . w, w -= V h[256..]; the block partial sums of w . w
+// are left at partial + 2 k nblk (reduced by kr_publish).  partial: (2 k + 1) * nblk doubles with
+// nblk = kr_arnoldi_nblk(n); k <= 256.
+void kr_arnoldi_step(const double* V, int64_t ldv, int k, double* w, int64_t n, double* partial, int nblk,
+                     double* h, hipStream_t st);
 int kr_arnoldi_nblk(int64_t n);
-// host_dst / host_tag: device addresses of host-mapped, coherent pinned memory; the tag is written
-// last, after a system-scope fence
-void kr_publish(const double* src, int n, double* host_dst, unsigned* host_tag, unsigned seq, hipStream_t st);
+// Copy src[0..n) to host_dst, with src[n - 1] first set to the sum of pnorm[0..nblk) unless pnorm is
+// NULL.  host_dst / host_tag: device addresses of host-mapped, coherent pinned memory; the tag is
+// written last, after a system-scope fence
+void kr_publish(double* src, int n, const double* pnorm, int nblk, double* host_dst, unsigned* host_tag,
+                unsigned seq, hipStream_t st);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

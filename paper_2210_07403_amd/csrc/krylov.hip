@@ -197,17 +197,43 @@ __global__ void k_adj_coefs(int stokes, int dim, int64_t n_ib, int nc, double hD
 constexpr int kArnChunk = 256;
 constexpr int kArnGroup = 8;
 
+// Sum of p[0..nblk) by one wave: lane strides, then a butterfly.  Every wave and workgroup that
+// sums the same values gets the same bits (the butterfly's pairwise sums commute), so a dot product
+// reduced redundantly by each workgroup that needs it equals the copy the host receives.
+__device__ __forceinline__ double wave_sum(const double* __restrict__ p, int nblk, int lane) {
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += p[b];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  return s;
+}
+
+// Arnoldi vector work on 256-element blocks.  mode 0: pout[j][b] = block b's part of V_j . w.
+// mode 1 / 2: h_j = the sums of pin[j][*] (the previous mode's dots, reduced in every workgroup;
+// workgroup 0 also stores them to hout), w -= V h, then mode 1 pout[j][b] = V_j . w, mode 2
+// pout[0][b] = w . w; j < k <= 256.
 template <int MODE>
 __global__ __launch_bounds__(kB) void k_arnoldi(const double* __restrict__ V, int64_t ldv, int k, double* w,
-                                                const double* __restrict__ h, int64_t n, int nblk,
-                                                double* __restrict__ partial) {
+                                                const double* __restrict__ pin, double* __restrict__ hout,
+                                                int64_t n, int nblk, double* __restrict__ pout) {
   __shared__ double red[kArnGroup][kB];
+  __shared__ double hs[256];
   const int64_t e = (int64_t)blockIdx.x * kArnChunk + threadIdx.x;
   const bool in = e < n;
   double we = in ? w[e] : 0.0;
-  if (MODE > 0 && in) {
-    for (int j = 0; j < k; ++j) we -= V[j * ldv + e] * h[j];
-    w[e] = we;
+  if (MODE > 0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < k; j += kB / 64) {
+      const double v = wave_sum(pin + (int64_t)j * nblk, nblk, lane);
+      if (lane == 0) hs[j] = v;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+      for (int j = threadIdx.x; j < k; j += kB) hout[j] = hs[j];
+    if (in) {
+      for (int j = 0; j < k; ++j) we -= V[j * ldv + e] * hs[j];
+      w[e] = we;
+    }
   }
   const int nd = MODE == 2 ? 1 : k;
   for (int d0 = 0; d0 < nd; d0 += kArnGroup) {
@@ -226,25 +252,9 @@ __global__ __launch_bounds__(kB) void k_arnoldi(const double* __restrict__ V, in
       }
       __syncthreads();
     }
-    if (threadIdx.x < kArnGroup && d0 + threadIdx.x < nd) partial[(d0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < kArnGroup && d0 + threadIdx.x < nd) pout[(d0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
     __syncthreads();
   }
-}
-
-// out[d] = sum over blocks of partial[d][b]: strided per-thread sums, then a fixed tree
-__global__ __launch_bounds__(kB) void k_arnoldi_reduce(const double* __restrict__ partial, int nblk,
-                                                       double* __restrict__ out) {
-  __shared__ double red[kB];
-  const int d = blockIdx.x;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kB) s += partial[d * nblk + b];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = kB / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[d] = red[0];
 }
 
 // ------------------------------------------------------------------ batched (segmented) vectors
@@ -313,8 +323,16 @@ __global__ void k_bscale(const double* __restrict__ src, const double* __restric
 
 // Copy n doubles into host-mapped memory, then (after a system-scope fence) the sequence tag, so a
 // host that sees the tag sees the values.
-__global__ __launch_bounds__(kB) void k_publish(const double* __restrict__ src, int n, double* dst,
-                                                unsigned* tag, unsigned seq) {
+// With pnorm set, src[n - 1] is first set to the sum of pnorm[0..nblk) (as k_arnoldi reduces).
+__global__ __launch_bounds__(kB) void k_publish(double* src, int n, const double* __restrict__ pnorm, int nblk,
+                                                double* dst, unsigned* tag, unsigned seq) {
+  if (pnorm) {
+    if (threadIdx.x < 64) {
+      const double v = wave_sum(pnorm, nblk, threadIdx.x);
+      if (threadIdx.x == 0) src[n - 1] = v;
+    }
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i < n; i += kB) dst[i] = src[i];
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -381,18 +399,23 @@ void kr_border(const double* q, const double* ds, int64_t n_ib, int nq, double e
 
 int kr_arnoldi_nblk(int64_t n) { return (int)((n + kArnChunk - 1) / kArnChunk) > 0 ? (int)((n + kArnChunk - 1) / kArnChunk) : 1; }
 
-void kr_arnoldi(int mode, const double* V, int64_t ldv, int k, double* w, const double* h, int64_t n, double* partial,
-                int nblk, double* out, hipStream_t st) {
-  if (mode == 0) hipLaunchKernelGGL(k_arnoldi<0>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
-  else if (mode == 1) hipLaunchKernelGGL(k_arnoldi<1>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
-  else hipLaunchKernelGGL(k_arnoldi<2>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, h, n, nblk, partial);
+void kr_arnoldi_step(const double* V, int64_t ldv, int k, double* w, int64_t n, double* partial, int nblk,
+                     double* h, hipStream_t st) {
+  if (k < 1 || k > 256) throw Error(-2, "Arnoldi step: 1 <= k <= 256");
+  double* p0 = partial;
+  double* p1 = partial + (int64_t)k * nblk;
+  double* p2 = p1 + (int64_t)k * nblk;
+  hipLaunchKernelGGL(k_arnoldi<0>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, nullptr, nullptr, n, nblk, p0);
   IBDL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_arnoldi_reduce, dim3(mode == 2 ? 1 : k), dim3(kB), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL(k_arnoldi<1>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, p0, h, n, nblk, p1);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_arnoldi<2>, dim3(nblk), dim3(kB), 0, st, V, ldv, k, w, p1, h + 256, n, nblk, p2);
   IBDL_LAUNCH_CHECK();
 }
 
-void kr_publish(const double* src, int n, double* host_dst, unsigned* host_tag, unsigned seq, hipStream_t st) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kB), 0, st, src, n, host_dst, host_tag, seq);
+void kr_publish(double* src, int n, const double* pnorm, int nblk, double* host_dst, unsigned* host_tag,
+                unsigned seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kB), 0, st, src, n, pnorm, nblk, host_dst, host_tag, seq);
   IBDL_LAUNCH_CHECK();
 }
 
