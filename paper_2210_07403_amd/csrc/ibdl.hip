@@ -738,11 +738,11 @@ double host_norm(ibdl_s* h, const double* v, int64_t n) {
   return sqrt(h->hostbuf[0]);
 }
 
-// Publish n device doubles (the last one first reduced from pnorm, see kr_publish) to slot `slot`
+// Publish n device doubles (src[norm_at] first reduced from pnorm, see kr_publish) to slot `slot`
 // of the host-mapped buffer (stream-ordered); returns the sequence number its tag will carry.
-unsigned publish(ibdl_s* h, double* src, int n, const double* pnorm, int nblk, int slot) {
+unsigned publish(ibdl_s* h, double* src, int n, const double* pnorm, int nblk, int norm_at, int slot) {
   const unsigned seq = ++h->seq;
-  kr_publish(src, n, pnorm, nblk, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq, h->st);
+  kr_publish(src, n, pnorm, nblk, norm_at, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq, h->st);
   return seq;
 }
 
@@ -812,25 +812,19 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   const int nblk = kr_nblk(n);
   const int anblk = kr_arnoldi_nblk(n);
   ensure_partial(h, std::max(nblk * (maxit + 2), anblk * (2 * maxit + 3)));
-  const double beta = host_norm(h, b, n);
   *iters = 0;
   *relres = 0.0;
-  if (!(beta > 0.0)) {
-    IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
-    if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
-    return IBDL_OK;
-  }
   const bool graph = ensure_graph(h, trans);
   double* gin = graph ? h->gx : nullptr;
-  kr_scale(b, 1.0 / beta, h->V, n, h->st);
-  if (graph) IBDL_HIP(hipMemcpyAsync(h->gx, h->V, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+  // |b|^2 (small[520]) and V[0] = b / |b| (also the graph's input) on the device, so that step 0 is
+  // queued without a host round trip; the host learns |b| with step 0's values
+  kr_multidot(b, n, 1, b, n, h->partial, nblk, h->small + 520, h->st);
+  kr_scale_norm(b, h->small + 520, 0.0, h->V, gin, n, h->st);
   std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0);
-  gv[0] = beta;
   int k = 0;
   double res = 1.0;
-  // h->small: first Gram-Schmidt coefficients [0, 256), second [256, 512), |w|^2 at 512
+  // h->small: first Gram-Schmidt coefficients [0, 256), second [256, 512), |w|^2 at 512, |b|^2 at 520
   double* hn = h->small + 512;
-  const double tiny = 1e-300 * beta;
   unsigned seq[2] = {0, 0};
   // queue Arnoldi step j (V[j] is in place, and in gx for the graph); returns where w is
   auto step = [&](int j) -> double* {
@@ -843,14 +837,15 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
       apply_any(h, h->V + (int64_t)j * n, w, false, trans);
     }
     kr_arnoldi_step(h->V, n, j + 1, w, n, h->partial, anblk, h->small, h->st);
-    seq[j & 1] = publish(h, h->small, 513, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, j & 1);
+    seq[j & 1] = publish(h, h->small, 521, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, 512, j & 1);
     return w;
   };
   double* w = step(0);
-  auto next = [&](int j) {   // queue step j + 1 behind step j
-    kr_scale_norm(w, hn, tiny, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
+  auto next = [&](int j) {   // queue step j + 1 behind step j (a breakdown is found by the host)
+    kr_scale_norm(w, hn, 0.0, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
     w = step(j + 1);
   };
+  double beta = 0.0, tiny = 0.0;
   std::vector<double> rs(maxit, 1.0);   // residual estimates of the steps the host has finished
   for (int j = 0; j < maxit; ++j) {
     // Step j + 1 is queued ahead unless step j is predicted to converge: the residual ratio of the
@@ -860,6 +855,17 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     if (ahead && j >= 2) ahead = rs[j - 1] * (rs[j - 1] / rs[j - 2]) > tol;
     if (ahead) next(j);
     const volatile double* hv = wait_published(h, j & 1, seq[j & 1]);
+    if (j == 0) {
+      beta = sqrt(std::max((double)hv[520], 0.0));
+      if (!(beta > 0.0)) {   // b = 0: x = 0 (behind the queued steps, which ran on zeros)
+        if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
+        IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
+        IBDL_HIP(hipStreamSynchronize(h->st));
+        return IBDL_OK;
+      }
+      gv[0] = beta;
+      tiny = 1e-300 * beta;
+    }
     double* Hj = &H[(size_t)j * (maxit + 1)];
     for (int i = 0; i <= j; ++i) Hj[i] = hv[i] + hv[256 + i];
     const double hnext = sqrt(std::max((double)hv[512], 0.0));

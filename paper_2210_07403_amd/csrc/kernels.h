@@ -214,7 +214,7 @@ void kr_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w
 void kr_lincomb(const double* V, int64_t ldv, int k, const double* y, double* x, int64_t n, hipStream_t st);
 void kr_scale(const double* src, double s, double* dst, int64_t n, hipStream_t st);
 // dst (and dst2 unless NULL) = src / sqrt(max(*nrm2, 0)) with the norm read on the device; zero
-// when the norm is not above floor
+// when the norm is not above floor or not finite
 void kr_scale_norm(const double* src, const double* nrm2, double floor, double* dst, double* dst2, int64_t n,
                    hipStream_t st);
 void kr_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t st);
@@ -230,11 +230,11 @@ int kr_nblk(int64_t n);
 void kr_arnoldi_step(const double* V, int64_t ldv, int k, double* w, int64_t n, double* partial, int nblk,
                      double* h, hipStream_t st);
 int kr_arnoldi_nblk(int64_t n);
-// Copy src[0..n) to host_dst, with src[n - 1] first set to the sum of pnorm[0..nblk) unless pnorm is
-// NULL.  host_dst / host_tag: device addresses of host-mapped, coherent pinned memory; the tag is
+// Copy src[0..n) to host_dst, with src[norm_at] first set to the sum of pnorm[0..nblk) unless pnorm
+// is NULL.  host_dst / host_tag: device addresses of host-mapped, coherent pinned memory; the tag is
 // written last, after a system-scope fence
-void kr_publish(double* src, int n, const double* pnorm, int nblk, double* host_dst, unsigned* host_tag,
-                unsigned seq, hipStream_t st);
+void kr_publish(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
+                unsigned* host_tag, unsigned seq, hipStream_t st);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

@@ -69,7 +69,7 @@ __global__ void k_scale_norm(const double* src, const double* __restrict__ nrm2,
                              double* dst2, int64_t n) {
   const double v = *nrm2;
   const double h = sqrt(v > 0.0 ? v : 0.0);
-  const double s = h > floor ? 1.0 / h : 0.0;
+  const double s = (h > floor && h < INFINITY) ? 1.0 / h : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const double x = src[e] * s;
     dst[e] = x;
@@ -323,13 +323,13 @@ __global__ void k_bscale(const double* __restrict__ src, const double* __restric
 
 // Copy n doubles into host-mapped memory, then (after a system-scope fence) the sequence tag, so a
 // host that sees the tag sees the values.
-// With pnorm set, src[n - 1] is first set to the sum of pnorm[0..nblk) (as k_arnoldi reduces).
+// With pnorm set, src[norm_at] is first set to the sum of pnorm[0..nblk) (as k_arnoldi reduces).
 __global__ __launch_bounds__(kB) void k_publish(double* src, int n, const double* __restrict__ pnorm, int nblk,
-                                                double* dst, unsigned* tag, unsigned seq) {
+                                                int norm_at, double* dst, unsigned* tag, unsigned seq) {
   if (pnorm) {
     if (threadIdx.x < 64) {
       const double v = wave_sum(pnorm, nblk, threadIdx.x);
-      if (threadIdx.x == 0) src[n - 1] = v;
+      if (threadIdx.x == 0) src[norm_at] = v;
     }
     __syncthreads();
   }
@@ -413,9 +413,9 @@ void kr_arnoldi_step(const double* V, int64_t ldv, int k, double* w, int64_t n, 
   IBDL_LAUNCH_CHECK();
 }
 
-void kr_publish(double* src, int n, const double* pnorm, int nblk, double* host_dst, unsigned* host_tag,
-                unsigned seq, hipStream_t st) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kB), 0, st, src, n, pnorm, nblk, host_dst, host_tag, seq);
+void kr_publish(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
+                unsigned* host_tag, unsigned seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kB), 0, st, src, n, pnorm, nblk, norm_at, host_dst, host_tag, seq);
   IBDL_LAUNCH_CHECK();
 }
 
