@@ -68,7 +68,6 @@ def stage_cost(spec, prec, pr):
     _, nseg, tile = pr.spread_tiles()
     Rb = nseg * tile[0] * t
     b = {
-        "fill": ("hbm", c * Ra),
         "fft_x_fwd": ("hbm", c * (Rb + Ca)),
         "fft_x_inv": ("hbm", o * (Ca + Ra)),
         "interp": ("hbm", spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2)),

@@ -234,7 +234,7 @@ ibdl_status_t ibdl_set_timing(ibdl_t h, int32_t enable);
 /* Accumulated milliseconds and launch counts per stage since ibdl_set_timing(h, 1), stage ids:
  * 0 spread, 1 x-axis forward FFT, 2 y-axis forward FFT (3-D), 3 fused last-axis FFT + multiplier,
  * 4 y-axis inverse FFT (3-D), 5 x-axis inverse FFT, 6 interpolation, 7 Krylov vectors (not
- * instrumented), 8 zero fill of the spread fields.
+ * instrumented), 8 zero fill (none in the current operator apply: always 0).
  * ms and count are host arrays of cap entries (cap >= 9 returns every stage).  Synchronises on the
  * recorded events. */
 ibdl_status_t ibdl_get_timing(ibdl_t h, double* ms, int64_t* count, int32_t cap);

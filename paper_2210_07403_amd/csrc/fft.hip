@@ -257,12 +257,15 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   __shared__ int64_t rbase[kBlock];   // row index of each block row (active-row list or contiguous)
   __shared__ unsigned long long rseg[kBlock];   // busy x-segments of each block row
+  __shared__ int64_t rsub[kBlock];              // forcing row to subtract, or -1
   for (int r = tid; r < RPB; r += NT) {
     rbase[r] = r < nvalid ? rl.row(row0 + r) : 0;
     rseg[r] = r < nvalid ? rl.segmask(row0 + r) : 0ull;
+    rsub[r] = r < nvalid ? rl.sub_row(row0 + r) : -1;
   }
   __syncthreads();
   const C* src = reinterpret_cast<const C*>(in);
+  const C* sub = static_cast<const C*>(rl.sub);
   // every load of a thread is issued before the first LDS write (RPB * M values, M / T per thread)
   constexpr int K = M / RC::T;
   C ld[K];
@@ -271,6 +274,10 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
     const int e = tid + j * NT, r = e / M, c = e - r * M;
     ld[j] = mk<C>(0, 0);
     if ((rseg[r] >> (c >> rl.seg_log2)) & 1ull) ld[j] = src[rbase[r] * M + c];
+    if (rsub[r] >= 0) {
+      const C f = sub[rsub[r] * M + c];
+      ld[j] = mk<C>(ld[j].x - f.x, ld[j].y - f.y);
+    }
   }
 #pragma unroll
   for (int j = 0; j < K; ++j) {

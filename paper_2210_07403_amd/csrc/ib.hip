@@ -169,7 +169,7 @@ __global__ void k_row_segments(MarkerGeom g, const int* __restrict__ tile_off, c
                                int64_t nact, unsigned long long* __restrict__ seg) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nact) return;
-  const int w = rows[r], y = w % g.n[1], z = w / g.n[1];
+  const int w = rows ? rows[r] : (int)r, y = w % g.n[1], z = w / g.n[1];
   const int64_t strip = y / g.tile[1] + (int64_t)g.ntile[1] * (g.dim == 3 ? z / g.tile[2] : 0);
   unsigned long long m = 0;
   for (int t = 0; t < g.ntile[0]; ++t) {
@@ -705,16 +705,6 @@ __global__ void k_rows_list(const int* __restrict__ lo, const int* __restrict__ 
   for (int k = threadIdx.x; k < cnt[z]; k += blockDim.x) rows[off[z] + k] = z * ny + lo[z] + k;
 }
 
-// one wave per listed row, 16-byte stores
-template <typename T>
-__global__ __launch_bounds__(64) void k_fill_rows(T* __restrict__ y, const int* __restrict__ rows, int64_t nact,
-                                                  int nx, int64_t rpf) {
-  const int64_t r = blockIdx.x;
-  const int64_t row = rows[r % nact] + (r / nact) * rpf;
-  float4* dst = reinterpret_cast<float4*>(y + row * nx);
-  const int nv = nx * (int)sizeof(T) / 16;
-  for (int v = threadIdx.x; v < nv; v += 64) dst[v] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
 
 // ------------------------------------------------------------------ kernel-derivative gather
 // One thread per marker over its K^D window (K = 4: taps 1..4 of the 6-node window; K = 6: all),
@@ -880,14 +870,6 @@ void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int*
   IBDL_LAUNCH_CHECK();
 }
 
-template <typename T>
-void grid_fill_rows(T* y, const int* rows, int64_t nact, int nx, int nfields, int64_t rpf, hipStream_t st) {
-  const int64_t nb = nact * nfields;
-  if (nb == 0) return;
-  if ((nx * (int)sizeof(T)) % 16 != 0) throw Error(-2, "grid_fill_rows: rows must be a multiple of 16 bytes");
-  hipLaunchKernelGGL((k_fill_rows<T>), dim3((unsigned)nb), dim3(64), 0, st, y, rows, nact, nx, rpf);
-  IBDL_LAUNCH_CHECK();
-}
 
 template <typename T>
 void grid_fill_zero(T* y, int64_t n, hipStream_t st) {
@@ -986,7 +968,6 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
   template void spread<T>(const SpreadArgs&, const cplx<T>*, T*, hipStream_t);            \
   template void weight_table<T>(const double*, int64_t, cplx<T>*, hipStream_t);           \
   template void grid_fill_zero<T>(T*, int64_t, hipStream_t);                              \
-  template void grid_fill_rows<T>(T*, const int*, int64_t, int, int, int64_t, hipStream_t); \
   template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
   template void gather_dx<T>(const GatherArgs&, hipStream_t);                             \

@@ -60,7 +60,8 @@ struct ibdl_s {
   int4* busy_tmp = nullptr;
   int* busy_off = nullptr;
   int nbusy = 0;
-  unsigned long long* seg = nullptr;   // busy x-segments of each active row (RowList::seg)
+  unsigned long long* seg = nullptr;       // busy x-segments of each active row (RowList::seg)
+  unsigned long long* seg_all = nullptr;   // busy x-segments of every row of a field
   // active rows (rows of the markers' windows): list for the x passes, per-plane limits for y
   int *row_lo = nullptr, *row_hi = nullptr, *row_cnt = nullptr, *row_off = nullptr, *rows = nullptr;
   int2* row_lim = nullptr;
@@ -281,19 +282,26 @@ enum RowsMode { ROWS_DENSE = 0, ROWS_SPARSE = 1, ROWS_OUT = 2 };
 
 template <typename T>
 void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md,
-              int rows = ROWS_DENSE, bool busy_only = false) {
+              int rows = ROWS_DENSE, bool busy_only = false, const T* sub = nullptr, int sub_f0 = 0, int nsub = 0) {
   const int64_t rows_per_field = h->ntot / h->n[0];
   const bool sin = rows == ROWS_SPARSE, sout = rows != ROWS_DENSE;
   RowList rl_in, rl_out;
   RowMask fwd, inv, fused;
+  rl_in.rpf = rows_per_field;
+  if (busy_only) {   // src holds a spread's output: only its busy tiles were written
+    rl_in.seg = sin ? h->seg : h->seg_all;
+    rl_in.seg_log2 = __builtin_ctz((unsigned)h->geom.tile[0] / 2);
+  }
+  rl_in.sub = sub;   // minus a dense forcing on fields sub_f0 .. sub_f0 + nsub - 1
+  rl_in.sub_f0 = sub_f0;
+  rl_in.nsub = nsub;
   if (sout) {
     rl_out.rows = h->rows;
     rl_out.nact = h->nact;
     rl_out.rpf = rows_per_field;
-    if (sin) rl_in = rl_out;
-    if (sin && busy_only) {   // src holds a spread's output: only its busy tiles were written
-      rl_in.seg = h->seg;
-      rl_in.seg_log2 = __builtin_ctz((unsigned)h->geom.tile[0] / 2);
+    if (sin) {
+      rl_in.rows = h->rows;
+      rl_in.nact = h->nact;
     }
     if (h->dim == 3) {
       fwd.lim = inv.lim = h->row_lim;
@@ -336,12 +344,6 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   }
 }
 
-// zero nf spread fields: the active rows only when the pipeline runs sparse
-template <typename T> void clear_fields(ibdl_s* h, T* y, int nf, bool sparse) {
-  StageTimer t(h, ST_FILL);
-  if (sparse) grid_fill_rows<T>(y, h->rows, h->nact, h->n[0], nf, h->ntot / h->n[0], h->st);
-  else grid_fill_zero<T>(y, h->ntot * nf, h->st);
-}
 
 SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
   SpreadArgs a{};
@@ -438,19 +440,15 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
   // FD: the mass term of the fused field carries eta q and m; a forcing is subtracted afterwards
   a.mass = pl.mode == SP_FDDIV ? ((h->cfg.eta > 0 || m != nullptr) ? 1 : 0) : (mass ? 1 : 0);
   a.m = m;
-  // sparse without forcing: the x pass reads the spread's busy tiles only, nothing to clear
-  const bool busy_only = sparse && g == nullptr;
-  if (!busy_only) clear_fields<T>(h, W.real, pl.nf, sparse);
+  // The x pass reads the spread's busy tiles only (nothing to clear) and subtracts the forcing g
+  // from its field(s) as it loads them.
   {
     StageTimer t(h, ST_SPREAD);
     spread_w<T>(h, a, W, W.real);
   }
-  if (g) {
-    if (pl.mode == SP_STOKES) grid_axpby<T>(W.real + 3 * h->ntot, -1.0, g, 1.0, 2 * h->ntot, h->st);
-    else if (pl.mode == SP_FDDIV) grid_axpby<T>(W.real, -1.0, g, 1.0, h->ntot, h->st);
-    else grid_axpby<T>(W.real + h->dim * h->ntot, -1.0, g, 1.0, h->ntot, h->st);
-  }
-  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse ? ROWS_SPARSE : ROWS_DENSE, busy_only);
+  const int sub_f0 = pl.mode == SP_STOKES ? 3 : (pl.mode == SP_FDDIV ? 0 : h->dim);
+  pipeline<T>(h, W, W.real, pl.nf, dst, pl.nout, pl.md, sparse ? ROWS_SPARSE : ROWS_DENSE, true, g, sub_f0,
+              g ? (pl.mode == SP_STOKES ? 2 : 1) : 0);
 }
 
 // Launch shapes of the apply's FFT passes by measurement: rows per block of the x passes, lines
@@ -987,6 +985,8 @@ void build_markers(ibdl_s* h) {
   h->lim2d[1] = l2.y;
   {   // busy x-segments of the active rows; their count is reported by ibdl_spread_tiles
     markers_row_segments(h->geom, h->tile_off, h->rows, na, h->seg, h->st);
+    markers_row_segments(h->geom, h->tile_off, nullptr, (int64_t)h->n[1] * (h->dim == 3 ? h->n[2] : 1), h->seg_all,
+                         h->st);
     std::vector<unsigned long long> seg(na);
     if (na > 0)
       IBDL_HIP(hipMemcpyAsync(seg.data(), h->seg, sizeof(unsigned long long) * na, hipMemcpyDeviceToHost, h->st));
@@ -1074,6 +1074,8 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->row_lim = (int2*)h->dalloc<int>(sizeof(int2) * nplanes);
     h->rows = (int*)h->dalloc<int>(sizeof(int) * (int64_t)h->n[1] * nplanes);
     h->seg = (unsigned long long*)h->dalloc<unsigned long long>(sizeof(unsigned long long) * (int64_t)h->n[1] * nplanes);
+    h->seg_all =
+        (unsigned long long*)h->dalloc<unsigned long long>(sizeof(unsigned long long) * (int64_t)h->n[1] * nplanes);
     h->small = (double*)h->dalloc<double>(sizeof(double) * 1024);
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);

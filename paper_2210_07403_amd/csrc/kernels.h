@@ -21,14 +21,26 @@ enum FieldKind {
 // nothing else, so with seg set the forward x pass reads only the busy x-segments of a row and takes
 // the others as zero: seg[r] has bit t set when x-segment t (2^seg_log2 complex values, one tile
 // wide) of listed row r is in a busy tile.  The fields need no clearing then.
+// With sub set, the forward x pass reads (field f, row w) minus sub[(f - sub_f0) * rpf + w] for the
+// nsub fields from sub_f0 on (a dense forcing of the grid type, [nsub][rows per field][nx]).
 struct RowList {
   const int* rows = nullptr;   // active rows of one field, increasing (NULL: every row)
   int64_t nact = 0;            // active rows per field
   int64_t rpf = 0;             // rows per field
-  const unsigned long long* seg = nullptr;   // busy x-segments per listed row (NULL: read everything)
-  int seg_log2 = 3;
+  const unsigned long long* seg = nullptr;   // busy x-segments per listed row, or per row without a
+  int seg_log2 = 3;                          // list (NULL: read everything)
+  const void* sub = nullptr;
+  int sub_f0 = 0, nsub = 0;
   __device__ int64_t row(int64_t r) const { return rows ? (int64_t)rows[r % nact] + (r / nact) * rpf : r; }
-  __device__ unsigned long long segmask(int64_t r) const { return seg ? seg[r % nact] : ~0ull; }
+  __device__ unsigned long long segmask(int64_t r) const {
+    return seg ? seg[rows ? r % nact : r % rpf] : ~0ull;
+  }
+  __device__ int64_t sub_row(int64_t r) const {   // row of sub to subtract from listed row r, or -1
+    if (!sub) return -1;
+    const int64_t f = rows ? r / nact : r / rpf;
+    const int64_t w = rows ? (int64_t)rows[r % nact] : r % rpf;
+    return (f >= sub_f0 && f < sub_f0 + nsub) ? (f - sub_f0) * rpf + w : -1;
+  }
 };
 struct RowMask {
   const int2* lim = nullptr;   // per plane z: rows y in [lim.x, lim.y] matter (NULL: all)
@@ -126,13 +138,10 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
 // the count is off[planes].  planes = nz in 3-D, 1 in 2-D.
 void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int* hi, int* cnt, int* off, int2* lim,
                   int* rows, hipStream_t st);
-// seg[r] = bit mask of the busy tiles along x that listed row r (rows[r], r < nact) passes through
-// (ntile[0] <= 64)
+// seg[r] = bit mask of the busy tiles along x that listed row r (rows[r], r < nact; row r itself
+// when rows is NULL) passes through (ntile[0] <= 64)
 void markers_row_segments(const MarkerGeom& g, const int* tile_off, const int* rows, int64_t nact,
                           unsigned long long* seg, hipStream_t st);
-// zero the listed rows of nfields fields (rpf rows per field, nx values per row)
-template <typename T>
-void grid_fill_rows(T* y, const int* rows, int64_t nact, int nx, int nfields, int64_t rpf, hipStream_t st);
 
 enum SpreadMode {
   SP_PLAIN = 0,     // nf fields: coef_c = f[i][c] ds_i h^-D
