@@ -125,7 +125,11 @@ __device__ __forceinline__ void stage_compute(C* v, int i, const C* __restrict__
   }
 }
 
-template <int N, int S, int RMX, typename C>
+// LDS slot of line element e: e * es, or, for a contiguous line (es = 1) with PAD > 0, e plus one
+// pad slot every 2^PAD elements, so that a stage's strided stores do not fall into the same banks
+template <int PAD> __device__ __forceinline__ int lslot(int e, int es) { return PAD ? e + (e >> PAD) : e * es; }
+
+template <int N, int S, int RMX, int PAD = 0, typename C>
 __device__ __forceinline__ void stage_store(const C* v, int i, C* lds, int es) {
   using P = Plan<N, RMX>;
   constexpr int R = P::radix(S), PP = P::pw(S), NB = P::RMAX / R, TT = P::T;
@@ -134,14 +138,14 @@ __device__ __forceinline__ void stage_store(const C* v, int i, C* lds, int es) {
     const int b = i + m * TT;
     const int k = b & (PP - 1);
 #pragma unroll
-    for (int j = 0; j < R; ++j) lds[((b - k) * R + k + j * PP) * es] = v[m + j * NB];
+    for (int j = 0; j < R; ++j) lds[lslot<PAD>((b - k) * R + k + j * PP, es)] = v[m + j * NB];
   }
 }
 
-template <int N, int RMX, typename C>
+template <int N, int RMX, int PAD = 0, typename C>
 __device__ __forceinline__ void line_load(C* v, int i, const C* lds, int es) {
 #pragma unroll
-  for (int s = 0; s < RMX; ++s) v[s] = lds[(i + s * Plan<N, RMX>::T) * es];
+  for (int s = 0; s < RMX; ++s) v[s] = lds[lslot<PAD>(i + s * Plan<N, RMX>::T, es)];
 }
 
 // Global loads / stores of a line's register elements i + s*T: element o0 + (i + s*T) * es of the
@@ -204,17 +208,17 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // Full line transform on registers v (pattern i + s*T).  All threads of the block must call it
 // (it contains block barriers when N needs more than one stage).  lds: this line's exchange
 // buffer with element stride es; the caller must not rely on its contents afterwards.
-template <int N, bool INV, bool BATCH = false, int RMX = plan_rmax(N), int S = 0, typename C>
+template <int N, bool INV, bool BATCH = false, int RMX = plan_rmax(N), int PAD = 0, int S = 0, typename C>
 __device__ __forceinline__ void fft_line(C* v, int i, C* lds, int es, const C* __restrict__ tw, int tws) {
   if constexpr (S < Plan<N, RMX>::NST) {
     stage_compute<N, S, INV, BATCH, RMX>(v, i, tw, tws);
     if constexpr (S + 1 < Plan<N, RMX>::NST) {
       __syncthreads();
-      stage_store<N, S, RMX>(v, i, lds, es);
+      stage_store<N, S, RMX, PAD>(v, i, lds, es);
       __syncthreads();
-      line_load<N, RMX>(v, i, lds, es);
+      line_load<N, RMX, PAD>(v, i, lds, es);
     }
-    fft_line<N, INV, BATCH, RMX, S + 1>(v, i, lds, es, tw, tws);
+    fft_line<N, INV, BATCH, RMX, PAD, S + 1>(v, i, lds, es, tw, tws);
   }
 }
 
@@ -233,7 +237,8 @@ constexpr int xrmax(int M) { return plan_rmax(M) < 8 ? plan_rmax(M) : 8; }   // 
 template <typename TR, int M> struct RowCfg {
   static constexpr int RMX = xrmax(M);
   static constexpr int T = Plan<M, RMX>::T;
-  static constexpr int LS = M + 1;  // LDS row stride (complex elements)
+  static constexpr int PAD = 3;      // line exchanges pad one slot every 8 elements
+  static constexpr int LS = M + (M >> PAD) + 1;  // LDS row stride (complex elements)
   static constexpr int R0 = kBlock / T;
   static constexpr int RL = pow2floor((kLdsBytes - 2 * M * (int)sizeof(cplx<TR>)) / (LS * (int)sizeof(cplx<TR>)));
   static constexpr int RPB = (R0 < RL ? R0 : RL) > 0 ? (R0 < RL ? R0 : RL) : 1;
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   const int row = tid / RC::T, i = tid - row * RC::T;
   C v[RC::RMX];
   if (row < RPB) line_load<M, RC::RMX>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, false, false, RC::RMX>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
+  fft_line<M, false, false, RC::RMX, RC::PAD>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
   if (row < RPB) {
 #pragma unroll
@@ -341,8 +346,8 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   }
 #pragma unroll
   for (int j = 0; j < KI; ++j) {
-    const int e = tid + j * NT;
-    if (e < RPB * (M + 1)) lds[e] = ld[j];
+    const int e = tid + j * NT, r = e / (M + 1), k = e - r * (M + 1);
+    if (e < RPB * (M + 1)) lds[r * RC::LS + k] = ld[j];
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{M-k}) + i conj(W^k) (X_k - conj X_{M-k}); each thread owns a pair (k, M-k)
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   const int row = tid / RC::T, i = tid - row * RC::T;
   C v[RC::RMX];
   if (row < RPB) line_load<M, RC::RMX>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, true, false, RC::RMX>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
+  fft_line<M, true, false, RC::RMX, RC::PAD>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
   if (row < RPB) {
 #pragma unroll
