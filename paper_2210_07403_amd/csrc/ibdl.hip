@@ -897,8 +897,9 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   }
   for (int i = 0; i < k; ++i) h->hostbuf[i] = y[i];
   IBDL_HIP(hipMemcpyAsync(h->small + 768, h->hostbuf, sizeof(double) * k, hipMemcpyHostToDevice, h->st));
+  // x is left to the stream: the caller's next work is queued behind it.  hostbuf is not written
+  // again before a later wait on this stream has passed the copy.
   kr_lincomb(h->V, n, k, h->small + 768, x, n, h->st);
-  IBDL_HIP(hipStreamSynchronize(h->st));
   *iters = k;
   *relres = res;
   return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;
