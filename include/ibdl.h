@@ -201,6 +201,30 @@ ibdl_status_t ibdl_batch_query(ibdl_batch_t b, int32_t group, int32_t* ngroups, 
 /* Message of the last failure on the batch (or of the last failed ibdl_batch_create for NULL). */
 const char* ibdl_batch_last_error(ibdl_batch_t b);
 
+/* Indicator function of the interior of the markers' closed curve(s), two-dimensional handles
+ * only (Sec. 5.3.4, flagging interior and exterior points).  chi is the mean-zero solution of
+ * Delta chi + S~ 1 = 0 (S~: the dipole spread of the unit density with the handle's kernel,
+ * normals and discretisation; the normals point out of the interior), shifted so that the node at
+ * the origin corner is 0; the curve then carries about 1/2, and chi = 1 where the shifted field is
+ * at least 1/2, else 0.  chi and regularized (the shifted field before the threshold; may be NULL)
+ * are [ny][nx] of the grid type, device, owned by the caller.  Asynchronous on the handle's
+ * stream. */
+ibdl_status_t ibdl_indicator(ibdl_t h, void* chi, void* regularized);
+
+/* Near-boundary interpolation, two-dimensional scalar handles (Sec. 5.3.3, interpolation for
+ * near-boundary points).  out = u, except at the nodes p with omega != 0 whose nearest marker is
+ * within m1 h: there x_A = the point closest to p on the segment between the two nearest markers
+ * (if the projection leaves it, the two of the three nearest markers farthest apart, projection
+ * clamped), u(x_A) = the linear interpolation of Ub (device double [n_ib]) between them,
+ * x_B = x_A + m2 h (p - x_A) / |p - x_A|, u(x_B) = the bilinear interpolation of u, and
+ * out(p) = the linear interpolation between u(x_A) and u(x_B) at p.  Distances are plain
+ * Euclidean (the curve keeps clear of the box faces); ties between markers go to the lower index.
+ * omega (the nodes of the PDE domain, e.g. ibdl_indicator's chi or 1 - chi), u, out: [ny][nx] of
+ * the grid type, device; out must not alias u.  1 <= m1 < m2 <= 16 (the thesis uses m1 = 6,
+ * m2 = 8 with finite differences).  Asynchronous on the handle's stream. */
+ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, const void* u, double m1, double m2,
+                                 void* out);
+
 /* Sizes of the handle: n_aug (unknowns), grid points per component, grid components of the
  * solution (nq).  Any output pointer may be NULL. */
 ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq);

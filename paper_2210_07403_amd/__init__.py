@@ -192,6 +192,27 @@ class Problem:
         B.check(B.load().ibdl_active_rows(self._h, ctypes.byref(a), ctypes.byref(t)), self._h)
         return int(a.value), int(t.value)
 
+    def indicator(self, regularized=False):
+        """Indicator of the interior of the markers' curve (2-D): chi [ny][nx] of the grid type,
+        and the regularized field before the threshold when regularized=True."""
+        chi = self._grid(1)[0]
+        reg = self._grid(1)[0] if regularized else None
+        B.check(B.load().ibdl_indicator(self._h, chi.data_ptr(), reg.data_ptr() if reg is not None else None),
+                self._h)
+        return (chi, reg) if regularized else chi
+
+    def near_boundary(self, Ub, omega, u, m1=6.0, m2=8.0):
+        """u with its near-boundary nodes of omega replaced by the interpolation of Sec. 5.3.3 (2-D)."""
+        ub = _dev_f64(Ub, self.device).reshape(-1)
+        if ub.numel() != self.n_ib:
+            raise ValueError("Ub must have n_ib entries")
+        om = self._as_grid(omega, 1)
+        ut = self._as_grid(u, 1)
+        out = self._grid(1)[0]
+        B.check(B.load().ibdl_near_boundary(self._h, ub.data_ptr(), om.data_ptr(), ut.data_ptr(), float(m1),
+                                            float(m2), out.data_ptr()), self._h)
+        return out
+
     def spread_tiles(self):
         """(busy tiles, busy row segments the apply's forward x pass reads per field, tile shape)."""
         nb, ns = ctypes.c_int64(), ctypes.c_int64()

@@ -65,6 +65,8 @@ _SIGS = {
     "ibdl_set_timing": (c_int32, [c_void_p, c_int32]),
     "ibdl_set_graph": (c_int32, [c_void_p, c_int32]),
     "ibdl_spread_tiles": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ibdl_indicator": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ibdl_near_boundary": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
     "ibdl_get_timing": (c_int32, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int64), c_int32]),
 }
 

@@ -101,6 +101,11 @@ struct ibdl_s {
       graph[k] = nullptr;
     }
   }
+  double* ones = nullptr;     // indicator: the unit density [n_ib]
+  unsigned char* nb_flag = nullptr;   // near-boundary scratch: node flags [grid]
+  int* nb_count = nullptr;            // near-boundary scratch: listed nodes [1]
+  int* nb_list = nullptr;             // near-boundary scratch: node list
+  int64_t nb_cap = 0;
   double* g64 = nullptr;      // refinement: the forcing widened to double ([nq][grid])
   double* vx = nullptr;       // refinement: correction of one round [n_aug]
   double* adj_m = nullptr;    // adjoint: interpolated fields / gather weights [n_ib][8]
@@ -1015,6 +1020,53 @@ template <typename F> ibdl_status_t guarded(ibdl_s* h, F&& fn) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ near-boundary tools (2-D)
+// Indicator of the interior of the markers' curve(s): Delta chi = -S~ 1 (mean zero), shifted to
+// 0 at the corner node, thresholded at 1/2 (Sec. 5.3.4).
+template <typename T> void indicator_t(ibdl_s* h, T* chi, T* reg) {
+  const int nf = h->fd() ? 1 : h->dim;
+  GridWork<T>& W = ensure_fields<T>(h, nf);
+  if (!h->ones) h->ones = (double*)h->dalloc<double>(sizeof(double) * h->n_ib);
+  fill_value(h->ones, 1.0, h->n_ib, h->st);
+  SpreadArgs a = spread_args(h, h->fd() ? SP_FDDIV : SP_SCALAR_VEC, nf, h->ones);
+  a.mass = 0;
+  spread_w<T>(h, a, W, W.real);
+  MultDesc md = base_desc<T>(h, W);
+  md.mode = 0;
+  md.stokes = 0;
+  md.c2 = 1.0;
+  md.c0 = 0.0;
+  md.alpha = -1.0;
+  md.nc = nf;
+  if (h->fd()) md.fk[0] = FK_MASS;
+  else
+    for (int d = 0; d < h->dim; ++d) md.fk[d] = FK_DX + d;
+  pipeline<T>(h, W, W.real, nf, W.real, 1, md, ROWS_DENSE, true);
+  indicator_finish<T>(W.real, h->ntot, chi, reg, h->st);
+}
+
+// Near-boundary interpolation (Sec. 5.3.3) of u into out on the nodes of omega.
+template <typename T>
+void near_boundary_t(ibdl_s* h, const double* Ub, const T* omega, const T* u, double m1, double m2, T* out) {
+  const int64_t cap = near_list_cap(h->n_ib, m1, h->ntot);
+  if (!h->nb_flag) {
+    h->nb_flag = (unsigned char*)h->dalloc<double>((size_t)h->ntot);
+    h->nb_count = (int*)h->dalloc<int>(sizeof(int));
+  }
+  if (h->nb_cap < cap) {
+    if (h->nb_list) h->dfree(h->nb_list);
+    h->nb_list = (int*)h->dalloc<int>(sizeof(int) * cap);
+    h->nb_cap = cap;
+  }
+  NearGeom g;
+  g.nx = h->n[0];
+  g.ny = h->n[1];
+  g.ox = h->geom.origin[0];
+  g.oy = h->geom.origin[1];
+  g.h = h->h;
+  near_boundary<T>(h->X, Ub, h->n_ib, g, m1, m2, omega, u, out, h->nb_flag, h->nb_count, h->nb_list, h->st);
+}
+
 extern "C" {
 
 ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* X, const double* nrm,
@@ -1137,6 +1189,33 @@ ibdl_status_t ibdl_spread(ibdl_t h, const double* f, int32_t nc, void* grid) {
       grid_fill_zero<double>((double*)grid, h->ntot * nc, h->st);
       spread_w<double>(h, a, ensure_work<double>(h), (double*)grid);
     }
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_indicator(ibdl_t h, void* chi, void* regularized) {
+  return guarded(h, [&]() {
+    if (!chi) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the indicator function is two-dimensional");
+    if (h->mixed()) indicator_t<float>(h, (float*)chi, (float*)regularized);
+    else indicator_t<double>(h, (double*)chi, (double*)regularized);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, const void* u, double m1, double m2,
+                                 void* out) {
+  return guarded(h, [&]() {
+    if (!Ub || !omega || !u || !out) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (out == u) throw Error(IBDL_ERR_ARG, "out must not alias u");
+    if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is two-dimensional");
+    if (h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is for scalar problems");
+    if (!(m1 >= 1.0 && m2 > m1 && m2 <= 16.0)) throw Error(IBDL_ERR_ARG, "need 1 <= m1 < m2 <= 16");
+    if (h->n_ib < 2) throw Error(IBDL_ERR_ARG, "the interpolation needs at least two markers");
+    if (h->mixed())
+      near_boundary_t<float>(h, Ub, (const float*)omega, (const float*)u, m1, m2, (float*)out);
+    else
+      near_boundary_t<double>(h, Ub, (const double*)omega, (const double*)u, m1, m2, (double*)out);
     return IBDL_OK;
   });
 }

@@ -266,6 +266,25 @@ void kb_lincomb(const double* V, int64_t ldv, int k, const double* Y, int ys, co
                 hipStream_t st);
 void kb_scale(const double* src, const double* sc, const KrylovSegments& sg, double* dst, hipStream_t st);
 
+// ------------------------------------------------------------------ near-boundary tools (2-D)
+struct NearGeom {
+  int nx, ny;       // grid points per axis
+  double ox, oy;    // origin
+  double h;
+};
+// chi = (reg_in - reg_in[0] >= 1/2), reg_out (unless NULL) = reg_in - reg_in[0]; n values
+template <typename T>
+void indicator_finish(const T* reg_in, int64_t n, T* chi, T* reg_out, hipStream_t st);
+void fill_value(double* x, double v, int64_t n, hipStream_t st);
+// capacity of the node list near_boundary needs
+int64_t near_list_cap(int64_t n_ib, double m1, int64_t npoints);
+// out = u, then every node with omega != 0 within m1 h of a marker X[i] (2-D, [n_ib][2]) gets the
+// near-boundary interpolation (boundary values Ub, second point m2 h inside).  Scratch: flag
+// [nx * ny] bytes, count [1], list [near_list_cap].
+template <typename T>
+void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGeom& g, double m1, double m2,
+                   const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st);
+
 // ------------------------------------------------------------------ adjoint, marker side
 // y = h^-D ds (.) (combination of the interpolated adjoint fields G [n_ib][ng]) + b p + eta ds pu
 void adj_combine(int stokes, int dim, int64_t n_ib, int ng, double hDinv, double eta, const double* G,
