@@ -199,7 +199,34 @@ def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
                       "sequential_fp64_ms": round(1e3 * tseq, 3),
                       "speedup_batched_mixed_vs_sequential_fp64": round(tseq / (res["mixed"]["ms"] * 1e-3), 2),
                       "speedup_batched_fp64_vs_sequential_fp64": round(tseq / (res["fp64"]["ms"] * 1e-3), 2)}
+    print("# extras: near-boundary tools", file=sys.stderr, flush=True)
+    out["near_boundary_star1024"] = _near_boundary_timing(dev)
     return out
+
+
+def _near_boundary_timing(dev):
+    """Indicator function and near-boundary interpolation (m1 = 6, m2 = 8) on the 1024^2 star
+    (4096 markers), FP64: times, nodes corrected, and the nearest-marker scan's rate (every
+    corrected node tests all markers: 8 flops per pair)."""
+    import numpy as np
+    import torch
+    import paper_2210_07403_amd as ibdl
+    from workloads import problems as P
+    s = P.cfg2_star_poisson(1024, 4096)
+    m = s.markers
+    pr = ibdl.Problem(s.dim, s.n, s.L, s.origin, m.X, m.nrm, m.ds, pde=s.pde, kappa=s.kappa, kernel=s.kernel,
+                      disc=s.disc, precision="fp64", device=dev)
+    data = torch.as_tensor(np.asarray(s.data, dtype=np.float64), device=dev)
+    _, u, _ = pr.solve(data, None, tol=1e-8, maxit=100)
+    chi = pr.indicator()
+    pr.near_boundary(data, chi, u)
+    t_ind, _ = _timed(lambda: pr.indicator(), 5)
+    t_nb, fixed = _timed(lambda: pr.near_boundary(data, chi, u), 5)
+    ncorr = int(torch.count_nonzero(fixed != u))
+    pairs = ncorr * s.n_ib
+    pr.close()
+    return {"indicator_ms": round(1e3 * t_ind, 3), "near_boundary_ms": round(1e3 * t_nb, 3),
+            "nodes_corrected": ncorr, "scan_TFLOP_s": round(8 * pairs / t_nb / 1e12, 3)}
 
 
 def cpu_baseline(spec, budget_s=20.0):

@@ -220,10 +220,16 @@ ibdl_status_t ibdl_indicator(ibdl_t h, void* chi, void* regularized);
  * out(p) = the linear interpolation between u(x_A) and u(x_B) at p.  Distances are plain
  * Euclidean (the curve keeps clear of the box faces); ties between markers go to the lower index.
  * omega (the nodes of the PDE domain, e.g. ibdl_indicator's chi or 1 - chi), u, out: [ny][nx] of
- * the grid type, device; out must not alias u.  1 <= m1 < m2 <= 16 (the thesis uses m1 = 6,
- * m2 = 8 with finite differences).  Asynchronous on the handle's stream. */
+ * the grid type, device; out must not alias u.  Needs 1 <= m1 < m2 <= 64 (ibdl_near_widths gives
+ * the thesis's values) and at least two markers.  Asynchronous on the handle's stream. */
 ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, const void* u, double m1, double m2,
                                  void* out);
+
+/* The interpolation widths of Sec. 5.5 (interpolation widths) for the handle's discretisation:
+ * with finite-difference symbols m1 = 6, m2 = 8; with Fourier spectral symbols
+ * m1 = 2 (log2 nx - 4), at least 2, and m2 = m1 + 2.  Host only, synchronous; two-dimensional
+ * handles; either pointer may be NULL. */
+ibdl_status_t ibdl_near_widths(ibdl_t h, double* m1, double* m2);
 
 /* Sizes of the handle: n_aug (unknowns), grid points per component, grid components of the
  * solution (nq).  Any output pointer may be NULL. */

@@ -21,6 +21,9 @@ point p of Omega (chi = 1) within m1 meshwidths of Gamma (distance to the neares
 The bilinear samples read the uncorrected field.  Ties between equally distant markers go to the
 lower marker index.
 
+Widths (Sec. 5.5, interpolation widths): m1 = 6, m2 = 8 with finite differences; with Fourier
+spectral symbols m1 grows by 2 per doubling of N, m1 = 2 (log2 N - 4), and m2 = m1 + 2.
+
 Parity: pinned by tests/test_oracle_nearbdry.py (exactness on linear fields, geometric properties
 of x_A and x_B, nearest markers against brute force, the indicator of a circle against its closed
 form away from the boundary).
@@ -31,6 +34,15 @@ import numpy as np
 
 from . import grid as G
 from .ib import Grid, spread
+
+
+def widths(disc: str, N: int):
+    """(m1, m2) of the thesis's rules for a grid of N points per side; at least m1 = 2 on coarse
+    spectral grids (N < 32), where the logarithmic rule would give no width at all."""
+    if disc == "fd2":
+        return 6.0, 8.0
+    m1 = max(2.0 * (np.log2(N) - 4.0), 2.0)
+    return m1, m1 + 2.0
 
 
 def indicator(grid: Grid, X, nrm, ds, kernel: str, disc: str, regularized: bool = False):

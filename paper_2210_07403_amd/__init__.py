@@ -201,8 +201,19 @@ class Problem:
                 self._h)
         return (chi, reg) if regularized else chi
 
-    def near_boundary(self, Ub, omega, u, m1=6.0, m2=8.0):
-        """u with its near-boundary nodes of omega replaced by the interpolation of Sec. 5.3.3 (2-D)."""
+    def near_widths(self):
+        """(m1, m2) of the thesis's width rules (Sec. 5.5) for this handle's discretisation."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        B.check(B.load().ibdl_near_widths(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return float(a.value), float(b.value)
+
+    def near_boundary(self, Ub, omega, u, m1=None, m2=None):
+        """u with its near-boundary nodes of omega replaced by the interpolation of Sec. 5.3.3 (2-D);
+        m1, m2 default to near_widths()."""
+        if m1 is None or m2 is None:
+            d1, d2 = self.near_widths()
+            m1 = d1 if m1 is None else m1
+            m2 = d2 if m2 is None else m2
         ub = _dev_f64(Ub, self.device).reshape(-1)
         if ub.numel() != self.n_ib:
             raise ValueError("Ub must have n_ib entries")

@@ -67,6 +67,7 @@ _SIGS = {
     "ibdl_spread_tiles": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ibdl_indicator": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_near_boundary": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
+    "ibdl_near_widths": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_get_timing": (c_int32, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int64), c_int32]),
 }
 

@@ -1210,12 +1210,22 @@ ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, 
     if (out == u) throw Error(IBDL_ERR_ARG, "out must not alias u");
     if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is two-dimensional");
     if (h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is for scalar problems");
-    if (!(m1 >= 1.0 && m2 > m1 && m2 <= 16.0)) throw Error(IBDL_ERR_ARG, "need 1 <= m1 < m2 <= 16");
+    if (!(m1 >= 1.0 && m2 > m1 && m2 <= 64.0)) throw Error(IBDL_ERR_ARG, "need 1 <= m1 < m2 <= 64");
     if (h->n_ib < 2) throw Error(IBDL_ERR_ARG, "the interpolation needs at least two markers");
     if (h->mixed())
       near_boundary_t<float>(h, Ub, (const float*)omega, (const float*)u, m1, m2, (float*)out);
     else
       near_boundary_t<double>(h, Ub, (const double*)omega, (const double*)u, m1, m2, (double*)out);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_near_widths(ibdl_t h, double* m1, double* m2) {
+  return guarded(h, [&]() {
+    if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is two-dimensional");
+    const double w1 = h->fd() ? 6.0 : std::max(2.0 * (log2((double)h->n[0]) - 4.0), 2.0);
+    if (m1) *m1 = w1;
+    if (m2) *m2 = w1 + 2.0;
     return IBDL_OK;
   });
 }

@@ -4,7 +4,7 @@
 // The indicator's grid solve runs through the FFT pipeline (ibdl.hip); here are its last step
 // (shift to 0 at the corner node, threshold at 1/2) and the three kernels of the interpolation:
 // marking the nodes within m1 h of a marker, listing the marked nodes of Omega, and the
-// per-node interpolation (three nearest markers by a scan of all markers staged through LDS).
+// per-node interpolation (three nearest markers by a scan of all markers, one wave per node).
 #include <algorithm>
 #include <cmath>
 
@@ -120,60 +120,71 @@ __device__ double bilinear(const T* __restrict__ u, const NearGeom& g, double bx
   return ax * ay * u11 + ay * (1.0 - ax) * u01 + ax * (1.0 - ay) * u10 + (1.0 - ax - ay + ax * ay) * u00;
 }
 
-constexpr int kNB = 256;
+constexpr int kNB = 256;        // threads per block: four waves, one node per wave at a time
+constexpr int kNBBlocks = 2048; // grid-stride over the listed nodes
 
+// One wave per listed node: the lanes scan the markers in a strided split, each keeping its own
+// three nearest by (distance, index), and a butterfly of exchanges merges them; the order is total
+// (indices differ), so every lane ends with the same three markers the sequential scan finds.
 template <typename T>
 __global__ __launch_bounds__(kNB) void k_near_fix(const double* __restrict__ X, const double* __restrict__ Ub,
                                                   int64_t n_ib, NearGeom g, double m2, const int* __restrict__ count,
                                                   const int* __restrict__ list, const T* __restrict__ u,
                                                   T* __restrict__ out) {
-  __shared__ double2 sx[kNB];
   const int n = *count;
-  const int k = blockIdx.x * kNB + threadIdx.x;
-  if (blockIdx.x * kNB >= n) return;   // uniform per block
-  const bool live = k < n;
-  const int e = live ? list[k] : 0;
-  const int pi = e % g.nx, pj = e / g.nx;
-  const double px = g.ox + pi * g.h, py = g.oy + pj * g.h;
-  Near3 nr;
-  nr.init();
-  for (int64_t c0 = 0; c0 < n_ib; c0 += kNB) {
-    __syncthreads();
-    if (c0 + threadIdx.x < n_ib) sx[threadIdx.x] = make_double2(X[2 * (c0 + threadIdx.x)], X[2 * (c0 + threadIdx.x) + 1]);
-    __syncthreads();
-    const int cn = n_ib - c0 < kNB ? (int)(n_ib - c0) : kNB;
-    for (int m = 0; m < cn; ++m) nr.push(dist2(px, py, sx[m].x, sx[m].y), (int)(c0 + m));
-  }
-  if (!live) return;
-  int a = nr.i[0], b = nr.i[1];
-  double t = seg_param(px, py, X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1]);
-  if (!(t >= 0.0 && t <= 1.0) && n_ib >= 3) {   // the two of the three nearest markers farthest apart
-    const int p3[3][2] = {{nr.i[0], nr.i[1]}, {nr.i[0], nr.i[2]}, {nr.i[1], nr.i[2]}};
-    double best = -1.0;
-    for (int q = 0; q < 3; ++q) {
-      const double s = dist2(X[2 * p3[q][0]], X[2 * p3[q][0] + 1], X[2 * p3[q][1]], X[2 * p3[q][1] + 1]);
-      if (s > best) {
-        best = s;
-        a = p3[q][0];
-        b = p3[q][1];
-      }
+  const int lane = threadIdx.x & 63;
+  const int nwaves = gridDim.x * (kNB / 64);
+  const double2* __restrict__ X2 = reinterpret_cast<const double2*>(X);
+  for (int k = blockIdx.x * (kNB / 64) + (threadIdx.x >> 6); k < n; k += nwaves) {
+    const int e = list[k];
+    const int pi = e % g.nx, pj = e / g.nx;
+    const double px = g.ox + pi * g.h, py = g.oy + pj * g.h;
+    Near3 nr;
+    nr.init();
+    for (int64_t m = lane; m < n_ib; m += 64) {
+      const double2 q = X2[m];
+      nr.push(dist2(px, py, q.x, q.y), (int)m);
     }
-    t = seg_param(px, py, X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1]);
+    for (int off = 32; off >= 1; off >>= 1) {
+      double od[3];
+      int oi[3];
+      for (int c = 0; c < 3; ++c) {
+        od[c] = __shfl_xor(nr.d[c], off, 64);
+        oi[c] = __shfl_xor(nr.i[c], off, 64);
+      }
+      for (int c = 0; c < 3; ++c) nr.push(od[c], oi[c]);
+    }
+    if (lane != 0) continue;
+    int a = nr.i[0], b = nr.i[1];
+    double t = seg_param(px, py, X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1]);
+    if (!(t >= 0.0 && t <= 1.0) && n_ib >= 3) {   // the two of the three nearest markers farthest apart
+      const int p3[3][2] = {{nr.i[0], nr.i[1]}, {nr.i[0], nr.i[2]}, {nr.i[1], nr.i[2]}};
+      double best = -1.0;
+      for (int q = 0; q < 3; ++q) {
+        const double s = dist2(X[2 * p3[q][0]], X[2 * p3[q][0] + 1], X[2 * p3[q][1]], X[2 * p3[q][1] + 1]);
+        if (s > best) {
+          best = s;
+          a = p3[q][0];
+          b = p3[q][1];
+        }
+      }
+      t = seg_param(px, py, X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1]);
+    }
+    const double tc = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double x1 = X[2 * a], y1 = X[2 * a + 1], x2 = X[2 * b], y2 = X[2 * b + 1];
+    const double xa = x2 + tc * (x1 - x2), ya = y2 + tc * (y1 - y2);
+    const double l12 = sqrt(dist2(x1, y1, x2, y2));
+    const double uA = Ub[a] * sqrt(dist2(xa, ya, x2, y2)) / l12 + Ub[b] * sqrt(dist2(xa, ya, x1, y1)) / l12;
+    const double dpa = sqrt(dist2(px, py, xa, ya));
+    double up = uA;
+    if (dpa > 0.0) {
+      const double xb = xa + (px - xa) / dpa * (m2 * g.h), yb = ya + (py - ya) / dpa * (m2 * g.h);
+      const double uB = bilinear<T>(u, g, xb, yb);
+      const double dab = sqrt(dist2(xb, yb, xa, ya));
+      up = uA * sqrt(dist2(xb, yb, px, py)) / dab + uB * dpa / dab;
+    }
+    out[e] = (T)up;
   }
-  const double tc = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-  const double x1 = X[2 * a], y1 = X[2 * a + 1], x2 = X[2 * b], y2 = X[2 * b + 1];
-  const double xa = x2 + tc * (x1 - x2), ya = y2 + tc * (y1 - y2);
-  const double l12 = sqrt(dist2(x1, y1, x2, y2));
-  const double uA = Ub[a] * sqrt(dist2(xa, ya, x2, y2)) / l12 + Ub[b] * sqrt(dist2(xa, ya, x1, y1)) / l12;
-  const double dpa = sqrt(dist2(px, py, xa, ya));
-  double up = uA;
-  if (dpa > 0.0) {
-    const double xb = xa + (px - xa) / dpa * (m2 * g.h), yb = ya + (py - ya) / dpa * (m2 * g.h);
-    const double uB = bilinear<T>(u, g, xb, yb);
-    const double dab = sqrt(dist2(xb, yb, xa, ya));
-    up = uA * sqrt(dist2(xb, yb, px, py)) / dab + uB * dpa / dab;
-  }
-  out[e] = (T)up;
 }
 
 }  // namespace
@@ -210,9 +221,10 @@ void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGe
   hipLaunchKernelGGL((k_near_list<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flag, omega, n, count,
                      list);
   IBDL_LAUNCH_CHECK();
-  const int64_t cap = near_list_cap(n_ib, m1, n);
-  hipLaunchKernelGGL((k_near_fix<T>), dim3((unsigned)((cap + kNB - 1) / kNB)), dim3(kNB), 0, st, X, Ub, n_ib, g, m2,
-                     count, list, u, out);
+  const int64_t waves = near_list_cap(n_ib, m1, n);
+  const int64_t nblk = std::min<int64_t>((waves + kNB / 64 - 1) / (kNB / 64), kNBBlocks);
+  hipLaunchKernelGGL((k_near_fix<T>), dim3((unsigned)nblk), dim3(kNB), 0, st, X, Ub, n_ib, g, m2, count, list, u,
+                     out);
   IBDL_LAUNCH_CHECK();
 }
 

@@ -83,6 +83,30 @@ def test_near_boundary_matches_oracle(name, precision, m1, m2):
     pr.close()
 
 
+@pytest.mark.parametrize("N,disc", [(64, "fd2"), (64, "spectral"), (128, "spectral"), (256, "spectral")])
+def test_near_widths_match_oracle(N, disc):
+    pr = make_problem(P.helmholtz_circle(N, 0.75, disc=disc), "fp64")
+    assert pr.near_widths() == NB.widths(disc, N)
+    pr.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_near_boundary_default_widths_spectral(precision):
+    """Spectral symbols at 128^2: the default widths (m1 = 6, m2 = 8 by the logarithmic rule)."""
+    spec = P.helmholtz_circle(128, 0.75, data="linear", disc="spectral")
+    g = _grid(spec)
+    xs, ys = g.nodes()
+    omega = spec.inside(xs, ys).astype(np.float64)
+    u = _field(spec, precision, 11)
+    Ub = np.cos(2 * spec.markers.X[:, 0]) + spec.markers.X[:, 1]
+    pr = make_problem(spec, precision)
+    got = to_np(pr.near_boundary(Ub, omega, u))
+    m1, m2 = NB.widths("spectral", 128)
+    want = NB.near_boundary(g, spec.markers.X, Ub, omega, u, m1, m2)
+    assert np.max(np.abs(got - want)) / np.max(np.abs(want)) < TOL_U[precision]
+    pr.close()
+
+
 def test_pipeline_reduces_max_error():
     """The thesis's linear-solution problem (Sec. 5.5) end to end on the GPU in FP64: solve,
     recover, indicator, interpolation with m1 = 6, m2 = 8; against the oracle's own pipeline."""

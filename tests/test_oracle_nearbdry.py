@@ -5,6 +5,8 @@
 * the bilinear sample reproduces bilinear functions exactly;
 * every step of the interpolation is exact for linear functions, so a field that is linear
   except on the near-boundary points is restored to the linear function there;
+* the width rules give the values the thesis states: 6 and 8 with finite differences, and with
+  spectral symbols m1 from 4 to 20 over N = 64 ... 16384, growing by 2 per doubling, m2 = m1 + 2;
 * the indicator of a circle equals the closed-form inside test at distance of more than 2h from
   the circle, and the regularized field is close to 1/2 on the markers;
 * on the thesis's linear-solution Helmholtz problem (Sec. 5.5: Delta u - u = -(x+y) in the disk,
@@ -20,6 +22,15 @@ from oracle import nearbdry as NB
 from oracle.gmres import gmres
 from oracle.ib import Grid
 from workloads import problems as P
+
+
+def test_width_rules():
+    assert NB.widths("fd2", 1024) == (6.0, 8.0)
+    assert NB.widths("spectral", 64) == (4.0, 6.0)
+    assert NB.widths("spectral", 16384) == (20.0, 22.0)
+    for k in range(6, 14):
+        a, b = NB.widths("spectral", 2 ** k), NB.widths("spectral", 2 ** (k + 1))
+        assert b[0] - a[0] == 2.0 and b[1] == b[0] + 2.0
 
 
 def test_nearest_markers_match_kdtree():
