@@ -11,15 +11,18 @@ operators A, right-hand sides, grid recovery, dense assembly), gmres
 (textbook GMRES), norms (error norms), adjoint (exact gradients of a loss of the
 grid solution with respect to the markers and the boundary data, by forward-mode
 differentiation of the forward map with dense solves), nearbdry (the indicator function of the
-discretized curve and the near-boundary interpolation, 2-D).
+discretized curve and the near-boundary interpolation, 2-D), drag (net force, torque, flux and the
+dimensionless drag of a Stokes solution, 2-D).
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
 closed forms, kernel identities, adjointness, real-space stencils, PDE
 residuals and the iteration counts the thesis prints; the gradients by central
 differences of the pinned forward map (tests/test_oracle_adjoint.py); the near-boundary tools by
 linear exactness, brute force and the closed-form indicator of a circle
-(tests/test_oracle_nearbdry.py).  The 3-D operator has
+(tests/test_oracle_nearbdry.py); the drag by the thesis's printed drag table (asymptotic forms,
+first-order convergence to the reference values), the solvability condition and symmetry
+(tests/test_oracle_drag.py).  The 3-D operator has
 no printed thesis value; it is pinned by closed-form convergence only.
 """
-from . import adjoint, delta, gmres, grid, ib, ibdl, nearbdry, norms  # noqa: F401
+from . import adjoint, delta, drag, gmres, grid, ib, ibdl, nearbdry, norms  # noqa: F401
 from .ibdl import Setup  # noqa: F401

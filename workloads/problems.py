@@ -241,6 +241,22 @@ def stokes_exterior_circle(N, eta=10.0, k=0.0, alpha=1.0, tol=1e-8):
                        lambda x, y: np.hypot(x, y) >= 0.75, meta=dict(curve=curve, alpha=alpha))
 
 
+def cylinder_array(N, c, eta=10.0, alpha=1.0, tol=1e-10):
+    """Sec. 6.5 (Stokes flow around a periodic array of cylinders): Stokes (mu = 1, k = 0) in the
+    periodic box [-0.5, 0.5]^2 outside the disk of area fraction c at the origin, u = 0 on the
+    circle, driven by g = (-1, 0); completed IBDL, spectral, ds ~ alpha h.  The forcing is
+    extended by the same constant inside the disk."""
+    n, L, o = _grid(2, N, 1.0, -0.5)
+    h = 1.0 / N
+    r = math.sqrt(c / math.pi)
+    curve = geo.PolarCurve((0.0, 0.0), r)
+    mk = curve.markers(geo.n_ib_for_spacing(curve.perimeter(), h, alpha)).flipped()
+    g = np.stack([-np.ones((N, N)), np.zeros((N, N))])
+    return ProblemSpec(f"cylinder_array_N{N}_c{c}", 2, n, L, o, "stokes", 0.0, 1.0, "dirichlet", float(eta),
+                       "peskin4", "spectral", mk, np.zeros((mk.X.shape[0], 2)), g, tol, None,
+                       lambda x, y: np.hypot(x, y) >= r, meta=dict(curve=curve, c=c, r=r, alpha=alpha))
+
+
 # ---------------------------------------------------------------- workloads
 def harmonic_poly_2d(rng, center=(0.5, 0.5), degree=4):
     """u = sum_k a_k * {Re, Im}(z - c)^n, n = 1..degree, a_k ~ N(0, 1): harmonic."""
