@@ -231,6 +231,26 @@ ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, 
  * handles; either pointer may be NULL. */
 ibdl_status_t ibdl_near_widths(ibdl_t h, double* m1, double* m2);
 
+/* Net force and torque of a two-dimensional Stokes solution with the completed method (Sec. 6.1,
+ * exterior domains; Sec. 6.5, Stokes flow around a periodic array of cylinders).  The single layer
+ * of strength eta Q carries the whole net force, B = -eta sum_i ds_i Q_i, and the torque about the
+ * coordinate origin, L = -eta sum_i ds_i (X_i,x Q_i,y - X_i,y Q_i,x), with X as the handle was given
+ * it.  q: device double [n_aug], the unknowns of ibdl_solve (Q as [n_ib][2] first).  out: device
+ * double [3] = (B_x, B_y, L), owned by the caller.  Summed in a fixed order (the same bits every
+ * call).  Without the completion (eta = 0) all three are 0.  Asynchronous on the handle's
+ * stream; IBDL_ERR_UNSUPPORTED for scalar or three-dimensional handles. */
+ibdl_status_t ibdl_net_force(ibdl_t h, const double* q, double* out);
+
+/* Line integral of one component of a two-dimensional grid field over a grid line: h times the sum
+ * of the line's nodes (the rectangle rule, exact for the trigonometric polynomials the periodic
+ * grid resolves).  axis 0 takes the line on which x has node index `index` (summed over y), axis 1
+ * the line on which y has node index `index`.  Sec. 6.5 takes the x velocity over the box face
+ * x = origin_x (comp 0, axis 0, index 0) as the flux U of its drag D = B_x / (mu U).  u: device,
+ * grid type, [nq][ny][nx] as ibdl_solve writes it; 0 <= comp < nq; 0 <= index < n[axis].  out:
+ * device double [1], owned by the caller; the sum is in double in a fixed order.  Asynchronous on
+ * the handle's stream. */
+ibdl_status_t ibdl_line_integral(ibdl_t h, const void* u, int32_t comp, int32_t axis, int64_t index, double* out);
+
 /* Sizes of the handle: n_aug (unknowns), grid points per component, grid components of the
  * solution (nq).  Any output pointer may be NULL. */
 ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t* nq);

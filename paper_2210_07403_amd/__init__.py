@@ -201,6 +201,24 @@ class Problem:
                 self._h)
         return (chi, reg) if regularized else chi
 
+    def net_force(self, q):
+        """(B_x, B_y, L) of a 2-D completed Stokes solution q (Sec. 6.1, Sec. 6.5): device double [3]."""
+        qt = _dev_f64(q, self.device).reshape(-1)
+        if qt.numel() != self.n_aug:
+            raise ValueError(f"q must have n_aug = {self.n_aug} entries")
+        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        B.check(B.load().ibdl_net_force(self._h, qt.data_ptr(), out.data_ptr()), self._h)
+        return out
+
+    def line_integral(self, u, comp=0, axis=0, index=0):
+        """h times the sum of component comp of the 2-D grid field u over the grid line on which
+        coordinate `axis` has node index `index`: device double [1]."""
+        ut = self._as_grid(u, self.nq)
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        B.check(B.load().ibdl_line_integral(self._h, ut.data_ptr(), int(comp), int(axis), int(index),
+                                            out.data_ptr()), self._h)
+        return out
+
     def near_widths(self):
         """(m1, m2) of the thesis's width rules (Sec. 5.5) for this handle's discretisation."""
         a, b = ctypes.c_double(), ctypes.c_double()

@@ -1220,6 +1220,31 @@ ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, 
   });
 }
 
+ibdl_status_t ibdl_net_force(ibdl_t h, const double* q, double* out) {
+  return guarded(h, [&]() {
+    if (!q || !out) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (h->dim != 2 || !h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the net force is for 2-D Stokes handles");
+    net_force(h->X, q, h->ds, h->n_ib, h->cfg.eta, out, h->st);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_line_integral(ibdl_t h, const void* u, int32_t comp, int32_t axis, int64_t index, double* out) {
+  return guarded(h, [&]() {
+    if (!u || !out) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "line integrals are for 2-D handles");
+    if (comp < 0 || comp >= h->nq) throw Error(IBDL_ERR_ARG, "comp out of range");
+    if (axis != 0 && axis != 1) throw Error(IBDL_ERR_ARG, "axis must be 0 or 1");
+    if (index < 0 || index >= h->n[axis]) throw Error(IBDL_ERR_ARG, "index out of range");
+    const int64_t nx = h->n[0], ny = h->n[1];
+    const int64_t first = (int64_t)comp * h->ntot + (axis == 0 ? index : index * nx);
+    const int64_t stride = axis == 0 ? nx : 1, len = axis == 0 ? ny : nx;
+    if (h->mixed()) line_sum<float>((const float*)u + first, stride, len, h->h, out, h->st);
+    else line_sum<double>((const double*)u + first, stride, len, h->h, out, h->st);
+    return IBDL_OK;
+  });
+}
+
 ibdl_status_t ibdl_near_widths(ibdl_t h, double* m1, double* m2) {
   return guarded(h, [&]() {
     if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is two-dimensional");

@@ -285,6 +285,14 @@ template <typename T>
 void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGeom& g, double m1, double m2,
                    const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st);
 
+// ------------------------------------------------------------------ force and line integrals (2-D)
+// out[3] = (B_x, B_y, L) of the completed density Q [n_ib][2]: B = -eta sum ds Q, L = -eta sum ds X x Q
+void net_force(const double* X, const double* Q, const double* ds, int64_t n_ib, double eta, double* out,
+               hipStream_t st);
+// out[0] = h * sum_k u[k * stride], k < n
+template <typename T>
+void line_sum(const T* u, int64_t stride, int64_t n, double h, double* out, hipStream_t st);
+
 // ------------------------------------------------------------------ adjoint, marker side
 // y = h^-D ds (.) (combination of the interpolated adjoint fields G [n_ib][ng]) + b p + eta ds pu
 void adj_combine(int stokes, int dim, int64_t n_ib, int ng, double hDinv, double eta, const double* G,
