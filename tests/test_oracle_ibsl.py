@@ -9,6 +9,7 @@
 * iteration counts against the thesis's table for the Helmholtz circle (N = 64 and 128, all four
   spacings): never fewer, and at most 15 % + 2 more (marker phase and the stopping test of the
   thesis's MINRES are not printed);
+* the same for the Brinkman circle (Sec. 2.4.2's table; N = 64 and 128, ds ~ 2 dx and 1.5 dx);
 * solutions converge at first order, on the nodes with r < 0.15, to the closed forms: I_2(r) sin 2 theta / I_2(1/4) (Helmholtz) and 32 x y
   (Poisson, with the border row 1^T F = 0 that g~ = 0 imposes).
 """
@@ -25,6 +26,7 @@ from oracle.minres import minres
 from workloads import problems as P
 
 TABLE = json.loads((pathlib.Path(__file__).parent / "golden" / "ibsl_iterations.json").read_text())
+BRINK = json.loads((pathlib.Path(__file__).parent / "golden" / "ibsl_iterations_brinkman.json").read_text())
 
 
 def _sym(n, seed, indefinite=True):
@@ -94,6 +96,16 @@ def test_iteration_counts_against_table(N):
         _, it, _, ok = minres(o.apply, o.rhs(s.data, s.g), 1e-8, 20000, o.wt)
         assert ok
         assert w <= it <= 1.15 * w + 2, (N, a, it, w)
+
+
+@pytest.mark.parametrize("N,alpha", [(64, 2.0), (64, 1.5), (128, 2.0)])
+def test_brinkman_iteration_counts_against_table(N, alpha):
+    w = BRINK["rows"][str(N)][BRINK["alpha"].index(alpha)]
+    s = P.brinkman_circle(N, alpha)
+    o = IBSL.from_spec(s)
+    _, it, _, ok = minres(o.apply, o.rhs(s.data, s.g), 1e-8, 20000, o.wt)
+    assert ok
+    assert w <= it <= 1.15 * w + 2, (N, alpha, it, w)
 
 
 def _interior_error(s, o, q):
