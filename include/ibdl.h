@@ -60,6 +60,7 @@ enum { IBDL_BC_DIRICHLET = 0, IBDL_BC_NEUMANN = 1 };
 enum { IBDL_K_PESKIN4 = 0, IBDL_K_COS4 = 1, IBDL_K_BSPLINE6 = 2 };
 enum { IBDL_DISC_FD2 = 0, IBDL_DISC_SPECTRAL = 1 };
 enum { IBDL_FP64 = 0, IBDL_MIXED = 1 };
+enum { IBDL_METHOD_DL = 0, IBDL_METHOD_SL = 1 };
 
 typedef struct {
   int32_t dim;        /* 2 or 3                                                             */
@@ -80,6 +81,15 @@ typedef struct {
   int32_t precision;  /* IBDL_FP64, or IBDL_MIXED: float grid, spread, FFT and interpolation;
                          double marker data and Krylov iteration                            */
   void*   stream;     /* hipStream_t                                                        */
+  int32_t method;     /* IBDL_METHOD_DL (0): the double layer method, everything above.
+                         IBDL_METHOD_SL: the single layer method of Chapter 2 (IBSL): the Schur
+                         complement -S* L^-1 S (Sec. 2.2.3), with u_bar and the border rows
+                         sum_i (ds_i / mean ds) F_i = (h^D / mean ds) sum_x g~ when L is singular
+                         (Poisson, Sec. 2.2.4; Stokes, Sec. 2.3.2), and L^-1 P for Brinkman and
+                         Stokes (Sec. 2.3.1); Dirichlet data, eta = 0; the normals are not used
+                         (nrm may be NULL).  ibdl_solve then runs MINRES.  With equal spacings the
+                         border rows are the thesis's 1^T F.  Not available: the transposed
+                         operator, the adjoint, refinement, batches, the indicator function. */
 } ibdl_config_t;
 
 typedef struct {
@@ -126,7 +136,13 @@ ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y);
  *   type, Sec. 5.3.2 and 5.3.3 grid recovery) or NULL; info: optional host struct.
  * The right-hand side is b = U_b - S* L^-1 g~ (Dirichlet; Stokes with P), b = S* L^-1 (S V_b - g~)
  * (Neumann), plus h^dim sum(g~) in the border rows.  Returns IBDL_NOT_CONVERGED if maxit is
- * reached (outputs hold the last iterate). */
+ * reached (outputs hold the last iterate).
+ * Single layer handles (IBDL_METHOD_SL) run MINRES instead (Sec. 2.2.3; x0 = 0, the Lanczos
+ * three-term recurrence without reorthogonalisation, Givens rotations, all on the device), in the
+ * inner product with weights ds_i / mean(ds) per marker entry and 1 per u_bar entry, to the
+ * recurrence residual |r| <= tol |b| in that norm; maxit <= 1000000; info->iters counts MINRES
+ * iterations, info->krylov_relres is the recurrence residual and the history its values; the
+ * grid solution is u = L^-1 (g~ - S F) (P in front for Stokes) + u_bar. */
 ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, double tol,
                          int32_t maxit, double* q, void* u_grid, ibdl_info_t* info);
 

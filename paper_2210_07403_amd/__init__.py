@@ -40,11 +40,12 @@ class Problem:
 
     X, nrm: (n_ib, dim) marker positions and unit normals pointing out of Omega; ds: (n_ib,)
     quadrature weights.  Grid tensors are (ncomp, [nz,] ny, nx) of float64 (precision="fp64") or
-    float32 (precision="mixed").
+    float32 (precision="mixed").  method="sl" makes a single layer (IBSL) handle, solved with
+    MINRES; its normals are not used (nrm may be None).
     """
 
     def __init__(self, dim, n, L, origin, X, nrm, ds, pde="screened", kappa=0.0, mu=1.0, bc="dirichlet",
-                 eta=0.0, kernel="peskin4", disc="fd2", precision="fp64", device="cuda"):
+                 eta=0.0, kernel="peskin4", disc="fd2", precision="fp64", device="cuda", method="dl"):
         lib = B.load()
         self.device = torch.device(device)
         self.dim = int(dim)
@@ -65,14 +66,17 @@ class Problem:
         cfg.kernel = B.KERNEL[kernel]
         cfg.disc = B.DISC[disc]
         cfg.precision = B.PRECISION[precision]
+        cfg.method = B.METHOD[method]
+        self.method = method
         self.stream = torch.cuda.current_stream(self.device)
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         self._cfg = cfg
-        Xd, Nd, Dd = _dev_f64(X, self.device), _dev_f64(nrm, self.device), _dev_f64(ds, self.device)
+        Xd, Dd = _dev_f64(X, self.device), _dev_f64(ds, self.device)
+        Nd = _dev_f64(nrm, self.device) if nrm is not None else None
         self.n_ib = int(Dd.shape[0])
         self._h = ctypes.c_void_p()
-        B.check(lib.ibdl_create(ctypes.byref(cfg), self.n_ib, Xd.data_ptr(), Nd.data_ptr(), Dd.data_ptr(),
-                                ctypes.byref(self._h)), None)
+        B.check(lib.ibdl_create(ctypes.byref(cfg), self.n_ib, Xd.data_ptr(), Nd.data_ptr() if Nd is not None else None,
+                                Dd.data_ptr(), ctypes.byref(self._h)), None)
         n_aug, pts, nq = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         B.check(lib.ibdl_query(self._h, ctypes.byref(n_aug), ctypes.byref(pts), ctypes.byref(nq)), self._h)
         self.n_aug, self.grid_points, self.nq = int(n_aug.value), int(pts.value), int(nq.value)
@@ -277,16 +281,17 @@ class Problem:
         gt = self._as_grid(g, self.nq) if g is not None else None
         q = torch.empty(self.n_aug, dtype=torch.float64, device=self.device)
         u = self._grid(self.nq) if want_u else None
-        hist = (ctypes.c_double * 256)()
+        cap = max(256, min(int(maxit), 1 << 20))
+        hist = (ctypes.c_double * cap)()
         info = B.Info()
         info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
-        info.history_cap = 256
+        info.history_cap = cap
         st = B.load().ibdl_solve(self._h, dt.data_ptr(), gt.data_ptr() if gt is not None else None, float(tol),
                                  int(maxit), q.data_ptr(), u.data_ptr() if u is not None else None,
                                  ctypes.byref(info))
         B.check(st, self._h)
         res = SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64,
-                        [hist[i] for i in range(min(info.iters, 256))])
+                        [hist[i] for i in range(min(info.iters, cap))])
         if u is not None and self.nq == 1:
             u = u[0]
         return q, u, res

@@ -16,6 +16,7 @@ BC = {"dirichlet": 0, "neumann": 1}
 KERNEL = {"peskin4": 0, "cos4": 1, "bspline6": 2}
 DISC = {"fd2": 0, "spectral": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
+METHOD = {"dl": 0, "sl": 1}
 STATUS = {0: "IBDL_OK", 1: "IBDL_NOT_CONVERGED", -1: "IBDL_ERR_ARG", -2: "IBDL_ERR_UNSUPPORTED",
           -3: "IBDL_ERR_NOMEM", -4: "IBDL_ERR_HIP", -5: "IBDL_ERR_NONFINITE", -6: "IBDL_ERR_STATE"}
 
@@ -23,7 +24,8 @@ STATUS = {0: "IBDL_OK", 1: "IBDL_NOT_CONVERGED", -1: "IBDL_ERR_ARG", -2: "IBDL_E
 class Config(ctypes.Structure):
     _fields_ = [("dim", c_int32), ("n", c_int64 * 3), ("L", c_double * 3), ("origin", c_double * 3),
                 ("pde", c_int32), ("kappa", c_double), ("mu", c_double), ("bc", c_int32), ("eta", c_double),
-                ("kernel", c_int32), ("disc", c_int32), ("precision", c_int32), ("stream", c_void_p)]
+                ("kernel", c_int32), ("disc", c_int32), ("precision", c_int32), ("stream", c_void_p),
+                ("method", c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -455,6 +455,7 @@ void validate_batch(int32_t nprob, const ibdl_config_t* cfgs, const int64_t* n_i
       throw Error(IBDL_ERR_ARG, "screened Poisson needs a finite kappa > 0");
     if (c.bc != IBDL_BC_DIRICHLET || c.eta != 0.0)
       throw Error(IBDL_ERR_UNSUPPORTED, "batches hold plain Dirichlet problems (bc Dirichlet, eta = 0)");
+    if (c.method != IBDL_METHOD_DL) throw Error(IBDL_ERR_UNSUPPORTED, "batches hold double layer problems");
     if (c.disc != IBDL_DISC_FD2) throw Error(IBDL_ERR_UNSUPPORTED, "batches use the finite-difference symbols");
     if (c.kernel != IBDL_K_PESKIN4 && c.kernel != IBDL_K_COS4)
       throw Error(IBDL_ERR_UNSUPPORTED, "batches use a 4-point kernel");

@@ -48,6 +48,15 @@ struct ibdl_s {
   int nq = 1;
   bool has_ubar = false;
   int64_t n_aug = 0;
+  // Single-layer method (IBSL): the density spreads with weight 1 and no dipole (normals held at
+  // zero), no identity term, border rows sum_i (ds_i / mean ds) F_i; solved with MINRES.
+  bool sl = false;
+  double sl_border = 0.0;       // 1 / mean(ds)
+  double* mr = nullptr;         // MINRES vectors vprev, w1, w2 [3][n_aug]
+  double* mr_state = nullptr;   // two copies of the scalar recurrence state (32 doubles)
+  double* mr_wt = nullptr;      // inner-product weights [n_aug]
+  double* mr_hist = nullptr;
+  int64_t mr_hist_cap = 0;
   hipStream_t st = nullptr;
   hipStream_t aux = nullptr;    // second stream: the double-precision residual beside the recovery
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -181,6 +190,10 @@ struct ibdl_s {
   bool stokes() const { return cfg.pde == IBDL_PDE_STOKES; }
   bool neumann() const { return cfg.bc == IBDL_BC_NEUMANN; }
   bool fd() const { return cfg.disc == IBDL_DISC_FD2; }
+  // identity term of the operator: Q/2 (Dirichlet), -U/2 (Neumann), none for the single layer
+  double half() const { return sl ? 0.0 : (neumann() ? -0.5 : 0.5); }
+  // border rows: eta sum ds Q (completed double layer), sum (ds / mean ds) F (single layer)
+  double border_w() const { return sl ? sl_border : cfg.eta; }
   double kappa() const { return cfg.pde == IBDL_PDE_POISSON ? 0.0 : cfg.kappa; }
   // grid fields needed at once (real and spectral)
   int fields_needed() const {
@@ -535,9 +548,8 @@ template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
     W.tuned = true;
   }
   density_to_grid<T>(h, q, nullptr, nullptr, W.real, true);
-  const double half = h->neumann() ? -0.5 : 0.5;
   const double* ub = h->has_ubar ? q + h->n_ib * h->nq : nullptr;
-  InterpArgs ia = interp_args(h, h->nq, 1.0, half, q, ub);
+  InterpArgs ia = interp_args(h, h->nq, 1.0, h->half(), q, ub);
   {
     StageTimer t(h, ST_INTERP);
     interp<T>(ia, W.wtab, W.real, y, h->st);
@@ -545,7 +557,7 @@ template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
   if (h->has_ubar) {
     const int nblk = kr_nblk(h->n_ib);
     ensure_partial(h, nblk * h->nq);
-    kr_border(q, h->ds, h->n_ib, h->nq, h->cfg.eta, y + h->n_ib * h->nq, h->partial, nblk, h->st);
+    kr_border(q, h->ds, h->n_ib, h->nq, h->border_w(), y + h->n_ib * h->nq, h->partial, nblk, h->st);
   }
 }
 
@@ -590,7 +602,7 @@ template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, doub
       const int nblk = 256;
       ensure_partial(h, nblk * h->nq);
       grid_sum<T>(g, h->nq, h->ntot, h->partial, nblk, b + nb, h->st);
-      const double hD = pow(h->h, (double)h->dim);
+      const double hD = pow(h->h, (double)h->dim) * (h->sl ? h->sl_border : 1.0);
       kr_scale(b + nb, hD, b + nb, h->nq, h->st);
     } else {
       IBDL_HIP(hipMemsetAsync(b + nb, 0, sizeof(double) * h->nq, h->st));
@@ -910,6 +922,62 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;
 }
 
+// MINRES for the single layer method, x0 = 0 (the device recurrences of minres.hip).  The
+// iterations are queued in groups of 16 between looks at the device state: the state's done flag
+// freezes x at the first iteration that meets tol, so the later iterations of a group cost their
+// applies but change nothing.
+int minres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
+           double* relres) {
+  const int64_t n = h->n_aug;
+  if (!h->mr) {
+    h->mr = (double*)h->dalloc<double>(sizeof(double) * 3 * n);
+    h->mr_state = (double*)h->dalloc<double>(sizeof(double) * 32);
+  }
+  if (h->mr_hist_cap < maxit) {
+    if (h->mr_hist) h->dfree(h->mr_hist);
+    h->mr_hist = (double*)h->dalloc<double>(sizeof(double) * maxit);
+    h->mr_hist_cap = maxit;
+  }
+  ensure_partial(h, 2 * mr_nblk(n));
+  const bool graph = ensure_graph(h, false);
+  if (!h->gx) {
+    h->gx = (double*)h->dalloc<double>(sizeof(double) * n);
+    h->gy = (double*)h->dalloc<double>(sizeof(double) * n);
+  }
+  double *vprev = h->mr, *w1 = h->mr + n, *w2 = h->mr + 2 * n;
+  double* st[2] = {h->mr_state, h->mr_state + 16};
+  mr_start(b, h->mr_wt, n, tol, h->gx, vprev, w1, w2, x, h->partial, st[0], h->st);
+  double* hs = h->hostbuf + 900;   // host copy of the state
+  int k = 0;
+  bool done = false;
+  while (k < maxit && !done) {
+    const int group = std::min(16, maxit - k);
+    for (int i = 0; i < group; ++i, ++k) {
+      if (graph) IBDL_HIP(hipGraphLaunch(h->gexec[0], h->st));
+      else apply_any(h, h->gx, h->gy, false);
+      mr_iteration(h->gx, vprev, h->gy, w1, w2, x, h->mr_wt, n, h->partial, st[k & 1], st[(k + 1) & 1], h->mr_hist,
+                   h->mr_hist_cap, h->st);
+    }
+    IBDL_HIP(hipMemcpyAsync(hs, st[k & 1], sizeof(double) * MR_NSTATE, hipMemcpyDeviceToHost, h->st));
+    IBDL_HIP(hipStreamSynchronize(h->st));
+    if (!std::isfinite(hs[MR_ETA])) throw Error(IBDL_ERR_NONFINITE, "non-finite value in the Lanczos process");
+    done = hs[MR_DONE] != 0.0;
+  }
+  const int it = (int)hs[MR_ITERS];
+  const double beta1 = hs[MR_BETA1];
+  const double res = beta1 > 0.0 ? fabs(hs[MR_ETA]) / beta1 : 0.0;
+  if (info && info->history && it > 0) {
+    const int nh = std::min(it, info->history_cap);
+    if (nh > 0) {
+      IBDL_HIP(hipMemcpyAsync(info->history, h->mr_hist, sizeof(double) * nh, hipMemcpyDeviceToHost, h->st));
+      IBDL_HIP(hipStreamSynchronize(h->st));
+    }
+  }
+  *iters = it;
+  *relres = res;
+  return done ? IBDL_OK : IBDL_NOT_CONVERGED;
+}
+
 // Gradients of a loss of the recovered grid solution (dL/du = psi) with respect to the marker
 // positions and the boundary data, by the adjoint method: A^T mu = (du/dq)^T psi, dL/ddata = mu.
 template <typename T>
@@ -969,6 +1037,29 @@ void validate(const ibdl_config_t* c, int64_t n_ib) {
   if (c->kernel == IBDL_K_BSPLINE6 && c->pde == IBDL_PDE_STOKES && c->disc == IBDL_DISC_FD2)
     throw Error(IBDL_ERR_UNSUPPORTED, "finite-difference Stokes with the B-spline kernel is not implemented");
   if (c->precision != IBDL_FP64 && c->precision != IBDL_MIXED) throw Error(IBDL_ERR_ARG, "unknown precision");
+  if (c->method != IBDL_METHOD_DL && c->method != IBDL_METHOD_SL) throw Error(IBDL_ERR_ARG, "unknown method");
+  if (c->method == IBDL_METHOD_SL && (c->bc != IBDL_BC_DIRICHLET || c->eta != 0))
+    throw Error(IBDL_ERR_UNSUPPORTED, "the single layer method takes Dirichlet data and no completion (eta = 0)");
+}
+
+// Single layer: normals held at zero (no dipole), 1 / mean(ds) for the border rows, and the MINRES
+// inner-product weights ds_i / mean(ds) per marker entry, 1 per u_bar entry.
+void sl_markers(ibdl_s* h) {
+  IBDL_HIP(hipMemsetAsync(h->nrm, 0, sizeof(double) * h->n_ib * h->dim, h->st));
+  std::vector<double> ds(h->n_ib);
+  IBDL_HIP(hipMemcpyAsync(ds.data(), h->ds, sizeof(double) * h->n_ib, hipMemcpyDeviceToHost, h->st));
+  IBDL_HIP(hipStreamSynchronize(h->st));
+  double sum = 0.0;
+  for (double v : ds) sum += v;
+  if (!(sum > 0) || !std::isfinite(sum)) throw Error(IBDL_ERR_ARG, "the spacings ds must have a positive finite sum");
+  const double mean = sum / (double)h->n_ib;
+  h->sl_border = 1.0 / mean;
+  std::vector<double> wt(h->n_aug, 1.0);
+  for (int64_t i = 0; i < h->n_ib; ++i)
+    for (int c = 0; c < h->nq; ++c) wt[i * h->nq + c] = ds[i] / mean;
+  if (!h->mr_wt) h->mr_wt = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
+  IBDL_HIP(hipMemcpyAsync(h->mr_wt, wt.data(), sizeof(double) * h->n_aug, hipMemcpyHostToDevice, h->st));
+  IBDL_HIP(hipStreamSynchronize(h->st));
 }
 
 void build_markers(ibdl_s* h) {
@@ -1079,8 +1170,11 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
   std::unique_ptr<ibdl_s> h(new ibdl_s());
   try {
     validate(cfg, n_ib);
-    if (!X || !nrm || !ds) throw Error(IBDL_ERR_ARG, "marker arrays must be non-NULL device pointers");
+    if (!X || !ds || (!nrm && cfg->method != IBDL_METHOD_SL))
+      throw Error(IBDL_ERR_ARG, "marker arrays must be non-NULL device pointers");
     h->cfg = *cfg;
+    h->sl = cfg->method == IBDL_METHOD_SL;
+    if (h->sl) h->cfg.eta = 1.0;   // the single layer spreads the density with weight 1
     h->st = (hipStream_t)cfg->stream;
     h->dim = cfg->dim;
     for (int d = 0; d < 3; ++d) h->n[d] = d < h->dim ? (int)cfg->n[d] : 1;
@@ -1091,7 +1185,7 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->nspec = h->nxp * h->n[1] * h->n[2];
     h->n_ib = n_ib;
     h->nq = h->stokes() ? h->dim : 1;
-    h->has_ubar = cfg->eta > 0 && h->kappa() == 0.0;
+    h->has_ubar = h->cfg.eta > 0 && h->kappa() == 0.0;
     h->n_aug = n_ib * h->nq + (h->has_ubar ? h->nq : 0);
     MarkerGeom& g = h->geom;
     g.dim = h->dim;
@@ -1144,8 +1238,9 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     IBDL_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     IBDL_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
-    IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
+    if (!h->sl) IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * n_ib, hipMemcpyDeviceToDevice, h->st));
+    if (h->sl) sl_markers(h.get());
     build_markers(h.get());
     if (h->mixed()) ensure_work<float>(h.get());
     else ensure_work<double>(h.get());
@@ -1162,10 +1257,11 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
 
 ibdl_status_t ibdl_set_markers(ibdl_t h, const double* X, const double* nrm, const double* ds) {
   return guarded(h, [&]() {
-    if (!X || !nrm || !ds) throw Error(IBDL_ERR_ARG, "marker arrays must be non-NULL");
+    if (!X || !ds || (!nrm && !h->sl)) throw Error(IBDL_ERR_ARG, "marker arrays must be non-NULL");
     IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
-    IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
+    if (!h->sl) IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * h->n_ib, hipMemcpyDeviceToDevice, h->st));
+    if (h->sl) sl_markers(h);
     build_markers(h);
     return IBDL_OK;
   });
@@ -1197,6 +1293,7 @@ ibdl_status_t ibdl_indicator(ibdl_t h, void* chi, void* regularized) {
   return guarded(h, [&]() {
     if (!chi) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the indicator function is two-dimensional");
+    if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "the indicator function needs the normals of a double layer handle");
     if (h->mixed()) indicator_t<float>(h, (float*)chi, (float*)regularized);
     else indicator_t<double>(h, (double*)chi, (double*)regularized);
     return IBDL_OK;
@@ -1289,12 +1386,14 @@ ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, doubl
   return guarded(h, [&]() {
     if (!data || !q) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (!(tol >= 0) || !std::isfinite(tol)) throw Error(IBDL_ERR_ARG, "tol must be finite and >= 0");
-    if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
+    if (maxit < 1 || maxit > (h->sl ? 1000000 : 200))
+      throw Error(IBDL_ERR_ARG, h->sl ? "maxit must be in [1, 1000000]" : "maxit must be in [1, 200]");
     if (h->mixed()) rhs_t<float>(h, data, (const float*)g_grid, h->vb);
     else rhs_t<double>(h, data, (const double*)g_grid, h->vb);
     int iters = 0;
     double relres = 0;
-    const int status = gmres(h, h->vb, tol, maxit, q, info, &iters, &relres);
+    const int status = h->sl ? minres(h, h->vb, tol, maxit, q, info, &iters, &relres)
+                             : gmres(h, h->vb, tol, maxit, q, info, &iters, &relres);
     // True residual ||b - A q|| / ||b|| with a double-precision apply.  On a mixed handle it uses
     // the double work arrays and the recovery the float ones, so it runs on the second stream
     // beside the recovery.
@@ -1345,6 +1444,7 @@ ibdl_status_t ibdl_backward(ibdl_t h, const double* q, const void* u_grid, const
     if (!(tol >= 0) || !std::isfinite(tol)) throw Error(IBDL_ERR_ARG, "tol must be finite and >= 0");
     if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
     if (h->neumann()) throw Error(IBDL_ERR_UNSUPPORTED, "the adjoint is implemented for Dirichlet problems");
+    if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "the adjoint is implemented for the double layer method");
     if (h->mixed())
       return backward_t<float>(h, q, (const float*)u_grid, (const float*)dL_du, tol, maxit, dL_dX, dL_ddata, info);
     return backward_t<double>(h, q, (const double*)u_grid, (const double*)dL_du, tol, maxit, dL_dX, dL_ddata, info);
@@ -1355,6 +1455,7 @@ ibdl_status_t ibdl_apply_transpose(ibdl_t h, const double* p, double* y) {
   return guarded(h, [&]() {
     if (!p || !y) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (p == y) throw Error(IBDL_ERR_ARG, "p and y must not alias");
+    if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "the transposed operator is implemented for the double layer method");
     apply_any(h, p, y, false, true);
     return IBDL_OK;
   });
@@ -1368,6 +1469,7 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
     if (!(inner_tol > 0 && inner_tol < 1)) throw Error(IBDL_ERR_ARG, "inner_tol must be in (0, 1)");
     if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
     if (max_rounds < 1 || max_rounds > 50) throw Error(IBDL_ERR_ARG, "max_rounds must be in [1, 50]");
+    if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "refinement is implemented for the double layer method");
     const int64_t n = h->n_aug;
     // right-hand side in double: the forcing of a mixed handle is widened first
     const double* g64 = nullptr;

@@ -285,6 +285,19 @@ template <typename T>
 void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGeom& g, double m1, double m2,
                    const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st);
 
+// ------------------------------------------------------------------ MINRES (device recurrences)
+// State slots of the double-buffered scalar recurrence (MR_NSTATE doubles per copy).
+enum { MR_BETA = 0, MR_C1, MR_S1, MR_C2, MR_S2, MR_ETA, MR_BETA1, MR_DONE, MR_ITERS, MR_ALPHA, MR_TOL, MR_NSTATE };
+int mr_nblk(int64_t n);
+// beta1 = |b|_wt; v = b / beta1; vprev = w1 = w2 = x = 0; state initialised.  partial: mr_nblk(n).
+void mr_start(const double* b, const double* wt, int64_t n, double tol, double* v, double* vprev, double* w1,
+              double* w2, double* x, double* partial, double* state, hipStream_t st);
+// One iteration after p = A v: reads state `in`, writes state `out` (another copy); hist[k-1] =
+// the recurrence residual / beta1.  partial: 2 mr_nblk(n) doubles.
+void mr_iteration(double* v, double* vprev, double* p, double* w1, double* w2, double* x, const double* wt,
+                  int64_t n, double* partial, const double* in, double* out, double* hist, int64_t hist_cap,
+                  hipStream_t st);
+
 // ------------------------------------------------------------------ force and line integrals (2-D)
 // out[3] = (B_x, B_y, L) of the completed density Q [n_ib][2]: B = -eta sum ds Q, L = -eta sum ds X x Q
 void net_force(const double* X, const double* Q, const double* ds, int64_t n_ib, double eta, double* out,

@@ -1,0 +1,203 @@
+// MINRES (Paige and Saunders) on the device, for the symmetric Schur complements of the single
+// layer method (Sec. 2.2.3: solved with MINRES to a relative residual of 1e-8).
+//
+// Per iteration, after the operator apply p = A v_k: (1) block partials of alpha_k = <v_k, p>;
+// (2) every workgroup reduces them in the same fixed order, p -= alpha_k v_k + beta_k v_{k-1},
+// block partials of <p, p>; (3) every workgroup reduces those to beta_{k+1}, applies the two
+// previous Givens rotations to the new tridiagonal column, forms the new rotation, and updates
+// w_k = (v_k - delta w_{k-1} - epsilon w_{k-2}) / gamma, x += c eta w_k, v_{k+1} = p / beta_{k+1}
+// element by element.  The inner product carries weights wt (self-adjointness of the operator
+// with unequal spacings).  The scalar recurrence state lives in device memory, double-buffered
+// (each iteration reads one copy and writes the other), so the host never has to take part in an
+// iteration; once the recurrence residual reaches tol |b| the state's done flag freezes x, and the
+// later kernels of iterations the host had queued return at once.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace ibdl {
+namespace {
+
+constexpr int kMB = 256;
+constexpr int kMElems = 2048;   // elements per workgroup (8 per thread)
+
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kMB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+// sum of p[0 .. nblk) in a fixed order (the same bits in every workgroup)
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ p, int nblk, double* lds) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kMB) s += p[b];
+  return block_sum(s, lds);
+}
+
+__global__ __launch_bounds__(kMB) void k_mr_wdot(const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ wt, int64_t n,
+                                                 const double* __restrict__ state, double* __restrict__ partial) {
+  __shared__ double lds[kMB];
+  if (state && state[MR_DONE] != 0.0) return;
+  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < kMElems; k += kMB) {
+    const int64_t e = e0 + k;
+    if (e < n) s += wt[e] * a[e] * b[e];
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kMB) void k_mr_start(const double* __restrict__ b, int64_t n,
+                                                  const double* __restrict__ partial, int nblk, double tol,
+                                                  double* __restrict__ v, double* __restrict__ vprev,
+                                                  double* __restrict__ w1, double* __restrict__ w2,
+                                                  double* __restrict__ x, double* __restrict__ state) {
+  __shared__ double lds[kMB];
+  const double beta1 = sqrt(fmax(reduce_partials(partial, nblk, lds), 0.0));
+  const double inv = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+  for (int k = threadIdx.x; k < kMElems; k += kMB) {
+    const int64_t e = e0 + k;
+    if (e < n) {
+      v[e] = b[e] * inv;
+      vprev[e] = 0.0;
+      w1[e] = 0.0;
+      w2[e] = 0.0;
+      x[e] = 0.0;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    state[MR_BETA] = 0.0;
+    state[MR_C1] = 1.0;
+    state[MR_S1] = 0.0;
+    state[MR_C2] = 1.0;
+    state[MR_S2] = 0.0;
+    state[MR_ETA] = beta1;
+    state[MR_BETA1] = beta1;
+    state[MR_DONE] = beta1 > 0.0 ? 0.0 : 1.0;
+    state[MR_ITERS] = 0.0;
+    state[MR_ALPHA] = 0.0;
+    state[MR_TOL] = tol;
+  }
+}
+
+// alpha = <v, p>; p -= alpha v + beta vprev; partial2 = block partials of <p, p>
+__global__ __launch_bounds__(kMB) void k_mr_lanczos(const double* __restrict__ v, const double* __restrict__ vprev,
+                                                    double* __restrict__ p, const double* __restrict__ wt, int64_t n,
+                                                    const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ partial2, const double* __restrict__ in,
+                                                    double* __restrict__ out) {
+  __shared__ double lds[kMB];
+  if (in[MR_DONE] != 0.0) return;
+  const double alpha = reduce_partials(partial, nblk, lds);
+  const double beta = in[MR_BETA];
+  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < kMElems; k += kMB) {
+    const int64_t e = e0 + k;
+    if (e < n) {
+      const double pe = p[e] - alpha * v[e] - beta * vprev[e];
+      p[e] = pe;
+      s += wt[e] * pe * pe;
+    }
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) partial2[blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[MR_ALPHA] = alpha;
+}
+
+__global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, double* __restrict__ vprev,
+                                                   const double* __restrict__ p, double* __restrict__ w1,
+                                                   double* __restrict__ w2, double* __restrict__ x, int64_t n,
+                                                   const double* __restrict__ partial2, int nblk,
+                                                   const double* __restrict__ in, double* __restrict__ out,
+                                                   double* __restrict__ hist, int64_t hist_cap) {
+  __shared__ double lds[kMB];
+  if (in[MR_DONE] != 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x < MR_NSTATE) out[threadIdx.x] = in[threadIdx.x];
+    return;
+  }
+  const double beta_next = sqrt(fmax(reduce_partials(partial2, nblk, lds), 0.0));
+  const double alpha = out[MR_ALPHA];
+  const double beta = in[MR_BETA], c1 = in[MR_C1], s1 = in[MR_S1], c2 = in[MR_C2], s2 = in[MR_S2];
+  const double eta = in[MR_ETA], beta1 = in[MR_BETA1], tol = in[MR_TOL];
+  // the two previous rotations on the new column (beta_k, alpha_k, beta_{k+1}), then a new one
+  const double eps = s2 * beta;
+  const double d0 = c2 * beta;
+  const double delta = c1 * d0 + s1 * alpha;
+  const double g0 = -s1 * d0 + c1 * alpha;
+  const double gamma = hypot(g0, beta_next);
+  const double c = gamma > 0.0 ? g0 / gamma : 1.0;
+  const double s = gamma > 0.0 ? beta_next / gamma : 0.0;
+  const double ginv = gamma > 0.0 ? 1.0 / gamma : 0.0;
+  const double step = c * eta;
+  const double eta_new = -s * eta;
+  const bool done = fabs(eta_new) <= tol * beta1 || !(beta_next > 0.0);
+  const double binv = beta_next > 0.0 ? 1.0 / beta_next : 0.0;
+  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+  for (int k = threadIdx.x; k < kMElems; k += kMB) {
+    const int64_t e = e0 + k;
+    if (e < n) {
+      const double ve = v[e], a1 = w1[e];
+      const double we = (ve - delta * a1 - eps * w2[e]) * ginv;
+      x[e] += step * we;
+      w2[e] = a1;
+      w1[e] = we;
+      vprev[e] = ve;
+      v[e] = p[e] * binv;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double it = in[MR_ITERS] + 1.0;
+    out[MR_BETA] = beta_next;
+    out[MR_C1] = c;
+    out[MR_S1] = s;
+    out[MR_C2] = c1;
+    out[MR_S2] = s1;
+    out[MR_ETA] = eta_new;
+    out[MR_BETA1] = beta1;
+    out[MR_DONE] = done ? 1.0 : 0.0;
+    out[MR_ITERS] = it;
+    out[MR_TOL] = tol;
+    const int64_t j = (int64_t)in[MR_ITERS];
+    if (j < hist_cap) hist[j] = beta1 > 0.0 ? fabs(eta_new) / beta1 : 0.0;
+  }
+}
+
+}  // namespace
+
+int mr_nblk(int64_t n) { return n > 0 ? (int)((n + kMElems - 1) / kMElems) : 1; }
+
+void mr_start(const double* b, const double* wt, int64_t n, double tol, double* v, double* vprev, double* w1,
+              double* w2, double* x, double* partial, double* state, hipStream_t st) {
+  const int nblk = mr_nblk(n);
+  hipLaunchKernelGGL(k_mr_wdot, dim3(nblk), dim3(kMB), 0, st, b, b, wt, n, (const double*)nullptr, partial);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mr_start, dim3(nblk), dim3(kMB), 0, st, b, n, partial, nblk, tol, v, vprev, w1, w2, x, state);
+  IBDL_LAUNCH_CHECK();
+}
+
+void mr_iteration(double* v, double* vprev, double* p, double* w1, double* w2, double* x, const double* wt,
+                  int64_t n, double* partial, const double* in, double* out, double* hist, int64_t hist_cap,
+                  hipStream_t st) {
+  const int nblk = mr_nblk(n);
+  double* partial2 = partial + nblk;
+  hipLaunchKernelGGL(k_mr_wdot, dim3(nblk), dim3(kMB), 0, st, v, p, wt, n, in, partial);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mr_lanczos, dim3(nblk), dim3(kMB), 0, st, v, vprev, p, wt, n, partial, nblk, partial2, in,
+                     out);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mr_update, dim3(nblk), dim3(kMB), 0, st, v, vprev, p, w1, w2, x, n, partial2, nblk, in, out,
+                     hist, hist_cap);
+  IBDL_LAUNCH_CHECK();
+}
+
+}  // namespace ibdl

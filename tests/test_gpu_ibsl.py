@@ -1,0 +1,152 @@
+"""GPU parity of the single layer method (IBDL_METHOD_SL): the Schur complement applies of
+Chapter 2 and the device MINRES, against the oracle (oracle/ibsl.py, oracle/minres.py) and the
+thesis's MINRES iteration tables.
+
+Tolerances: applies 1e-12 (FP64) / 2e-5 (mixed) relative to the max-norm; well-conditioned
+solves (ds ~ 2 dx, tens to a hundred iterations) at tol 1e-12: density and grid solution 1e-7
+relative to the oracle's (the condition number times the tolerance); iteration counts of the well-conditioned solves within 2 % (at least 2) of the oracle's; on the
+ill-conditioned ones (hundreds of iterations) within 6 % (at least 3): the Lanczos vectors lose
+orthogonality on both sides but with other roundings, and the residual then creeps along
+plateaus whose exit moves by a few iterations; and within the oracle's own band
+[printed, 1.15 printed + 2] of the thesis's tables."""
+import json
+import pathlib
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2210_07403_amd as ibdl
+from oracle.ib import Grid
+from oracle.ibsl import IBSL
+from oracle.minres import minres
+from workloads import problems as P
+
+from _helpers import to_np
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs an MI355X")]
+
+GOLD = pathlib.Path(__file__).parent / "golden"
+HELM = json.loads((GOLD / "ibsl_iterations.json").read_text())
+BRINK = json.loads((GOLD / "ibsl_iterations_brinkman.json").read_text())
+
+
+def _poisson_circle(N, alpha):
+    s = P.helmholtz_circle(N, alpha)
+    return P.ProblemSpec(**{**s.__dict__, "pde": "poisson", "kappa": 0.0, "exact": lambda x, y: 32.0 * x * y})
+
+
+def _sl(spec, precision="fp64"):
+    m = spec.markers
+    return ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, None, m.ds, pde=spec.pde, kappa=spec.kappa,
+                        mu=spec.mu, kernel=spec.kernel, disc=spec.disc, precision=precision, method="sl")
+
+
+CASES = {
+    "helmholtz_fd": lambda: P.helmholtz_circle(64, 1.0),
+    "helmholtz_spectral": lambda: P.helmholtz_circle(64, 1.0, disc="spectral"),
+    "poisson_fd": lambda: _poisson_circle(64, 1.0),
+    "brinkman": lambda: P.brinkman_circle(64, 1.5),
+    "stokes": lambda: P.ProblemSpec(**{**P.brinkman_circle(64, 1.5).__dict__, "kappa": 0.0}),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_apply_matches_oracle(name, precision):
+    spec = CASES[name]()
+    o = IBSL.from_spec(spec)
+    pr = _sl(spec, precision)
+    assert pr.n_aug == o.n_aug
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        q = rng.standard_normal(o.n_aug)
+        got = to_np(pr.apply(q))
+        want = o.apply(q)
+        tol = 1e-12 if precision == "fp64" else 2e-5
+        assert np.max(np.abs(got - want)) < tol * np.max(np.abs(want))
+    pr.close()
+
+
+@pytest.mark.parametrize("name", ["helmholtz_fd", "poisson_fd", "brinkman", "stokes"])
+def test_minres_solve_matches_oracle(name):
+    spec = CASES[name]()
+    ref = P.helmholtz_circle(64, 2.0) if name in ("helmholtz_fd", "poisson_fd") else P.brinkman_circle(64, 2.0)
+    spec = P.ProblemSpec(**{**spec.__dict__, "markers": ref.markers, "data": ref.data})
+    o = IBSL.from_spec(spec)
+    b = o.rhs(spec.data, spec.g)
+    qo, ito, _, ok = minres(o.apply, b, 1e-12, 5000, o.wt)
+    assert ok
+    pr = _sl(spec)
+    q, u, info = pr.solve(spec.data, spec.g, tol=1e-12, maxit=5000)
+    assert info.status == 0
+    assert abs(info.iters - ito) <= max(2, int(0.02 * ito)), (info.iters, ito)
+    q = to_np(q)
+    assert np.max(np.abs(q - qo)) < 1e-7 * np.max(np.abs(qo))
+    uo = o.recover(qo, spec.g)
+    assert np.max(np.abs(to_np(u) - uo)) < 1e-7 * np.max(np.abs(uo))
+    assert info.true_relres_fp64 < 1e-10
+    assert len(info.history) == info.iters and info.history[-1] <= 1e-12
+    if o.has_ubar:   # border rows: sum of (ds / mean ds) F equals (h^D / mean ds) sum g~
+        F, _ = o.split(q)
+        w = spec.markers.ds / np.mean(spec.markers.ds)
+        tot = np.sum(w[:, None] * F, axis=0) if F.ndim == 2 else np.sum(w * F)
+        assert np.allclose(tot, b[o.n_ib * o.nq:], atol=1e-9 * np.max(np.abs(F)))
+    pr.close()
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_helmholtz_iteration_counts(N):
+    for a, w in zip(HELM["alpha"], HELM["rows"][str(N)]):
+        spec = P.helmholtz_circle(N, a)
+        o = IBSL.from_spec(spec)
+        _, ito, _, _ = minres(o.apply, o.rhs(spec.data, spec.g), 1e-8, 20000, o.wt)
+        pr = _sl(spec)
+        _, _, info = pr.solve(spec.data, None, tol=1e-8, maxit=20000, want_u=False)
+        pr.close()
+        assert info.status == 0
+        assert abs(info.iters - ito) <= max(3, int(0.06 * ito)), (N, a, info.iters, ito)
+        assert w <= info.iters <= 1.15 * w + 2, (N, a, info.iters, w)
+
+
+@pytest.mark.parametrize("N,alpha", [(64, 2.0), (64, 1.5), (128, 2.0)])
+def test_brinkman_iteration_counts(N, alpha):
+    w = BRINK["rows"][str(N)][BRINK["alpha"].index(alpha)]
+    spec = P.brinkman_circle(N, alpha)
+    pr = _sl(spec)
+    _, _, info = pr.solve(spec.data, spec.g, tol=1e-8, maxit=20000, want_u=False)
+    pr.close()
+    assert info.status == 0
+    assert w <= info.iters <= 1.15 * w + 2, (N, alpha, info.iters, w)
+
+
+def test_mixed_solve_and_closed_form():
+    """Mixed precision on the Helmholtz circle (ds ~ dx): the float-applied operator's MINRES
+    reaches 1e-6 and its grid solution is as close to the closed form as the FP64 one."""
+    spec = P.helmholtz_circle(128, 1.0)
+    xs, ys = Grid(spec.dim, spec.n, spec.L, spec.origin).nodes()
+    inner = np.hypot(xs, ys) < 0.15
+    errs = {}
+    for prec in ("fp64", "mixed"):
+        pr = _sl(spec, prec)
+        _, u, info = pr.solve(spec.data, None, tol=1e-6, maxit=20000)
+        assert info.status == 0
+        errs[prec] = np.max(np.abs(to_np(u) - spec.exact(xs, ys))[inner])
+        pr.close()
+    assert errs["fp64"] < 0.025
+    assert abs(errs["mixed"] - errs["fp64"]) < 0.05 * errs["fp64"]
+
+
+def test_rejects():
+    spec = P.helmholtz_circle(64, 1.0)
+    m = spec.markers
+    with pytest.raises(ibdl.IBDLError):
+        ibdl.Problem(2, spec.n, spec.L, spec.origin, m.X, None, m.ds, pde="screened", kappa=1.0, eta=1.0,
+                     method="sl")
+    pr = _sl(spec)
+    with pytest.raises(ibdl.IBDLError):
+        pr.apply_transpose(np.zeros(pr.n_aug))
+    with pytest.raises(ibdl.IBDLError):
+        pr.indicator()
+    pr.close()
