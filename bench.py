@@ -203,7 +203,40 @@ def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
     out["near_boundary_star1024"] = _near_boundary_timing(dev)
     print("# extras: cylinder array drag", file=sys.stderr, flush=True)
     out["cylinder_array_drag"] = _cylinder_drag(dev)
+    print("# extras: single vs double layer", file=sys.stderr, flush=True)
+    out["ibsl_vs_ibdl_helmholtz1024"] = _ibsl_vs_ibdl(dev)
     return out
+
+
+def _ibsl_vs_ibdl(dev):
+    """The thesis's central contrast on its Helmholtz circle (Delta u - u = 0 in r < 1/4,
+    u = sin 2 theta), 1024^2, ds ~ dx, FD, FP64, tol 1e-8: the single layer Schur complement with
+    MINRES against the double layer operator with GMRES; iterations, solve time, time per
+    iteration, and the interior error of each grid solution against the closed form."""
+    import numpy as np
+    import paper_2210_07403_amd as ibdl
+    from workloads import problems as P
+    s = P.helmholtz_circle(1024, 1.0)
+    m = s.markers
+    h = s.L[0] / s.n[0]
+    ax = [s.origin[d] + h * np.arange(s.n[d]) for d in range(2)]
+    ys, xs = np.meshgrid(ax[1], ax[0], indexing="ij")
+    inner = np.hypot(xs, ys) < 0.15
+    exact = s.exact(xs, ys)
+    res = {"workload": "Helmholtz circle r = 0.25, 1024^2, %d markers (ds ~ dx), FD, FP64, tol 1e-8" % m.X.shape[0]}
+    for meth, maxit in (("sl", 100000), ("dl", 100)):
+        pr = ibdl.Problem(s.dim, s.n, s.L, s.origin, m.X, m.nrm, m.ds, pde=s.pde, kappa=s.kappa, kernel=s.kernel,
+                          disc=s.disc, precision="fp64", device=dev, method=meth)
+        pr.solve(s.data, None, tol=1e-8, maxit=maxit)
+        reps = 1 if meth == "sl" else 5
+        t, (_, u, info) = _timed(lambda: pr.solve(s.data, None, tol=1e-8, maxit=maxit), reps)
+        err = float(np.max(np.abs(u.cpu().numpy() - exact)[inner]))
+        res[meth] = {"iters": info.iters, "solve_ms": round(1e3 * t, 3),
+                     "ms_per_iteration": round(1e3 * t / max(info.iters, 1), 4),
+                     "true_relres": info.true_relres_fp64, "max_error_r_lt_0.15": err}
+        pr.close()
+    res["time_ratio_sl_over_dl"] = round(res["sl"]["solve_ms"] / res["dl"]["solve_ms"], 1)
+    return res
 
 
 def _cylinder_drag(dev):

@@ -86,7 +86,7 @@ typedef struct {
                          complement -S* L^-1 S (Sec. 2.2.3), with u_bar and the border rows
                          sum_i (ds_i / mean ds) F_i = (h^D / mean ds) sum_x g~ when L is singular
                          (Poisson, Sec. 2.2.4; Stokes, Sec. 2.3.2), and L^-1 P for Brinkman and
-                         Stokes (Sec. 2.3.1); Dirichlet data, eta = 0; the normals are not used
+                         Stokes (Sec. 2.3.1); 2-D, Dirichlet data, eta = 0; the normals are not used
                          (nrm may be NULL).  ibdl_solve then runs MINRES.  With equal spacings the
                          border rows are the thesis's 1^T F.  Not available: the transposed
                          operator, the adjoint, refinement, batches, the indicator function. */

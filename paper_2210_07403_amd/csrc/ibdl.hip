@@ -1038,6 +1038,8 @@ void validate(const ibdl_config_t* c, int64_t n_ib) {
     throw Error(IBDL_ERR_UNSUPPORTED, "finite-difference Stokes with the B-spline kernel is not implemented");
   if (c->precision != IBDL_FP64 && c->precision != IBDL_MIXED) throw Error(IBDL_ERR_ARG, "unknown precision");
   if (c->method != IBDL_METHOD_DL && c->method != IBDL_METHOD_SL) throw Error(IBDL_ERR_ARG, "unknown method");
+  if (c->method == IBDL_METHOD_SL && c->dim != 2)
+    throw Error(IBDL_ERR_UNSUPPORTED, "the single layer method is implemented in 2-D");
   if (c->method == IBDL_METHOD_SL && (c->bc != IBDL_BC_DIRICHLET || c->eta != 0))
     throw Error(IBDL_ERR_UNSUPPORTED, "the single layer method takes Dirichlet data and no completion (eta = 0)");
 }

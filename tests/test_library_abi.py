@@ -32,6 +32,7 @@ def _cfg(**kw):
     c.disc = kw.get("disc", 0)
     c.precision = kw.get("precision", 0)
     c.stream = None
+    c.method = kw.get("method", 0)
     return c
 
 
@@ -49,6 +50,10 @@ def _cfg(**kw):
     (dict(kernel=7), -1),
     (dict(precision=3), -1),
     (dict(eta=float("nan")), -1),
+    (dict(method=2), -1),
+    (dict(method=1, eta=1.0), -2),            # the single layer takes no completion
+    (dict(method=1, bc=1), -2),
+    (dict(method=1, dim=3), -2),
 ])
 def test_create_rejects_invalid_config(kw, code):
     lib = B.load()
