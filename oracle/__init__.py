@@ -13,7 +13,7 @@ grid solution with respect to the markers and the boundary data, by forward-mode
 differentiation of the forward map with dense solves), nearbdry (the indicator function of the
 discretized curve and the near-boundary interpolation, 2-D), drag (net force, torque, flux and the
 dimensionless drag of a Stokes solution, 2-D), ibsl (the single layer method's Schur complements,
-Chapter 2) and minres (textbook MINRES).
+Chapter 2), minres (textbook MINRES) and ns (one step of the Navier-Stokes IMEX scheme).
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
 closed forms, kernel identities, adjointness, real-space stencils, PDE
@@ -23,8 +23,10 @@ linear exactness, brute force and the closed-form indicator of a circle
 (tests/test_oracle_nearbdry.py); the drag by the thesis's printed drag table (asymptotic forms,
 first-order convergence to the reference values), the solvability condition and symmetry
 (tests/test_oracle_drag.py); MINRES against GMRES and dense solves, IBSL by symmetry, the
-thesis's MINRES iteration table and closed-form solutions (tests/test_oracle_ibsl.py).  The 3-D operator has
+thesis's MINRES iteration table and closed-form solutions (tests/test_oracle_ibsl.py); the
+Navier-Stokes step by the Taylor-Green nonlinear term, consistency on linear data and the exact
+decaying shear wave (tests/test_oracle_ns.py).  The 3-D operator has
 no printed thesis value; it is pinned by closed-form convergence only.
 """
-from . import adjoint, delta, drag, gmres, grid, ib, ibdl, ibsl, minres, nearbdry, norms  # noqa: F401
+from . import adjoint, delta, drag, gmres, grid, ib, ibdl, ibsl, minres, nearbdry, norms, ns  # noqa: F401
 from .ibdl import Setup  # noqa: F401
