@@ -227,16 +227,17 @@ const char* ibdl_batch_last_error(ibdl_batch_t b);
  * stream. */
 ibdl_status_t ibdl_indicator(ibdl_t h, void* chi, void* regularized);
 
-/* Near-boundary interpolation, two-dimensional scalar handles (Sec. 5.3.3, interpolation for
- * near-boundary points).  out = u, except at the nodes p with omega != 0 whose nearest marker is
+/* Near-boundary interpolation, two-dimensional handles (Sec. 5.3.3, interpolation for
+ * near-boundary points); Stokes handles interpolate each velocity component the same way.
+ * out = u, except at the nodes p with omega != 0 whose nearest marker is
  * within m1 h: there x_A = the point closest to p on the segment between the two nearest markers
  * (if the projection leaves it, the two of the three nearest markers farthest apart, projection
- * clamped), u(x_A) = the linear interpolation of Ub (device double [n_ib]) between them,
+ * clamped), u(x_A) = the linear interpolation of Ub (device double [n_ib][nq]) between them,
  * x_B = x_A + m2 h (p - x_A) / |p - x_A|, u(x_B) = the bilinear interpolation of u, and
  * out(p) = the linear interpolation between u(x_A) and u(x_B) at p.  Distances are plain
  * Euclidean (the curve keeps clear of the box faces); ties between markers go to the lower index.
- * omega (the nodes of the PDE domain, e.g. ibdl_indicator's chi or 1 - chi), u, out: [ny][nx] of
- * the grid type, device; out must not alias u.  Needs 1 <= m1 < m2 <= 64 (ibdl_near_widths gives
+ * omega (the nodes of the PDE domain, e.g. ibdl_indicator's chi or 1 - chi): [ny][nx]; u, out:
+ * [nq][ny][nx]; both of the grid type, device; out must not alias u.  Needs 1 <= m1 < m2 <= 64 (ibdl_near_widths gives
  * the thesis's values) and at least two markers.  Asynchronous on the handle's stream. */
 ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, const void* u, double m1, double m2,
                                  void* out);
@@ -246,6 +247,39 @@ ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, 
  * m1 = 2 (log2 nx - 4), at least 2, and m2 = m1 + 2.  Host only, synchronous; two-dimensional
  * handles; either pointer may be NULL. */
 ibdl_status_t ibdl_near_widths(ibdl_t h, double* m1, double* m2);
+
+/* The nonlinear term (u . grad) u of a two-dimensional velocity field (Sec. 6.5, Navier-Stokes:
+ * numerical implementation), 2-D Stokes handles: out[c] = u_0 d_x u_c + u_1 d_y u_c with the
+ * handle's derivative symbols (Fourier: i k, 0 at the Nyquist index; finite differences:
+ * centred).  u, out: device [2][ny][nx] of the grid type, owned by the caller, not aliased.
+ * Asynchronous on the handle's stream. */
+ibdl_status_t ibdl_advection(ibdl_t h, const void* u, void* out);
+
+typedef struct {
+  double  rho;        /* density                                                            */
+  double  dt;         /* time step; the handle's kappa^2 must equal 3 rho / (2 dt)           */
+  double  m1, m2;     /* near-boundary interpolation widths (m1 = 0: no interpolation)        */
+  int32_t strip;      /* width in grid columns of the inflow strip along x = origin (0: none) */
+  double  u_inf;      /* strip velocity (u_inf, 0)                                           */
+  double  tol;        /* GMRES tolerance of the Brinkman solve                               */
+  int32_t maxit;      /* GMRES iteration limit (<= 200)                                      */
+} ibdl_ns_params_t;
+
+/* One step of the Navier-Stokes IMEX scheme with the completed IBDL method (Sec. 6.5): BDF2 in
+ * time for the viscous and boundary terms, the nonlinear term extrapolated from the two previous
+ * steps.  u^{n+1} solves the Brinkman problem of the handle (2-D Stokes, mu, kappa^2 =
+ * 3 rho / (2 dt), eta) with the forcing g~ = rho ((-4 u^n + u^{n-1}) / (2 dt) + 2 N^n - N^{n-1}),
+ * N = (u . grad) u, and the boundary data Ub = U_b^{n+1} (device double [n_ib][2]); it is then
+ * recovered on the grid, near-boundary interpolated on the nodes of omega (device [ny][nx] of the
+ * grid type; may be NULL when m1 = 0), reset to (u_inf, 0) on the inflow strip, and its nonlinear
+ * term is formed from the interpolated field.  State (device [2][ny][nx] of the grid type, owned
+ * by the caller, four distinct buffers): on entry u = u^n, u_prev = u^{n-1}, n = N(u^n),
+ * n_prev = N(u^{n-1}); on return u = u^{n+1}, u_prev = u^n, n = N(u^{n+1}), n_prev = N(u^n).
+ * q: device double [n_aug], the density of the step.  info (optional host struct): the GMRES
+ * iterations and residual of the step; true_relres_fp64 is -1 (not computed).  Synchronises the
+ * handle's stream once per GMRES iteration, like ibdl_solve. */
+ibdl_status_t ibdl_ns_step(ibdl_t h, const ibdl_ns_params_t* p, const double* Ub, const void* omega, void* u_prev,
+                           void* u, void* n_prev, void* n, double* q, ibdl_info_t* info);
 
 /* Net force and torque of a two-dimensional Stokes solution with the completed method (Sec. 6.1,
  * exterior domains; Sec. 6.5, Stokes flow around a periodic array of cylinders).  The single layer

@@ -205,6 +205,32 @@ class Problem:
                 self._h)
         return (chi, reg) if regularized else chi
 
+    def advection(self, u):
+        """(u . grad) u of a 2-D velocity field [2][ny][nx] (Sec. 6.5)."""
+        ut = self._as_grid(u, 2)
+        out = self._grid(2)
+        B.check(B.load().ibdl_advection(self._h, ut.data_ptr(), out.data_ptr()), self._h)
+        return out
+
+    def ns_step(self, state, Ub, rho, dt, omega=None, m1=0.0, m2=0.0, strip=0, u_inf=0.0, tol=1e-8, maxit=100):
+        """One Navier-Stokes IMEX step (Sec. 6.5) on state = [u_prev, u, n_prev, n] (four grid
+        tensors of shape (2, ny, nx), updated in place); returns (q, SolveInfo)."""
+        p = B.NSParams(float(rho), float(dt), float(m1), float(m2), int(strip), float(u_inf), float(tol), int(maxit))
+        ub = _dev_f64(Ub, self.device).reshape(-1)
+        if ub.numel() != 2 * self.n_ib:
+            raise ValueError("Ub must have 2 n_ib entries")
+        for t in state:
+            if not (isinstance(t, torch.Tensor) and t.dtype == self.grid_dtype and t.is_contiguous()
+                    and t.numel() == 2 * self.grid_points and t.device.type == self.device.type):
+                raise ValueError("state tensors must be contiguous (2, ny, nx) grid tensors on the device")
+        om = self._as_grid(omega, 1) if omega is not None else None
+        q = torch.empty(self.n_aug, dtype=torch.float64, device=self.device)
+        info = B.Info()
+        st = B.load().ibdl_ns_step(self._h, ctypes.byref(p), ub.data_ptr(), om.data_ptr() if om is not None else None,
+                                   *[t.data_ptr() for t in state], q.data_ptr(), ctypes.byref(info))
+        B.check(st, self._h)
+        return q, SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64, [])
+
     def net_force(self, q):
         """(B_x, B_y, L) of a 2-D completed Stokes solution q (Sec. 6.1, Sec. 6.5): device double [3]."""
         qt = _dev_f64(q, self.device).reshape(-1)
@@ -237,11 +263,13 @@ class Problem:
             m1 = d1 if m1 is None else m1
             m2 = d2 if m2 is None else m2
         ub = _dev_f64(Ub, self.device).reshape(-1)
-        if ub.numel() != self.n_ib:
-            raise ValueError("Ub must have n_ib entries")
+        if ub.numel() != self.n_ib * self.nq:
+            raise ValueError("Ub must have n_ib * nq entries")
         om = self._as_grid(omega, 1)
-        ut = self._as_grid(u, 1)
-        out = self._grid(1)[0]
+        ut = self._as_grid(u, self.nq)
+        out = self._grid(self.nq)
+        if self.nq == 1:
+            out = out[0]
         B.check(B.load().ibdl_near_boundary(self._h, ub.data_ptr(), om.data_ptr(), ut.data_ptr(), float(m1),
                                             float(m2), out.data_ptr()), self._h)
         return out

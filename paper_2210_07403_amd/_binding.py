@@ -33,6 +33,11 @@ class Info(ctypes.Structure):
                 ("true_relres_fp64", c_double), ("history", ctypes.POINTER(c_double)), ("history_cap", c_int32)]
 
 
+class NSParams(ctypes.Structure):
+    _fields_ = [("rho", c_double), ("dt", c_double), ("m1", c_double), ("m2", c_double), ("strip", c_int32),
+                ("u_inf", c_double), ("tol", c_double), ("maxit", c_int32)]
+
+
 _lib = None
 
 _SIGS = {
@@ -70,6 +75,9 @@ _SIGS = {
     "ibdl_indicator": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_near_boundary": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
     "ibdl_near_widths": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ibdl_advection": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ibdl_ns_step": (c_int32, [c_void_p, ctypes.POINTER(NSParams), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, ctypes.POINTER(Info)]),
     "ibdl_net_force": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_line_integral": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int64, c_void_p]),
     "ibdl_get_timing": (c_int32, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int64), c_int32]),

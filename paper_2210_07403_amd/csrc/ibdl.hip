@@ -13,6 +13,7 @@
 
 #include "../../include/ibdl.h"
 #include "kernels.h"
+#include "ns.h"
 #include "tables.h"
 #include "tune.h"
 
@@ -57,6 +58,7 @@ struct ibdl_s {
   double* mr_wt = nullptr;      // inner-product weights [n_aug]
   double* mr_hist = nullptr;
   int64_t mr_hist_cap = 0;
+  void* ns_scratch = nullptr;   // Navier-Stokes step: forcing and raw velocity, [4][grid] of the grid type
   hipStream_t st = nullptr;
   hipStream_t aux = nullptr;    // second stream: the double-precision residual beside the recovery
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -1157,7 +1159,54 @@ void near_boundary_t(ibdl_s* h, const double* Ub, const T* omega, const T* u, do
   g.ox = h->geom.origin[0];
   g.oy = h->geom.origin[1];
   g.h = h->h;
-  near_boundary<T>(h->X, Ub, h->n_ib, g, m1, m2, omega, u, out, h->nb_flag, h->nb_count, h->nb_list, h->st);
+  near_boundary<T>(h->X, Ub, h->nq, h->n_ib, g, m1, m2, omega, u, out, h->nb_flag, h->nb_count, h->nb_list, h->st);
+}
+
+// (u . grad) u of a 2-D velocity field: the four spectral (or centred-difference) derivatives by
+// two gradient passes of the FFT pipeline (symbol i k~, no inverse), then the products.
+template <typename T> void advection_t(ibdl_s* h, const T* u, T* out) {
+  GridWork<T>& W = ensure_fields<T>(h, 4);
+  MultDesc md = base_desc<T>(h, W);
+  md.mode = 1;
+  md.stokes = 0;
+  md.c2 = 0.0;
+  md.c0 = -1.0;   // multiplier alpha sc / (c2 sigma - c0) = sc: a plain derivative
+  md.alpha = 1.0;
+  md.nc = 1;
+  md.fk[0] = FK_MASS;
+  for (int c = 0; c < 2; ++c) pipeline<T>(h, W, u + c * h->ntot, 1, W.real + 2 * c * h->ntot, 2, md, ROWS_DENSE);
+  ns_advect_combine<T>(u, W.real, h->ntot, out, h->st);
+}
+
+// One step of the Navier-Stokes IMEX scheme (Sec. 6.5).  On entry u = u^n, u_prev = u^{n-1},
+// n = N(u^n), n_prev = N(u^{n-1}); on return u = u^{n+1} (recovered, near-boundary interpolated,
+// strip reset), u_prev = u^n, n = N(u^{n+1}), n_prev = N(u^n), q = the density.
+template <typename T>
+int ns_step_t(ibdl_s* h, const ibdl_ns_params_t& p, const double* Ub, const T* omega, T* u_prev, T* u, T* n_prev,
+              T* n, double* q, ibdl_info_t* info) {
+  const int64_t nn = 2 * h->ntot;
+  if (!h->ns_scratch) h->ns_scratch = h->dalloc<T>(sizeof(T) * 2 * nn);
+  T* g = static_cast<T*>(h->ns_scratch);
+  T* raw = g + nn;
+  ns_forcing<T>(u, u_prev, n, n_prev, p.rho, p.dt, nn, g, h->st);
+  IBDL_HIP(hipMemcpyAsync(u_prev, u, sizeof(T) * nn, hipMemcpyDeviceToDevice, h->st));
+  IBDL_HIP(hipMemcpyAsync(n_prev, n, sizeof(T) * nn, hipMemcpyDeviceToDevice, h->st));
+  rhs_t<T>(h, Ub, g, h->vb);
+  int iters = 0;
+  double relres = 0.0;
+  const int status = gmres(h, h->vb, p.tol, p.maxit, q, info, &iters, &relres);
+  recover_t<T>(h, q, Ub, g, raw);
+  if (p.m1 > 0) near_boundary_t<T>(h, Ub, omega, raw, p.m1, p.m2, u);
+  else IBDL_HIP(hipMemcpyAsync(u, raw, sizeof(T) * nn, hipMemcpyDeviceToDevice, h->st));
+  ns_strip<T>(u, h->n[0], h->n[1], p.strip, p.u_inf, h->st);
+  advection_t<T>(h, u, n);
+  if (info) {
+    info->iters = iters;
+    info->status = status;
+    info->krylov_relres = relres;
+    info->true_relres_fp64 = -1.0;   // not computed in a time step
+  }
+  return status;
 }
 
 extern "C" {
@@ -1308,7 +1357,6 @@ ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, 
     if (!Ub || !omega || !u || !out) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (out == u) throw Error(IBDL_ERR_ARG, "out must not alias u");
     if (h->dim != 2) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is two-dimensional");
-    if (h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the near-boundary interpolation is for scalar problems");
     if (!(m1 >= 1.0 && m2 > m1 && m2 <= 64.0)) throw Error(IBDL_ERR_ARG, "need 1 <= m1 < m2 <= 64");
     if (h->n_ib < 2) throw Error(IBDL_ERR_ARG, "the interpolation needs at least two markers");
     if (h->mixed())
@@ -1316,6 +1364,46 @@ ibdl_status_t ibdl_near_boundary(ibdl_t h, const double* Ub, const void* omega, 
     else
       near_boundary_t<double>(h, Ub, (const double*)omega, (const double*)u, m1, m2, (double*)out);
     return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_advection(ibdl_t h, const void* u, void* out) {
+  return guarded(h, [&]() {
+    if (!u || !out) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (u == out) throw Error(IBDL_ERR_ARG, "out must not alias u");
+    if (h->dim != 2 || !h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the nonlinear term is for 2-D Stokes handles");
+    if (h->mixed()) advection_t<float>(h, (const float*)u, (float*)out);
+    else advection_t<double>(h, (const double*)u, (double*)out);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_ns_step(ibdl_t h, const ibdl_ns_params_t* p, const double* Ub, const void* omega, void* u_prev,
+                           void* u, void* n_prev, void* n, double* q, ibdl_info_t* info) {
+  return guarded(h, [&]() {
+    if (!p || !Ub || !u_prev || !u || !n_prev || !n || !q) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (h->dim != 2 || !h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the Navier-Stokes step is for 2-D Stokes handles");
+    if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "the Navier-Stokes step uses the double layer method");
+    if (!(p->rho > 0) || !(p->dt > 0) || !std::isfinite(p->rho) || !std::isfinite(p->dt))
+      throw Error(IBDL_ERR_ARG, "rho and dt must be positive and finite");
+    const double k2 = 1.5 * p->rho / p->dt;
+    if (fabs(h->cfg.kappa * h->cfg.kappa - k2) > 1e-10 * k2)
+      throw Error(IBDL_ERR_ARG, "the handle's kappa^2 must equal 3 rho / (2 dt)");
+    if (p->m1 != 0 && !(p->m1 >= 1.0 && p->m2 > p->m1 && p->m2 <= 64.0))
+      throw Error(IBDL_ERR_ARG, "need m1 = 0 or 1 <= m1 < m2 <= 64");
+    if (p->m1 != 0 && !omega) throw Error(IBDL_ERR_ARG, "omega is needed for the near-boundary interpolation");
+    if (p->strip < 0 || p->strip > h->n[0]) throw Error(IBDL_ERR_ARG, "strip width out of range");
+    if (!std::isfinite(p->u_inf) || !(p->tol >= 0)) throw Error(IBDL_ERR_ARG, "u_inf and tol must be finite");
+    if (p->maxit < 1 || p->maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
+    const void* ptrs[4] = {u_prev, u, n_prev, n};
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (ptrs[a] == ptrs[b]) throw Error(IBDL_ERR_ARG, "u_prev, u, n_prev and n must be distinct");
+    if (h->mixed())
+      return ns_step_t<float>(h, *p, Ub, (const float*)omega, (float*)u_prev, (float*)u, (float*)n_prev, (float*)n, q,
+                              info);
+    return ns_step_t<double>(h, *p, Ub, (const double*)omega, (double*)u_prev, (double*)u, (double*)n_prev,
+                             (double*)n, q, info);
   });
 }
 

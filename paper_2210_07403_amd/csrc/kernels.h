@@ -278,11 +278,12 @@ void indicator_finish(const T* reg_in, int64_t n, T* chi, T* reg_out, hipStream_
 void fill_value(double* x, double v, int64_t n, hipStream_t st);
 // capacity of the node list near_boundary needs
 int64_t near_list_cap(int64_t n_ib, double m1, int64_t npoints);
-// out = u, then every node with omega != 0 within m1 h of a marker X[i] (2-D, [n_ib][2]) gets the
-// near-boundary interpolation (boundary values Ub, second point m2 h inside).  Scratch: flag
-// [nx * ny] bytes, count [1], list [near_list_cap].
+// out = u ([nc][ny][nx]), then every node with omega != 0 within m1 h of a marker X[i] (2-D,
+// [n_ib][2]) gets the near-boundary interpolation of each component c (boundary values
+// Ub[i * nc + c], second point m2 h inside).  Scratch: flag [nx * ny] bytes, count [1], list
+// [near_list_cap].
 template <typename T>
-void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGeom& g, double m1, double m2,
+void near_boundary(const double* X, const double* Ub, int nc, int64_t n_ib, const NearGeom& g, double m1, double m2,
                    const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st);
 
 // ------------------------------------------------------------------ MINRES (device recurrences)

@@ -128,7 +128,7 @@ constexpr int kNBBlocks = 2048; // grid-stride over the listed nodes
 // (indices differ), so every lane ends with the same three markers the sequential scan finds.
 template <typename T>
 __global__ __launch_bounds__(kNB) void k_near_fix(const double* __restrict__ X, const double* __restrict__ Ub,
-                                                  int64_t n_ib, NearGeom g, double m2, const int* __restrict__ count,
+                                                  int ubs, int64_t n_ib, NearGeom g, double m2, const int* __restrict__ count,
                                                   const int* __restrict__ list, const T* __restrict__ u,
                                                   T* __restrict__ out) {
   const int n = *count;
@@ -174,7 +174,8 @@ __global__ __launch_bounds__(kNB) void k_near_fix(const double* __restrict__ X, 
     const double x1 = X[2 * a], y1 = X[2 * a + 1], x2 = X[2 * b], y2 = X[2 * b + 1];
     const double xa = x2 + tc * (x1 - x2), ya = y2 + tc * (y1 - y2);
     const double l12 = sqrt(dist2(x1, y1, x2, y2));
-    const double uA = Ub[a] * sqrt(dist2(xa, ya, x2, y2)) / l12 + Ub[b] * sqrt(dist2(xa, ya, x1, y1)) / l12;
+    const double uA = Ub[(int64_t)a * ubs] * sqrt(dist2(xa, ya, x2, y2)) / l12 +
+                      Ub[(int64_t)b * ubs] * sqrt(dist2(xa, ya, x1, y1)) / l12;
     const double dpa = sqrt(dist2(px, py, xa, ya));
     double up = uA;
     if (dpa > 0.0) {
@@ -209,10 +210,10 @@ int64_t near_list_cap(int64_t n_ib, double m1, int64_t npoints) {
 }
 
 template <typename T>
-void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGeom& g, double m1, double m2,
+void near_boundary(const double* X, const double* Ub, int nc, int64_t n_ib, const NearGeom& g, double m1, double m2,
                    const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st) {
   const int64_t n = (int64_t)g.nx * g.ny;
-  IBDL_HIP(hipMemcpyAsync(out, u, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
+  IBDL_HIP(hipMemcpyAsync(out, u, sizeof(T) * n * nc, hipMemcpyDeviceToDevice, st));
   IBDL_HIP(hipMemsetAsync(flag, 0, n, st));
   IBDL_HIP(hipMemsetAsync(count, 0, sizeof(int), st));
   if (n_ib == 0) return;
@@ -223,14 +224,16 @@ void near_boundary(const double* X, const double* Ub, int64_t n_ib, const NearGe
   IBDL_LAUNCH_CHECK();
   const int64_t waves = near_list_cap(n_ib, m1, n);
   const int64_t nblk = std::min<int64_t>((waves + kNB / 64 - 1) / (kNB / 64), kNBBlocks);
-  hipLaunchKernelGGL((k_near_fix<T>), dim3((unsigned)nblk), dim3(kNB), 0, st, X, Ub, n_ib, g, m2, count, list, u,
-                     out);
-  IBDL_LAUNCH_CHECK();
+  for (int c = 0; c < nc; ++c) {   // component c: boundary values Ub[i * nc + c], field c
+    hipLaunchKernelGGL((k_near_fix<T>), dim3((unsigned)nblk), dim3(kNB), 0, st, X, Ub + c, nc, n_ib, g, m2, count,
+                       list, u + c * n, out + c * n);
+    IBDL_LAUNCH_CHECK();
+  }
 }
 
 #define IBDL_NB_INST(T)                                                                                    \
   template void indicator_finish<T>(const T*, int64_t, T*, T*, hipStream_t);                              \
-  template void near_boundary<T>(const double*, const double*, int64_t, const NearGeom&, double, double,  \
+  template void near_boundary<T>(const double*, const double*, int, int64_t, const NearGeom&, double, double, \
                                  const T*, const T*, T*, unsigned char*, int*, int*, hipStream_t);
 IBDL_NB_INST(float)
 IBDL_NB_INST(double)
