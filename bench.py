@@ -211,7 +211,69 @@ def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
     out["cylinder_array_drag"] = _cylinder_drag(dev)
     print("# extras: single vs double layer", file=sys.stderr, flush=True)
     out["ibsl_vs_ibdl_helmholtz1024"] = _ibsl_vs_ibdl(dev)
+    print("# extras: Navier-Stokes cylinder", file=sys.stderr, flush=True)
+    out["ns_cylinder_re100"] = ns_cylinder(dev, 100.0, 200, 5)
     return out
+
+
+def ns_cylinder(dev, re, steps, warm, report_every=0, precision="fp64"):
+    """Flow past a cylinder with the Navier-Stokes IMEX scheme (Sec. 6.5's setting): periodic box
+    [0, 8]^2 on 1024^2 (dx = 2^-7), cylinder r = 0.15 at (1.85, 4), rho = 1, u_inf = 1 on a 4-column
+    inflow strip, Re = 2 r rho u_inf / mu, dt = 1.8e-3, completed IBDL (eta = 10), spectral,
+    near-boundary interpolation m1 = 3, m2 = 4; starts from the uniform flow.  Times `steps` steps
+    after `warm`, and reports the drag coefficient C_D = B_1 / (rho u_inf^2 r) of the last step by
+    the control volume [0.5, 3.203125] x [2.8125, 5.1875]."""
+    import math
+    import numpy as np
+    import torch
+    import paper_2210_07403_amd as ibdl
+    from workloads import geometry as geo
+    N, L, r, c0 = 1024, 8.0, 0.15, (1.85, 4.0)
+    rho, u_inf, dt, eta = 1.0, 1.0, 1.8e-3, 10.0
+    mu = 2 * r * rho * u_inf / re
+    h = L / N
+    curve = geo.PolarCurve(c0, r)
+    mk = curve.markers(geo.n_ib_for_spacing(curve.perimeter(), h, 1.0)).flipped()
+    pr = ibdl.Problem(2, (N, N), (L, L), (0.0, 0.0), mk.X, mk.nrm, mk.ds, pde="stokes",
+                      kappa=math.sqrt(1.5 * rho / dt), mu=mu, eta=eta, kernel="peskin4", disc="spectral",
+                      precision=precision, device=dev)
+    ax = h * np.arange(N)
+    ys, xs = np.meshgrid(ax, ax, indexing="ij")
+    omega = torch.as_tensor((np.hypot(xs - c0[0], ys - c0[1]) >= r).astype(np.float64), device=dev).to(pr.grid_dtype)
+    u0 = torch.zeros((2, N, N), dtype=pr.grid_dtype, device=dev)
+    u0[0] = u_inf
+    state = [u0.clone(), u0.clone(), torch.zeros_like(u0), torch.zeros_like(u0)]
+    g = torch.empty_like(u0)
+    Ub = np.zeros((mk.X.shape[0], 2))
+    box = (int(round(0.5 / h)), int(round(3.203125 / h)), int(round(2.8125 / h)), int(round(5.1875 / h)))
+    iters = []
+    hist = []
+
+    def cd():
+        p = pr.pressure(q, g)
+        B = pr.cv_force(state[1], state[0], dt, p, omega, rho, box).cpu().numpy()
+        return float(B[0] / (rho * u_inf ** 2 * r)), float(B[1] / (rho * u_inf ** 2 * r))
+
+    for _ in range(warm):
+        q, info = pr.ns_step(state, Ub, rho, dt, omega, 3, 4, 4, u_inf, tol=1e-8, maxit=100, g_out=g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        q, info = pr.ns_step(state, Ub, rho, dt, omega, 3, 4, 4, u_inf, tol=1e-8, maxit=100, g_out=g)
+        iters.append(info.iters)
+        if report_every and (k + 1) % report_every == 0:
+            cdx, cdy = cd()
+            hist.append((round((warm + k + 1) * dt, 4), round(cdx, 5), round(cdy, 5)))
+            print(f"# t = {hist[-1][0]}: C_D = {hist[-1][1]}, C_L = {hist[-1][2]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cdx, cdy = cd()
+    pr.close()
+    return {"workload": "flow past a cylinder, Re = %g, [0, 8]^2 on 1024^2, %d markers, dt = 1.8e-3, eta = 10, "
+                        "spectral, %s, GMRES tol 1e-8" % (re, mk.X.shape[0], precision),
+            "steps": steps, "ms_per_step": round(1e3 * el / steps, 3), "steps_per_sec": round(steps / el, 1),
+            "mean_gmres_iters": round(float(np.mean(iters)), 2), "t_end": round((warm + steps) * dt, 4),
+            "C_D": round(cdx, 5), "C_L": round(cdy, 5), "history": hist}
 
 
 def _ibsl_vs_ibdl(dev):
@@ -339,7 +401,16 @@ def main():
                     help="skip the mixed-vs-FP64, adjoint and batched measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (counter calibration runs)")
+    ap.add_argument("--ns-cylinder", type=int, default=0, metavar="STEPS",
+                    help="only run the Navier-Stokes cylinder for STEPS steps and print its JSON line")
+    ap.add_argument("--ns-re", type=float, default=10.0)
     args = ap.parse_args()
+    if args.ns_cylinder > 0:
+        import torch
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        print(json.dumps(ns_cylinder(dev, args.ns_re, args.ns_cylinder, 0, report_every=max(args.ns_cylinder // 40, 1))))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the IBDL library has no multi-GPU path (see the design notes); "
               "run with --gpus 1", file=sys.stderr)

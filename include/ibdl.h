@@ -275,11 +275,32 @@ typedef struct {
  * term is formed from the interpolated field.  State (device [2][ny][nx] of the grid type, owned
  * by the caller, four distinct buffers): on entry u = u^n, u_prev = u^{n-1}, n = N(u^n),
  * n_prev = N(u^{n-1}); on return u = u^{n+1}, u_prev = u^n, n = N(u^{n+1}), n_prev = N(u^n).
- * q: device double [n_aug], the density of the step.  info (optional host struct): the GMRES
+ * q: device double [n_aug], the density of the step; g_out (optional, [2][ny][nx] of the grid
+ * type): the step's forcing g~, which ibdl_pressure needs.  info (optional host struct): the GMRES
  * iterations and residual of the step; true_relres_fp64 is -1 (not computed).  Synchronises the
  * handle's stream once per GMRES iteration, like ibdl_solve. */
 ibdl_status_t ibdl_ns_step(ibdl_t h, const ibdl_ns_params_t* p, const double* Ub, const void* omega, void* u_prev,
-                           void* u, void* n_prev, void* n, double* q, ibdl_info_t* info);
+                           void* u, void* n_prev, void* n, double* q, void* g_out, ibdl_info_t* info);
+
+/* Pressure of a two-dimensional Brinkman / Stokes solution (Sec. 6.5, with the system of Sec. 6.1
+ * and 6.3): taking the divergence of (mu Delta - k^2) u - grad p + eta S Q + mu div(S A) = g~ with
+ * div u = -S(Q.n) gives p = Delta_0^-1 [div(eta S Q + mu div(S A) - g~) - (mu Delta - k^2) S(Q.n)],
+ * the mean-zero solution.  q: device double [n_aug] (ibdl_solve's); g_grid: the forcing
+ * ([2][ny][nx], grid type) or NULL; p: device [ny][nx] of the grid type, owned by the caller.
+ * Asynchronous on the handle's stream. */
+ibdl_status_t ibdl_pressure(ibdl_t h, const double* q, const void* g_grid, void* p);
+
+/* Force on a body by a control volume (Sec. 6.5): over the grid box R of node indices
+ * box = {i0, i1, j0, j1} (x from i0 to i1, y from j0 to j1, inclusive; 0 <= i0 < i1 < nx,
+ * 0 <= j0 < j1 < ny) around the body,
+ *   B = -rho int_{R'} u_t dx + oint_{dR} (sigma - rho u u^T) . n_R dl,  sigma = -p I + mu (grad u + grad u^T),
+ * R' = the nodes of R with omega != 0 (the fluid), u_t = (u - u_prev) / dt (the volume term is
+ * left out when u_prev is NULL: steady flow), the velocity gradients by the handle's derivative
+ * symbols, both integrals by the trapezoidal rule on the nodes.  u, u_prev: [2][ny][nx], p, omega:
+ * [ny][nx], device, grid type.  out: device double [2].  2-D Stokes handles (mu from the handle).
+ * Asynchronous on the handle's stream. */
+ibdl_status_t ibdl_cv_force(ibdl_t h, const void* u, const void* u_prev, double dt, const void* p, const void* omega,
+                            double rho, const int32_t* box, double* out);
 
 /* Net force and torque of a two-dimensional Stokes solution with the completed method (Sec. 6.1,
  * exterior domains; Sec. 6.5, Stokes flow around a periodic array of cylinders).  The single layer

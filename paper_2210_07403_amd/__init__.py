@@ -212,14 +212,16 @@ class Problem:
         B.check(B.load().ibdl_advection(self._h, ut.data_ptr(), out.data_ptr()), self._h)
         return out
 
-    def ns_step(self, state, Ub, rho, dt, omega=None, m1=0.0, m2=0.0, strip=0, u_inf=0.0, tol=1e-8, maxit=100):
+    def ns_step(self, state, Ub, rho, dt, omega=None, m1=0.0, m2=0.0, strip=0, u_inf=0.0, tol=1e-8, maxit=100,
+                g_out=None):
         """One Navier-Stokes IMEX step (Sec. 6.5) on state = [u_prev, u, n_prev, n] (four grid
-        tensors of shape (2, ny, nx), updated in place); returns (q, SolveInfo)."""
+        tensors of shape (2, ny, nx), updated in place; g_out, if given, receives the step's
+        forcing); returns (q, SolveInfo)."""
         p = B.NSParams(float(rho), float(dt), float(m1), float(m2), int(strip), float(u_inf), float(tol), int(maxit))
         ub = _dev_f64(Ub, self.device).reshape(-1)
         if ub.numel() != 2 * self.n_ib:
             raise ValueError("Ub must have 2 n_ib entries")
-        for t in state:
+        for t in list(state) + ([g_out] if g_out is not None else []):
             if not (isinstance(t, torch.Tensor) and t.dtype == self.grid_dtype and t.is_contiguous()
                     and t.numel() == 2 * self.grid_points and t.device.type == self.device.type):
                 raise ValueError("state tensors must be contiguous (2, ny, nx) grid tensors on the device")
@@ -227,9 +229,32 @@ class Problem:
         q = torch.empty(self.n_aug, dtype=torch.float64, device=self.device)
         info = B.Info()
         st = B.load().ibdl_ns_step(self._h, ctypes.byref(p), ub.data_ptr(), om.data_ptr() if om is not None else None,
-                                   *[t.data_ptr() for t in state], q.data_ptr(), ctypes.byref(info))
+                                   *[t.data_ptr() for t in state], q.data_ptr(),
+                                   g_out.data_ptr() if g_out is not None else None, ctypes.byref(info))
         B.check(st, self._h)
         return q, SolveInfo(info.iters, info.status, info.krylov_relres, info.true_relres_fp64, [])
+
+    def pressure(self, q, g=None):
+        """Mean-zero pressure of a 2-D Brinkman / Stokes solution (density q, forcing g)."""
+        qt = _dev_f64(q, self.device).reshape(-1)
+        gt = self._as_grid(g, 2) if g is not None else None
+        out = self._grid(1)[0]
+        B.check(B.load().ibdl_pressure(self._h, qt.data_ptr(), gt.data_ptr() if gt is not None else None,
+                                       out.data_ptr()), self._h)
+        return out
+
+    def cv_force(self, u, u_prev, dt, p, omega, rho, box):
+        """Control-volume force (Sec. 6.5) over the grid box (i0, i1, j0, j1), u_t = (u - u_prev) / dt
+        (no volume term for u_prev None): device double [2]."""
+        up_ = self._as_grid(u_prev, 2) if u_prev is not None else None
+        u_ = self._as_grid(u, 2)
+        p_ = self._as_grid(p, 1)
+        om = self._as_grid(omega, 1)
+        bx = (ctypes.c_int32 * 4)(*[int(v) for v in box])
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        B.check(B.load().ibdl_cv_force(self._h, u_.data_ptr(), up_.data_ptr() if up_ is not None else None, float(dt),
+                                       p_.data_ptr(), om.data_ptr(), float(rho), bx, out.data_ptr()), self._h)
+        return out
 
     def net_force(self, q):
         """(B_x, B_y, L) of a 2-D completed Stokes solution q (Sec. 6.1, Sec. 6.5): device double [3]."""

@@ -77,7 +77,10 @@ _SIGS = {
     "ibdl_near_widths": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_advection": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_ns_step": (c_int32, [c_void_p, ctypes.POINTER(NSParams), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                               c_void_p, c_void_p, ctypes.POINTER(Info)]),
+                               c_void_p, c_void_p, c_void_p, ctypes.POINTER(Info)]),
+    "ibdl_pressure": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ibdl_cv_force": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_double, c_void_p,
+                                c_void_p]),
     "ibdl_net_force": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_line_integral": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int64, c_void_p]),
     "ibdl_get_timing": (c_int32, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int64), c_int32]),

@@ -445,6 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, 
 //   Stokes:  u^ = alpha*sc * [ i k~ s^/ell + (1/lam) P^ (G^ + mu v^) ],  ell = -sigma,
 //            lam = c2*ell + c0, P^ = I - k~ k~^T / ell (I at ell = 0), s = (A11 + A22)/2,
 //            v_i = sum_j i k~_j A_ij; 1/ell and 1/lam read as 0 where they vanish.
+//   pressure (mode 3, Stokes fields, one output; the G fields hold eta S Q - g~):
+//            p^ = alpha*sc * [ -i k~_j G^_j + mu k~_i k~_j A^_ij + (c2 sigma - c0) s^ ] / ell.
 template <typename T>
 __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, T sig, const T* kt) {
   using C = cplx<T>;
@@ -462,6 +464,16 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
   const T P0 = (o == 0 ? (T)1 : (T)0) - ko * kt[0] * il;
   const T P1 = (o == 1 ? (T)1 : (T)0) - ko * kt[1] * il;
   const T mu = (T)md.mu, a = (T)(md.alpha * md.sc);
+  if (md.mode == 3) {   // pressure (2-D): [i k~.(g^ - f^) + (c2 sigma - c0) s^] / ell
+    const T lamh = (T)0.5 * ((T)md.c2 * sig - (T)md.c0);
+    switch (fk) {
+      case FK_A11: return mk<C>(a * il * (mu * kt[0] * kt[0] + lamh), 0);
+      case FK_A12: return mk<C>(a * il * ((T)2 * mu * kt[0] * kt[1]), 0);
+      case FK_A22: return mk<C>(a * il * (mu * kt[1] * kt[1] + lamh), 0);
+      case FK_G1: return mk<C>(0, -a * il * kt[0]);
+      default: return mk<C>(0, -a * il * kt[1]);
+    }
+  }
   switch (fk) {
     case FK_A11: return mk<C>(0, a * ((T)0.5 * ko * il + mu * is * P0 * kt[0]));
     case FK_A12: return mk<C>(0, a * (mu * is * (P0 * kt[1] + P1 * kt[0])));
@@ -769,6 +781,8 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
     else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5)
       hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
+    else if (md.mode == 3 && md.stokes && md.dim == 2 && no == 1)
+      hipLaunchKernelGGL((k_fused<T, N, 1, true>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
     else if (md.mode != 0)
       throw Error(-2, "fused pass: unsupported transposed multiplier");
     else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)

@@ -1178,17 +1178,52 @@ template <typename T> void advection_t(ibdl_s* h, const T* u, T* out) {
   ns_advect_combine<T>(u, W.real, h->ntot, out, h->st);
 }
 
+// Mean-zero pressure of the Brinkman / Stokes grid solution with density q and forcing g: the
+// spread fields of the apply (the single-layer fields carry eta S Q - g~) through the pressure
+// multiplier.
+template <typename T> void pressure_t(ibdl_s* h, const double* q, const T* g, T* p) {
+  GridWork<T>& W = ensure_work<T>(h);
+  const bool mass = h->cfg.eta > 0 || g != nullptr;
+  DensityPlan pl = density_plan<T>(h, W, mass);
+  SpreadArgs a = spread_args(h, pl.mode, pl.nf, q);
+  a.mass = mass ? 1 : 0;
+  a.m = nullptr;
+  spread_w<T>(h, a, W, W.real);
+  MultDesc md = pl.md;
+  md.mode = 3;
+  md.alpha = 1.0;
+  pipeline<T>(h, W, W.real, pl.nf, p, 1, md, ROWS_DENSE, true, g, 3, g ? 2 : 0);
+}
+
+// Control-volume force (Sec. 6.5) of u with time derivative ut and pressure p over a grid box.
+template <typename T>
+void cv_force_t(ibdl_s* h, const T* u, const T* uprev, double dt, const T* p, const T* omega, double rho,
+                const int* box, double* out) {
+  GridWork<T>& W = ensure_fields<T>(h, 4);
+  MultDesc md = base_desc<T>(h, W);
+  md.mode = 1;
+  md.stokes = 0;
+  md.c2 = 0.0;
+  md.c0 = -1.0;
+  md.alpha = 1.0;
+  md.nc = 1;
+  md.fk[0] = FK_MASS;
+  for (int c = 0; c < 2; ++c) pipeline<T>(h, W, u + c * h->ntot, 1, W.real + 2 * c * h->ntot, 2, md, ROWS_DENSE);
+  cv_force<T>(u, uprev, dt, p, omega, W.real, h->n[0], h->n[1], box, h->h, rho, h->cfg.mu, out, h->st);
+}
+
 // One step of the Navier-Stokes IMEX scheme (Sec. 6.5).  On entry u = u^n, u_prev = u^{n-1},
 // n = N(u^n), n_prev = N(u^{n-1}); on return u = u^{n+1} (recovered, near-boundary interpolated,
 // strip reset), u_prev = u^n, n = N(u^{n+1}), n_prev = N(u^n), q = the density.
 template <typename T>
 int ns_step_t(ibdl_s* h, const ibdl_ns_params_t& p, const double* Ub, const T* omega, T* u_prev, T* u, T* n_prev,
-              T* n, double* q, ibdl_info_t* info) {
+              T* n, double* q, T* g_out, ibdl_info_t* info) {
   const int64_t nn = 2 * h->ntot;
   if (!h->ns_scratch) h->ns_scratch = h->dalloc<T>(sizeof(T) * 2 * nn);
   T* g = static_cast<T*>(h->ns_scratch);
   T* raw = g + nn;
   ns_forcing<T>(u, u_prev, n, n_prev, p.rho, p.dt, nn, g, h->st);
+  if (g_out) IBDL_HIP(hipMemcpyAsync(g_out, g, sizeof(T) * nn, hipMemcpyDeviceToDevice, h->st));
   IBDL_HIP(hipMemcpyAsync(u_prev, u, sizeof(T) * nn, hipMemcpyDeviceToDevice, h->st));
   IBDL_HIP(hipMemcpyAsync(n_prev, n, sizeof(T) * nn, hipMemcpyDeviceToDevice, h->st));
   rhs_t<T>(h, Ub, g, h->vb);
@@ -1379,7 +1414,7 @@ ibdl_status_t ibdl_advection(ibdl_t h, const void* u, void* out) {
 }
 
 ibdl_status_t ibdl_ns_step(ibdl_t h, const ibdl_ns_params_t* p, const double* Ub, const void* omega, void* u_prev,
-                           void* u, void* n_prev, void* n, double* q, ibdl_info_t* info) {
+                           void* u, void* n_prev, void* n, double* q, void* g_out, ibdl_info_t* info) {
   return guarded(h, [&]() {
     if (!p || !Ub || !u_prev || !u || !n_prev || !n || !q) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (h->dim != 2 || !h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the Navier-Stokes step is for 2-D Stokes handles");
@@ -1395,15 +1430,45 @@ ibdl_status_t ibdl_ns_step(ibdl_t h, const ibdl_ns_params_t* p, const double* Ub
     if (p->strip < 0 || p->strip > h->n[0]) throw Error(IBDL_ERR_ARG, "strip width out of range");
     if (!std::isfinite(p->u_inf) || !(p->tol >= 0)) throw Error(IBDL_ERR_ARG, "u_inf and tol must be finite");
     if (p->maxit < 1 || p->maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
-    const void* ptrs[4] = {u_prev, u, n_prev, n};
-    for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b)
-        if (ptrs[a] == ptrs[b]) throw Error(IBDL_ERR_ARG, "u_prev, u, n_prev and n must be distinct");
+    const void* ptrs[5] = {u_prev, u, n_prev, n, g_out};
+    for (int a = 0; a < 5; ++a)
+      for (int b = a + 1; b < 5; ++b)
+        if (ptrs[a] && ptrs[a] == ptrs[b]) throw Error(IBDL_ERR_ARG, "u_prev, u, n_prev, n and g_out must be distinct");
     if (h->mixed())
       return ns_step_t<float>(h, *p, Ub, (const float*)omega, (float*)u_prev, (float*)u, (float*)n_prev, (float*)n, q,
-                              info);
+                              (float*)g_out, info);
     return ns_step_t<double>(h, *p, Ub, (const double*)omega, (double*)u_prev, (double*)u, (double*)n_prev,
-                             (double*)n, q, info);
+                             (double*)n, q, (double*)g_out, info);
+  });
+}
+
+ibdl_status_t ibdl_pressure(ibdl_t h, const double* q, const void* g_grid, void* p) {
+  return guarded(h, [&]() {
+    if (!q || !p) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (h->dim != 2 || !h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the pressure is for 2-D Stokes handles");
+    if (h->mixed()) pressure_t<float>(h, q, (const float*)g_grid, (float*)p);
+    else pressure_t<double>(h, q, (const double*)g_grid, (double*)p);
+    return IBDL_OK;
+  });
+}
+
+ibdl_status_t ibdl_cv_force(ibdl_t h, const void* u, const void* u_prev, double dt, const void* p, const void* omega,
+                            double rho, const int32_t* box, double* out) {
+  return guarded(h, [&]() {
+    if (!u || !p || !omega || !box || !out) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    if (u_prev && !(dt > 0 && std::isfinite(dt))) throw Error(IBDL_ERR_ARG, "dt must be positive and finite");
+    if (h->dim != 2 || !h->stokes()) throw Error(IBDL_ERR_UNSUPPORTED, "the control-volume force is for 2-D Stokes handles");
+    if (!(box[0] >= 0 && box[0] < box[1] && box[1] < h->n[0] && box[2] >= 0 && box[2] < box[3] && box[3] < h->n[1]))
+      throw Error(IBDL_ERR_ARG, "box must satisfy 0 <= i0 < i1 < nx and 0 <= j0 < j1 < ny");
+    if (!std::isfinite(rho)) throw Error(IBDL_ERR_ARG, "rho must be finite");
+    const int b[4] = {box[0], box[1], box[2], box[3]};
+    if (h->mixed())
+      cv_force_t<float>(h, (const float*)u, (const float*)u_prev, dt, (const float*)p, (const float*)omega, rho, b,
+                        out);
+    else
+      cv_force_t<double>(h, (const double*)u, (const double*)u_prev, dt, (const double*)p, (const double*)omega, rho,
+                         b, out);
+    return IBDL_OK;
   });
 }
 

@@ -62,7 +62,8 @@ struct RowMask {
 };
 
 struct MultDesc {
-  int mode;         // 0: forward multiplier; 1: scalar gradient outputs; 2: transposed Stokes
+  int mode;         // 0: forward multiplier; 1: scalar gradient outputs; 2: transposed Stokes;
+                    // 3: Stokes pressure
   int dim;          // 2 or 3
   int nxh;          // nx/2 + 1 modes along x
   int nxp;          // row pitch of the half spectrum (>= nxh; lines with x index >= nxh are padding)

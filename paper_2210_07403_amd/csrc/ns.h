@@ -17,4 +17,12 @@ void ns_advect_combine(const T* u, const T* G, int64_t n, T* out, hipStream_t st
 template <typename T>
 void ns_strip(T* u, int nx, int ny, int width, double u_inf, hipStream_t st);
 
+// Control-volume force over the grid box box = (i0, i1, j0, j1) (inclusive node indices):
+// out[2] = oint (sigma - rho u u^T) . n dl - rho int omega u_t dx, sigma = -p I + mu (grad u +
+// grad u^T), G[2c + d] = d_d u_c, u_t = (u - uprev) / dt (no volume term when uprev is NULL);
+// trapezoidal weights on the nodes.
+template <typename T>
+void cv_force(const T* u, const T* uprev, double dt, const T* p, const T* omega, const T* G, int nx, int ny,
+              const int* box, double h, double rho, double mu, double* out, hipStream_t st);
+
 }  // namespace ibdl

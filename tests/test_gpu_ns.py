@@ -125,6 +125,45 @@ def test_shear_wave_on_the_gpu():
     pr.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pressure_matches_oracle(precision):
+    rho, mu, dt = 1.0, 0.05, 0.01
+    mk, o, pr = _setup(64, rho, mu, dt, precision=precision)
+    xs, ys = o.grid.nodes()
+    gf = np.stack([np.sin(2 * np.pi * ys) + 0.3, np.cos(2 * np.pi * xs) * np.sin(4 * np.pi * ys)])
+    Ub = np.stack([np.cos(mk.X[:, 1]), np.sin(mk.X[:, 0])], 1)
+    q, _, info = pr.solve(Ub, gf, tol=1e-12 if precision == "fp64" else 1e-6, maxit=200)
+    qn = to_np(q)
+    gd = gf.astype(np.float64 if precision == "fp64" else np.float32).astype(np.float64)
+    got = to_np(pr.pressure(q, gf))
+    want = ns.pressure(o, qn, gd)
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    assert np.max(np.abs(got - want)) < tol * np.max(np.abs(want))
+    pr.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cv_force_matches_oracle(precision):
+    mk, o, pr = _setup(64, 1.0, 0.05, 0.01, precision=precision)
+    xs, ys = o.grid.nodes()
+    dt_ = np.float64 if precision == "fp64" else np.float32
+    rnd = lambda a: a.astype(dt_).astype(np.float64)
+    u = rnd(np.stack([1 + 0.3 * np.sin(2 * np.pi * ys) * np.cos(2 * np.pi * xs), 0.2 * np.sin(4 * np.pi * xs)]))
+    up = rnd(u - 0.01 * np.stack([np.cos(2 * np.pi * xs), np.sin(2 * np.pi * ys)]))
+    ut = (u - up) / 0.01
+    p = rnd(np.sin(2 * np.pi * (xs + ys)))
+    omega = (np.hypot(xs - 0.5, ys - 0.5) >= 0.15).astype(np.float64)
+    box = (8, 55, 6, 50)
+    got = to_np(pr.cv_force(u, up, 0.01, p, omega, 1.3, box))
+    want = ns.cv_force(o.grid, u, ut, p, omega, 1.3, 0.05, box, "spectral")
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    assert np.max(np.abs(got - want)) < tol * (1 + np.max(np.abs(want)))
+    steady = to_np(pr.cv_force(u, None, 0.0, p, omega, 1.3, box))
+    want0 = ns.cv_force(o.grid, u, 0 * ut, p, omega, 1.3, 0.05, box, "spectral")
+    assert np.max(np.abs(steady - want0)) < tol * (1 + np.max(np.abs(want0)))
+    pr.close()
+
+
 def test_rejects():
     mk, o, pr = _setup(64, 1.0, 0.05, 0.01)
     z = [torch.zeros((2, 64, 64), dtype=torch.float64, device=pr.device) for _ in range(4)]

@@ -16,6 +16,21 @@ def test_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_binding_argument_counts_match_the_header():
+    """Every declaration's parameter count equals the binding's argtypes (a wrong count would pass
+    arguments into the wrong slots)."""
+    import re
+    text = open(B.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decls = dict(re.findall(r"\b(ibdl_[a-z_]+)\s*\(([^;{]*?)\)\s*;", text))
+    assert len(decls) >= 30
+    for name, params in decls.items():
+        params = params.strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        assert name in B._SIGS, name
+        assert len(B._SIGS[name][1]) == n, (name, n, len(B._SIGS[name][1]))
+
+
 def _cfg(**kw):
     c = B.Config()
     c.dim = kw.get("dim", 2)
