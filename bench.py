@@ -269,11 +269,35 @@ def ns_cylinder(dev, re, steps, warm, report_every=0, precision="fp64"):
     el = time.perf_counter() - t0
     cdx, cdy = cd()
     pr.close()
+    st = strouhal(hist, 2 * r / u_inf)
     return {"workload": "flow past a cylinder, Re = %g, [0, 8]^2 on 1024^2, %d markers, dt = 1.8e-3, eta = 10, "
                         "spectral, %s, GMRES tol 1e-8" % (re, mk.X.shape[0], precision),
             "steps": steps, "ms_per_step": round(1e3 * el / steps, 3), "steps_per_sec": round(steps / el, 1),
             "mean_gmres_iters": round(float(np.mean(iters)), 2), "t_end": round((warm + steps) * dt, 4),
-            "C_D": round(cdx, 5), "C_L": round(cdy, 5), "history": hist}
+            "C_D": round(cdx, 5), "C_L": round(cdy, 5), "strouhal_second_half": st, "history": hist}
+
+
+def strouhal(hist, d_over_u):
+    """St = D / (u_inf T) from the mean spacing T of the upward zero crossings of C_L - mean(C_L)
+    over the second half of a (t, C_D, C_L) history; None without at least three crossings or with
+    a lift amplitude below 1e-3."""
+    if len(hist) < 8:
+        return None
+    h2 = hist[len(hist) // 2:]
+    t = [a for a, _, _ in h2]
+    cl = [c for _, _, c in h2]
+    m = sum(cl) / len(cl)
+    if max(abs(c - m) for c in cl) < 1e-3:
+        return None
+    ups = []
+    for k in range(1, len(cl)):
+        a, b = cl[k - 1] - m, cl[k] - m
+        if a < 0 <= b:
+            ups.append(t[k - 1] + (t[k] - t[k - 1]) * (-a) / (b - a))
+    if len(ups) < 3:
+        return None
+    period = (ups[-1] - ups[0]) / (len(ups) - 1)
+    return round(d_over_u / period, 4)
 
 
 def _ibsl_vs_ibdl(dev):
@@ -404,12 +428,14 @@ def main():
     ap.add_argument("--ns-cylinder", type=int, default=0, metavar="STEPS",
                     help="only run the Navier-Stokes cylinder for STEPS steps and print its JSON line")
     ap.add_argument("--ns-re", type=float, default=10.0)
+    ap.add_argument("--ns-every", type=int, default=0, help="drag/lift sample interval in steps (0: STEPS / 40)")
     args = ap.parse_args()
     if args.ns_cylinder > 0:
         import torch
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
-        print(json.dumps(ns_cylinder(dev, args.ns_re, args.ns_cylinder, 0, report_every=max(args.ns_cylinder // 40, 1))))
+        every = args.ns_every if args.ns_every > 0 else max(args.ns_cylinder // 40, 1)
+        print(json.dumps(ns_cylinder(dev, args.ns_re, args.ns_cylinder, 0, report_every=every)))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the IBDL library has no multi-GPU path (see the design notes); "
