@@ -89,3 +89,15 @@ def test_null_pointers_rejected():
     assert lib.ibdl_create(None, 10, None, None, None, ctypes.byref(h)) == -1
     assert lib.ibdl_apply(None, None, None) == -1
     assert lib.ibdl_destroy(None) == -1
+    # the entry points beyond the operator reject a NULL handle before touching anything
+    assert lib.ibdl_indicator(None, None, None) == -1
+    assert lib.ibdl_near_boundary(None, None, None, None, 6.0, 8.0, None) == -1
+    assert lib.ibdl_near_widths(None, None, None) == -1
+    assert lib.ibdl_net_force(None, None, None) == -1
+    assert lib.ibdl_line_integral(None, None, 0, 0, 0, None) == -1
+    assert lib.ibdl_advection(None, None, None) == -1
+    p = B.NSParams(1.0, 0.01, 0.0, 0.0, 0, 0.0, 1e-8, 10)
+    assert lib.ibdl_ns_step(None, ctypes.byref(p), None, None, None, None, None, None, None, None, None) == -1
+    assert lib.ibdl_pressure(None, None, None, None) == -1
+    box = (ctypes.c_int32 * 4)(1, 2, 1, 2)
+    assert lib.ibdl_cv_force(None, None, None, 0.0, None, None, 1.0, box, None) == -1
