@@ -429,7 +429,17 @@ def main():
                     help="only run the Navier-Stokes cylinder for STEPS steps and print its JSON line")
     ap.add_argument("--ns-re", type=float, default=10.0)
     ap.add_argument("--ns-every", type=int, default=0, help="drag/lift sample interval in steps (0: STEPS / 40)")
+    ap.add_argument("--only", choices=["near_boundary", "cylinder_array", "ibsl", "ns"], default=None,
+                    help="only run one of the measurements beyond the hot path and print its JSON line")
     args = ap.parse_args()
+    if args.only:
+        import torch
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        run = {"near_boundary": _near_boundary_timing, "cylinder_array": _cylinder_drag, "ibsl": _ibsl_vs_ibdl,
+               "ns": lambda d: ns_cylinder(d, 100.0, 200, 5)}[args.only]
+        print(json.dumps(run(dev)))
+        return
     if args.ns_cylinder > 0:
         import torch
         dev = torch.device("cuda:0")

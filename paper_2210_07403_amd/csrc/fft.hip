@@ -404,8 +404,14 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
 template <typename T> constexpr int rmax_t(int N) {
   return sizeof(T) == 8 && N <= 256 && plan_rmax(N) > 8 ? 8 : plan_rmax(N);
 }
-template <typename T, int N> struct TileCfg {
-  static constexpr int RMX = rmax_t<T>(N);
+// Elements per thread of the fused last-axis passes: the passes that keep two accumulators or two
+// input spectra per element (Stokes, the transposed Stokes pass) and the 1024-point double
+// passes hold 8 instead of 16, which keeps them clear of register spills and raises occupancy.
+template <typename T> constexpr int fused_rmax(int N, int nacc) {
+  return plan_rmax(N) > 8 && (nacc >= 2 || (sizeof(T) == 8 && N >= 1024)) ? 8 : rmax_t<T>(N);
+}
+template <typename T, int N, int RX = rmax_t<T>(N)> struct TileCfg {
+  static constexpr int RMX = RX;
   static constexpr int T_ = Plan<N, RMX>::T;
   static constexpr int W0 = kBlock / T_;
   static constexpr int WL = kLdsBytes / (N * (int)sizeof(cplx<T>));
@@ -487,7 +493,7 @@ template <typename T, int N, int NO, bool STOKES>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                   const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
-  using TC = TileCfg<T, N>;
+  using TC = TileCfg<T, N, fused_rmax<T>(N, NO)>;
   constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -570,7 +576,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                    const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
-  using TC = TileCfg<T, N>;
+  using TC = TileCfg<T, N, fused_rmax<T>(N, 1)>;
   constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -606,7 +612,7 @@ template <typename T, int N, int NI, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data, int64_t P, int no, MultDesc md,
                                                       const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
-  using TC = TileCfg<T, N>;
+  using TC = TileCfg<T, N, fused_rmax<T>(N, NI)>;
   constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -772,27 +778,40 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
     throw Error(-2, "fused FFT pass: one problem's fields may not span 4 GiB");
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
-    using TC = TileCfg<T, N>;
-    const int W = pick(w, TC::W);
-    const int64_t nb = (P + W - 1) / W;
-    const size_t lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
-    const dim3 grid((unsigned)nb, (unsigned)batch), blk(W * TC::T_);
-    if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1)
+    // launch shape of a kernel whose tile configuration is TC: lines per block, grid, LDS
+    auto shape = [&](auto tc, int& W, dim3& grid, dim3& blk, size_t& lds) {
+      using TC = decltype(tc);
+      W = pick(w, TC::W);
+      grid = dim3((unsigned)((P + W - 1) / W), (unsigned)batch);
+      blk = dim3(W * TC::T_);
+      lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
+    };
+    int W = 0;
+    dim3 grid, blk;
+    size_t lds = 0;
+    if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1) {
+      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
-    else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5)
+    } else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5) {
+      shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
-    else if (md.mode == 3 && md.stokes && md.dim == 2 && no == 1)
+    } else if (md.mode == 3 && md.stokes && md.dim == 2 && no == 1) {
+      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused<T, N, 1, true>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    else if (md.mode != 0)
+    } else if (md.mode != 0) {
       throw Error(-2, "fused pass: unsupported transposed multiplier");
-    else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS)
+    } else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS) {
+      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    else if (!md.stokes && no == 1)
+    } else if (!md.stokes && no == 1) {
+      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused<T, N, 1, false>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    else if (md.stokes && no == 2)
+    } else if (md.stokes && no == 2) {
+      shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused<T, N, 2, true>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    else
+    } else {
       throw Error(-2, "fused pass: unsupported multiplier / output count");
+    }
   });
   IBDL_LAUNCH_CHECK();
 }

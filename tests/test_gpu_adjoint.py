@@ -63,6 +63,22 @@ def test_apply_transpose(name, precision):
     pr.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_apply_transpose_long_axis(precision):
+    """A 16 x 1024 Brinkman grid (completed): the transposed fused pass on 1024-point lines."""
+    base = P.brinkman_circle(16, 1.5)
+    spec = _jitter(P.ProblemSpec(**{**base.__dict__, "n": (16, 1024), "L": (2.0, 128.0), "g": None, "eta": 2.0}))
+    o = _oracle(spec)
+    A = o.assemble()
+    pr = make_problem(spec, precision)
+    p = np.random.default_rng(6).standard_normal(o.n_aug)
+    got = to_np(pr.apply_transpose(p))
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    assert relerr(got, A.T @ p) < tol, relerr(got, A.T @ p)
+    assert relerr(to_np(pr.apply(p)), A @ p) < tol
+    pr.close()
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_backward_fp64(name):
     spec = _jitter(CASES[name]())

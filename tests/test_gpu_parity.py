@@ -83,6 +83,13 @@ def test_spread_interp(gi, kernel, precision):
     dict(dim=2, n=(64, 64), L=(2.0, 2.0), pde="stokes", kappa=0.0, disc="spectral"),
     dict(dim=2, n=(32, 64), L=(1.0, 2.0), pde="stokes", kappa=2.0, disc="spectral"),
     dict(dim=2, n=(64, 64), L=(1.0, 1.0), pde="stokes", kappa=0.0, disc="fd2"),
+    # long last axes: the fused passes that hold 8 elements per thread (two accumulators, or
+    # 1024-point lines in double)
+    dict(dim=2, n=(16, 1024), L=(0.125, 8.0), pde="stokes", kappa=1.0, disc="spectral"),
+    dict(dim=2, n=(32, 256), L=(0.5, 4.0), pde="stokes", kappa=0.0, disc="spectral"),
+    dict(dim=2, n=(16, 128), L=(0.125, 1.0), pde="stokes", kappa=0.0, disc="fd2"),
+    dict(dim=2, n=(16, 1024), L=(0.125, 8.0), pde="screened", kappa=3.0, disc="fd2"),
+    dict(dim=2, n=(16, 1024), L=(0.125, 8.0), pde="screened", kappa=3.0, disc="spectral"),
 ])
 def test_grid_solve(case, precision):
     dim, n, L = case["dim"], case["n"], case["L"]
