@@ -489,6 +489,33 @@ __device__ __forceinline__ cplx<T> mult_coef(const MultDesc& md, int fk, int o, 
   }
 }
 
+// The Stokes coefficient of mult_coef with 1/ell and 1/lam of the mode given (2-D: k~ = (k0, k1)).
+template <typename T>
+__device__ __forceinline__ cplx<T> stokes_coef(const MultDesc& md, int fk, int o, T sig, T k0, T k1, T il, T is) {
+  using C = cplx<T>;
+  const T ko = o == 0 ? k0 : k1;
+  const T P0 = (o == 0 ? (T)1 : (T)0) - ko * k0 * il;
+  const T P1 = (o == 1 ? (T)1 : (T)0) - ko * k1 * il;
+  const T mu = (T)md.mu, a = (T)(md.alpha * md.sc);
+  if (md.mode == 3) {
+    const T lamh = (T)0.5 * ((T)md.c2 * sig - (T)md.c0);
+    switch (fk) {
+      case FK_A11: return mk<C>(a * il * (mu * k0 * k0 + lamh), 0);
+      case FK_A12: return mk<C>(a * il * ((T)2 * mu * k0 * k1), 0);
+      case FK_A22: return mk<C>(a * il * (mu * k1 * k1 + lamh), 0);
+      case FK_G1: return mk<C>(0, -a * il * k0);
+      default: return mk<C>(0, -a * il * k1);
+    }
+  }
+  switch (fk) {
+    case FK_A11: return mk<C>(0, a * ((T)0.5 * ko * il + mu * is * P0 * k0));
+    case FK_A12: return mk<C>(0, a * (mu * is * (P0 * k1 + P1 * k0)));
+    case FK_A22: return mk<C>(0, a * ((T)0.5 * ko * il + mu * is * P1 * k1));
+    case FK_G1: return mk<C>(a * is * P0, 0);
+    default: return mk<C>(a * is * P1, 0);
+  }
+}
+
 template <typename T, int N, int NO, bool STOKES>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                   const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
@@ -525,12 +552,21 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   for (int o = 0; o < NO; ++o)
 #pragma unroll
     for (int s = 0; s < RM; ++s) acc[o][s] = mk<C>(0, 0);
-  T gfac[RM];   // scalar multiplier alpha*sc / (c2 sigma - c0) of each register element
+  T gfac[RM];   // scalar: multiplier alpha*sc / (c2 sigma - c0); Stokes (2-D): 1/ell
+  T glam[STOKES ? RM : 1];   // Stokes: 1/lam
   if constexpr (!STOKES) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
       const T den = (T)md.c2 * (sig_l + sgl[i + s * TT]) - (T)md.c0;
       gfac[s] = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) * recip(den);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < RM; ++s) {
+      const T ell = -(sig_l + sgl[i + s * TT]);
+      gfac[s] = ell == (T)0 ? (T)0 : recip(ell);
+      const T lam = (T)md.c2 * ell + (T)md.c0;
+      glam[s] = lam == (T)0 ? (T)0 : recip(lam);
     }
   }
 
@@ -553,13 +589,12 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
       }
     } else {
 #pragma unroll
-      for (int s = 0; s < RM; ++s) {
+      for (int s = 0; s < RM; ++s) {   // Stokes is two-dimensional: k~ = (k~ across lines, k~ along)
         const int e = i + s * TT;
-        T kt[3] = {ktl[0], ktl[1], ktl[2]};
-        kt[la] = ktl_[e];
         const T sig = sig_l + sgl[e];
 #pragma unroll
-        for (int o = 0; o < NO; ++o) acc[o][s] = cadd(acc[o][s], cmul(mult_coef<T>(md, fk, o, sig, kt), v[s]));
+        for (int o = 0; o < NO; ++o)
+          acc[o][s] = cadd(acc[o][s], cmul(stokes_coef<T>(md, fk, o, sig, ktl[0], ktl_[e], gfac[s], glam[s]), v[s]));
       }
     }
   }
