@@ -342,9 +342,10 @@ ibdl_status_t ibdl_spread_tiles(ibdl_t h, int64_t* nbusy, int64_t* segments_read
  * last-axis pass; 0 = not measured yet, the largest shape is used).  Any pointer may be NULL. */
 ibdl_status_t ibdl_launch_shape(ibdl_t h, int32_t* rows_per_block, int32_t* lines_y, int32_t* lines_last);
 
-/* GMRES in ibdl_solve, ibdl_solve_refined and ibdl_backward replays each operator apply from a
- * HIP graph captured at the first apply (1, the default) or launches its kernels directly (0).
- * Both give the same bits.  Disabling drops the captured graphs. */
+/* GMRES and MINRES in ibdl_solve, ibdl_solve_refined, ibdl_backward and ibdl_ns_step replay each
+ * operator apply from a HIP graph captured at the first apply (1) or launch its kernels directly
+ * (0).  The default is 1 below 2^20 grid points, where an apply is shorter than its launches, and
+ * 0 from there on.  Both give the same bits.  Disabling drops the captured graphs. */
 ibdl_status_t ibdl_set_graph(ibdl_t h, int32_t enable);
 
 /* Profiling: enable (1) or disable (0) per-stage timing with HIP events recorded on the handle's

@@ -313,7 +313,8 @@ class Problem:
         return int(r.value), int(y.value), int(z.value)
 
     def set_graph(self, enable=True):
-        """Replay GMRES's operator applies from a captured HIP graph (default) or launch directly."""
+        """Replay the Krylov solvers' operator applies from a captured HIP graph or launch them
+        directly (the default is the graph below 2^20 grid points)."""
         B.check(B.load().ibdl_set_graph(self._h, 1 if enable else 0), self._h)
 
     def set_timing(self, enable=True):
