@@ -22,6 +22,8 @@ using namespace ibdl;
 namespace {
 
 constexpr int kSlot = 1024;   // doubles per host-mapped Arnoldi slot (h1, h2 and the norm)
+constexpr int kYOff = 2 * kSlot + 128;   // host-mapped doubles before the GMRES solution y
+constexpr int kYSlot = 256;
 
 template <typename T> struct GridWork {
   cplx<T>* tw[3] = {nullptr, nullptr, nullptr};
@@ -92,7 +94,8 @@ struct ibdl_s {
   double* hostbuf = nullptr;  // pinned host scratch (1024 doubles)
   // host-mapped coherent memory for the per-iteration Arnoldi values: the GPU writes them and a
   // sequence tag, the host polls the tag (no copy-engine transfer, no stream-sync wake-up)
-  // host-mapped Arnoldi values: two slots of kSlot doubles, then one 64-byte tag per slot
+  // host-mapped Arnoldi values: two slots of kSlot doubles, then one 64-byte tag per slot, then
+  // the least-squares solution y of the last GMRES call (kYSlot doubles, read by the device)
   double* hmap = nullptr;
   double* hmap_dev = nullptr;
   volatile unsigned* htag = nullptr;
@@ -914,11 +917,13 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (maxit + 1) + i] * y[c];
     y[i] = s / H[(size_t)i * (maxit + 1) + i];
   }
-  for (int i = 0; i < k; ++i) h->hostbuf[i] = y[i];
-  IBDL_HIP(hipMemcpyAsync(h->small + 768, h->hostbuf, sizeof(double) * k, hipMemcpyHostToDevice, h->st));
-  // x is left to the stream: the caller's next work is queued behind it.  hostbuf is not written
-  // again before a later wait on this stream has passed the copy.
-  kr_lincomb(h->V, n, k, h->small + 768, x, n, h->st);
+  // y goes to host-mapped memory, which the combination kernel reads directly (no copy launch).
+  // x is left to the stream: the caller's next work is queued behind it.  This slot is not
+  // written again before a later wait on this stream has passed the combination.
+  volatile double* ys = h->hmap + kYOff;
+  for (int i = 0; i < k; ++i) ys[i] = y[i];
+  std::atomic_thread_fence(std::memory_order_seq_cst);
+  kr_lincomb(h->V, n, k, h->hmap_dev + kYOff, x, n, h->st);
   *iters = k;
   *relres = res;
   return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;
@@ -1317,7 +1322,7 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->vb = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     h->vr = (double*)h->dalloc<double>(sizeof(double) * h->n_aug);
     IBDL_HIP(hipHostMalloc((void**)&h->hostbuf, sizeof(double) * 1024, hipHostMallocDefault));
-    IBDL_HIP(hipHostMalloc((void**)&h->hmap, sizeof(double) * 2 * kSlot + 128,
+    IBDL_HIP(hipHostMalloc((void**)&h->hmap, sizeof(double) * (kYOff + kYSlot),
                            hipHostMallocMapped | hipHostMallocCoherent));
     IBDL_HIP(hipHostGetDevicePointer((void**)&h->hmap_dev, h->hmap, 0));
     h->htag = reinterpret_cast<volatile unsigned*>(h->hmap + 2 * kSlot);
@@ -1553,37 +1558,37 @@ ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, doubl
     double relres = 0;
     const int status = h->sl ? minres(h, h->vb, tol, maxit, q, info, &iters, &relres)
                              : gmres(h, h->vb, tol, maxit, q, info, &iters, &relres);
-    // True residual ||b - A q|| / ||b|| with a double-precision apply.  On a mixed handle it uses
-    // the double work arrays and the recovery the float ones, so it runs on the second stream
-    // beside the recovery.
+    // True residual ||b - A q|| / ||b|| with a double-precision apply, queued on the handle's
+    // stream right behind the solution.  On a mixed handle it uses the double work arrays and the
+    // recovery the float ones, so the (shorter) recovery runs beside it on the second stream.
     const bool overlap = h->mixed() && u_grid;
     hipStream_t main = h->st;
     if (overlap) {
       IBDL_HIP(hipEventRecord(h->ev_fork, main));
       IBDL_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
-      h->st = h->aux;
     }
-    try {
-      apply_any(h, q, h->vr, true);
-      kr_axpby(h->vr, 1.0, h->vb, -1.0, h->n_aug, h->st);
-      const int nblk = kr_nblk(h->n_aug);
-      ensure_partial(h, nblk);
-      kr_multidot(h->vr, h->n_aug, 1, h->vr, h->n_aug, h->partial, nblk, h->small + 600, h->st);
-      kr_multidot(h->vb, h->n_aug, 1, h->vb, h->n_aug, h->partial, nblk, h->small + 601, h->st);
-      IBDL_HIP(hipMemcpyAsync(h->hostbuf + 600, h->small + 600, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    } catch (...) {
+    apply_any(h, q, h->vr, true);
+    kr_axpby(h->vr, 1.0, h->vb, -1.0, h->n_aug, h->st);
+    const int nblk = kr_nblk(h->n_aug);
+    ensure_partial(h, nblk);
+    kr_multidot(h->vr, h->n_aug, 1, h->vr, h->n_aug, h->partial, nblk, h->small + 600, h->st);
+    kr_multidot(h->vb, h->n_aug, 1, h->vb, h->n_aug, h->partial, nblk, h->small + 601, h->st);
+    IBDL_HIP(hipMemcpyAsync(h->hostbuf + 600, h->small + 600, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    if (u_grid) {
+      if (overlap) h->st = h->aux;
+      try {
+        if (h->mixed()) recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
+        else recover_t<double>(h, q, data, (const double*)g_grid, (double*)u_grid);
+      } catch (...) {
+        h->st = main;
+        throw;
+      }
       h->st = main;
-      throw;
     }
     if (overlap) {
       IBDL_HIP(hipEventRecord(h->ev_join, h->aux));
-      h->st = main;
+      IBDL_HIP(hipStreamWaitEvent(main, h->ev_join, 0));
     }
-    if (u_grid) {
-      if (h->mixed()) recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
-      else recover_t<double>(h, q, data, (const double*)g_grid, (double*)u_grid);
-    }
-    if (overlap) IBDL_HIP(hipStreamWaitEvent(main, h->ev_join, 0));
     IBDL_HIP(hipStreamSynchronize(main));
     const double rn = sqrt(std::max(h->hostbuf[600], 0.0)), bn = sqrt(std::max(h->hostbuf[601], 0.0));
     if (info) {

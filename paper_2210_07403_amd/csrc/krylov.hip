@@ -49,11 +49,15 @@ __global__ void k_gemv_sub(const double* __restrict__ V, int64_t ldv, int k, con
   }
 }
 
+// x = sum_j y_j V_j (k <= 256); y is read once per workgroup into LDS (it may live in host memory)
 __global__ void k_lincomb(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ y,
                           double* __restrict__ x, int64_t n) {
+  __shared__ double ys[256];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) ys[j] = y[j];
+  __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int j = 0; j < k; ++j) s += V[j * ldv + e] * y[j];
+    for (int j = 0; j < k; ++j) s += V[j * ldv + e] * ys[j];
     x[e] = s;
   }
 }
@@ -364,6 +368,7 @@ void kr_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w
 }
 
 void kr_lincomb(const double* V, int64_t ldv, int k, const double* y, double* x, int64_t n, hipStream_t st) {
+  if (k > 256) throw Error(-1, "kr_lincomb: at most 256 basis vectors");
   hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n)), dim3(256), 0, st, V, ldv, k, y, x, n);
   IBDL_LAUNCH_CHECK();
 }
