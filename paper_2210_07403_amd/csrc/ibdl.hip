@@ -758,14 +758,6 @@ double host_norm(ibdl_s* h, const double* v, int64_t n) {
   return sqrt(h->hostbuf[0]);
 }
 
-// Publish n device doubles (src[norm_at] first reduced from pnorm, see kr_publish) to slot `slot`
-// of the host-mapped buffer (stream-ordered); returns the sequence number its tag will carry.
-unsigned publish(ibdl_s* h, double* src, int n, const double* pnorm, int nblk, int norm_at, int slot) {
-  const unsigned seq = ++h->seq;
-  kr_publish(src, n, pnorm, nblk, norm_at, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq, h->st);
-  return seq;
-}
-
 // Wait for a publication: poll its tag for up to 2 ms (an iteration's GPU work is well below that),
 // then fall back to a stream synchronisation, after which the tag must be there.
 const volatile double* wait_published(ibdl_s* h, int slot, unsigned seq) {
@@ -844,10 +836,10 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   int k = 0;
   double res = 1.0;
   // h->small: first Gram-Schmidt coefficients [0, 256), second [256, 512), |w|^2 at 512, |b|^2 at 520
-  double* hn = h->small + 512;
   unsigned seq[2] = {0, 0};
-  // queue Arnoldi step j (V[j] is in place, and in gx for the graph); returns where w is
-  auto step = [&](int j) -> double* {
+  // queue Arnoldi step j (V[j] is in place, and in gx for the graph): apply, orthogonalise,
+  // publish the values to the host and, in the same launch, normalise w into V[j+1] (and gx)
+  auto step = [&](int j) {
     double* w;
     if (graph) {
       IBDL_HIP(hipGraphLaunch(h->gexec[trans ? 1 : 0], h->st));
@@ -857,14 +849,13 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
       apply_any(h, h->V + (int64_t)j * n, w, false, trans);
     }
     kr_arnoldi_step(h->V, n, j + 1, w, n, h->partial, anblk, h->small, h->st);
-    seq[j & 1] = publish(h, h->small, 521, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, 512, j & 1);
-    return w;
+    const int slot = j & 1;
+    seq[slot] = ++h->seq;
+    kr_publish_scale(h->small, 521, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, 512, h->hmap_dev + slot * kSlot,
+                     h->htag_dev + 16 * slot, seq[slot], w, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
   };
-  double* w = step(0);
-  auto next = [&](int j) {   // queue step j + 1 behind step j (a breakdown is found by the host)
-    kr_scale_norm(w, hn, 0.0, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
-    w = step(j + 1);
-  };
+  step(0);
+  auto next = [&](int j) { step(j + 1); };   // queue step j + 1 (a breakdown is found by the host)
   double beta = 0.0, tiny = 0.0;
   std::vector<double> rs(maxit, 1.0);   // residual estimates of the steps the host has finished
   for (int j = 0; j < maxit; ++j) {

@@ -245,6 +245,12 @@ int kr_arnoldi_nblk(int64_t n);
 // written last, after a system-scope fence
 void kr_publish(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
                 unsigned* host_tag, unsigned seq, hipStream_t st);
+// kr_publish of the Arnoldi values (norm partials reduced, src copied to the host slot, tag
+// written) and, in the same launch, dst (and dst2 if set) = w / |w| over nv entries (0 where the
+// norm is 0 or not finite), every workgroup reducing the partials itself in the same order.
+void kr_publish_scale(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
+                      unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2, int64_t nv,
+                      hipStream_t st);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

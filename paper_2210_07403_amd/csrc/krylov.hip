@@ -345,12 +345,53 @@ __global__ __launch_bounds__(kB) void k_publish(double* src, int n, const double
   }
 }
 
+// k_publish and, in the same launch, the normalisation of w into the next basis vector: every
+// workgroup reduces the norm partials itself (in the same order, so with the same bits) and
+// scales its part of w into vdst (and vdst2) by 1/|w|, or by 0 where |w| is 0 or not finite;
+// workgroup 0 also stores |w|^2 at src[norm_at], copies src to the host slot and writes the tag.
+__global__ __launch_bounds__(kB) void k_publish_scale(double* src, int n, const double* __restrict__ pnorm, int nblk,
+                                                      int norm_at, double* dst, unsigned* tag, unsigned seq,
+                                                      const double* w, double* vdst, double* vdst2, int64_t nv) {
+  __shared__ double nrm2;
+  if (threadIdx.x < 64) {
+    const double v = wave_sum(pnorm, nblk, threadIdx.x);
+    if (threadIdx.x == 0) nrm2 = v;
+  }
+  __syncthreads();
+  const double v = nrm2;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) src[norm_at] = v;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kB) dst[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence_system();
+      *reinterpret_cast<volatile unsigned*>(tag) = seq;
+    }
+  }
+  const double h = sqrt(v > 0.0 ? v : 0.0);
+  const double sc = (h > 0.0 && h < INFINITY) ? 1.0 / h : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv; e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = w[e] * sc;
+    vdst[e] = x;
+    if (vdst2) vdst2[e] = x;
+  }
+}
+
 inline unsigned blocks_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
 }
 
 }  // namespace
+
+void kr_publish_scale(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
+                      unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2, int64_t nv,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_publish_scale, dim3(blocks_for(nv)), dim3(kB), 0, st, src, n, pnorm, nblk, norm_at, host_dst,
+                     host_tag, seq, w, dst, dst2, nv);
+  IBDL_LAUNCH_CHECK();
+}
 
 int kr_nblk(int64_t n) { return (int)((n + kElemsPerBlock - 1) / kElemsPerBlock) > 0 ? (int)((n + kElemsPerBlock - 1) / kElemsPerBlock) : 1; }
 
