@@ -413,6 +413,80 @@ def cpu_baseline(spec, budget_s=20.0):
                       f"(single-threaded numpy/pocketfft) in {el:.1f} s on {cpu} ({os.cpu_count()} logical CPUs)"}
 
 
+def _per_call(fn, max_reps=3, budget_s=4.0):
+    """Seconds per call of fn over a bounded sample (at least one call)."""
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= max_reps:
+            return el / reps, reps
+
+
+def cpu_baseline_extras(extras):
+    """The FP64 numpy oracle beside the measurements beyond the hot path, each on a bounded sample
+    of its workload (one or a few applies, or a sample of nodes), scaled to the GPU figure it sits
+    next to; single-threaded numpy / pocketfft."""
+    import math
+    import numpy as np
+    import oracle
+    from oracle import nearbdry as NB
+    from oracle.ibsl import IBSL
+    from oracle.ib import Grid
+    from workloads import geometry as geo
+    from workloads import problems as P
+    out = {}
+    if "near_boundary_star1024" in extras:
+        s = P.cfg2_star_poisson(1024, 4096)
+        m = s.markers
+        g = Grid(s.dim, s.n, s.L, s.origin)
+        t_ind, _ = _per_call(lambda: NB.indicator(g, m.X, m.nrm, m.ds, s.kernel, s.disc), 1)
+        xs, ys = g.nodes()
+        u = np.sin(3 * xs + 1) * np.cos(2 * ys)
+        nodes = np.argwhere((np.abs(np.hypot(xs - 0.5, ys - 0.5) - 0.3) < 0.02))[:200]
+        t_node, _ = _per_call(lambda: [NB.correct_point(g, m.X, s.data, u, np.array([xs[j, i], ys[j, i]]), 8)
+                                       for j, i in nodes], 1)
+        n_corr = extras["near_boundary_star1024"]["nodes_corrected"]
+        out["near_boundary_star1024"] = {
+            "indicator_ms": round(1e3 * t_ind, 1),
+            "near_boundary_ms": round(1e3 * t_node / len(nodes) * n_corr, 1),
+            "sample": f"one indicator; the interpolation of {len(nodes)} nodes scaled to {n_corr}"}
+    if "cylinder_array_drag" in extras:
+        s = P.cylinder_array(1024, 0.1)
+        o = oracle.Setup.from_spec(s)
+        q = np.random.default_rng(0).standard_normal(o.n_aug)
+        t_app, _ = _per_call(lambda: o.apply(q), 1)
+        it = extras["cylinder_array_drag"]["fp64"]["iters"]
+        out["cylinder_array_drag"] = {"apply_ms": round(1e3 * t_app, 1),
+                                      "solve_ms_estimate": round(1e3 * t_app * (it + 3), 1),
+                                      "sample": f"one FP64 apply, times {it} GMRES iterations + 3 (right-hand side, "
+                                                "true residual, recovery)"}
+    if "ibsl_vs_ibdl_helmholtz1024" in extras:
+        s = P.helmholtz_circle(1024, 1.0)
+        o = IBSL.from_spec(s)
+        q = np.random.default_rng(0).standard_normal(o.n_aug)
+        t_app, _ = _per_call(lambda: o.apply(q), 1)
+        it = extras["ibsl_vs_ibdl_helmholtz1024"]["sl"]["iters"]
+        out["ibsl_vs_ibdl_helmholtz1024"] = {"sl_apply_ms": round(1e3 * t_app, 1),
+                                             "sl_solve_ms_estimate": round(1e3 * t_app * it, 1),
+                                             "sample": f"one FP64 single-layer apply, times {it} MINRES iterations"}
+    if "ns_cylinder_re100" in extras:
+        N, L, r, rho, dt = 1024, 8.0, 0.15, 1.0, 1.8e-3
+        curve = geo.PolarCurve((1.85, 4.0), r)
+        mk = curve.markers(geo.n_ib_for_spacing(curve.perimeter(), L / N, 1.0)).flipped()
+        o = oracle.Setup(2, (N, N), (L, L), (0.0, 0.0), mk.X, mk.nrm, mk.ds, "stokes", math.sqrt(1.5 * rho / dt),
+                         2 * r / 100.0, "dirichlet", 10.0, "peskin4", "spectral")
+        q = np.random.default_rng(0).standard_normal(o.n_aug)
+        t_app, _ = _per_call(lambda: o.apply(q), 1)
+        it = extras["ns_cylinder_re100"]["mean_gmres_iters"]
+        out["ns_cylinder_re100"] = {"apply_ms": round(1e3 * t_app, 1),
+                                    "step_ms_estimate": round(1e3 * t_app * (it + 3), 1),
+                                    "sample": f"one FP64 apply, times {it} GMRES iterations + 3 (right-hand side, "
+                                              "recovery, nonlinear term)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,6 +644,10 @@ def main():
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec)
+        if extras:
+            print("# timing the CPU oracle beside the other measurements", file=sys.stderr, flush=True)
+            for k, v in cpu_baseline_extras(extras).items():
+                out[k]["cpu_baseline"] = v
     print(json.dumps(out), flush=True)
 
 
