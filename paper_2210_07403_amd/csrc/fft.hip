@@ -404,9 +404,10 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
 template <typename T> constexpr int rmax_t(int N) {
   return sizeof(T) == 8 && N <= 256 && plan_rmax(N) > 8 ? 8 : plan_rmax(N);
 }
-// Elements per thread of the fused last-axis passes: the passes that keep two accumulators or two
-// input spectra per element (Stokes, the transposed Stokes pass) and the 1024-point double
-// passes hold 8 instead of 16, which keeps them clear of register spills and raises occupancy.
+// Elements per thread of the general fused last-axis passes: those that keep two accumulators or
+// two input spectra per element (Stokes, the transposed Stokes pass) and the 1024-point double
+// ones hold 8 instead of 16, which keeps them clear of register spills and raises occupancy (the
+// single-field pass k_fused1 keeps the default).
 template <typename T> constexpr int fused_rmax(int N, int nacc) {
   return plan_rmax(N) > 8 && (nacc >= 2 || (sizeof(T) == 8 && N >= 1024)) ? 8 : rmax_t<T>(N);
 }
@@ -611,7 +612,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                    const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
-  using TC = TileCfg<T, N, fused_rmax<T>(N, 1)>;
+  using TC = TileCfg<T, N>;   // one field, one real factor: no spills at 16 elements per thread
   constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -836,7 +837,7 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
     } else if (md.mode != 0) {
       throw Error(-2, "fused pass: unsupported transposed multiplier");
     } else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS) {
-      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
+      shape(TileCfg<T, N>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
     } else if (!md.stokes && no == 1) {
       shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
