@@ -406,10 +406,12 @@ template <typename T> constexpr int rmax_t(int N) {
 }
 // Elements per thread of the general fused last-axis passes: those that keep two accumulators or
 // two input spectra per element (Stokes, the transposed Stokes pass) and the 1024-point double
-// ones hold 8 instead of 16, which keeps them clear of register spills and raises occupancy (the
-// single-field pass k_fused1 keeps the default).
+// ones hold 8 instead of 16, and 4 for double two-accumulator lines of 512 points or more, which
+// keeps them clear of register spills and raises occupancy (the single-field pass k_fused1 keeps
+// the default).
 template <typename T> constexpr int fused_rmax(int N, int nacc) {
-  return plan_rmax(N) > 8 && (nacc >= 2 || (sizeof(T) == 8 && N >= 1024)) ? 8 : rmax_t<T>(N);
+  return (sizeof(T) == 8 && nacc >= 2 && N >= 512) ? 4   // double, two accumulators, long lines
+         : (plan_rmax(N) > 8 && (nacc >= 2 || (sizeof(T) == 8 && N >= 1024)) ? 8 : rmax_t<T>(N));
 }
 template <typename T, int N, int RX = rmax_t<T>(N)> struct TileCfg {
   static constexpr int RMX = RX;
