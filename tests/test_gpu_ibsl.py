@@ -150,3 +150,13 @@ def test_rejects():
     with pytest.raises(ibdl.IBDLError):
         pr.indicator()
     pr.close()
+
+
+def test_zero_data_gives_zero_density():
+    """b = 0: MINRES stops before its first iteration with F = 0, u = 0 (Poisson, with u_bar)."""
+    spec = _poisson_circle(64, 1.0)
+    pr = _sl(spec)
+    q, u, info = pr.solve(np.zeros(spec.markers.X.shape[0]), None, tol=1e-8, maxit=100)
+    assert info.status == 0 and info.iters == 0
+    assert np.all(to_np(q) == 0) and np.all(to_np(u) == 0)
+    pr.close()

@@ -170,3 +170,21 @@ def test_rejects_unsupported():
     with pytest.raises(ibdl.IBDLError):
         pr.near_boundary(spec.data, np.ones(g.shape), u, 8, 6)
     pr.close()
+
+
+def test_degenerate_masks():
+    """An empty domain mask changes nothing; a full mask with the smallest width changes only the
+    nodes within h of a marker, as the oracle says."""
+    spec = CASES["circle64_fd"]()
+    g = _grid(spec)
+    u = _field(spec, "fp64", 3)
+    Ub = np.ones(spec.markers.X.shape[0])
+    pr = make_problem(spec, "fp64")
+    got = to_np(pr.near_boundary(Ub, np.zeros(g.shape), u, 6, 8))
+    assert np.array_equal(got, u)
+    full = np.ones(g.shape)
+    got = to_np(pr.near_boundary(Ub, full, u, 1, 2))
+    want = NB.near_boundary(g, spec.markers.X, Ub, full, u, 1, 2)
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+    assert 0 < np.sum(got != u) == len(NB.near_points(g, spec.markers.X, full, 1))
+    pr.close()

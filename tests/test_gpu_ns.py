@@ -176,3 +176,15 @@ def test_rejects():
     with pytest.raises(ibdl.IBDLError):
         spec_pr.advection(np.zeros((2, 64, 64)))
     spec_pr.close()
+
+
+def test_step_from_rest_stays_at_rest():
+    """u = 0 with U_b = 0 and no strip: the forcing, the solve and the nonlinear term are all zero."""
+    mk, o, pr = _setup(64, 1.0, 0.05, 0.01)
+    z = [torch.zeros((2, 64, 64), dtype=torch.float64, device=pr.device) for _ in range(4)]
+    g = torch.ones_like(z[0])
+    q, info = pr.ns_step(z, np.zeros((mk.X.shape[0], 2)), 1.0, 0.01, None, 0, 0, 0, 0.0, g_out=g)
+    assert info.status == 0 and info.iters == 0
+    assert all(bool(torch.all(t == 0)) for t in z) and bool(torch.all(g == 0))
+    assert bool(torch.all(q == 0))
+    pr.close()
