@@ -331,6 +331,27 @@ def _ibsl_vs_ibdl(dev):
     return res
 
 
+def _adjoint_timing(dev):
+    """Forward solve and adjoint backward on the 256^3 sphere, mixed path (the adjoint row alone)."""
+    import numpy as np
+    import torch
+    import paper_2210_07403_amd as ibdl
+    spec, prec, _ = workload("sphere256")
+    m = spec.markers
+    pr = ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, m.nrm, m.ds, pde=spec.pde, kappa=spec.kappa,
+                      mu=spec.mu, bc=spec.bc, eta=spec.eta, kernel=spec.kernel, disc=spec.disc, precision=prec,
+                      device=dev)
+    data = torch.as_tensor(np.asarray(spec.data, dtype=np.float64), device=dev)
+    g = torch.as_tensor(spec.g, device=dev).to(pr.grid_dtype) if spec.g is not None else None
+    q, u, _ = pr.solve(data, g, tol=spec.tol, maxit=100)
+    psi = torch.randn(u.shape, dtype=u.dtype, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+    pr.backward(q, u, psi, tol=spec.tol, maxit=100)
+    t_fw, _ = _timed(lambda: pr.solve(data, g, tol=spec.tol, maxit=100), 3)
+    t_bw, (_, _, ib) = _timed(lambda: pr.backward(q, u, psi, tol=spec.tol, maxit=100), 3)
+    pr.close()
+    return {"forward_solve_ms": round(1e3 * t_fw, 3), "backward_ms": round(1e3 * t_bw, 3), "adjoint_iters": ib.iters}
+
+
 def _cylinder_drag(dev):
     """Stokes flow past the periodic cylinder array (area fraction 0.1, 1024^2, spectral,
     ds ~ h, eta = 10, tol 1e-10): solve + recovery time, GMRES iterations, net force, flux and
@@ -503,7 +524,7 @@ def main():
                     help="only run the Navier-Stokes cylinder for STEPS steps and print its JSON line")
     ap.add_argument("--ns-re", type=float, default=10.0)
     ap.add_argument("--ns-every", type=int, default=0, help="drag/lift sample interval in steps (0: STEPS / 40)")
-    ap.add_argument("--only", choices=["near_boundary", "cylinder_array", "ibsl", "ns"], default=None,
+    ap.add_argument("--only", choices=["near_boundary", "cylinder_array", "ibsl", "ns", "adjoint"], default=None,
                     help="only run one of the measurements beyond the hot path and print its JSON line")
     args = ap.parse_args()
     if args.only:
@@ -511,7 +532,7 @@ def main():
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         run = {"near_boundary": _near_boundary_timing, "cylinder_array": _cylinder_drag, "ibsl": _ibsl_vs_ibdl,
-               "ns": lambda d: ns_cylinder(d, 100.0, 200, 5)}[args.only]
+               "ns": lambda d: ns_cylinder(d, 100.0, 200, 5), "adjoint": _adjoint_timing}[args.only]
         print(json.dumps(run(dev)))
         return
     if args.ns_cylinder > 0:

@@ -633,8 +633,9 @@ int adj_nout(ibdl_s* h) {
   return h->dim + (h->cfg.eta > 0 ? 1 : 0);
 }
 
-template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst, bool sparse = false,
-                                    bool busy_only = false) {
+// rows: ROWS_SPARSE for the transposed apply (spread input), ROWS_OUT for a dense input whose
+// adjoint fields are only interpolated at the markers next (their active rows)
+template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* dst, int rows, bool busy_only = false) {
   MultDesc md = base_desc<T>(h, W);
   const int nout = adj_nout(h);
   md.alpha = 1.0;
@@ -648,7 +649,7 @@ template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* 
     md.nc = 1;
     md.fk[0] = FK_MASS;
   }
-  pipeline<T>(h, W, src, md.nc, dst, nout, md, sparse ? ROWS_SPARSE : ROWS_DENSE, busy_only);
+  pipeline<T>(h, W, src, md.nc, dst, nout, md, rows, busy_only);
 }
 
 void ensure_adj(ibdl_s* h) {
@@ -681,7 +682,7 @@ template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
     StageTimer t(h, ST_SPREAD);
     spread_w<T>(h, a, W, W.real);
   }
-  adj_grid<T>(h, W, W.real, W.real, true, true);
+  adj_grid<T>(h, W, W.real, W.real, ROWS_SPARSE, true);
   const double half = h->neumann() ? -0.5 : 0.5;
   const double* pu = h->has_ubar ? p + h->n_ib * h->nq : nullptr;
   adj_markers<T>(h, W, p, half, pu, y);
@@ -697,7 +698,7 @@ template <typename T> void adj_rhs_t(ibdl_s* h, const T* psi, double* g) {
   GridWork<T>& W = ensure_fields<T>(h, std::max(adj_nout(h), h->nq));
   ensure_adj(h);
   IBDL_HIP(hipMemcpyAsync(W.real, psi, sizeof(T) * h->ntot * h->nq, hipMemcpyDeviceToDevice, h->st));
-  adj_grid<T>(h, W, W.real, W.real);
+  adj_grid<T>(h, W, W.real, W.real, ROWS_OUT);
   adj_markers<T>(h, W, nullptr, 0.0, nullptr, g);
   if (h->has_ubar) {
     const int nblk = 256;
@@ -719,7 +720,7 @@ template <typename T> void grad_X_t(ibdl_s* h, const double* q, const T* u, cons
   spread_w<T>(h, a, W, W.real);
   if (h->stokes()) grid_axpby<T>(W.real, 1.0, psi, -1.0, h->ntot * h->nq, h->st);
   else grid_axpby<T>(W.real, -1.0, psi, 1.0, h->ntot, h->st);
-  adj_grid<T>(h, W, W.real, W.real);
+  adj_grid<T>(h, W, W.real, W.real, ROWS_OUT);
   const int nout = adj_nout(h);
   const int nc = h->nq + nout;
   const double hDinv = 1.0 / pow(h->h, (double)h->dim);
