@@ -643,6 +643,61 @@ __global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __
   }
 }
 
+// Transpose of the fused FD divergence spread (SP_FDDIV), for the scalar transposed operator with
+// centred differences.  Per marker, over the 6-node window (G_d spans all 6 taps, W the inner 4),
+//   v_i = sum_y w(y) [sum_d n_id G_d(y) prod_{e != d} W_e(y) + eta prod_e W_e(y)]
+// and, since Phi D_d = -(the G_d-weighted interpolation) when D_d is the centred difference,
+//   y_i = -h^-D ds_i v_i + b p_i + eta ds_i pu        (p = a.x, b = a.b; pu: the ubar entries or null)
+// which equals h^-D ds_i (sum_d n_id Phi D_d w - eta Phi w) + b p_i + eta ds_i pu.
+// 3-D: 32 lanes per marker, one per (y, z) stencil row of the 6 x 6 window less its 4 corners
+// (W_y and W_z both vanish there); 2-D: 8 lanes, the first 6 one per y row.  Each lane reads the 6
+// x taps of its row against A G_x + B W_x; the row sums are reduced by a fixed butterfly.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_interp_div(InterpArgs a, const cplx<T>* __restrict__ wtab,
+                                                    const T* __restrict__ u, const double* __restrict__ nrm,
+                                                    const double* __restrict__ ds, double eta, double hDinv,
+                                                    const double* __restrict__ pu, double* __restrict__ y) {
+  constexpr int RL = (D == 3) ? 32 : 8;
+  const int64_t gid = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t i = gid / RL;
+  const int r = (int)(gid % RL);
+  const bool valid = i < a.n_ib;
+  const int64_t im = valid ? i : 0;
+  const MarkerGeom& g = a.g;
+  const cplx<T>* row = wtab + im * 24;       // axis d taps at row[d*8 + t], t < 6
+  int ty = r, tz = 0;
+  if (D == 3) {
+    const int k = r + 1 + (r >= 4 ? 1 : 0) + (r >= 28 ? 1 : 0);   // skips k = 0, 5, 30, 35
+    ty = k % 6;
+    tz = k / 6;
+  }
+  const bool live = D == 3 || r < 6;
+  const cplx<T> py = row[8 + (live ? ty : 0)];
+  const cplx<T> pz = D == 3 ? row[16 + tz] : mk<cplx<T>>((T)1, (T)0);
+  const T n0 = (T)nrm[im * D], n1 = (T)nrm[im * D + 1], n2 = D == 3 ? (T)nrm[im * D + 2] : (T)0;
+  const T A = n0 * py.x * pz.x;
+  const T B = n1 * py.y * pz.x + n2 * py.x * pz.y + (T)eta * py.x * pz.x;
+  const int sx = a.s[im * 3 + 0], sy = a.s[im * 3 + 1], sz = a.s[im * 3 + 2];
+  const int64_t base = ((int64_t)(D == 3 ? ((sz + tz) & (g.n[2] - 1)) : 0) * g.n[1] + ((sy + ty) & (g.n[1] - 1))) *
+                       g.n[0];
+  T v = 0;
+  if (live) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const cplx<T> px = row[t];
+      v += u[base + ((sx + t) & (g.n[0] - 1))] * (A * px.y + B * px.x);
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < RL; off <<= 1) v += __shfl_xor(v, off, RL);
+  if (valid && r == 0) {
+    double o = -hDinv * ds[i] * (double)v;
+    if (a.x) o += a.b * a.x[i];
+    if (pu) o += eta * ds[i] * pu[0];
+    y[i] = o;
+  }
+}
+
 // ------------------------------------------------------------------ active rows
 // Rows y of plane z that a marker's 6-node window meets: [s_y, s_y + 5] for z in [s_z, s_z + 5]
 // (mod n); a window that wraps around y marks the whole plane.
@@ -923,6 +978,19 @@ void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, h
 }
 
 template <typename T>
+void interp_div(const InterpArgs& a, const cplx<T>* wtab, const T* u, const double* nrm, const double* ds, double eta,
+                double hDinv, const double* pu, double* y, hipStream_t st) {
+  if (a.n_ib == 0) return;
+  if (a.kernel == KID_BSPLINE6) throw Error(-2, "interp_div: 4-point kernels only");
+  const int64_t lanes = a.n_ib * (a.g.dim == 3 ? 32 : 8);
+  const dim3 grid((unsigned)((lanes + 255) / 256));
+  if (a.g.dim == 2)
+    hipLaunchKernelGGL((k_interp_div<T, 2>), grid, dim3(256), 0, st, a, wtab, u, nrm, ds, eta, hDinv, pu, y);
+  else hipLaunchKernelGGL((k_interp_div<T, 3>), grid, dim3(256), 0, st, a, wtab, u, nrm, ds, eta, hDinv, pu, y);
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
 void gather_dx(const GatherArgs& a, hipStream_t st) {
   if (a.n_ib == 0) return;
   if (a.nfield < 1 || a.nfield > 8) throw Error(-1, "gather_dx: 1..8 fields");
@@ -969,6 +1037,8 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
   template void weight_table<T>(const double*, int64_t, cplx<T>*, hipStream_t);           \
   template void grid_fill_zero<T>(T*, int64_t, hipStream_t);                              \
   template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
+  template void interp_div<T>(const InterpArgs&, const cplx<T>*, const T*, const double*, const double*, double, \
+                              double, const double*, double*, hipStream_t);                \
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
   template void gather_dx<T>(const GatherArgs&, hipStream_t);                             \
   template void grid_add_const<T>(T*, const double*, int, int64_t, hipStream_t);          \

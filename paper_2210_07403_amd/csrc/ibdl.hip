@@ -652,6 +652,26 @@ template <typename T> void adj_grid(ibdl_s* h, GridWork<T>& W, const T* src, T* 
   pipeline<T>(h, W, src, md.nc, dst, nout, md, rows, busy_only);
 }
 
+// FD scalar: the transposed operator is taken as the exact transpose of the forward's fused
+// divergence spread, so the grid part forms the one field w = L^-1 v (instead of D_d w and w) and
+// the marker side is the dual-weight interpolation interp_div.
+bool adj_folded(ibdl_s* h) { return !h->stokes() && h->fd() && h->cfg.kernel != IBDL_K_BSPLINE6; }
+
+template <typename T> void adj_solve(ibdl_s* h, GridWork<T>& W, const T* src, T* dst, int rows, bool busy_only) {
+  MultDesc md = base_desc<T>(h, W);
+  md.nc = 1;
+  md.fk[0] = FK_MASS;
+  md.alpha = 1.0;
+  pipeline<T>(h, W, src, 1, dst, 1, md, rows, busy_only);
+}
+
+template <typename T> void adj_markers_div(ibdl_s* h, GridWork<T>& W, const double* p, double b, const double* pu,
+                                           double* y) {
+  InterpArgs ia = interp_args(h, 1, 1.0, b, p, nullptr);
+  StageTimer t(h, ST_INTERP);
+  interp_div<T>(ia, W.wtab, W.real, h->nrm, h->ds, h->cfg.eta, 1.0 / pow(h->h, (double)h->dim), pu, y, h->st);
+}
+
 void ensure_adj(ibdl_s* h) {
   if (h->adj_m) return;
   h->adj_m = (double*)h->dalloc<double>(sizeof(double) * h->n_ib * 8);
@@ -674,7 +694,8 @@ template <typename T> void adj_markers(ibdl_s* h, GridWork<T>& W, const double* 
 
 // y = A^T p
 template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
-  GridWork<T>& W = ensure_fields<T>(h, std::max(adj_nout(h), h->nq));
+  const bool fold = adj_folded(h);
+  GridWork<T>& W = ensure_fields<T>(h, fold ? h->nq : std::max(adj_nout(h), h->nq));
   ensure_adj(h);
   SpreadArgs a = spread_args(h, SP_PLAIN, h->nq, p);
   a.raw = 1;
@@ -682,10 +703,15 @@ template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
     StageTimer t(h, ST_SPREAD);
     spread_w<T>(h, a, W, W.real);
   }
-  adj_grid<T>(h, W, W.real, W.real, ROWS_SPARSE, true);
   const double half = h->neumann() ? -0.5 : 0.5;
   const double* pu = h->has_ubar ? p + h->n_ib * h->nq : nullptr;
-  adj_markers<T>(h, W, p, half, pu, y);
+  if (fold) {
+    adj_solve<T>(h, W, W.real, W.real, ROWS_SPARSE, true);
+    adj_markers_div<T>(h, W, p, half, pu, y);
+  } else {
+    adj_grid<T>(h, W, W.real, W.real, ROWS_SPARSE, true);
+    adj_markers<T>(h, W, p, half, pu, y);
+  }
   if (h->has_ubar) {
     const int nblk = kr_nblk(h->n_ib);
     ensure_partial(h, nblk * h->nq);
@@ -695,11 +721,17 @@ template <typename T> void apply_adj_t(ibdl_s* h, const double* p, double* y) {
 
 // right-hand side of the adjoint system: the gradient of <psi, u> with respect to q
 template <typename T> void adj_rhs_t(ibdl_s* h, const T* psi, double* g) {
-  GridWork<T>& W = ensure_fields<T>(h, std::max(adj_nout(h), h->nq));
+  const bool fold = adj_folded(h);
+  GridWork<T>& W = ensure_fields<T>(h, fold ? h->nq : std::max(adj_nout(h), h->nq));
   ensure_adj(h);
   IBDL_HIP(hipMemcpyAsync(W.real, psi, sizeof(T) * h->ntot * h->nq, hipMemcpyDeviceToDevice, h->st));
-  adj_grid<T>(h, W, W.real, W.real, ROWS_OUT);
-  adj_markers<T>(h, W, nullptr, 0.0, nullptr, g);
+  if (fold) {
+    adj_solve<T>(h, W, W.real, W.real, ROWS_OUT, false);
+    adj_markers_div<T>(h, W, nullptr, 0.0, nullptr, g);
+  } else {
+    adj_grid<T>(h, W, W.real, W.real, ROWS_OUT);
+    adj_markers<T>(h, W, nullptr, 0.0, nullptr, g);
+  }
   if (h->has_ubar) {
     const int nblk = 256;
     ensure_partial(h, nblk * h->nq);

@@ -194,6 +194,11 @@ struct InterpArgs {
   const int* pid;      // batch: marker i reads fields at u + pid[i] * nf * (grid points); or null
 };
 template <typename T> void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, hipStream_t st);
+// Transpose of the SP_FDDIV spread (4-point kernels): y_i = -h^-D ds_i sum_y w(y) [sum_d n_id G_d W W
+// + eta W W W] + b p_i + eta ds_i pu, with p = a.x and b = a.b (p, pu may be null); one field w.
+template <typename T>
+void interp_div(const InterpArgs& a, const cplx<T>* wtab, const T* u, const double* nrm, const double* ds, double eta,
+                double hDinv, const double* pu, double* y, hipStream_t st);
 
 // Kernel-derivative gather: out[i][e] = sum_x F_i(x) d/dX_ie prod_d phi((x_d - X_id)/h), with
 // F_i(x) = sum_k coef[i][k] field_k(x) (field_k of the grid type; at most 8 fields).

@@ -40,6 +40,7 @@ CASES = {
     "brinkman_bspline": lambda: P.ProblemSpec(**{**P.brinkman_circle(16, 1.5).__dict__, "kernel": "bspline6"}),
     "brinkman_eta": lambda: P.ProblemSpec(**{**P.brinkman_circle(16, 1.5).__dict__, "eta": 2.0}),
     "sphere_3d": lambda: P.cfg3_sphere(16, 2),
+    "sphere_3d_completed": lambda: P.ProblemSpec(**{**P.cfg3_sphere(16, 2).__dict__, "eta": 2.0}),
 }
 
 
