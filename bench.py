@@ -514,7 +514,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere256", choices=["sphere256", "star1024", "circle64"])
-    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-vs-FP64, adjoint and batched measurements")
@@ -592,6 +592,17 @@ def main():
     ev1.record(pr.stream)
     ev1.synchronize()
     apply_ms = ev0.elapsed_time(ev1) / args.apply_reps
+    # the distribution of single applies (an event pair around each, same stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.apply_reps)]
+    for e0, e1 in evs:
+        e0.record(pr.stream)
+        pr.apply(q)
+        e1.record(pr.stream)
+    evs[-1][1].synchronize()
+    single = np.sort([e0.elapsed_time(e1) for e0, e1 in evs])
+    apply_pct = {"p10": float(np.percentile(single, 10)), "median": float(np.median(single)),
+                 "p90": float(np.percentile(single, 90))}
     pr.set_timing(True)
     for _ in range(args.apply_reps):
         pr.apply(q)
@@ -649,6 +660,7 @@ def main():
         "true_relres_fp64": max(relres),
         "apply_only_per_sec": round(1e3 / apply_ms, 2),
         "apply_ms": round(apply_ms, 5),
+        "apply_single_ms": {k: round(v, 5) for k, v in apply_pct.items()},
         "apply_effective_GB_s": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1),
         "apply_frac_hbm_peak": round(apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "model_U_GB": round(mu / 1e9, 4),

@@ -160,7 +160,9 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
  * With Phi the interpolation matrix (S* = Phi, Sec. 2.2.2), S = h^-D Phi^T diag(ds) and the grid
  * operators' transposes (L^-1 symmetric, D_d^T = -D_d with the Nyquist reading of the spectral
  * derivative), A^T p = J p/2 + K^T Phi^T p (+ eta ds p_ubar; u_bar rows: sum_i p_i), where K is the
- * density-to-grid map of the operator.  p, y: device double [n_aug], must not alias. */
+ * density-to-grid map of the operator.  With finite-difference symbols the scalar K^T is applied
+ * as the exact transpose of the forward map's fused divergence spread (one grid field).
+ * p, y: device double [n_aug], must not alias. */
 ibdl_status_t ibdl_apply_transpose(ibdl_t h, const double* p, double* y);
 
 /* Gradients of a loss L(u) of the grid solution of ibdl_solve with respect to the marker positions
