@@ -2,7 +2,8 @@
 
 * 256^3 sphere (73,962 markers), mixed precision: the operator apply against the FP64 oracle on
   every marker (2e-5), the FP64 apply (1e-12), and the mixed solve at 1e-8 against the oracle's
-  solution (1e-5); the recovered grid solution on a sample of nodes.
+  solution (1e-5); the recovered grid solution on a sample of nodes; the transposed apply on
+  sampled entries and by adjointness against the oracle's forward apply.
 * 1024^2 star (4,096 markers), Dirichlet and Neumann, FP64: apply (1e-12) and solve (1e-10).
 * 512^2 exterior Stokes star (1,024 markers, eta = 10, spectral), FP64: apply (1e-12) and solve
   (1e-10, with ubar), and the 1e-8 iteration count against the oracle's.
@@ -43,6 +44,30 @@ def test_sphere256_apply_and_solve():
     idx = tuple(rng.integers(0, 256, (3, 4096)))
     ugn = to_np(ug)
     assert np.max(np.abs(ugn[idx] - uo[idx])) / np.max(np.abs(uo)) < 1e-5
+    pr.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sphere256_apply_transpose(precision):
+    """A^T p at full size (the backward's transposed apply), against the oracle's forward apply:
+    sampled entries (A^T p)_i = p . (A e_i), one oracle apply per sample, and the adjointness
+    <A^T p, q> = <p, A q> for a random q."""
+    spec = P.cfg3_sphere(256, 86)
+    o = make_oracle(spec)
+    pr = make_problem(spec, precision)
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(pr.n_aug)
+    q = P.random_density(spec, seed=0)
+    got = to_np(pr.apply_transpose(p))
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    scale = np.linalg.norm(got) / np.sqrt(got.size)
+    for i in rng.integers(0, pr.n_aug, 3):
+        e = np.zeros(pr.n_aug)
+        e[i] = 1.0
+        want_i = float(p @ o.apply(e))
+        assert abs(got[i] - want_i) < tol * scale, (i, got[i], want_i)
+    lhs, rhs = float(got @ q), float(p @ o.apply(q))
+    assert abs(lhs - rhs) < tol * np.linalg.norm(got) * np.linalg.norm(q), (lhs, rhs)
     pr.close()
 
 
