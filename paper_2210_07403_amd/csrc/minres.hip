@@ -40,18 +40,24 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ p, 
   return block_sum(s, lds);
 }
 
-__global__ __launch_bounds__(kMB) void k_mr_wdot(const double* __restrict__ a, const double* __restrict__ b,
-                                                 const double* __restrict__ wt, int64_t n,
-                                                 const double* __restrict__ state, double* __restrict__ partial) {
-  __shared__ double lds[kMB];
-  if (state && state[MR_DONE] != 0.0) return;
-  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+// workgroup blk's part of <a, b>_wt
+__device__ __forceinline__ double mr_wdot_part(const double* __restrict__ a, const double* __restrict__ b,
+                                               const double* __restrict__ wt, int64_t n, int blk, double* lds) {
+  const int64_t e0 = (int64_t)blk * kMElems;
   double s = 0.0;
   for (int k = threadIdx.x; k < kMElems; k += kMB) {
     const int64_t e = e0 + k;
     if (e < n) s += wt[e] * a[e] * b[e];
   }
-  s = block_sum(s, lds);
+  return block_sum(s, lds);
+}
+
+__global__ __launch_bounds__(kMB) void k_mr_wdot(const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ wt, int64_t n,
+                                                 const double* __restrict__ state, double* __restrict__ partial) {
+  __shared__ double lds[kMB];
+  if (state && state[MR_DONE] != 0.0) return;
+  const double s = mr_wdot_part(a, b, wt, n, blockIdx.x, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
@@ -89,17 +95,11 @@ __global__ __launch_bounds__(kMB) void k_mr_start(const double* __restrict__ b, 
   }
 }
 
-// alpha = <v, p>; p -= alpha v + beta vprev; partial2 = block partials of <p, p>
-__global__ __launch_bounds__(kMB) void k_mr_lanczos(const double* __restrict__ v, const double* __restrict__ vprev,
-                                                    double* __restrict__ p, const double* __restrict__ wt, int64_t n,
-                                                    const double* __restrict__ partial, int nblk,
-                                                    double* __restrict__ partial2, const double* __restrict__ in,
-                                                    double* __restrict__ out) {
-  __shared__ double lds[kMB];
-  if (in[MR_DONE] != 0.0) return;
-  const double alpha = reduce_partials(partial, nblk, lds);
-  const double beta = in[MR_BETA];
-  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+// p -= alpha v + beta vprev on workgroup blk's elements; returns their part of <p, p>_wt
+__device__ __forceinline__ double mr_lanczos_part(const double* __restrict__ v, const double* __restrict__ vprev,
+                                                  double* __restrict__ p, const double* __restrict__ wt, int64_t n,
+                                                  double alpha, double beta, int blk, double* lds) {
+  const int64_t e0 = (int64_t)blk * kMElems;
   double s = 0.0;
   for (int k = threadIdx.x; k < kMElems; k += kMB) {
     const int64_t e = e0 + k;
@@ -109,24 +109,31 @@ __global__ __launch_bounds__(kMB) void k_mr_lanczos(const double* __restrict__ v
       s += wt[e] * pe * pe;
     }
   }
-  s = block_sum(s, lds);
+  return block_sum(s, lds);
+}
+
+// alpha = <v, p>; p -= alpha v + beta vprev; partial2 = block partials of <p, p>
+__global__ __launch_bounds__(kMB) void k_mr_lanczos(const double* __restrict__ v, const double* __restrict__ vprev,
+                                                    double* __restrict__ p, const double* __restrict__ wt, int64_t n,
+                                                    const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ partial2, const double* __restrict__ in,
+                                                    double* __restrict__ out) {
+  __shared__ double lds[kMB];
+  if (in[MR_DONE] != 0.0) return;
+  const double alpha = reduce_partials(partial, nblk, lds);
+  const double s = mr_lanczos_part(v, vprev, p, wt, n, alpha, in[MR_BETA], blockIdx.x, lds);
   if (threadIdx.x == 0) partial2[blockIdx.x] = s;
   if (blockIdx.x == 0 && threadIdx.x == 0) out[MR_ALPHA] = alpha;
 }
 
-__global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, double* __restrict__ vprev,
-                                                   const double* __restrict__ p, double* __restrict__ w1,
-                                                   double* __restrict__ w2, double* __restrict__ x, int64_t n,
-                                                   const double* __restrict__ partial2, int nblk,
-                                                   const double* __restrict__ in, double* __restrict__ out,
-                                                   double* __restrict__ hist, int64_t hist_cap) {
-  __shared__ double lds[kMB];
-  if (in[MR_DONE] != 0.0) {
-    if (blockIdx.x == 0 && threadIdx.x < MR_NSTATE) out[threadIdx.x] = in[threadIdx.x];
-    return;
-  }
-  const double beta_next = sqrt(fmax(reduce_partials(partial2, nblk, lds), 0.0));
-  const double alpha = out[MR_ALPHA];
+// the rotations and the element updates of workgroup blk, from beta_{k+1} and alpha_k; workgroup 0
+// writes the new state
+__device__ __forceinline__ void mr_update_part(double* __restrict__ v, double* __restrict__ vprev,
+                                               const double* __restrict__ p, double* __restrict__ w1,
+                                               double* __restrict__ w2, double* __restrict__ x, int64_t n,
+                                               double beta_next, double alpha, const double* __restrict__ in,
+                                               double* __restrict__ out, double* __restrict__ hist, int64_t hist_cap,
+                                               int blk) {
   const double beta = in[MR_BETA], c1 = in[MR_C1], s1 = in[MR_S1], c2 = in[MR_C2], s2 = in[MR_S2];
   const double eta = in[MR_ETA], beta1 = in[MR_BETA1], tol = in[MR_TOL];
   // the two previous rotations on the new column (beta_k, alpha_k, beta_{k+1}), then a new one
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, doubl
   const double eta_new = -s * eta;
   const bool done = fabs(eta_new) <= tol * beta1 || !(beta_next > 0.0);
   const double binv = beta_next > 0.0 ? 1.0 / beta_next : 0.0;
-  const int64_t e0 = (int64_t)blockIdx.x * kMElems;
+  const int64_t e0 = (int64_t)blk * kMElems;
   for (int k = threadIdx.x; k < kMElems; k += kMB) {
     const int64_t e = e0 + k;
     if (e < n) {
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, doubl
       v[e] = p[e] * binv;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     const double it = in[MR_ITERS] + 1.0;
     out[MR_BETA] = beta_next;
     out[MR_C1] = c;
@@ -170,6 +177,43 @@ __global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, doubl
     const int64_t j = (int64_t)in[MR_ITERS];
     if (j < hist_cap) hist[j] = beta1 > 0.0 ? fabs(eta_new) / beta1 : 0.0;
   }
+}
+
+__global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, double* __restrict__ vprev,
+                                                   const double* __restrict__ p, double* __restrict__ w1,
+                                                   double* __restrict__ w2, double* __restrict__ x, int64_t n,
+                                                   const double* __restrict__ partial2, int nblk,
+                                                   const double* __restrict__ in, double* __restrict__ out,
+                                                   double* __restrict__ hist, int64_t hist_cap) {
+  __shared__ double lds[kMB];
+  if (in[MR_DONE] != 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x < MR_NSTATE) out[threadIdx.x] = in[threadIdx.x];
+    return;
+  }
+  const double beta_next = sqrt(fmax(reduce_partials(partial2, nblk, lds), 0.0));
+  mr_update_part(v, vprev, p, w1, w2, x, n, beta_next, out[MR_ALPHA], in, out, hist, hist_cap, blockIdx.x);
+}
+
+// A whole iteration in one workgroup when the vectors fit one (n <= kMElems): the three kernels
+// above in sequence, with the same sums in the same order (each partial is reduced from the one
+// value, as reduce_partials does over a single block), so the same bits in one launch.
+__global__ __launch_bounds__(kMB) void k_mr_iter1(double* __restrict__ v, double* __restrict__ vprev,
+                                                  double* __restrict__ p, double* __restrict__ w1,
+                                                  double* __restrict__ w2, double* __restrict__ x,
+                                                  const double* __restrict__ wt, int64_t n,
+                                                  const double* __restrict__ in, double* __restrict__ out,
+                                                  double* __restrict__ hist, int64_t hist_cap) {
+  __shared__ double lds[kMB];
+  if (in[MR_DONE] != 0.0) {
+    if (threadIdx.x < MR_NSTATE) out[threadIdx.x] = in[threadIdx.x];
+    return;
+  }
+  const double a_part = mr_wdot_part(v, p, wt, n, 0, lds);
+  const double alpha = block_sum(threadIdx.x == 0 ? a_part : 0.0, lds);
+  const double b_part = mr_lanczos_part(v, vprev, p, wt, n, alpha, in[MR_BETA], 0, lds);
+  if (threadIdx.x == 0) out[MR_ALPHA] = alpha;
+  const double beta_next = sqrt(fmax(block_sum(threadIdx.x == 0 ? b_part : 0.0, lds), 0.0));
+  mr_update_part(v, vprev, p, w1, w2, x, n, beta_next, alpha, in, out, hist, hist_cap, 0);
 }
 
 }  // namespace
@@ -189,6 +233,12 @@ void mr_iteration(double* v, double* vprev, double* p, double* w1, double* w2, d
                   int64_t n, double* partial, const double* in, double* out, double* hist, int64_t hist_cap,
                   hipStream_t st) {
   const int nblk = mr_nblk(n);
+  if (nblk == 1) {
+    hipLaunchKernelGGL(k_mr_iter1, dim3(1), dim3(kMB), 0, st, v, vprev, p, w1, w2, x, wt, n, in, out, hist,
+                       hist_cap);
+    IBDL_LAUNCH_CHECK();
+    return;
+  }
   double* partial2 = partial + nblk;
   hipLaunchKernelGGL(k_mr_wdot, dim3(nblk), dim3(kMB), 0, st, v, p, wt, n, in, partial);
   IBDL_LAUNCH_CHECK();
