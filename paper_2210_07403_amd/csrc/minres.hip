@@ -126,57 +126,71 @@ __global__ __launch_bounds__(kMB) void k_mr_lanczos(const double* __restrict__ v
   if (blockIdx.x == 0 && threadIdx.x == 0) out[MR_ALPHA] = alpha;
 }
 
-// the rotations and the element updates of workgroup blk, from beta_{k+1} and alpha_k; workgroup 0
-// writes the new state
+// The two previous rotations on the new column (beta_k, alpha_k, beta_{k+1}), then a new one.
+struct MrRot {
+  double eps, delta, ginv, step, binv, c, s, eta_new;
+  bool done;
+};
+__device__ __forceinline__ MrRot mr_rotation(const double* __restrict__ in, double beta_next, double alpha) {
+  const double beta = in[MR_BETA], c1 = in[MR_C1], s1 = in[MR_S1], c2 = in[MR_C2], s2 = in[MR_S2];
+  const double eta = in[MR_ETA], beta1 = in[MR_BETA1], tol = in[MR_TOL];
+  MrRot r;
+  r.eps = s2 * beta;
+  const double d0 = c2 * beta;
+  r.delta = c1 * d0 + s1 * alpha;
+  const double g0 = -s1 * d0 + c1 * alpha;
+  const double gamma = hypot(g0, beta_next);
+  r.c = gamma > 0.0 ? g0 / gamma : 1.0;
+  r.s = gamma > 0.0 ? beta_next / gamma : 0.0;
+  r.ginv = gamma > 0.0 ? 1.0 / gamma : 0.0;
+  r.step = r.c * eta;
+  r.eta_new = -r.s * eta;
+  r.done = fabs(r.eta_new) <= tol * beta1 || !(beta_next > 0.0);
+  r.binv = beta_next > 0.0 ? 1.0 / beta_next : 0.0;
+  return r;
+}
+
+// the new state (one thread)
+__device__ __forceinline__ void mr_store_state(const double* __restrict__ in, double* __restrict__ out,
+                                               const MrRot& r, double beta_next, double* __restrict__ hist,
+                                               int64_t hist_cap) {
+  const double beta1 = in[MR_BETA1];
+  out[MR_BETA] = beta_next;
+  out[MR_C1] = r.c;
+  out[MR_S1] = r.s;
+  out[MR_C2] = in[MR_C1];
+  out[MR_S2] = in[MR_S1];
+  out[MR_ETA] = r.eta_new;
+  out[MR_BETA1] = beta1;
+  out[MR_DONE] = r.done ? 1.0 : 0.0;
+  out[MR_ITERS] = in[MR_ITERS] + 1.0;
+  out[MR_TOL] = in[MR_TOL];
+  const int64_t j = (int64_t)in[MR_ITERS];
+  if (j < hist_cap) hist[j] = beta1 > 0.0 ? fabs(r.eta_new) / beta1 : 0.0;
+}
+
+// the element updates of workgroup blk, from beta_{k+1} and alpha_k; workgroup 0 writes the state
 __device__ __forceinline__ void mr_update_part(double* __restrict__ v, double* __restrict__ vprev,
                                                const double* __restrict__ p, double* __restrict__ w1,
                                                double* __restrict__ w2, double* __restrict__ x, int64_t n,
                                                double beta_next, double alpha, const double* __restrict__ in,
                                                double* __restrict__ out, double* __restrict__ hist, int64_t hist_cap,
                                                int blk) {
-  const double beta = in[MR_BETA], c1 = in[MR_C1], s1 = in[MR_S1], c2 = in[MR_C2], s2 = in[MR_S2];
-  const double eta = in[MR_ETA], beta1 = in[MR_BETA1], tol = in[MR_TOL];
-  // the two previous rotations on the new column (beta_k, alpha_k, beta_{k+1}), then a new one
-  const double eps = s2 * beta;
-  const double d0 = c2 * beta;
-  const double delta = c1 * d0 + s1 * alpha;
-  const double g0 = -s1 * d0 + c1 * alpha;
-  const double gamma = hypot(g0, beta_next);
-  const double c = gamma > 0.0 ? g0 / gamma : 1.0;
-  const double s = gamma > 0.0 ? beta_next / gamma : 0.0;
-  const double ginv = gamma > 0.0 ? 1.0 / gamma : 0.0;
-  const double step = c * eta;
-  const double eta_new = -s * eta;
-  const bool done = fabs(eta_new) <= tol * beta1 || !(beta_next > 0.0);
-  const double binv = beta_next > 0.0 ? 1.0 / beta_next : 0.0;
+  const MrRot r = mr_rotation(in, beta_next, alpha);
   const int64_t e0 = (int64_t)blk * kMElems;
   for (int k = threadIdx.x; k < kMElems; k += kMB) {
     const int64_t e = e0 + k;
     if (e < n) {
       const double ve = v[e], a1 = w1[e];
-      const double we = (ve - delta * a1 - eps * w2[e]) * ginv;
-      x[e] += step * we;
+      const double we = (ve - r.delta * a1 - r.eps * w2[e]) * r.ginv;
+      x[e] += r.step * we;
       w2[e] = a1;
       w1[e] = we;
       vprev[e] = ve;
-      v[e] = p[e] * binv;
+      v[e] = p[e] * r.binv;
     }
   }
-  if (blk == 0 && threadIdx.x == 0) {
-    const double it = in[MR_ITERS] + 1.0;
-    out[MR_BETA] = beta_next;
-    out[MR_C1] = c;
-    out[MR_S1] = s;
-    out[MR_C2] = c1;
-    out[MR_S2] = s1;
-    out[MR_ETA] = eta_new;
-    out[MR_BETA1] = beta1;
-    out[MR_DONE] = done ? 1.0 : 0.0;
-    out[MR_ITERS] = it;
-    out[MR_TOL] = tol;
-    const int64_t j = (int64_t)in[MR_ITERS];
-    if (j < hist_cap) hist[j] = beta1 > 0.0 ? fabs(eta_new) / beta1 : 0.0;
-  }
+  if (blk == 0 && threadIdx.x == 0) mr_store_state(in, out, r, beta_next, hist, hist_cap);
 }
 
 __global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, double* __restrict__ vprev,
@@ -196,7 +210,9 @@ __global__ __launch_bounds__(kMB) void k_mr_update(double* __restrict__ v, doubl
 
 // A whole iteration in one workgroup when the vectors fit one (n <= kMElems): the three kernels
 // above in sequence, with the same sums in the same order (each partial is reduced from the one
-// value, as reduce_partials does over a single block), so the same bits in one launch.
+// value, as reduce_partials does over a single block), so the same bits in one launch.  Each
+// thread loads its entries of every vector once, at the start, and keeps them in registers.
+constexpr int kME = kMElems / kMB;   // entries per thread
 __global__ __launch_bounds__(kMB) void k_mr_iter1(double* __restrict__ v, double* __restrict__ vprev,
                                                   double* __restrict__ p, double* __restrict__ w1,
                                                   double* __restrict__ w2, double* __restrict__ x,
@@ -208,12 +224,57 @@ __global__ __launch_bounds__(kMB) void k_mr_iter1(double* __restrict__ v, double
     if (threadIdx.x < MR_NSTATE) out[threadIdx.x] = in[threadIdx.x];
     return;
   }
-  const double a_part = mr_wdot_part(v, p, wt, n, 0, lds);
-  const double alpha = block_sum(threadIdx.x == 0 ? a_part : 0.0, lds);
-  const double b_part = mr_lanczos_part(v, vprev, p, wt, n, alpha, in[MR_BETA], 0, lds);
+  double rv[kME], rp[kME], rw[kME], rq[kME], r1[kME], r2[kME], rx[kME];
+#pragma unroll
+  for (int i = 0; i < kME; ++i) {
+    const int64_t e = threadIdx.x + (int64_t)i * kMB;
+    const bool ok = e < n;
+    rv[i] = ok ? v[e] : 0.0;
+    rp[i] = ok ? p[e] : 0.0;
+    rw[i] = ok ? wt[e] : 0.0;
+    rq[i] = ok ? vprev[e] : 0.0;
+    r1[i] = ok ? w1[e] : 0.0;
+    r2[i] = ok ? w2[e] : 0.0;
+    rx[i] = ok ? x[e] : 0.0;
+  }
+  // alpha = <v, p>
+  double sa = 0.0;
+#pragma unroll
+  for (int i = 0; i < kME; ++i)
+    if (threadIdx.x + (int64_t)i * kMB < n) sa += rw[i] * rv[i] * rp[i];
+  sa = block_sum(sa, lds);
+  const double alpha = block_sum(threadIdx.x == 0 ? sa : 0.0, lds);
+  // p -= alpha v + beta vprev; <p, p>
+  const double beta = in[MR_BETA];
+  double sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < kME; ++i) {
+    const int64_t e = threadIdx.x + (int64_t)i * kMB;
+    if (e < n) {
+      const double pe = rp[i] - alpha * rv[i] - beta * rq[i];
+      rp[i] = pe;
+      p[e] = pe;
+      sb += rw[i] * pe * pe;
+    }
+  }
   if (threadIdx.x == 0) out[MR_ALPHA] = alpha;
-  const double beta_next = sqrt(fmax(block_sum(threadIdx.x == 0 ? b_part : 0.0, lds), 0.0));
-  mr_update_part(v, vprev, p, w1, w2, x, n, beta_next, alpha, in, out, hist, hist_cap, 0);
+  sb = block_sum(sb, lds);
+  const double beta_next = sqrt(fmax(block_sum(threadIdx.x == 0 ? sb : 0.0, lds), 0.0));
+  const MrRot r = mr_rotation(in, beta_next, alpha);
+#pragma unroll
+  for (int i = 0; i < kME; ++i) {
+    const int64_t e = threadIdx.x + (int64_t)i * kMB;
+    if (e < n) {
+      const double ve = rv[i], a1 = r1[i];
+      const double we = (ve - r.delta * a1 - r.eps * r2[i]) * r.ginv;
+      x[e] = rx[i] + r.step * we;
+      w2[e] = a1;
+      w1[e] = we;
+      vprev[e] = ve;
+      v[e] = rp[i] * r.binv;
+    }
+  }
+  if (threadIdx.x == 0) mr_store_state(in, out, r, beta_next, hist, hist_cap);
 }
 
 }  // namespace
