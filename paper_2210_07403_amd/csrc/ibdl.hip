@@ -881,9 +881,14 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
       w = h->V + (int64_t)(j + 1) * n;
       apply_any(h, h->V + (int64_t)j * n, w, false, trans);
     }
-    kr_arnoldi_step(h->V, n, j + 1, w, n, h->partial, anblk, h->small, h->st);
     const int slot = j & 1;
     seq[slot] = ++h->seq;
+    if (n <= kSmallN) {   // one workgroup holds the vectors: the whole step in one launch
+      kr_arnoldi_small(h->V, n, j + 1, w, n, h->small, 521, 512, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot,
+                       seq[slot], h->V + (int64_t)(j + 1) * n, gin, h->st);
+      return;
+    }
+    kr_arnoldi_step(h->V, n, j + 1, w, n, h->partial, anblk, h->small, h->st);
     kr_publish_scale(h->small, 521, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, 512, h->hmap_dev + slot * kSlot,
                      h->htag_dev + 16 * slot, seq[slot], w, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
   };

@@ -256,6 +256,12 @@ void kr_publish(double* src, int n, const double* pnorm, int nblk, int norm_at, 
 void kr_publish_scale(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
                       unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2, int64_t nv,
                       hipStream_t st);
+// kr_arnoldi_step and kr_publish_scale in one workgroup and one launch for n <= kSmallN: h[j],
+// h[256 + j] and w as kr_arnoldi_step leaves them, h[norm_at] = |w|^2, h[0..nsrc) copied to the host
+// slot, the tag, and dst (dst2) = w / |w| (deterministic; its sums group the entries differently)
+constexpr int kSmallN = 256;
+void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n, double* h, int nsrc, int norm_at,
+                      double* host_dst, unsigned* host_tag, unsigned seq, double* dst, double* dst2, hipStream_t st);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

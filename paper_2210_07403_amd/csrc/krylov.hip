@@ -378,6 +378,75 @@ __global__ __launch_bounds__(kB) void k_publish_scale(double* src, int n, const 
   }
 }
 
+// The Arnoldi step and its publication in one workgroup and one launch, for vectors of at most
+// kB entries (the marker systems of small problems, where the four launches of the blocked path
+// are mostly launch latency): thread t owns entry t and keeps it in a register; the dot products
+// are taken eight at a time, a butterfly in each wave and then the four waves' sums in order
+// (deterministic; the rounding differs from the blocked path's tree).
+__device__ __forceinline__ void wg_sum8(double (&v)[kArnGroup], double (*lds)[kArnGroup]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int g = 0; g < kArnGroup; ++g)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[g] += __shfl_xor(v[g], off);
+  if (lane == 0)
+#pragma unroll
+    for (int g = 0; g < kArnGroup; ++g) lds[wave][g] = v[g];
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < kArnGroup; ++g) v[g] = ((lds[0][g] + lds[1][g]) + lds[2][g]) + lds[3][g];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kB) void k_arnoldi_small(const double* __restrict__ V, int64_t ldv, int k, double* w,
+                                                      int64_t n, double* h, int nsrc, int norm_at, double* dst,
+                                                      unsigned* tag, unsigned seq, double* vdst, double* vdst2) {
+  __shared__ double lds[4][kArnGroup];
+  __shared__ double hs[256];
+  const int e = threadIdx.x;
+  const bool in = e < n;
+  double we = in ? w[e] : 0.0;
+  // two Gram-Schmidt passes: h[j] = V_j . w, w -= V h; h[256 + j] = V_j . w, w -= V h[256..]
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int d0 = 0; d0 < k; d0 += kArnGroup) {
+      double acc[kArnGroup];
+#pragma unroll
+      for (int g = 0; g < kArnGroup; ++g) acc[g] = (in && d0 + g < k) ? V[(int64_t)(d0 + g) * ldv + e] * we : 0.0;
+      wg_sum8(acc, lds);
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int g = 0; g < kArnGroup; ++g)
+          if (d0 + g < k) hs[d0 + g] = acc[g];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += kB) h[256 * pass + j] = hs[j];
+    if (in) {
+      for (int j = 0; j < k; ++j) we -= V[(int64_t)j * ldv + e] * hs[j];
+      w[e] = we;
+    }
+    __syncthreads();
+  }
+  // |w|^2, the publication (values, then the tag after a system-scope fence), w / |w|
+  double sq[kArnGroup] = {we * we, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  wg_sum8(sq, lds);
+  const double v = sq[0];
+  if (threadIdx.x == 0) h[norm_at] = v;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nsrc; i += kB) dst[i] = h[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned*>(tag) = seq;
+  }
+  const double nr = sqrt(v > 0.0 ? v : 0.0);
+  const double sc = (nr > 0.0 && nr < INFINITY) ? 1.0 / nr : 0.0;
+  if (in) {
+    const double x = we * sc;
+    vdst[e] = x;
+    if (vdst2) vdst2[e] = x;
+  }
+}
+
 inline unsigned blocks_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
@@ -390,6 +459,14 @@ void kr_publish_scale(double* src, int n, const double* pnorm, int nblk, int nor
                       hipStream_t st) {
   hipLaunchKernelGGL(k_publish_scale, dim3(blocks_for(nv)), dim3(kB), 0, st, src, n, pnorm, nblk, norm_at, host_dst,
                      host_tag, seq, w, dst, dst2, nv);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n, double* h, int nsrc, int norm_at,
+                      double* host_dst, unsigned* host_tag, unsigned seq, double* dst, double* dst2, hipStream_t st) {
+  if (n > kSmallN || k < 1 || k > 256) throw Error(-2, "kr_arnoldi_small: n <= kSmallN and 1 <= k <= 256");
+  hipLaunchKernelGGL(k_arnoldi_small, dim3(1), dim3(kB), 0, st, V, ldv, k, w, n, h, nsrc, norm_at, host_dst, host_tag,
+                     seq, dst, dst2);
   IBDL_LAUNCH_CHECK();
 }
 
