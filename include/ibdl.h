@@ -125,6 +125,20 @@ ibdl_status_t ibdl_interp(ibdl_t h, const void* grid, int32_t nc, double* f);
  * Stokes u = L^-1 P rhs with rhs, u of dim components.  rhs and u may alias. */
 ibdl_status_t ibdl_grid_solve(ibdl_t h, const void* rhs, void* u);
 
+/* ibdl_grid_solve without a handle and without allocating: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same operator and layouts as ibdl_grid_solve for the grid, PDE, discretisation and precision
+ * that cfg describes (dim, n, L, pde, kappa, mu, disc, precision, stream; markers, bc, eta and
+ * kernel are ignored): scalar u = L^-1 rhs (mean-zero branch for Poisson), Stokes u = L^-1 P rhs.
+ * rhs and u are device arrays owned by the caller ([nq][grid] of the grid type) and may alias.
+ * The half spectra and the FFT tables live in a fixed static device array of 32 MiB per GPU, held
+ * until the process ends: grids that need more (for example 3-D 256^3) return
+ * IBDL_ERR_UNSUPPORTED before any device work.  Calls no hipMalloc, hipFree or other allocating
+ * routine.  Asynchronous on cfg->stream, on the current device.  Every call on one GPU shares that
+ * array and leaves its contents behind: calls that overlap on one GPU (two streams, two host
+ * threads) race.  ibdl_last_error(NULL) describes a failure. */
+ibdl_status_t ibdl_grid_solve_static(const ibdl_config_t* cfg, const void* rhs, void* u);
+
 /* y = A q for the handle's operator; q, y: device double [n_aug] (must not alias). */
 ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y);
 
@@ -363,7 +377,8 @@ ibdl_status_t ibdl_set_timing(ibdl_t h, int32_t enable);
  * recorded events. */
 ibdl_status_t ibdl_get_timing(ibdl_t h, double* ms, int64_t* count, int32_t cap);
 
-/* Message of the last failure on this handle (or of the last failed ibdl_create when h is NULL).
+/* Message of the last failure on this handle (or, when h is NULL, of the last failed ibdl_create or
+ * ibdl_grid_solve_static).
  * The string stays valid until the next call on the handle. */
 const char* ibdl_last_error(ibdl_t h);
 

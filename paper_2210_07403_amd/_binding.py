@@ -47,6 +47,7 @@ _SIGS = {
     "ibdl_spread": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     "ibdl_interp": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     "ibdl_grid_solve": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ibdl_grid_solve_static": (c_int32, [ctypes.POINTER(Config), c_void_p, c_void_p]),
     "ibdl_apply": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ibdl_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                              ctypes.POINTER(Info)]),

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libibdl.so")
-SOURCES = ["fft.hip", "ib.hip", "krylov.hip", "tune.hip", "nearbdry.hip", "force.hip", "minres.hip", "ns.hip", "ibdl.hip", "batch.hip"]
+SOURCES = ["fft.hip", "ib.hip", "krylov.hip", "tune.hip", "nearbdry.hip", "force.hip", "minres.hip", "ns.hip", "ibdl.hip", "batch.hip", "static_solve.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

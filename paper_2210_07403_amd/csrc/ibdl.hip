@@ -41,6 +41,11 @@ std::string g_create_error;
 
 }  // namespace
 
+namespace ibdl {
+// the message ibdl_last_error(NULL) returns: the last failed ibdl_create or handle-free call
+void set_global_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace ibdl
+
 struct ibdl_s {
   ibdl_config_t cfg{};
   int dim = 2;
