@@ -180,6 +180,25 @@ def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
     out["adjoint"] = {"forward_solve_ms": round(1e3 * t_fw, 3), "backward_ms": round(1e3 * t_bw, 3),
                       "adjoint_iters": ib.iters, "adjoint_true_relres": ib.true_relres_fp64}
     print("# extras: batch of 64", file=sys.stderr, flush=True)
+    out["batch64"] = _batch_timing(dev)
+    print("# extras: near-boundary tools", file=sys.stderr, flush=True)
+    out["near_boundary_star1024"] = _near_boundary_timing(dev)
+    print("# extras: cylinder array drag", file=sys.stderr, flush=True)
+    out["cylinder_array_drag"] = _cylinder_drag(dev)
+    print("# extras: single vs double layer", file=sys.stderr, flush=True)
+    out["ibsl_vs_ibdl_helmholtz1024"] = _ibsl_vs_ibdl(dev)
+    print("# extras: Navier-Stokes cylinder", file=sys.stderr, flush=True)
+    out["ns_cylinder_re100"] = ns_cylinder(dev, 100.0, 200, 5)
+    return out
+
+
+def _batch_timing(dev):
+    """Config 4: 64 independent 2-D Poisson problems batched (mixed and FP64) against the same
+    problems solved one after another in FP64."""
+    import numpy as np
+    import torch
+    import paper_2210_07403_amd as ibdl
+    from workloads import problems as P
     specs = P.cfg4_batch()
     dicts = [dict(dim=s.dim, n=s.n, L=s.L, origin=s.origin, X=s.markers.X, nrm=s.markers.nrm, ds=s.markers.ds,
                   pde=s.pde, kappa=s.kappa, kernel=s.kernel) for s in specs]
@@ -200,20 +219,11 @@ def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
     tseq, _ = _timed(lambda: [p_.solve(d_, None, tol=1e-8, maxit=100, want_u=False) for p_, d_ in zip(probs, bdata)], 2)
     for p_ in probs:
         p_.close()
-    out["batch64"] = {"workload": "64 2-D Poisson Dirichlet problems, grids 128/256/512, 256-2048 markers, tol 1e-8",
-                      "batched_mixed": res["mixed"], "batched_fp64": res["fp64"],
-                      "sequential_fp64_ms": round(1e3 * tseq, 3),
-                      "speedup_batched_mixed_vs_sequential_fp64": round(tseq / (res["mixed"]["ms"] * 1e-3), 2),
-                      "speedup_batched_fp64_vs_sequential_fp64": round(tseq / (res["fp64"]["ms"] * 1e-3), 2)}
-    print("# extras: near-boundary tools", file=sys.stderr, flush=True)
-    out["near_boundary_star1024"] = _near_boundary_timing(dev)
-    print("# extras: cylinder array drag", file=sys.stderr, flush=True)
-    out["cylinder_array_drag"] = _cylinder_drag(dev)
-    print("# extras: single vs double layer", file=sys.stderr, flush=True)
-    out["ibsl_vs_ibdl_helmholtz1024"] = _ibsl_vs_ibdl(dev)
-    print("# extras: Navier-Stokes cylinder", file=sys.stderr, flush=True)
-    out["ns_cylinder_re100"] = ns_cylinder(dev, 100.0, 200, 5)
-    return out
+    return {"workload": "64 2-D Poisson Dirichlet problems, grids 128/256/512, 256-2048 markers, tol 1e-8",
+            "batched_mixed": res["mixed"], "batched_fp64": res["fp64"],
+            "sequential_fp64_ms": round(1e3 * tseq, 3),
+            "speedup_batched_mixed_vs_sequential_fp64": round(tseq / (res["mixed"]["ms"] * 1e-3), 2),
+            "speedup_batched_fp64_vs_sequential_fp64": round(tseq / (res["fp64"]["ms"] * 1e-3), 2)}
 
 
 def ns_cylinder(dev, re, steps, warm, report_every=0, precision="fp64"):
@@ -524,7 +534,8 @@ def main():
                     help="only run the Navier-Stokes cylinder for STEPS steps and print its JSON line")
     ap.add_argument("--ns-re", type=float, default=10.0)
     ap.add_argument("--ns-every", type=int, default=0, help="drag/lift sample interval in steps (0: STEPS / 40)")
-    ap.add_argument("--only", choices=["near_boundary", "cylinder_array", "ibsl", "ns", "adjoint"], default=None,
+    ap.add_argument("--only", choices=["near_boundary", "cylinder_array", "ibsl", "ns", "adjoint", "batch"],
+                    default=None,
                     help="only run one of the measurements beyond the hot path and print its JSON line")
     args = ap.parse_args()
     if args.only:
@@ -532,7 +543,8 @@ def main():
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         run = {"near_boundary": _near_boundary_timing, "cylinder_array": _cylinder_drag, "ibsl": _ibsl_vs_ibdl,
-               "ns": lambda d: ns_cylinder(d, 100.0, 200, 5), "adjoint": _adjoint_timing}[args.only]
+               "ns": lambda d: ns_cylinder(d, 100.0, 200, 5), "adjoint": _adjoint_timing,
+               "batch": _batch_timing}[args.only]
         print(json.dumps(run(dev)))
         return
     if args.ns_cylinder > 0:

@@ -197,10 +197,15 @@ ibdl_status_t ibdl_backward(ibdl_t h, const double* q, const void* u_grid, const
 /* ---------------------------------------------------------------- batches of problems
  * Many independent plain scalar Dirichlet problems (Sec. 5.3.2: screened Poisson or Poisson,
  * eta = 0, finite-difference symbols, a 4-point kernel), of any grid sizes and marker counts,
- * solved together.  Problems with the same grid (sizes, box, origin, kappa) share one launch per
- * stage; the batched operator is replayed from a HIP graph every GMRES iteration; the FFT
- * passes' launch shapes are chosen by timing per (dim, grid, precision, problem count).  All
- * problems share dim, precision and kernel. */
+ * solved together.  Problems with the same grid (sizes, box, origin, kappa) form a group.  In 2-D
+ * the spread of every group is one persistent launch over a single work queue of busy tiles and
+ * the interpolation of every group one launch; the FFT passes run once per group.  The batched
+ * operator is replayed from a HIP graph every GMRES iteration, and each iteration's Arnoldi step,
+ * Givens rotations and convergence test run on the device for every problem in one launch, so the
+ * host only watches the published residuals.  The FFT passes' launch shapes and the 2-D spread's
+ * tile shape are chosen by timing per (dim, grid, precision, problem count, markers per problem)
+ * and kept in a JSON file ($IBDL_TUNE_CACHE, else ~/.cache/ibdl/tune.json; an empty
+ * IBDL_TUNE_CACHE keeps them in memory only).  All problems share dim, precision and kernel. */
 typedef struct ibdl_batch_s* ibdl_batch_t;
 
 /* cfgs[p], n_ib[p]: host arrays of nprob configurations and marker counts; X[p], nrm[p], ds[p]:
@@ -224,11 +229,12 @@ ibdl_status_t ibdl_batch_solve(ibdl_batch_t b, const double* const* data, double
 /* Replay the batched apply from a captured HIP graph (1, the default) or launch it directly (0). */
 ibdl_status_t ibdl_batch_set_graph(ibdl_batch_t b, int32_t enable);
 
-/* Number of grid groups; for group >= 0 also its problem count, grid sizes n[3] and the launch
- * shapes chosen for its FFT passes (rows per block of the x passes, lines per block of the fused
- * pass).  Any output pointer may be NULL. */
+/* Number of grid groups; for group >= 0 also its problem count, grid sizes n[3], the launch shapes
+ * chosen for its FFT passes (rows per block of the x passes, lines per block of the fused pass) and
+ * the tile width along x of its 2-D spread (16, 32 or 64 nodes, tiles of 256 nodes; 16 in 3-D).
+ * Any output pointer may be NULL. */
 ibdl_status_t ibdl_batch_query(ibdl_batch_t b, int32_t group, int32_t* ngroups, int32_t* nprob_in_group,
-                               int32_t* n, int32_t* rows_per_block, int32_t* lines_per_block);
+                               int32_t* n, int32_t* rows_per_block, int32_t* lines_per_block, int32_t* tile_x);
 
 /* Message of the last failure on the batch (or of the last failed ibdl_batch_create for NULL). */
 const char* ibdl_batch_last_error(ibdl_batch_t b);

@@ -418,17 +418,18 @@ class Batch:
         B.check_batch(B.load().ibdl_batch_set_graph(self._h, 1 if enable else 0), self._h)
 
     def groups(self):
-        """[{nprob, n, rows_per_block, lines_per_block}] of the grid groups."""
+        """[{nprob, n, rows_per_block, lines_per_block, tile_x}] of the grid groups."""
         lib = B.load()
         ng = ctypes.c_int32()
-        B.check_batch(lib.ibdl_batch_query(self._h, -1, ctypes.byref(ng), None, None, None, None), self._h)
+        B.check_batch(lib.ibdl_batch_query(self._h, -1, ctypes.byref(ng), None, None, None, None, None), self._h)
         out = []
         for g in range(ng.value):
-            npg, rpb, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            npg, rpb, w, tx = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
             n = (ctypes.c_int32 * 3)()
             B.check_batch(lib.ibdl_batch_query(self._h, g, None, ctypes.byref(npg), n, ctypes.byref(rpb),
-                                               ctypes.byref(w)), self._h)
-            out.append(dict(nprob=npg.value, n=tuple(n), rows_per_block=rpb.value, lines_per_block=w.value))
+                                               ctypes.byref(w), ctypes.byref(tx)), self._h)
+            out.append(dict(nprob=npg.value, n=tuple(n), rows_per_block=rpb.value, lines_per_block=w.value,
+                            tile_x=tx.value))
         return out
 
     def apply(self, qs):

@@ -63,7 +63,8 @@ _SIGS = {
     "ibdl_batch_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p, c_void_p]),
     "ibdl_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "ibdl_batch_query": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
-                                   ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+                                   ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                   ctypes.POINTER(c_int32)]),
     "ibdl_batch_last_error": (ctypes.c_char_p, [c_void_p]),
     "ibdl_active_rows": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),
     "ibdl_launch_shape": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),

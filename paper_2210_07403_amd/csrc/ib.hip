@@ -170,7 +170,9 @@ __global__ void k_row_segments(MarkerGeom g, const int* __restrict__ tile_off, c
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nact) return;
   const int w = rows ? rows[r] : (int)r, y = w % g.n[1], z = w / g.n[1];
-  const int64_t strip = y / g.tile[1] + (int64_t)g.ntile[1] * (g.dim == 3 ? z / g.tile[2] : 0);
+  // z counts planes, or problems of a batch in 2-D (tile[2] = 1 there): tiles are numbered
+  // problem-major, so the strip index runs on across a batch's problems
+  const int64_t strip = y / g.tile[1] + (int64_t)g.ntile[1] * (z / g.tile[2]);
   unsigned long long m = 0;
   for (int t = 0; t < g.ntile[0]; ++t) {
     const int64_t id = strip * g.ntile[0] + t;
@@ -462,25 +464,28 @@ __global__ __launch_bounds__(64 * NW) void k_spread3m(SpreadArgs a, const cplx<T
   }
 }
 
-// 2-D: lane (x, y-group) owns y = 4*yg + j' (j' < 4); the owning lane of a candidate writes its x row
-// and its tile-aligned y column (16 pairs) to LDS; coefficients and the x window start are broadcast.
-template <typename T, int NF>
-__global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
+// 2-D: a tile of TX x TY nodes (TX TY = 256, TY = 4 (64 / TX) rows); lane (x, y-group) owns
+// y = 4 yg + j' (j' < 4); the owning lane of a candidate writes its x row and its tile-aligned y
+// column (TY pairs) to LDS; coefficients and the x window start are broadcast.  s_x and s_y are the
+// caller's LDS: [4][LW][8] and [4][LW][TY] (T, T) pairs.
+template <typename T, int NF, int TX>
+__device__ __forceinline__ void spread2_tile(const SpreadArgs& a, const cplx<T>* __restrict__ wtab, T* __restrict__ out,
+                                             const int4 bt, cplx<T> (*s_x)[spread_lanes<T>()][8], cplx<T>* s_yraw) {
   using T2 = cplx<T>;
   constexpr int LW = spread_lanes<T>();
-  __shared__ T2 s_x[4][LW][8];
-  __shared__ T2 s_y[4][LW][kT2Y];
+  constexpr int TY = 256 / TX;
+  static_assert(TX * TY == 256 && TX >= 4 && TX <= 64, "2-D tile of 256 nodes, 64 lanes of 4 rows");
+  auto s_y = reinterpret_cast<T2 (*)[LW][TY]>(s_yraw);
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 bt = a.busy[blockIdx.x];
   const int tile = bt.x;
   const int ntl = g.ntile[0] * g.ntile[1];
   const int prob = tile / ntl, tl = tile - prob * ntl;
   const int tx = tl % g.ntile[0];
   const int ty = tl / g.ntile[0];
-  const int x0 = tx * kT2X, y0 = ty * kT2Y;
-  const int lx = lane % kT2X, yg = lane / kT2X;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int lx = lane % TX, yg = lane / TX;
   const int mx = g.n[0] - 1, my = g.n[1] - 1;
   const bool fddiv = NF == 1 && a.mode == SP_FDDIV;
   T acc[4][NF];
@@ -505,7 +510,7 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
       sx = a.s[m * 3 + 0];
       const int sy = a.s[m * 3 + 1];
 #pragma unroll
-      for (int y = 0; y < kT2Y; ++y) s_y[wave][lane][y] = row[8 + min((y0 + y - sy) & my, 6)];
+      for (int y = 0; y < TY; ++y) s_y[wave][lane][y] = row[8 + min((y0 + y - sy) & my, 6)];
       double c8[8];
       spread_coefs(a, m, 2, a.raw ? 1.0 : a.ds[m] / hD, c8);
 #pragma unroll
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
     }
     __syncthreads();
   }
-  T* red = reinterpret_cast<T*>(&s_y[0][0][0]);   // needs 4 * 4 * 64 values
+  T* red = reinterpret_cast<T*>(s_yraw);   // needs 4 * 4 * 64 values: [4][LW][TY] pairs hold them
   const int64_t ntot = (int64_t)g.n[0] * g.n[1];
   out += (int64_t)prob * a.nf * ntot;
 #pragma unroll
@@ -550,10 +555,45 @@ __global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __
       const int q = o >> 6, l = o & 63; // l: (x, y-group), q: y within the group
       const T v = ((red[(0 * 4 + q) * 64 + l] + red[(1 * 4 + q) * 64 + l]) + red[(2 * 4 + q) * 64 + l]) +
                   red[(3 * 4 + q) * 64 + l];
-      const int x = l % kT2X, y = 4 * (l / kT2X) + q;
+      const int x = l % TX, y = 4 * (l / TX) + q;
       out[c * ntot + (int64_t)(y0 + y) * g.n[0] + x0 + x] = v;
     }
     __syncthreads();
+  }
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_spread2(SpreadArgs a, const cplx<T>* __restrict__ wtab, T* __restrict__ out) {
+  constexpr int LW = spread_lanes<T>();
+  __shared__ cplx<T> s_x[4][LW][8];
+  __shared__ cplx<T> s_y[4 * LW * kT2Y];
+  spread2_tile<T, NF, kT2X>(a, wtab, out, a.busy[blockIdx.x], s_x, s_y);
+}
+
+// The spread of several grid groups (a batch) in one persistent launch over a single work list,
+// items[k] = (group, busy-tile index), ordered by decreasing candidate count across all groups:
+// workgroup b takes items b, b + G, b + 2 G, ... (G workgroups), so the longest tiles go first and
+// every workgroup ends with short ones.  (A shared atomic counter was measured slower: 4,500 tiles
+// serialise on one address.)  Each group has its own arguments, weight table, output fields and
+// tile width (16, 32 or 64 nodes along x); its densities are qbase + qoff.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread2_queue(const SpreadGroup* __restrict__ gd, const int2* __restrict__ items,
+                                                       int nitems, const double* __restrict__ qbase) {
+  constexpr int LW = spread_lanes<T>();
+  __shared__ cplx<T> s_x[4][LW][8];
+  __shared__ cplx<T> s_y[4 * LW * 16];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 gi = items[it];
+    const int gsel = __builtin_amdgcn_readfirstlane(gi.x);
+    SpreadArgs a = gd[gsel].a;
+    a.q = qbase + gd[gsel].qoff;
+    const int4 bt = a.busy[gi.y];
+    const cplx<T>* wt = reinterpret_cast<const cplx<T>*>(gd[gsel].wtab);
+    T* out = reinterpret_cast<T*>(gd[gsel].out);
+    const int tw = gd[gsel].tx;
+    if (tw == 32) spread2_tile<T, 1, 32>(a, wt, out, bt, s_x, s_y);
+    else if (tw == 64) spread2_tile<T, 1, 64>(a, wt, out, bt, s_x, s_y);
+    else spread2_tile<T, 1, 16>(a, wt, out, bt, s_x, s_y);
   }
 }
 
@@ -640,6 +680,47 @@ __global__ __launch_bounds__(256) void k_interp4(InterpArgs a, const cplx<T>* __
       if (a.ub) o += a.ub[c];
       out[i * a.nf + c] = o;
     }
+  }
+}
+
+// The interpolation (4-point kernels, 2-D) of several grid groups in one launch: marker i of the
+// concatenation belongs to the group g with m0[g] <= i < m0[g + 1] (gd[g].m0); it reads that group's
+// fields and weight table and writes out[i] = a S*u + b x[i] (one field per marker).
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp4_groups(const InterpGroup* __restrict__ gd, int ng, int64_t ntot_m,
+                                                        const double* __restrict__ xbase, double* __restrict__ out) {
+  constexpr int RL = 4;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / RL;
+  const int r = (int)(gid % RL);
+  const bool valid = i < ntot_m;
+  const int64_t ic = valid ? i : 0;
+  int gsel = 0;
+  while (gsel + 1 < ng && ic >= gd[gsel + 1].m0) ++gsel;
+  const InterpGroup& G = gd[gsel];
+  const MarkerGeom& g = G.a.g;
+  const int64_t im = ic - G.m0;
+  const cplx<T>* row = reinterpret_cast<const cplx<T>*>(G.wtab) + im * 24;
+  const int sx = G.a.s[im * 3 + 0], sy = G.a.s[im * 3 + 1];
+  const int ty = r & 3;
+  const T wyz = row[8 + 1 + ty].x;
+  const int64_t base = (int64_t)((sy + 1 + ty) & (g.n[1] - 1)) * g.n[0];
+  int ix[4];
+  T wx[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ix[t] = (sx + 1 + t) & (g.n[0] - 1);
+    wx[t] = row[1 + t].x;
+  }
+  const int64_t ntot = (int64_t)g.n[0] * g.n[1];
+  const T* uc = reinterpret_cast<const T*>(G.u) + (int64_t)G.a.pid[im] * ntot + base;
+  T v = ((uc[ix[0]] * wx[0] + uc[ix[1]] * wx[1]) + uc[ix[2]] * wx[2] + uc[ix[3]] * wx[3]) * wyz;
+#pragma unroll
+  for (int off = 1; off < RL; off <<= 1) v += __shfl_xor(v, off, RL);
+  if (valid && r == 0) {
+    double o = G.a.a * (double)v;
+    if (xbase) o += G.a.b * xbase[i];
+    out[i] = o;
   }
 }
 
@@ -954,6 +1035,24 @@ void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
 }
 
 template <typename T>
+void spread2_queue(const SpreadGroup* gd, const int2* items, int nitems, const double* qbase, int nblocks,
+                   hipStream_t st) {
+  if (nitems <= 0) return;
+  const int nb = nblocks > 0 ? (nblocks < nitems ? nblocks : nitems) : nitems;
+  hipLaunchKernelGGL((k_spread2_queue<T>), dim3((unsigned)nb), dim3(256), 0, st, gd, items, nitems, qbase);
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
+void interp4_groups(const InterpGroup* gd, int ng, int64_t ntot_m, const double* xbase, double* out, hipStream_t st) {
+  if (ntot_m <= 0) return;
+  const int64_t lanes = ntot_m * 4;
+  hipLaunchKernelGGL((k_interp4_groups<T>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, gd, ng, ntot_m,
+                     xbase, out);
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
 void weight_table(const double* wt, int64_t n_ib, cplx<T>* tab, hipStream_t st) {
   const int64_t n = n_ib * 24;
   if (n > 0) hipLaunchKernelGGL((k_wtab<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, wt, n_ib, tab);
@@ -1042,7 +1141,9 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
   template void grid_axpby<T>(T*, double, const T*, double, int64_t, hipStream_t);        \
   template void gather_dx<T>(const GatherArgs&, hipStream_t);                             \
   template void grid_add_const<T>(T*, const double*, int, int64_t, hipStream_t);          \
-  template void grid_sum<T>(const T*, int, int64_t, double*, int, double*, hipStream_t);
+  template void grid_sum<T>(const T*, int, int64_t, double*, int, double*, hipStream_t);  \
+  template void spread2_queue<T>(const SpreadGroup*, const int2*, int, const double*, int, hipStream_t); \
+  template void interp4_groups<T>(const InterpGroup*, int, int64_t, const double*, double*, hipStream_t);
 IBDL_IB_INST(float)
 IBDL_IB_INST(double)
 

@@ -91,6 +91,8 @@ struct ibdl_s {
   std::unique_ptr<GridWork<double>> w64;
   double* V = nullptr;
   int vcap = 0;
+  double* gm = nullptr;       // GMRES least-squares state on the device (kr_gmres_state_doubles)
+  int gmcap = 0;
   double* small = nullptr;    // 1024 doubles of small device scratch
   double* partial = nullptr;  // partial sums
   int pcap = 0;
@@ -846,19 +848,25 @@ bool ensure_graph(ibdl_s* h, bool trans) {
   return true;
 }
 
-// GMRES, x0 = 0, no restart; classical Gram-Schmidt twice on the device; Givens on the host.
-// The device runs one Arnoldi step ahead of the host: step j + 1 (normalise w_j into V[j+1] with
-// the norm the device computed, apply, orthogonalise, publish) is queued before the host waits for
-// step j's values, so the GPU does not idle on the host's Givens update and convergence test.  A
-// step queued after the last one the host uses only writes V[j+1] and scratch.
+// GMRES, x0 = 0, no restart; classical Gram-Schmidt twice, the Givens rotations and the
+// least-squares solution on the device, in double precision.  The device runs ahead of the host:
+// step j + 1 (normalise w_j into V[j+1] with the norm the device computed, apply, orthogonalise,
+// update the least-squares state, publish its residual) is queued before the host waits for step
+// j's residual.  The state freezes at the step that converges, so a step queued after it changes
+// nothing but V[j+2] and scratch.
 int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
           double* relres, bool trans = false) {
   const int64_t n = h->n_aug;
-  if (maxit > 255) throw Error(IBDL_ERR_ARG, "maxit must be at most 255");
+  if (maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be at most 200");
   if (h->vcap < maxit + 1) {
     h->V = (double*)h->dalloc<double>(sizeof(double) * n * (maxit + 1));
     h->vcap = maxit + 1;
   }
+  if (h->gmcap < maxit) {
+    h->gm = (double*)h->dalloc<double>(sizeof(double) * kr_gmres_state_doubles(maxit));
+    h->gmcap = maxit;
+  }
+  const int mx = h->gmcap;
   const int nblk = kr_nblk(n);
   const int anblk = kr_arnoldi_nblk(n);
   ensure_partial(h, std::max(nblk * (maxit + 2), anblk * (2 * maxit + 3)));
@@ -866,17 +874,13 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   *relres = 0.0;
   const bool graph = ensure_graph(h, trans);
   double* gin = graph ? h->gx : nullptr;
-  // |b|^2 (small[520]) and V[0] = b / |b| (also the graph's input) on the device, so that step 0 is
-  // queued without a host round trip; the host learns |b| with step 0's values
-  kr_multidot(b, n, 1, b, n, h->partial, nblk, h->small + 520, h->st);
-  kr_scale_norm(b, h->small + 520, 0.0, h->V, gin, n, h->st);
-  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0);
-  int k = 0;
-  double res = 1.0;
-  // h->small: first Gram-Schmidt coefficients [0, 256), second [256, 512), |w|^2 at 512, |b|^2 at 520
+  // |b|^2 (small[GM_BNORM2_AT]) and V[0] = b / |b| (also the graph's input) on the device, so that
+  // step 0 is queued without a host round trip; step 0's least-squares update takes |b| from there
+  kr_multidot(b, n, 1, b, n, h->partial, nblk, h->small + GM_BNORM2_AT, h->st);
+  kr_scale_norm(b, h->small + GM_BNORM2_AT, 0.0, h->V, gin, n, h->st);
   unsigned seq[2] = {0, 0};
-  // queue Arnoldi step j (V[j] is in place, and in gx for the graph): apply, orthogonalise,
-  // publish the values to the host and, in the same launch, normalise w into V[j+1] (and gx)
+  // queue Arnoldi step j (V[j] is in place, and in gx for the graph): apply, orthogonalise, update
+  // the least-squares state, publish it and, in the same launch, normalise w into V[j+1] (and gx)
   auto step = [&](int j) {
     double* w;
     if (graph) {
@@ -889,75 +893,47 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     const int slot = j & 1;
     seq[slot] = ++h->seq;
     if (n <= kSmallN) {   // one workgroup holds the vectors: the whole step in one launch
-      kr_arnoldi_small(h->V, n, j + 1, w, n, h->small, 521, 512, h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot,
-                       seq[slot], h->V + (int64_t)(j + 1) * n, gin, h->st);
+      kr_arnoldi_small(h->V, n, j + 1, w, n, h->small, 512, h->gm, mx, tol, h->hmap_dev + slot * kSlot,
+                       h->htag_dev + 16 * slot, seq[slot], h->V + (int64_t)(j + 1) * n, gin, h->st);
       return;
     }
     kr_arnoldi_step(h->V, n, j + 1, w, n, h->partial, anblk, h->small, h->st);
-    kr_publish_scale(h->small, 521, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, 512, h->hmap_dev + slot * kSlot,
-                     h->htag_dev + 16 * slot, seq[slot], w, h->V + (int64_t)(j + 1) * n, gin, n, h->st);
+    kr_publish_scale(h->small, h->partial + (int64_t)2 * (j + 1) * anblk, anblk, 512, h->gm, j, mx, tol,
+                     h->hmap_dev + slot * kSlot, h->htag_dev + 16 * slot, seq[slot], w, h->V + (int64_t)(j + 1) * n,
+                     gin, n, h->st);
   };
   step(0);
-  auto next = [&](int j) { step(j + 1); };   // queue step j + 1 (a breakdown is found by the host)
-  double beta = 0.0, tiny = 0.0;
-  std::vector<double> rs(maxit, 1.0);   // residual estimates of the steps the host has finished
+  int k = 0;
+  double res = 1.0;
+  std::vector<double> rs(maxit, 1.0);   // residual estimates of the steps the host has seen
   for (int j = 0; j < maxit; ++j) {
     // Step j + 1 is queued ahead unless step j is predicted to converge: the residual ratio of the
     // last two steps, applied once more, brings it to tol.  A step queued after convergence would
     // delay whatever follows on the stream by a whole apply.
     bool ahead = j + 1 < maxit;
     if (ahead && j >= 2) ahead = rs[j - 1] * (rs[j - 1] / rs[j - 2]) > tol;
-    if (ahead) next(j);
+    if (ahead) step(j + 1);
     const volatile double* hv = wait_published(h, j & 1, seq[j & 1]);
-    if (j == 0) {
-      beta = sqrt(std::max((double)hv[520], 0.0));
-      if (!(beta > 0.0)) {   // b = 0: x = 0 (behind the queued steps, which ran on zeros)
-        if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
-        IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
-        IBDL_HIP(hipStreamSynchronize(h->st));
-        return IBDL_OK;
-      }
-      gv[0] = beta;
-      tiny = 1e-300 * beta;
+    const double beta = hv[GM_BETA], hn = hv[GM_HN];
+    if (j == 0 && !(beta > 0.0)) {   // b = 0: x = 0 (behind the queued steps, which ran on zeros)
+      if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
+      IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
+      IBDL_HIP(hipStreamSynchronize(h->st));
+      return IBDL_OK;
     }
-    double* Hj = &H[(size_t)j * (maxit + 1)];
-    for (int i = 0; i <= j; ++i) Hj[i] = hv[i] + hv[256 + i];
-    const double hnext = sqrt(std::max((double)hv[512], 0.0));
-    if (!std::isfinite(hnext)) throw Error(IBDL_ERR_NONFINITE, "non-finite value in the Arnoldi process");
-    Hj[j + 1] = hnext;
-    const bool breakdown = !(hnext > tiny);
-    for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
-      Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
-      Hj[i] = t;
-    }
-    const double r = hypot(Hj[j], Hj[j + 1]);
-    cs[j] = Hj[j] / r;
-    sn[j] = Hj[j + 1] / r;
-    Hj[j] = r;
-    Hj[j + 1] = 0.0;
-    gv[j + 1] = -sn[j] * gv[j];
-    gv[j] = cs[j] * gv[j];
-    k = j + 1;
-    res = fabs(gv[j + 1]) / beta;
+    if (!std::isfinite(hn) || !std::isfinite((double)hv[GM_RES]))
+      throw Error(IBDL_ERR_NONFINITE, "non-finite value in the Arnoldi process");
+    res = hv[GM_RES];
     rs[j] = res;
+    k = (int)hv[GM_K];
     if (info && info->history && j < info->history_cap) info->history[j] = res;
-    if (res <= tol || breakdown) break;
-    if (!ahead && j + 1 < maxit) next(j);
+    if (hv[GM_DONE] != 0.0) break;
+    if (!ahead && j + 1 < maxit) step(j + 1);
   }
-  std::vector<double> y(k);
-  for (int i = k - 1; i >= 0; --i) {
-    double s = gv[i];
-    for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (maxit + 1) + i] * y[c];
-    y[i] = s / H[(size_t)i * (maxit + 1) + i];
-  }
-  // y goes to host-mapped memory, which the combination kernel reads directly (no copy launch).
-  // x is left to the stream: the caller's next work is queued behind it.  This slot is not
-  // written again before a later wait on this stream has passed the combination.
-  volatile double* ys = h->hmap + kYOff;
-  for (int i = 0; i < k; ++i) ys[i] = y[i];
-  std::atomic_thread_fence(std::memory_order_seq_cst);
-  kr_lincomb(h->V, n, k, h->hmap_dev + kYOff, x, n, h->st);
+  // y = R^-1 g on the device, then x = V y; both are left to the stream, so the caller's next work
+  // queues behind them
+  kr_gmres_y(h->gm, mx, h->st);
+  kr_lincomb(h->V, n, k, kr_gmres_ydev(h->gm, mx), x, n, h->st);
   *iters = k;
   *relres = res;
   return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;

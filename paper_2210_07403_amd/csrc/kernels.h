@@ -178,6 +178,21 @@ struct SpreadArgs {
 template <typename T> void grid_fill_zero(T* y, int64_t n, hipStream_t st);
 template <typename T> void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st);
 template <typename T> void weight_table(const double* wt, int64_t n_ib, cplx<T>* tab, hipStream_t st);
+// One grid group of a batch for the single-launch spread: its arguments (q is replaced by
+// qbase + qoff at run time), weight table, output fields (of the grid type) and 2-D tile width.
+struct SpreadGroup {
+  SpreadArgs a;
+  const void* wtab;
+  void* out;
+  int64_t qoff;
+  int tx;
+};
+// The FD divergence spread (one field, 2-D, 4-point kernels) of several groups in one persistent
+// launch of nblocks workgroups (0: one per item) over the work list items[k] = (group, busy-tile
+// index), workgroup b taking items b, b + nblocks, ...
+template <typename T>
+void spread2_queue(const SpreadGroup* gd, const int2* items, int nitems, const double* qbase, int nblocks,
+                   hipStream_t st);
 
 struct InterpArgs {
   MarkerGeom g;
@@ -194,6 +209,18 @@ struct InterpArgs {
   const int* pid;      // batch: marker i reads fields at u + pid[i] * nf * (grid points); or null
 };
 template <typename T> void interp(const InterpArgs& a, const cplx<T>* wtab, const T* u, double* out, hipStream_t st);
+// One grid group of a batch for the single-launch interpolation: arguments (a.pid set), weight table,
+// fields, and the index m0 of its first marker in the concatenation.
+struct InterpGroup {
+  InterpArgs a;
+  const void* wtab;
+  const void* u;
+  int64_t m0;
+};
+// out[i] = a S*u + b x[i] for the ntot_m markers of ng groups (2-D, 4-point kernels, one field),
+// x = xbase (may be null); gd: device array of ng groups in marker order.
+template <typename T>
+void interp4_groups(const InterpGroup* gd, int ng, int64_t ntot_m, const double* xbase, double* out, hipStream_t st);
 // Transpose of the SP_FDDIV spread (4-point kernels): y_i = -h^-D ds_i sum_y w(y) [sum_d n_id G_d W W
 // + eta W W W] + b p_i + eta ds_i pu, with p = a.x and b = a.b (p, pu may be null); one field w.
 template <typename T>
@@ -250,18 +277,33 @@ int kr_arnoldi_nblk(int64_t n);
 // written last, after a system-scope fence
 void kr_publish(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
                 unsigned* host_tag, unsigned seq, hipStream_t st);
-// kr_publish of the Arnoldi values (norm partials reduced, src copied to the host slot, tag
-// written) and, in the same launch, dst (and dst2 if set) = w / |w| over nv entries (0 where the
-// norm is 0 or not finite), every workgroup reducing the partials itself in the same order.
-void kr_publish_scale(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
-                      unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2, int64_t nv,
-                      hipStream_t st);
-// kr_arnoldi_step and kr_publish_scale in one workgroup and one launch for n <= kSmallN: h[j],
-// h[256 + j] and w as kr_arnoldi_step leaves them, h[norm_at] = |w|^2, h[0..nsrc) copied to the host
-// slot, the tag, and dst (dst2) = w / |w| (deterministic; its sums group the entries differently)
+// GMRES least-squares state in device memory (kr_gmres_state_doubles(mx) doubles for at most mx
+// steps): scalars GM_BETA (|b|), GM_RES (Krylov residual estimate / |b|), GM_K (steps the solution
+// uses), GM_DONE (1 once res <= tol or the process broke down: later steps leave the state alone),
+// GM_HN (|w| of the last step), then the rotations, the rotated right-hand side, the solution y and
+// the rotated Hessenberg columns.  The first GM_PUB scalars are what a step publishes to the host.
+enum { GM_BETA = 0, GM_RES = 1, GM_K = 2, GM_DONE = 3, GM_HN = 4, GM_PUB = 5, GM_HDR = 16 };
+// the Arnoldi scratch h holds the first Gram-Schmidt pass at [0, 256), the second at [256, 512),
+// |w|^2 at 512 and |b|^2 at GM_BNORM2_AT
+constexpr int GM_BNORM2_AT = 520;
+size_t kr_gmres_state_doubles(int mx);
+// End of Arnoldi step j (w orthogonalised by kr_arnoldi_step, its norm partials at pnorm): h[norm_at]
+// = |w|^2, the least-squares update of step j in gs (tolerance tol, at most mx <= 256 steps), the
+// state's first GM_PUB scalars copied to the host slot, the tag; and, in the same launch, dst (and
+// dst2 if set) = w / |w| over nv entries (0 where the norm is 0 or not finite), every workgroup
+// reducing the partials itself in the same order.
+void kr_publish_scale(double* h, const double* pnorm, int nblk, int norm_at, double* gs, int j, int mx, double tol,
+                      double* host_dst, unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2,
+                      int64_t nv, hipStream_t st);
+// kr_arnoldi_step and kr_publish_scale in one workgroup and one launch for n <= kSmallN (step k - 1,
+// k basis vectors); deterministic, its sums group the entries differently from the blocked path
 constexpr int kSmallN = 256;
-void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n, double* h, int nsrc, int norm_at,
-                      double* host_dst, unsigned* host_tag, unsigned seq, double* dst, double* dst2, hipStream_t st);
+void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n, double* h, int norm_at, double* gs,
+                      int mx, double tol, double* host_dst, unsigned* host_tag, unsigned seq, double* dst,
+                      double* dst2, hipStream_t st);
+// y = R^-1 g of the state's GM_K steps, in device memory at kr_gmres_ydev(gs, mx)
+void kr_gmres_y(double* gs, int mx, hipStream_t st);
+const double* kr_gmres_ydev(double* gs, int mx);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product
@@ -283,6 +325,27 @@ void kb_gemv_sub(const double* V, int64_t ldv, int k, const double* H, int hs, c
 void kb_lincomb(const double* V, int64_t ldv, int k, const double* Y, int ys, const KrylovSegments& sg, double* x,
                 hipStream_t st);
 void kb_scale(const double* src, const double* sc, const KrylovSegments& sg, double* dst, hipStream_t st);
+// Batched GMRES on the device, one workgroup per problem; off[p], len[p] (device) locate problem p's
+// segment of the batch vectors, bn2[p] = |b_p|^2, gsb + p * gstride its least-squares state
+// (kr_gmres_state_doubles(mx) doubles each).
+// Copy every problem's own array ptr[p] (device array of np device pointers) into its segment of a
+// batch vector (to_batch) or back, in one launch; maxlen: the largest len[p].
+void kb_seg_copy(const double* const* ptr, const int64_t* off, const int64_t* len, int np, int64_t maxlen,
+                 double* base, bool to_batch, hipStream_t st);
+// V[0] (and xin) = b / |b| per problem.
+void kb_gmres_start(const double* b, const int64_t* off, const int64_t* len, int np, const double* bn2, double* v0,
+                    double* xin, hipStream_t st);
+// Arnoldi step j of every problem (w = A V_j): CGS2, |w|, the least-squares update, then vnext (and
+// xin) = w / |w|; problems already converged write zeros and keep their state.
+// maxlen: the largest len[p] (problems of at most 4096 unknowns keep w in registers).
+void kb_arnoldi(const double* V, int64_t ldv, int j, double* w, const int64_t* off, const int64_t* len, int np,
+                int64_t maxlen, const double* bn2, double* gsb, int64_t gstride, int mx, double tol, double* vnext,
+                double* xin, hipStream_t st);
+// every problem's first GM_PUB state scalars to the host slot ([np][GM_PUB]), then the tag
+void kb_publish(const double* gsb, int64_t gstride, int np, double* host_dst, unsigned* host_tag, unsigned seq,
+                hipStream_t st);
+// Y[p][0..kmax) = the least-squares solution of problem p (zeros beyond its step count)
+void kb_gmres_y(double* gsb, int64_t gstride, int np, int mx, int kmax, double* Y, int ys, hipStream_t st);
 
 // ------------------------------------------------------------------ near-boundary tools (2-D)
 struct NearGeom {

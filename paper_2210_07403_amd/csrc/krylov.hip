@@ -1,6 +1,8 @@
 // Double-precision Krylov vector kernels (GMRES Arnoldi with classical Gram-Schmidt twice).
 // Reductions are two-level with a fixed order (per-block partial sums, then one pass over the
 // partials), so every dot product is deterministic.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace ibdl {
@@ -325,6 +327,113 @@ __global__ void k_bscale(const double* __restrict__ src, const double* __restric
     dst[e] = src[e] * sc[seg[e]];
 }
 
+// ------------------------------------------------------------------ GMRES least squares
+// The Givens-rotated Hessenberg matrix R, the rotations and the rotated right-hand side g of one
+// GMRES solve live in device memory (layout gm_* below), so the least-squares problem is updated
+// and solved on the device in double precision.  Step j's column is h1[i] + h2[i] (i <= j, the two
+// Gram-Schmidt passes) and |w| below it; the rotations of the earlier steps are applied to it, the
+// new rotation zeroes |w|, g is rotated, and res = |g[j+1]| / |b| is the Krylov residual estimate.
+// Once res <= tol or the Arnoldi process breaks down the state is frozen: steps queued after that
+// change nothing, and k stays the number of steps the solution uses.
+__device__ __forceinline__ double* gm_cs(double* gs) { return gs + GM_HDR; }
+__device__ __forceinline__ double* gm_sn(double* gs, int mx) { return gs + GM_HDR + mx; }
+__device__ __forceinline__ double* gm_g(double* gs, int mx) { return gs + GM_HDR + 2 * mx; }
+__device__ __forceinline__ double* gm_y(double* gs, int mx) { return gs + GM_HDR + 3 * mx + 1; }
+__device__ __forceinline__ double* gm_R(double* gs, int mx) { return gs + GM_HDR + 4 * mx + 2; }
+
+// Run by a whole workgroup of kB threads (the sequential rotation sweep by thread 0 on values staged
+// in LDS).  bnorm2 = |b|^2 (read at step 0), nrm2 = |w|^2 of this step.
+__device__ void givens_step(const double* __restrict__ h1, const double* __restrict__ h2, double nrm2,
+                            double bnorm2, int j, int mx, double tol, double* gs) {
+  __shared__ double col[257], c_s[256], s_s[256];
+  __shared__ int frozen;
+  if (threadIdx.x == 0) frozen = j > 0 && gs[GM_DONE] != 0.0;
+  __syncthreads();
+  if (frozen) return;
+  const double* cs = gm_cs(gs);
+  const double* sn = gm_sn(gs, mx);
+  for (int i = threadIdx.x; i <= j; i += kB) {
+    col[i] = h1[i] + h2[i];
+    if (i < j) {
+      c_s[i] = cs[i];
+      s_s[i] = sn[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* g = gm_g(gs, mx);
+    double beta;
+    if (j == 0) {
+      beta = sqrt(bnorm2 > 0.0 ? bnorm2 : 0.0);
+      gs[GM_BETA] = beta;
+      g[0] = beta;
+    } else {
+      beta = gs[GM_BETA];
+    }
+    const double hn = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = c_s[i] * col[i] + s_s[i] * col[i + 1];
+      col[i + 1] = -s_s[i] * col[i] + c_s[i] * col[i + 1];
+      col[i] = t;
+    }
+    double res = 0.0;
+    bool stop = true;
+    if (beta > 0.0) {
+      const double r = hypot(col[j], col[j + 1]);
+      const double c = col[j] / r, sv = col[j + 1] / r;
+      gm_cs(gs)[j] = c;
+      gm_sn(gs, mx)[j] = sv;
+      col[j] = r;
+      g[j + 1] = -sv * g[j];
+      g[j] = c * g[j];
+      res = fabs(g[j + 1]) / beta;
+      const bool breakdown = !(hn > 1e-300 * beta);
+      stop = res <= tol || breakdown || !(res == res);
+      gs[GM_K] = (double)(j + 1);
+    } else {
+      gs[GM_K] = 0.0;
+    }
+    gs[GM_RES] = res;
+    gs[GM_HN] = hn;
+    gs[GM_DONE] = stop ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double* R = gm_R(gs, mx) + (int64_t)j * (mx + 1);
+  for (int i = threadIdx.x; i <= j; i += kB) R[i] = col[i];
+}
+
+// The least-squares solution y = R^-1 g of the k = gs[GM_K] steps, by one workgroup: with k <= 64
+// the triangle is staged in LDS once, otherwise each column is read as the substitution reaches it.
+__global__ __launch_bounds__(kB) void k_gmres_y(double* gs, int mx) {
+  __shared__ double tri[64 * 64];
+  __shared__ double gv[256];
+  __shared__ double yv;
+  const int k = (int)gs[GM_K];
+  const double* R = gm_R(gs, mx);
+  const double* g = gm_g(gs, mx);
+  for (int i = threadIdx.x; i < k; i += kB) gv[i] = g[i];
+  const bool staged = k <= 64;
+  if (staged)
+    for (int e = threadIdx.x; e < k * k; e += kB) {
+      const int c = e / k, i = e - c * k;
+      tri[c * 64 + i] = i <= c ? R[(int64_t)c * (mx + 1) + i] : 0.0;
+    }
+  __syncthreads();
+  double* y = gm_y(gs, mx);
+  for (int c = k - 1; c >= 0; --c) {
+    const double* rc = staged ? tri + c * 64 : R + (int64_t)c * (mx + 1);
+    if (threadIdx.x == 0) {
+      yv = gv[c] / rc[c];
+      y[c] = yv;
+    }
+    __syncthreads();
+    const double v = yv;
+    for (int i = threadIdx.x; i < c; i += kB) gv[i] -= rc[i] * v;
+    __syncthreads();
+  }
+}
+
 // Copy n doubles into host-mapped memory, then (after a system-scope fence) the sequence tag, so a
 // host that sees the tag sees the values.
 // With pnorm set, src[norm_at] is first set to the sum of pnorm[0..nblk) (as k_arnoldi reduces).
@@ -345,13 +454,15 @@ __global__ __launch_bounds__(kB) void k_publish(double* src, int n, const double
   }
 }
 
-// k_publish and, in the same launch, the normalisation of w into the next basis vector: every
-// workgroup reduces the norm partials itself (in the same order, so with the same bits) and
-// scales its part of w into vdst (and vdst2) by 1/|w|, or by 0 where |w| is 0 or not finite;
-// workgroup 0 also stores |w|^2 at src[norm_at], copies src to the host slot and writes the tag.
-__global__ __launch_bounds__(kB) void k_publish_scale(double* src, int n, const double* __restrict__ pnorm, int nblk,
-                                                      int norm_at, double* dst, unsigned* tag, unsigned seq,
-                                                      const double* w, double* vdst, double* vdst2, int64_t nv) {
+// The end of an Arnoldi step in one launch: every workgroup reduces the norm partials itself (in the
+// same order, so with the same bits) and scales its part of w into vdst (and vdst2) by 1/|w|, or by
+// 0 where |w| is 0 or not finite; workgroup 0 also stores |w|^2 at h[norm_at], runs the step's
+// least-squares update (givens_step) and copies the state's scalars (GM_PUB of them) to the host
+// slot, then writes the tag.
+__global__ __launch_bounds__(kB) void k_publish_scale(double* h, const double* __restrict__ pnorm, int nblk,
+                                                      int norm_at, double* gs, int j, int mx, double tol, double* dst,
+                                                      unsigned* tag, unsigned seq, const double* w, double* vdst,
+                                                      double* vdst2, int64_t nv) {
   __shared__ double nrm2;
   if (threadIdx.x < 64) {
     const double v = wave_sum(pnorm, nblk, threadIdx.x);
@@ -360,17 +471,18 @@ __global__ __launch_bounds__(kB) void k_publish_scale(double* src, int n, const 
   __syncthreads();
   const double v = nrm2;
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) src[norm_at] = v;
+    if (threadIdx.x == 0) h[norm_at] = v;
+    givens_step(h, h + 256, v, h[GM_BNORM2_AT], j, mx, tol, gs);
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kB) dst[i] = src[i];
+    if (threadIdx.x < GM_PUB) dst[threadIdx.x] = gs[threadIdx.x];
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence_system();
       *reinterpret_cast<volatile unsigned*>(tag) = seq;
     }
   }
-  const double h = sqrt(v > 0.0 ? v : 0.0);
-  const double sc = (h > 0.0 && h < INFINITY) ? 1.0 / h : 0.0;
+  const double hh = sqrt(v > 0.0 ? v : 0.0);
+  const double sc = (hh > 0.0 && hh < INFINITY) ? 1.0 / hh : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv; e += (int64_t)gridDim.x * blockDim.x) {
     const double x = w[e] * sc;
     vdst[e] = x;
@@ -399,8 +511,9 @@ __device__ __forceinline__ void wg_sum8(double (&v)[kArnGroup], double (*lds)[kA
 }
 
 __global__ __launch_bounds__(kB) void k_arnoldi_small(const double* __restrict__ V, int64_t ldv, int k, double* w,
-                                                      int64_t n, double* h, int nsrc, int norm_at, double* dst,
-                                                      unsigned* tag, unsigned seq, double* vdst, double* vdst2) {
+                                                      int64_t n, double* h, int norm_at, double* gs, int mx,
+                                                      double tol, double* dst, unsigned* tag, unsigned seq,
+                                                      double* vdst, double* vdst2) {
   __shared__ double lds[4][kArnGroup];
   __shared__ double hs[256];
   const int e = threadIdx.x;
@@ -426,13 +539,16 @@ __global__ __launch_bounds__(kB) void k_arnoldi_small(const double* __restrict__
     }
     __syncthreads();
   }
-  // |w|^2, the publication (values, then the tag after a system-scope fence), w / |w|
+  // |w|^2, the least-squares update, the publication (values, then the tag after a system-scope
+  // fence), w / |w|
   double sq[kArnGroup] = {we * we, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   wg_sum8(sq, lds);
   const double v = sq[0];
   if (threadIdx.x == 0) h[norm_at] = v;
   __syncthreads();
-  for (int i = threadIdx.x; i < nsrc; i += kB) dst[i] = h[i];
+  givens_step(h, h + 256, v, h[GM_BNORM2_AT], k - 1, mx, tol, gs);
+  __syncthreads();
+  if (threadIdx.x < GM_PUB) dst[threadIdx.x] = gs[threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence_system();
@@ -447,6 +563,260 @@ __global__ __launch_bounds__(kB) void k_arnoldi_small(const double* __restrict__
   }
 }
 
+// ------------------------------------------------------------------ batched GMRES on the device
+// One workgroup per problem does a whole Arnoldi step of its problem: both classical Gram-Schmidt
+// passes over its segment [off[p], off[p] + len[p]) of the batch vectors (dot products eight at a
+// time, each a fixed tree over the workgroup), |w|^2, the least-squares update of its own state
+// gs + p * gstride (givens_step), and the normalisation of w into the next basis vector and the
+// apply's input xin.  A problem whose state was already frozen writes zeros there (its later
+// applies run on zeros) and changes nothing else.  The step number j comes from the host.
+__device__ __forceinline__ double wg_tree(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kB) void k_batch_arnoldi(const double* __restrict__ V, int64_t ldv, int j,
+                                                      double* __restrict__ w, const int64_t* __restrict__ off,
+                                                      const int64_t* __restrict__ len, const double* __restrict__ bn2,
+                                                      double* gsb, int64_t gstride, int mx, double tol,
+                                                      double* __restrict__ vnext, double* __restrict__ xin) {
+  __shared__ double red[kArnGroup][kB];
+  __shared__ double hv[2][256];
+  __shared__ int frozen;
+  const int p = blockIdx.x;
+  const int64_t beg = off[p], n = len[p];
+  double* gs = gsb + (int64_t)p * gstride;
+  if (threadIdx.x == 0) frozen = j > 0 && gs[GM_DONE] != 0.0;
+  __syncthreads();
+  if (frozen) {
+    for (int64_t e = threadIdx.x; e < n; e += kB) {
+      vnext[beg + e] = 0.0;
+      if (xin) xin[beg + e] = 0.0;
+    }
+    return;
+  }
+  const int k = j + 1;
+  double* wp = w + beg;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int d0 = 0; d0 < k; d0 += kArnGroup) {
+      double acc[kArnGroup];
+#pragma unroll
+      for (int g = 0; g < kArnGroup; ++g) acc[g] = 0.0;
+      for (int64_t e = threadIdx.x; e < n; e += kB) {
+        const double we = wp[e];
+#pragma unroll
+        for (int g = 0; g < kArnGroup; ++g)
+          if (d0 + g < k) acc[g] += V[(int64_t)(d0 + g) * ldv + beg + e] * we;
+      }
+#pragma unroll
+      for (int g = 0; g < kArnGroup; ++g) red[g][threadIdx.x] = acc[g];
+      __syncthreads();
+      for (int st = kB / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+#pragma unroll
+          for (int g = 0; g < kArnGroup; ++g) red[g][threadIdx.x] += red[g][threadIdx.x + st];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x < kArnGroup && d0 + threadIdx.x < k) hv[pass][d0 + threadIdx.x] = red[threadIdx.x][0];
+      __syncthreads();
+    }
+    for (int64_t e = threadIdx.x; e < n; e += kB) {
+      double we = wp[e];
+      for (int i = 0; i < k; ++i) we -= V[(int64_t)i * ldv + beg + e] * hv[pass][i];
+      wp[e] = we;
+    }
+    __syncthreads();
+  }
+  double sq = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += kB) sq += wp[e] * wp[e];
+  const double nrm2 = wg_tree(sq, &red[0][0]);
+  givens_step(hv[0], hv[1], nrm2, bn2[p], j, mx, tol, gs);
+  __syncthreads();
+  const double hn = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+  const double beta = gs[GM_BETA];
+  const double sc = (hn > 1e-300 * beta && hn < INFINITY) ? 1.0 / hn : 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += kB) {
+    const double x = wp[e] * sc;
+    vnext[beg + e] = x;
+    if (xin) xin[beg + e] = x;
+  }
+}
+
+// The same step for problems of at most 1024 R unknowns with 1024 threads per problem, each thread
+// keeping its R entries of w in registers: dot products eight at a time, a butterfly in each wave
+// and then the sixteen waves' sums in order (deterministic; grouped differently from the 256-thread
+// form above).  (Keeping the first eight basis vectors in registers as well, to read them once per
+// step, needs more than the 128 registers a thread has at this workgroup size: it spilled.)
+template <int R>
+__global__ __launch_bounds__(1024) void k_batch_arnoldi_r(const double* __restrict__ V, int64_t ldv, int j,
+                                                          double* __restrict__ w, const int64_t* __restrict__ off,
+                                                          const int64_t* __restrict__ len,
+                                                          const double* __restrict__ bn2, double* gsb, int64_t gstride,
+                                                          int mx, double tol, double* __restrict__ vnext,
+                                                          double* __restrict__ xin) {
+  constexpr int NT = 1024, NW = NT / 64;
+  __shared__ double part[NW][kArnGroup];
+  __shared__ double hv[2][256];
+  __shared__ int frozen;
+  const int p = blockIdx.x;
+  const int64_t beg = off[p], n = len[p];
+  double* gs = gsb + (int64_t)p * gstride;
+  if (threadIdx.x == 0) frozen = j > 0 && gs[GM_DONE] != 0.0;
+  __syncthreads();
+  if (frozen) {
+    for (int64_t e = threadIdx.x; e < n; e += NT) {
+      vnext[beg + e] = 0.0;
+      if (xin) xin[beg + e] = 0.0;
+    }
+    return;
+  }
+  const int k = j + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* vb = V + beg;
+  double we[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t e = threadIdx.x + (int64_t)r * NT;
+    we[r] = e < n ? w[beg + e] : 0.0;
+  }
+  auto block_sum8 = [&](double (&v)[kArnGroup]) {
+#pragma unroll
+    for (int g = 0; g < kArnGroup; ++g)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v[g] += __shfl_xor(v[g], o);
+    if (lane == 0)
+#pragma unroll
+      for (int g = 0; g < kArnGroup; ++g) part[wave][g] = v[g];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < kArnGroup; ++g) {
+      double t = part[0][g];
+      for (int q = 1; q < NW; ++q) t += part[q][g];
+      v[g] = t;
+    }
+    __syncthreads();
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int d0 = 0; d0 < k; d0 += kArnGroup) {
+      double acc[kArnGroup];
+#pragma unroll
+      for (int g = 0; g < kArnGroup; ++g) {
+        acc[g] = 0.0;
+        if (d0 + g < k)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int64_t e = threadIdx.x + (int64_t)r * NT;
+            if (e < n) acc[g] += vb[(int64_t)(d0 + g) * ldv + e] * we[r];
+          }
+      }
+      block_sum8(acc);
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int g = 0; g < kArnGroup; ++g)
+          if (d0 + g < k) hv[pass][d0 + g] = acc[g];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t e = threadIdx.x + (int64_t)r * NT;
+      double x = we[r];
+      if (e < n)
+        for (int i = 0; i < k; ++i) x -= vb[(int64_t)i * ldv + e] * hv[pass][i];
+      we[r] = e < n ? x : 0.0;
+    }
+  }
+  double sq[kArnGroup] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < R; ++r) sq[0] += we[r] * we[r];
+  block_sum8(sq);
+  const double nrm2 = sq[0];
+  givens_step(hv[0], hv[1], nrm2, bn2[p], j, mx, tol, gs);
+  __syncthreads();
+  const double hn = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+  const double beta = gs[GM_BETA];
+  const double sc = (hn > 1e-300 * beta && hn < INFINITY) ? 1.0 / hn : 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t e = threadIdx.x + (int64_t)r * NT;
+    if (e < n) {
+      const double x = we[r] * sc;
+      vnext[beg + e] = x;
+      if (xin) xin[beg + e] = x;
+    }
+  }
+}
+
+// Problem p's segment of a batch vector to or from its own array: to_batch: base[off[p] + e] =
+// ptr[p][e]; otherwise ptr[p][e] = base[off[p] + e] (one launch for every problem).
+__global__ void k_seg_copy(const double* const* __restrict__ ptr, const int64_t* __restrict__ off,
+                           const int64_t* __restrict__ len, double* __restrict__ base, int to_batch) {
+  const int p = blockIdx.y;
+  const int64_t n = len[p];
+  double* seg = base + off[p];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    if (to_batch) seg[e] = ptr[p][e];
+    else const_cast<double*>(ptr[p])[e] = seg[e];
+  }
+}
+
+// V[0] segment of problem p = b / |b| (0 when |b| is 0 or not finite), also into xin
+__global__ void k_batch_start(const double* __restrict__ b, const int64_t* __restrict__ off,
+                              const int64_t* __restrict__ len, const double* __restrict__ bn2,
+                              double* __restrict__ v0, double* __restrict__ xin) {
+  const int p = blockIdx.x;
+  const double nb = sqrt(bn2[p] > 0.0 ? bn2[p] : 0.0);
+  const double sc = (nb > 0.0 && nb < INFINITY) ? 1.0 / nb : 0.0;
+  for (int64_t e = threadIdx.x; e < len[p]; e += blockDim.x) {
+    const double x = b[off[p] + e] * sc;
+    v0[off[p] + e] = x;
+    if (xin) xin[off[p] + e] = x;
+  }
+}
+
+// The first GM_PUB scalars of every problem's state to the host slot, then the tag
+__global__ __launch_bounds__(kB) void k_batch_publish(const double* gsb, int64_t gstride, int np, double* dst,
+                                                      unsigned* tag, unsigned seq) {
+  for (int i = threadIdx.x; i < np * GM_PUB; i += kB) dst[i] = gsb[(int64_t)(i / GM_PUB) * gstride + i % GM_PUB];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned*>(tag) = seq;
+  }
+}
+
+// Per problem: y = R^-1 g of its GM_K steps into Y[p][0..kmax) (zeros beyond its own count)
+__global__ __launch_bounds__(kB) void k_batch_y(double* gsb, int64_t gstride, int mx, int kmax, double* Y, int ys) {
+  __shared__ double gv[256];
+  __shared__ double yv;
+  double* gs = gsb + (int64_t)blockIdx.x * gstride;
+  const int k = (int)gs[GM_K];
+  const double* R = gm_R(gs, mx);
+  const double* g = gm_g(gs, mx);
+  double* y = Y + (int64_t)blockIdx.x * ys;
+  for (int i = threadIdx.x; i < k; i += kB) gv[i] = g[i];
+  for (int i = k + threadIdx.x; i < kmax; i += kB) y[i] = 0.0;
+  __syncthreads();
+  for (int c = k - 1; c >= 0; --c) {
+    const double* rc = R + (int64_t)c * (mx + 1);
+    if (threadIdx.x == 0) {
+      yv = gv[c] / rc[c];
+      y[c] = yv;
+    }
+    __syncthreads();
+    const double v = yv;
+    for (int i = threadIdx.x; i < c; i += kB) gv[i] -= rc[i] * v;
+    __syncthreads();
+  }
+}
+
 inline unsigned blocks_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
@@ -454,21 +824,32 @@ inline unsigned blocks_for(int64_t n) {
 
 }  // namespace
 
-void kr_publish_scale(double* src, int n, const double* pnorm, int nblk, int norm_at, double* host_dst,
-                      unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2, int64_t nv,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_publish_scale, dim3(blocks_for(nv)), dim3(kB), 0, st, src, n, pnorm, nblk, norm_at, host_dst,
-                     host_tag, seq, w, dst, dst2, nv);
+void kr_publish_scale(double* h, const double* pnorm, int nblk, int norm_at, double* gs, int j, int mx, double tol,
+                      double* host_dst, unsigned* host_tag, unsigned seq, const double* w, double* dst, double* dst2,
+                      int64_t nv, hipStream_t st) {
+  if (j < 0 || j >= mx || mx > 256) throw Error(-2, "kr_publish_scale: 0 <= j < mx <= 256");
+  hipLaunchKernelGGL(k_publish_scale, dim3(blocks_for(nv)), dim3(kB), 0, st, h, pnorm, nblk, norm_at, gs, j, mx, tol,
+                     host_dst, host_tag, seq, w, dst, dst2, nv);
   IBDL_LAUNCH_CHECK();
 }
 
-void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n, double* h, int nsrc, int norm_at,
-                      double* host_dst, unsigned* host_tag, unsigned seq, double* dst, double* dst2, hipStream_t st) {
-  if (n > kSmallN || k < 1 || k > 256) throw Error(-2, "kr_arnoldi_small: n <= kSmallN and 1 <= k <= 256");
-  hipLaunchKernelGGL(k_arnoldi_small, dim3(1), dim3(kB), 0, st, V, ldv, k, w, n, h, nsrc, norm_at, host_dst, host_tag,
-                     seq, dst, dst2);
+void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n, double* h, int norm_at, double* gs,
+                      int mx, double tol, double* host_dst, unsigned* host_tag, unsigned seq, double* dst,
+                      double* dst2, hipStream_t st) {
+  if (n > kSmallN || k < 1 || k > mx || mx > 256) throw Error(-2, "kr_arnoldi_small: n <= kSmallN and 1 <= k <= mx <= 256");
+  hipLaunchKernelGGL(k_arnoldi_small, dim3(1), dim3(kB), 0, st, V, ldv, k, w, n, h, norm_at, gs, mx, tol, host_dst,
+                     host_tag, seq, dst, dst2);
   IBDL_LAUNCH_CHECK();
 }
+
+size_t kr_gmres_state_doubles(int mx) { return (size_t)GM_HDR + 4 * (size_t)mx + 2 + (size_t)mx * (mx + 1); }
+
+void kr_gmres_y(double* gs, int mx, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_y, dim3(1), dim3(kB), 0, st, gs, mx);
+  IBDL_LAUNCH_CHECK();
+}
+
+const double* kr_gmres_ydev(double* gs, int mx) { return gs + GM_HDR + 3 * mx + 1; }
 
 int kr_nblk(int64_t n) { return (int)((n + kElemsPerBlock - 1) / kElemsPerBlock) > 0 ? (int)((n + kElemsPerBlock - 1) / kElemsPerBlock) : 1; }
 
@@ -564,6 +945,49 @@ void kb_lincomb(const double* V, int64_t ldv, int k, const double* Y, int ys, co
 
 void kb_scale(const double* src, const double* sc, const KrylovSegments& sg, double* dst, hipStream_t st) {
   hipLaunchKernelGGL(k_bscale, dim3(blocks_for(sg.n)), dim3(256), 0, st, src, sc, sg.seg, dst, sg.n);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_seg_copy(const double* const* ptr, const int64_t* off, const int64_t* len, int np, int64_t maxlen,
+                 double* base, bool to_batch, hipStream_t st) {
+  const unsigned bx = (unsigned)std::min<int64_t>((maxlen + 255) / 256, 64);
+  hipLaunchKernelGGL(k_seg_copy, dim3(bx > 0 ? bx : 1, np), dim3(256), 0, st, ptr, off, len, base, to_batch ? 1 : 0);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_gmres_start(const double* b, const int64_t* off, const int64_t* len, int np, const double* bn2, double* v0,
+                    double* xin, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_start, dim3(np), dim3(256), 0, st, b, off, len, bn2, v0, xin);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_arnoldi(const double* V, int64_t ldv, int j, double* w, const int64_t* off, const int64_t* len, int np,
+                int64_t maxlen, const double* bn2, double* gsb, int64_t gstride, int mx, double tol, double* vnext,
+                double* xin, hipStream_t st) {
+  if (j < 0 || j >= mx || mx > 256) throw Error(-2, "kb_arnoldi: 0 <= j < mx <= 256");
+  if (maxlen <= 1024)
+    hipLaunchKernelGGL(k_batch_arnoldi_r<1>, dim3(np), dim3(1024), 0, st, V, ldv, j, w, off, len, bn2, gsb, gstride,
+                       mx, tol, vnext, xin);
+  else if (maxlen <= 2048)
+    hipLaunchKernelGGL(k_batch_arnoldi_r<2>, dim3(np), dim3(1024), 0, st, V, ldv, j, w, off, len, bn2, gsb, gstride,
+                       mx, tol, vnext, xin);
+  else if (maxlen <= 4096)
+    hipLaunchKernelGGL(k_batch_arnoldi_r<4>, dim3(np), dim3(1024), 0, st, V, ldv, j, w, off, len, bn2, gsb, gstride,
+                       mx, tol, vnext, xin);
+  else
+    hipLaunchKernelGGL(k_batch_arnoldi, dim3(np), dim3(kB), 0, st, V, ldv, j, w, off, len, bn2, gsb, gstride, mx, tol,
+                       vnext, xin);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_publish(const double* gsb, int64_t gstride, int np, double* host_dst, unsigned* host_tag, unsigned seq,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_publish, dim3(1), dim3(kB), 0, st, gsb, gstride, np, host_dst, host_tag, seq);
+  IBDL_LAUNCH_CHECK();
+}
+
+void kb_gmres_y(double* gsb, int64_t gstride, int np, int mx, int kmax, double* Y, int ys, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_y, dim3(np), dim3(kB), 0, st, gsb, gstride, mx, kmax, Y, ys);
   IBDL_LAUNCH_CHECK();
 }
 

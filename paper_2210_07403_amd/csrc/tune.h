@@ -1,4 +1,5 @@
-// Launch shapes of the FFT passes chosen by timing, remembered for the life of the process.
+// Launch shapes of the FFT passes and tile widths of the batched 2-D spread, chosen by timing;
+// remembered for the life of the process and in a JSON file per kind of GPU (tune.hip).
 #pragma once
 
 #include <array>
@@ -9,6 +10,8 @@ struct LaunchShape {
   int rpb = 0;   // rows per block of the x passes (0: the largest that fits)
   int wy = 0;    // lines per block of the strided y passes
   int wz = 0;    // lines per block of the fused last-axis pass
+  int tile = 0;  // 2-D spread tile width along x (batches; 0: not chosen)
+  int blocks = 0;  // workgroups of the batched persistent spread (0: not chosen)
 };
 
 // (kind, dim, n0, n1, n2, bytes per value, fields, size bucket)

@@ -140,3 +140,41 @@ def test_batch_rejects_unsupported():
     s = P.brinkman_circle(16, 1.5)
     with pytest.raises(ibdl.IBDLError):
         ibdl.Batch([dict(_as_dict(s), pde="stokes")], precision="fp64")
+
+
+_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
+import paper_2210_07403_amd as ibdl
+from workloads import problems as P
+from test_gpu_batch import _as_dict
+specs = [P.ProblemSpec(**{**s.__dict__, "g": None}) for s in P.cfg4_batch(nprob=6, seed=3, sizes=(64, 128))]
+bt = ibdl.Batch([_as_dict(s) for s in specs], precision="mixed")
+print(json.dumps(bt.groups()))
+"""
+
+
+def test_batch_tuning_persists_in_json_cache(tmp_path):
+    """The measured tile and launch shapes are written to the JSON file named by IBDL_TUNE_CACHE; a
+    second process reads them back and makes the same choices."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, IBDL_TUNE_CACHE=str(cache))
+    run = lambda: subprocess.run([sys.executable, "-c", _CHILD, root], env=env, capture_output=True, text=True,
+                                 timeout=240)
+    r1 = run()
+    assert r1.returncode == 0, r1.stderr[-2000:]
+    doc = json.loads(cache.read_text())
+    assert doc["format"] == "ibdl-tune-2" and doc["device"]
+    tiles = [e for e in doc["entries"] if e["key"][0] == 3]
+    assert len(tiles) == 2 and all(e["tile"] in (16, 32, 64) for e in tiles)
+    first = json.loads(r1.stdout.strip().splitlines()[-1])
+    before = cache.read_text()
+    r2 = run()
+    assert r2.returncode == 0, r2.stderr[-2000:]
+    assert json.loads(r2.stdout.strip().splitlines()[-1]) == first
+    assert cache.read_text() == before          # nothing measured again, nothing rewritten
