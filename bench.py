@@ -1,16 +1,19 @@
 #!/usr/bin/env python
-"""IBDL throughput on one MI355X: operator applies/s and GMRES solves/s at 1e-8, with the
-roofline of the dominant kernel and the FP64 CPU oracle timed on the host beside it.
+"""IBDL throughput on one MI355X: GMRES solves/s at a double-precision residual of 1e-8 and
+operator applies/s, with the roofline of the apply's dominant kernel and the FP64 CPU oracle
+timed on the host beside them.
 
-A step is one whole IBDL solve through the C ABI (ibdl_solve): right-hand side
-b = U_b - S* L^-1 g~, GMRES to ||b - A q|| / ||b|| <= 1e-8 (every iteration one operator apply:
-spread -> FFT passes with the fused multiplier -> interpolation), the double-precision true
-residual and the grid recovery u = L^-1 (g~ - S~ q).  Inputs are resident on the GPU before the
-timed region starts.
+A step is one whole IBDL solve through the C ABI on the 256^3 sphere workload with float grid
+work and double-precision Krylov vectors: ibdl_solve_refined, i.e. the right-hand side
+b = U_b - S* L^-1 g~ in double, GMRES on the float-applied operator (every iteration one operator
+apply: spread -> FFT passes with the fused multiplier -> interpolation; Arnoldi, Givens rotations
+and least squares in double on the device), double-precision residuals b - A q with corrections
+until ||b - A q|| / ||b|| <= 1e-8, and the grid recovery u = L^-1 (g~ - S~ q).  `value` is solves
+per second at that true residual.  Inputs are resident on the GPU before the timed region starts.
 
-Default workload: 3-D screened Poisson (kappa = 10) on a 256^3 periodic grid, sphere r = 0.3
-with 73,962 icosphere markers, Peskin 4-point kernel, finite differences, float grid work with
-double-precision Krylov (the mixed path).
+Beside it on the same JSON line: single operator applies, the stages' rates, the plain mixed and
+FP64 solves, every other workload of the method (the 64^2 circle, the 1024^2 star, the 512^2
+Stokes star with its gradient, the batch of 64) and the measurements beyond the hot path.
 """
 from __future__ import annotations
 
@@ -35,7 +38,7 @@ def workload(name):
     if name == "sphere256":
         return P.cfg3_sphere(256, 86), "mixed", (
             "3-D IBDL screened Poisson kappa=10, 256^3 periodic grid, sphere r=0.3, 73962 icosphere markers, "
-            "Peskin 4-point, FD2, float grid/spread/FFT + double GMRES, tol 1e-8")
+            "Peskin 4-point, FD2, float grid/spread/FFT + double GMRES and residuals, double-precision residual 1e-8")
     if name == "star1024":
         return P.cfg2_star_poisson(1024, 4096), "fp64", (
             "2-D IBDL Poisson Dirichlet, 1024^2 grid, star r=0.3(1+0.2cos5t), 4096 markers, Peskin 4-point, FD2, "
@@ -142,36 +145,20 @@ def _timed(fn, reps):
     return (time.perf_counter() - t0) / reps, out
 
 
-def measure_extras(spec, prec, pr, data, g, tol, mixed_relres, dev):
-    """The other rows of the path on this workload and the batched workload: FP64 at the accuracy
-    the mixed path reaches, the adjoint solve, and 64 problems batched vs one after another."""
+def measure_extras(spec, prec, pr, data, g, tol, dev):
+    """The other workloads of the method (the 64^2 circle, the 1024^2 star, the 512^2 Stokes star
+    with its gradient), the adjoint on this workload, 64 problems batched vs one after another,
+    and the measurements beyond the hot path."""
     import numpy as np
     import torch
     import paper_2210_07403_amd as ibdl
     from workloads import problems as P
     out = {}
     m = spec.markers
-    print("# extras: mixed vs FP64 at equal accuracy", file=sys.stderr, flush=True)
-    if prec == "mixed":
-        t_mix, (_, _, im) = _timed(lambda: pr.solve(data, g, tol=tol, maxit=100), 3)
-        p64 = ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, m.nrm, m.ds, pde=spec.pde, kappa=spec.kappa,
-                           mu=spec.mu, bc=spec.bc, eta=spec.eta, kernel=spec.kernel, disc=spec.disc,
-                           precision="fp64", device=dev)
-        g64 = g.double() if g is not None else None
-        tol64 = max(im.true_relres_fp64, 1e-14)
-        t64, (_, _, i64) = _timed(lambda: p64.solve(data, g64, tol=tol64, maxit=100), 3)
-        out["mixed_vs_fp64"] = {"mixed_ms": round(1e3 * t_mix, 3), "mixed_true_relres": im.true_relres_fp64,
-                                "mixed_iters": im.iters, "fp64_ms": round(1e3 * t64, 3),
-                                "fp64_true_relres": i64.true_relres_fp64, "fp64_iters": i64.iters,
-                                "fp64_tol": tol64, "speedup": round(t64 / t_mix, 3)}
-        # a double-precision true residual of 1e-8: refinement with float corrections vs FP64 GMRES
-        t_ir, (_, _, iir) = _timed(lambda: pr.solve_refined(data, g, tol=tol, maxit=100, inner_tol=1e-4), 3)
-        t64b, (_, _, i64b) = _timed(lambda: p64.solve(data, g64, tol=tol, maxit=100), 3)
-        out["refined_vs_fp64_at_1e-8"] = {"refined_ms": round(1e3 * t_ir, 3), "refined_true_relres": iir.true_relres_fp64,
-                                          "refined_inner_iters": iir.iters, "fp64_ms": round(1e3 * t64b, 3),
-                                          "fp64_true_relres": i64b.true_relres_fp64, "fp64_iters": i64b.iters,
-                                          "speedup": round(t64b / t_ir, 3)}
-        p64.close()
+    print("# extras: the 64^2 circle, the 1024^2 star, the 512^2 Stokes star", file=sys.stderr, flush=True)
+    out["cfg1_circle64"] = _cfg1_circle(dev)
+    out["cfg2_star1024"] = _cfg2_star(dev)
+    out["cfg5_stokes512"] = _cfg5_stokes(dev)
     print("# extras: adjoint", file=sys.stderr, flush=True)
     q, u, _ = pr.solve(data, g, tol=tol, maxit=100)
     psi = torch.randn(u.shape, dtype=u.dtype, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
@@ -417,31 +404,146 @@ def _near_boundary_timing(dev):
             "nodes_corrected": ncorr, "scan_TFLOP_s": round(8 * pairs / t_nb / 1e12, 3)}
 
 
-def cpu_baseline(spec, budget_s=20.0):
-    """Time the FP64 numpy oracle's operator apply on this host (bounded sample)."""
+def _problem(spec, prec, dev):
+    import paper_2210_07403_amd as ibdl
+    m = spec.markers
+    return ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, m.nrm, m.ds, pde=spec.pde, kappa=spec.kappa,
+                        mu=spec.mu, bc=spec.bc, eta=spec.eta, kernel=spec.kernel, disc=spec.disc, precision=prec,
+                        device=dev)
+
+
+def _cfg1_circle(dev):
+    """The 64^2 circle (cosine kernel, FP64, tol 1e-10): one solve in seconds, on the GPU and by
+    the oracle (right-hand side and textbook GMRES to the same tolerance)."""
     import numpy as np
     import oracle
+    from oracle.gmres import gmres
+    from workloads import problems as P
+    s = P.cfg1_circle_cos4()
+    pr = _problem(s, "fp64", dev)
+    g = pr._as_grid(s.g, 1)
+    pr.solve(s.data, g, tol=1e-10, maxit=100)
+    t, (_, _, info) = _timed(lambda: pr.solve(s.data, g, tol=1e-10, maxit=100), 20)
+    pr.close()
+    o = oracle.Setup.from_spec(s)
+
+    def osolve():
+        x, k, _ = gmres(o.apply, o.rhs(s.data, s.g), 1e-10, 100)
+        o.recover(x, s.data, s.g)
+        return k
+    t_o, _ = _per_call(osolve, 3, 10.0)
+    return {"workload": "2-D screened Poisson kappa=1, 64^2, circle r=0.25, 200 markers, cosine 4-point, FD2, FP64, "
+                        "tol 1e-10", "gpu_solve_s": round(t, 6), "iters": info.iters,
+            "true_relres": info.true_relres_fp64,
+            "cpu_baseline": {"oracle_solve_s": round(t_o, 4), "cores": 1, "kind": "oracle",
+                             "sample": "right-hand side, GMRES to 1e-10 and recovery, single-threaded numpy"}}
+
+
+def _cfg2_star(dev):
+    """The 1024^2 star (Poisson, 4096 markers, FD2), Dirichlet and Neumann: FP64 GMRES at 1e-8,
+    the mixed path at a Krylov residual of 1e-8, and refinement to a double-precision residual of
+    1e-8 (solves/s, iterations, true residual)."""
+    import numpy as np
+    import torch
+    from workloads import problems as P
+    out = {"workload": "2-D Poisson, 1024^2, star r=0.3(1+0.2cos5t), 4096 markers, Peskin 4-point, FD2, tol 1e-8"}
+    for bc in ("dirichlet", "neumann"):
+        s = P.cfg2_star_poisson(1024, 4096, bc=bc)
+        data = torch.as_tensor(np.asarray(s.data, dtype=np.float64), device=dev)
+        row = {}
+        for prec, kind in (("fp64", "solve"), ("mixed", "solve"), ("mixed", "refined")):
+            pr = _problem(s, prec, dev)
+            run = (lambda: pr.solve(data, None, tol=1e-8, maxit=150)) if kind == "solve" else \
+                (lambda: pr.solve_refined(data, None, tol=1e-8, maxit=150, inner_tol=1e-4))
+            run()
+            t, (_, _, info) = _timed(run, 10)
+            name = prec if kind == "solve" else "mixed_refined"
+            row[name] = {"solves_per_sec": round(1.0 / t, 1), "ms": round(1e3 * t, 4), "iters": info.iters,
+                         "true_relres": info.true_relres_fp64}
+            pr.close()
+        row["mixed_refined_vs_fp64_at_1e-8"] = round(row["fp64"]["ms"] / row["mixed_refined"]["ms"], 3)
+        out[bc] = row
+    return out
+
+
+def _cfg5_stokes(dev):
+    """The 512^2 exterior Stokes star (1024 markers, eta = 10, spectral, FP64): the forward solve at
+    1e-8 with the grid recovery, and the backward (adjoint GMRES and marker gradients) of
+    L = sum_x |w|^2 h^2."""
+    import numpy as np
+    import torch
+    from workloads import problems as P
+    s = P.cfg5_stokes_star(512, 1024)
+    pr = _problem(s, "fp64", dev)
+    data = torch.as_tensor(np.asarray(s.data, dtype=np.float64), device=dev)
+    h2 = (s.L[0] / s.n[0]) ** 2
+    q, w, _ = pr.solve(data, None, tol=1e-8, maxit=200)
+    psi = 2.0 * h2 * w
+    pr.backward(q, w, psi, tol=1e-8, maxit=200)
+    t_fw, (q, w, info) = _timed(lambda: pr.solve(data, None, tol=1e-8, maxit=200), 10)
+    t_bw, (_, _, ib) = _timed(lambda: pr.backward(q, w, psi, tol=1e-8, maxit=200), 10)
+    loss = float(h2 * torch.sum(w.double() ** 2))
+    pr.close()
+    return {"workload": "2-D exterior Stokes, 512^2, star r=0.25(1+0.15cos4t), 1024 markers, eta=10, spectral, FP64, "
+                        "tol 1e-8", "forward_ms": round(1e3 * t_fw, 4), "backward_ms": round(1e3 * t_bw, 4),
+            "forward_iters": info.iters, "adjoint_iters": ib.iters, "true_relres": info.true_relres_fp64,
+            "adjoint_true_relres": ib.true_relres_fp64, "loss": loss}
+
+
+def host_cpu():
+    """CPU model and logical CPU count of this host (lscpu when present)."""
+    import subprocess
+    model, count = platform.processor() or platform.machine(), os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                model = v.strip()
+            elif k.strip() == "CPU(s)":
+                count = int(v.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return model, count
+
+
+def cpu_baseline(spec):
+    """The FP64 numpy oracle's whole solve of the headline workload on this host: the right-hand
+    side, textbook GMRES to a residual of 1e-8 (MGS Arnoldi in exact double arithmetic, so the
+    Krylov residual is the true one) and the grid recovery, with the FFTs on every core the process
+    may use (scipy.fft workers); beside it one single-threaded operator apply, scaled by the
+    solve's apply count (iterations + right-hand side + recovery) to a single-threaded solve."""
+    import numpy as np
+    import oracle
+    from oracle import grid as G
+    from oracle.gmres import gmres
     from workloads.problems import random_density
     o = oracle.Setup.from_spec(spec)
-    q = random_density(spec, seed=0)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        o.apply(q)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s / 2 or reps >= 5:
-            break
-    cpu = platform.processor() or platform.machine()
+    model, ncpu = host_cpu()
+    workers = max(1, min(int(os.environ.get("OMP_NUM_THREADS", ncpu) or ncpu), ncpu))
+    iters = []
+
+    def osolve():
+        x, k, _ = gmres(o.apply, o.rhs(spec.data, spec.g), spec.tol, 100)
+        o.recover(x, spec.data, spec.g)
+        iters.append(k)
+    G.FFT_WORKERS = workers
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": reps / el, "unit": "applies/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} FP64 operator applies of the same workload by the numpy oracle "
-                      f"(single-threaded numpy/pocketfft) in {el:.1f} s on {cpu} ({os.cpu_count()} logical CPUs)"}
+        tn, _ = _per_call(osolve, 1)
+    finally:
+        G.FFT_WORKERS = None
+    k = iters[-1]
+    q = random_density(spec, seed=0)
+    t1, _ = _per_call(lambda: o.apply(q), 1)
+    est1 = t1 * (k + 2)
+    return {"value": round(1.0 / tn, 5), "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "solve_s": round(tn, 2), "oracle_iters": k,
+            "single_thread": {"value": round(1.0 / est1, 5), "unit": "solves/s", "cores": 1,
+                              "apply_s": round(t1, 2), "solve_s_estimate": round(est1, 2)},
+            "sample": f"one whole solve of the same workload (right-hand side, GMRES to 1e-8 in {k} iterations, "
+                      f"recovery) by the numpy oracle with its FFTs on {workers} threads (scipy.fft workers; the rest "
+                      f"is single-threaded numpy); single_thread: one apply on one thread times {k + 2}; host {model}, "
+                      f"{ncpu} logical CPUs"}
 
 
 def _per_call(fn, max_reps=3, budget_s=4.0):
@@ -483,6 +585,27 @@ def cpu_baseline_extras(extras):
             "indicator_ms": round(1e3 * t_ind, 1),
             "near_boundary_ms": round(1e3 * t_node / len(nodes) * n_corr, 1),
             "sample": f"one indicator; the interpolation of {len(nodes)} nodes scaled to {n_corr}"}
+    if "cfg2_star1024" in extras:
+        from oracle.gmres import gmres
+        s = P.cfg2_star_poisson(1024, 4096)
+        o = oracle.Setup.from_spec(s)
+
+        def osolve():
+            x, k, _ = gmres(o.apply, o.rhs(s.data, s.g), 1e-8, 150)
+            o.recover(x, s.data, s.g)
+        t, _ = _per_call(osolve, 1)
+        out["cfg2_star1024"] = {"dirichlet_solve_ms": round(1e3 * t, 1), "cores": 1,
+                                "sample": "one whole FP64 Dirichlet solve (right-hand side, GMRES to 1e-8, recovery)"}
+    if "cfg5_stokes512" in extras:
+        s = P.cfg5_stokes_star(512, 1024)
+        o = oracle.Setup.from_spec(s)
+        q = np.random.default_rng(0).standard_normal(o.n_aug)
+        t_app, _ = _per_call(lambda: o.apply(q), 1)
+        it = extras["cfg5_stokes512"]["forward_iters"]
+        out["cfg5_stokes512"] = {"apply_ms": round(1e3 * t_app, 1),
+                                 "forward_ms_estimate": round(1e3 * t_app * (it + 3), 1), "cores": 1,
+                                 "sample": f"one FP64 apply, times {it} GMRES iterations + 3 (right-hand side, "
+                                           "true residual, recovery)"}
     if "cylinder_array_drag" in extras:
         s = P.cylinder_array(1024, 0.1)
         o = oracle.Setup.from_spec(s)
@@ -525,6 +648,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere256", choices=["sphere256", "star1024", "circle64"])
     ap.add_argument("--apply-reps", type=int, default=100)
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="Krylov tolerance of each float GMRES round of the refined solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-vs-FP64, adjoint and batched measurements")
@@ -577,8 +702,9 @@ def main():
     g = torch.as_tensor(spec.g, device=dev).to(gdt).reshape((pr.nq,) + pr.grid_shape) if spec.g is not None else None
     tol = spec.tol
 
+    step = lambda: pr.solve_refined(data, g, tol=tol, maxit=100, inner_tol=args.inner_tol)
     for _ in range(args.warmup):
-        pr.solve(data, g, tol=tol, maxit=100)
+        step()
     torch.cuda.synchronize()
     print(f"# warmup done ({args.warmup} solves)", file=sys.stderr, flush=True)
 
@@ -586,12 +712,28 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, info = pr.solve(data, g, tol=tol, maxit=100)
+        _, _, info = step()
         iters.append(info.iters)
         relres.append(info.true_relres_fp64)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    print(f"# timed {args.steps} solves in {el:.3f} s, iterations {iters}", file=sys.stderr, flush=True)
+    print(f"# timed {args.steps} solves in {el:.3f} s, inner iterations {iters}, worst true residual "
+          f"{max(relres):.2e}", file=sys.stderr, flush=True)
+    # the same workload solved plainly: the mixed path stopped on its own Krylov residual of 1e-8 (its
+    # true residual stays at the float operator's level), and FP64 GMRES at 1e-8
+    t_mix, (_, _, im) = _timed(lambda: pr.solve(data, g, tol=tol, maxit=100), 5)
+    p64 = ibdl.Problem(spec.dim, spec.n, spec.L, spec.origin, m.X, m.nrm, m.ds, pde=spec.pde, kappa=spec.kappa,
+                       mu=spec.mu, bc=spec.bc, eta=spec.eta, kernel=spec.kernel, disc=spec.disc, precision="fp64",
+                       device=dev)
+    g64 = g.double() if g is not None else None
+    p64.solve(data, g64, tol=tol, maxit=100)
+    t64, (_, _, i64) = _timed(lambda: p64.solve(data, g64, tol=tol, maxit=100), 5)
+    p64.close()
+    plain = {"mixed_krylov_1e-8": {"solves_per_sec": round(1.0 / t_mix, 2), "ms": round(1e3 * t_mix, 4),
+                                   "iters": im.iters, "true_relres": im.true_relres_fp64},
+             "fp64_1e-8": {"solves_per_sec": round(1.0 / t64, 2), "ms": round(1e3 * t64, 4), "iters": i64.iters,
+                           "true_relres": i64.true_relres_fp64},
+             "refined_vs_fp64_speedup": round(t64 / (el / args.steps), 3)}
 
     # operator applies alone, and per-stage HIP-event timing on the handle's stream
     q = torch.as_tensor(random_density(spec, seed=0), device=dev)
@@ -650,12 +792,11 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
-    extras = {} if args.no_extras else measure_extras(spec, prec, pr, data, g, tol, max(relres), dev)
-    total_applies = int(sum(iters))
+    extras = {} if args.no_extras else measure_extras(spec, prec, pr, data, g, tol, dev)
     out = {
         "metric": METRIC,
-        "value": round(total_applies / el, 2),
-        "unit": "applies/s",
+        "value": round(args.steps / el, 3),
+        "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -666,11 +807,14 @@ def main():
         "dtype": "f32 grid + f64 Krylov" if prec == "mixed" else "f64",
         "data": "synthetic (seeded geometry and manufactured boundary data; no dataset)",
         "config": {"workload": desc, "grid": list(spec.n), "n_ib": spec.n_ib, "n_aug": pr.n_aug,
-                   "tol": tol, "precision": prec},
+                   "tol": tol, "residual": "double-precision ||b - A q|| / ||b||", "precision": prec,
+                   "solver": f"GMRES on the float-applied operator, double-precision residual corrections "
+                             f"(inner tolerance {args.inner_tol:g})"},
         "solves_per_sec": round(args.steps / el, 3),
-        "gmres_iterations": iters,
+        "inner_gmres_iterations": iters,
         "true_relres_fp64": max(relres),
-        "apply_only_per_sec": round(1e3 / apply_ms, 2),
+        "applies_per_sec": round(1e3 / apply_ms, 2),
+        "plain_solves": plain,
         "apply_ms": round(apply_ms, 5),
         "apply_single_ms": {k: round(v, 5) for k, v in apply_pct.items()},
         "apply_effective_GB_s": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1),

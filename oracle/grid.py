@@ -20,6 +20,24 @@ import numpy as np
 
 from .ib import Grid
 
+# Threads of the FFTs: None uses numpy.fft (one thread); a count uses scipy.fft with that many
+# workers (the same pocketfft transforms, for timing the oracle on all host cores).
+FFT_WORKERS = None
+
+
+def _fftn(f):
+    if FFT_WORKERS is None:
+        return np.fft.fftn(f)
+    import scipy.fft
+    return scipy.fft.fftn(f, workers=FFT_WORKERS)
+
+
+def _ifftn(f):
+    if FFT_WORKERS is None:
+        return np.fft.ifftn(f)
+    import scipy.fft
+    return scipy.fft.ifftn(f, workers=FFT_WORKERS)
+
 
 def _wavenumber_index(n):
     """Signed mode index m for FFT position j: 0, 1, ..., N/2-1, -N/2, ..., -1."""
@@ -60,8 +78,8 @@ def deriv(grid: Grid, f, d: int, disc: str):
     if disc == "fd2":
         ax = grid.axis(d)
         return (np.roll(f, -1, axis=ax) - np.roll(f, 1, axis=ax)) / (2.0 * grid.h)
-    fh = np.fft.fftn(f)
-    return np.real(np.fft.ifftn(1j * deriv_symbol(grid, disc, d) * fh))
+    fh = _fftn(f)
+    return np.real(_ifftn(1j * deriv_symbol(grid, disc, d) * fh))
 
 
 def laplacian(grid: Grid, f, disc: str):
@@ -71,16 +89,16 @@ def laplacian(grid: Grid, f, disc: str):
             ax = grid.axis(d)
             out = out + np.roll(f, -1, axis=ax) + np.roll(f, 1, axis=ax)
         return out / grid.h ** 2
-    return np.real(np.fft.ifftn(laplacian_symbol(grid, disc) * np.fft.fftn(f)))
+    return np.real(_ifftn(laplacian_symbol(grid, disc) * _fftn(f)))
 
 
 def solve(grid: Grid, rhs, disc: str, c0: float, c2: float = 1.0):
     """u with (c2 Delta - c0) u = rhs; mean-zero branch where the symbol vanishes."""
     lam = c2 * laplacian_symbol(grid, disc) - c0
-    rh = np.fft.fftn(rhs)
+    rh = _fftn(rhs)
     safe = np.where(lam == 0.0, 1.0, lam)
     uh = np.where(lam == 0.0, 0.0, rh / safe)
-    return np.real(np.fft.ifftn(uh))
+    return np.real(_ifftn(uh))
 
 
 def div(grid: Grid, F, disc: str):

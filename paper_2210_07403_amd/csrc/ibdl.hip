@@ -855,8 +855,9 @@ bool ensure_graph(ibdl_s* h, bool trans) {
 // j's residual.  The state freezes at the step that converges, so a step queued after it changes
 // nothing but V[j+2] and scratch.
 int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
-          double* relres, bool trans = false) {
+          double* relres, bool trans = false, double* beta_out = nullptr) {
   const int64_t n = h->n_aug;
+  if (beta_out) *beta_out = 0.0;
   if (maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be at most 200");
   if (h->vcap < maxit + 1) {
     h->V = (double*)h->dalloc<double>(sizeof(double) * n * (maxit + 1));
@@ -915,6 +916,7 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     if (ahead) step(j + 1);
     const volatile double* hv = wait_published(h, j & 1, seq[j & 1]);
     const double beta = hv[GM_BETA], hn = hv[GM_HN];
+    if (j == 0 && beta_out) *beta_out = beta;
     if (j == 0 && !(beta > 0.0)) {   // b = 0: x = 0 (behind the queued steps, which ran on zeros)
       if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
       IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
@@ -1656,30 +1658,64 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
     }
     rhs_t<double>(h, data, g64, h->vb);
     if (!h->vx) h->vx = (double*)h->dalloc<double>(sizeof(double) * n);
-    const double bn = host_norm(h, h->vb, n);
-    IBDL_HIP(hipMemcpyAsync(h->vr, h->vb, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
-    kr_scale(h->vb, 0.0, q, n, h->st);   // x0 = 0
+    const int nblk = kr_nblk(n);
+    ensure_partial(h, nblk);
+    // Round 0 solves A q = b directly into q (x0 = 0); round k > 0 adds the correction A d = r.
+    // GMRES reports |b| with its first step, so only the residual norm of each round reaches the
+    // host.  From round 1 on the float recovery of the new q is queued on the second stream beside
+    // the double-precision residual; if that residual still misses tol, the next round recomputes it.
     int total = 0, status = IBDL_NOT_CONVERGED;
-    double rn = bn, krylov = 0.0;
+    double rn = 0.0, bn = 0.0, krylov = 0.0;
+    bool recovered = false;
+    hipStream_t main = h->st;
     for (int round = 0; round < max_rounds; ++round) {
-      if (!(bn > 0) || rn <= tol * bn) {
+      int it = 0;
+      double rr = 0.0, beta = 0.0;
+      gmres(h, round == 0 ? h->vb : h->vr, inner_tol, maxit, round == 0 ? q : h->vx, nullptr, &it, &rr, false, &beta);
+      if (round == 0) {
+        bn = beta;
+        if (!(bn > 0)) {   // b = 0: q = 0 (GMRES wrote it)
+          rn = 0.0;
+          status = IBDL_OK;
+          break;
+        }
+      } else {
+        kr_axpby(q, 1.0, h->vx, 1.0, n, h->st);
+      }
+      total += it;
+      krylov = rr;
+      recovered = false;
+      const bool spec = round > 0 && u_grid && h->mixed();
+      if (spec) {
+        IBDL_HIP(hipEventRecord(h->ev_fork, main));
+        IBDL_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+      }
+      apply_any(h, q, h->vr, true);
+      kr_axpby(h->vr, 1.0, h->vb, -1.0, n, h->st);   // r = b - A q
+      kr_multidot(h->vr, n, 1, h->vr, n, h->partial, nblk, h->small + 600, h->st);
+      IBDL_HIP(hipMemcpyAsync(h->hostbuf + 600, h->small + 600, sizeof(double), hipMemcpyDeviceToHost, h->st));
+      if (spec) {
+        h->st = h->aux;
+        try {
+          recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
+        } catch (...) {
+          h->st = main;
+          throw;
+        }
+        h->st = main;
+        IBDL_HIP(hipEventRecord(h->ev_join, h->aux));
+        IBDL_HIP(hipStreamWaitEvent(main, h->ev_join, 0));
+        recovered = true;
+      }
+      IBDL_HIP(hipStreamSynchronize(main));
+      rn = sqrt(std::max(h->hostbuf[600], 0.0));
+      if (!std::isfinite(rn)) throw Error(IBDL_ERR_NONFINITE, "non-finite residual in refinement");
+      if (rn <= tol * bn) {
         status = IBDL_OK;
         break;
       }
-      // correction from the working-precision operator, then the true residual in double
-      int it = 0;
-      double rr = 0.0;
-      gmres(h, h->vr, inner_tol, maxit, h->vx, nullptr, &it, &rr);
-      total += it;
-      krylov = rr;
-      kr_axpby(q, 1.0, h->vx, 1.0, n, h->st);
-      apply_any(h, q, h->vr, true);
-      kr_axpby(h->vr, 1.0, h->vb, -1.0, n, h->st);
-      rn = host_norm(h, h->vr, n);
-      if (!std::isfinite(rn)) throw Error(IBDL_ERR_NONFINITE, "non-finite residual in refinement");
     }
-    if (rn <= tol * bn) status = IBDL_OK;
-    if (u_grid) {
+    if (u_grid && !recovered) {
       if (h->mixed()) recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
       else recover_t<double>(h, q, data, (const double*)g_grid, (double*)u_grid);
     }
