@@ -855,7 +855,7 @@ bool ensure_graph(ibdl_s* h, bool trans) {
 // j's residual.  The state freezes at the step that converges, so a step queued after it changes
 // nothing but V[j+2] and scratch.
 int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_info_t* info, int* iters,
-          double* relres, bool trans = false, double* beta_out = nullptr) {
+          double* relres, bool trans = false, double* beta_out = nullptr, double stop_beta = -1.0) {
   const int64_t n = h->n_aug;
   if (beta_out) *beta_out = 0.0;
   if (maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be at most 200");
@@ -911,12 +911,18 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     // Step j + 1 is queued ahead unless step j is predicted to converge: the residual ratio of the
     // last two steps, applied once more, brings it to tol.  A step queued after convergence would
     // delay whatever follows on the stream by a whole apply.
-    bool ahead = j + 1 < maxit;
+    bool ahead = j + 1 < maxit && !(j == 0 && stop_beta > 0.0);
     if (ahead && j >= 2) ahead = rs[j - 1] * (rs[j - 1] / rs[j - 2]) > tol;
     if (ahead) step(j + 1);
     const volatile double* hv = wait_published(h, j & 1, seq[j & 1]);
     const double beta = hv[GM_BETA], hn = hv[GM_HN];
     if (j == 0 && beta_out) *beta_out = beta;
+    // |b| already small enough for the caller: no solve (x is left alone)
+    if (j == 0 && stop_beta > 0.0 && beta <= stop_beta) {
+      *iters = 0;
+      *relres = 0.0;
+      return IBDL_OK;
+    }
     if (j == 0 && !(beta > 0.0)) {   // b = 0: x = 0 (behind the queued steps, which ran on zeros)
       if (!std::isfinite(beta)) throw Error(IBDL_ERR_NONFINITE, "right-hand side is not finite");
       IBDL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, h->st));
@@ -1661,17 +1667,20 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
     const int nblk = kr_nblk(n);
     ensure_partial(h, nblk);
     // Round 0 solves A q = b directly into q (x0 = 0); round k > 0 adds the correction A d = r.
-    // GMRES reports |b| with its first step, so only the residual norm of each round reaches the
-    // host.  From round 1 on the float recovery of the new q is queued on the second stream beside
-    // the double-precision residual; if that residual still misses tol, the next round recomputes it.
+    // GMRES reports |b| with its first step.  After each round the double-precision residual
+    // r = b - A q is formed on the device.  When the round's own Krylov residual predicts that r
+    // meets tol, the host reads |r| at once (and the float recovery of q runs beside that residual
+    // on the second stream); otherwise the next round starts without waiting, and its first step
+    // reports |r|: if that already meets tol, the round stops there and q stays as it is.
     int total = 0, status = IBDL_NOT_CONVERGED;
-    double rn = 0.0, bn = 0.0, krylov = 0.0;
-    bool recovered = false;
+    double rn = 0.0, bn = 0.0, krylov = 0.0, rprev = 0.0;
+    bool recovered = false, known = false;
     hipStream_t main = h->st;
     for (int round = 0; round < max_rounds; ++round) {
       int it = 0;
       double rr = 0.0, beta = 0.0;
-      gmres(h, round == 0 ? h->vb : h->vr, inner_tol, maxit, round == 0 ? q : h->vx, nullptr, &it, &rr, false, &beta);
+      gmres(h, round == 0 ? h->vb : h->vr, inner_tol, maxit, round == 0 ? q : h->vx, nullptr, &it, &rr, false, &beta,
+            round == 0 || known ? -1.0 : tol * bn);
       if (round == 0) {
         bn = beta;
         if (!(bn > 0)) {   // b = 0: q = 0 (GMRES wrote it)
@@ -1679,19 +1688,35 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
           status = IBDL_OK;
           break;
         }
+        rprev = bn;
       } else {
+        if (!known) {      // |r| of the previous round, from this round's first step
+          rn = beta;
+          if (!std::isfinite(rn)) throw Error(IBDL_ERR_NONFINITE, "non-finite residual in refinement");
+          if (it == 0) {
+            status = IBDL_OK;
+            break;
+          }
+          rprev = rn;
+        }
         kr_axpby(q, 1.0, h->vx, 1.0, n, h->st);
       }
       total += it;
       krylov = rr;
       recovered = false;
-      const bool spec = round > 0 && u_grid && h->mixed();
+      // predicted |r|: the round's Krylov reduction of its right-hand side, but not below the float
+      // operator's rounding (about 1e-7 of that right-hand side on a mixed handle)
+      const double floor = h->mixed() ? 1e-7 : 1e-15;
+      const bool last = std::max(rr, floor) * rprev <= tol * bn;
+      const bool spec = last && u_grid && h->mixed();
       if (spec) {
         IBDL_HIP(hipEventRecord(h->ev_fork, main));
         IBDL_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
       }
       apply_any(h, q, h->vr, true);
       kr_axpby(h->vr, 1.0, h->vb, -1.0, n, h->st);   // r = b - A q
+      known = last;
+      if (!last) continue;
       kr_multidot(h->vr, n, 1, h->vr, n, h->partial, nblk, h->small + 600, h->st);
       IBDL_HIP(hipMemcpyAsync(h->hostbuf + 600, h->small + 600, sizeof(double), hipMemcpyDeviceToHost, h->st));
       if (spec) {
@@ -1710,10 +1735,18 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
       IBDL_HIP(hipStreamSynchronize(main));
       rn = sqrt(std::max(h->hostbuf[600], 0.0));
       if (!std::isfinite(rn)) throw Error(IBDL_ERR_NONFINITE, "non-finite residual in refinement");
+      rprev = rn;
       if (rn <= tol * bn) {
         status = IBDL_OK;
         break;
       }
+    }
+    if (status != IBDL_OK && !known) {   // out of rounds with the last residual unread
+      kr_multidot(h->vr, n, 1, h->vr, n, h->partial, nblk, h->small + 600, h->st);
+      IBDL_HIP(hipMemcpyAsync(h->hostbuf + 600, h->small + 600, sizeof(double), hipMemcpyDeviceToHost, h->st));
+      IBDL_HIP(hipStreamSynchronize(h->st));
+      rn = sqrt(std::max(h->hostbuf[600], 0.0));
+      if (rn <= tol * bn) status = IBDL_OK;
     }
     if (u_grid && !recovered) {
       if (h->mixed()) recover_t<float>(h, q, data, (const float*)g_grid, (float*)u_grid);
