@@ -980,6 +980,11 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
   IBDL_LAUNCH_CHECK();
 }
 
+void exclusive_scan(const int* cnt, int* off, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, off, n);
+  IBDL_LAUNCH_CHECK();
+}
+
 void markers_row_segments(const MarkerGeom& g, const int* tile_off, const int* rows, int64_t nact,
                           unsigned long long* seg, hipStream_t st) {
   if (g.ntile[0] > 64) throw Error(-2, "markers_row_segments: more than 64 tiles along x");

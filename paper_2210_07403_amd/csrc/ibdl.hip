@@ -127,6 +127,8 @@ struct ibdl_s {
   int* nb_count = nullptr;            // near-boundary scratch: listed nodes [1]
   int* nb_list = nullptr;             // near-boundary scratch: node list
   int64_t nb_cap = 0;
+  int *nb_cell_cnt = nullptr, *nb_cell_off = nullptr, *nb_cell_list = nullptr;   // marker cells
+  bool nb_cells_ready = false;
   double* g64 = nullptr;      // refinement: the forcing widened to double ([nq][grid])
   double* vx = nullptr;       // refinement: correction of one round [n_aug]
   double* adj_m = nullptr;    // adjoint: interpolated fields / gather weights [n_ib][8]
@@ -1091,6 +1093,7 @@ void sl_markers(ibdl_s* h) {
 
 void build_markers(ibdl_s* h) {
   h->drop_graphs();
+  h->nb_cells_ready = false;
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
               h->busy_tmp, h->busy_off, h->st);
@@ -1182,7 +1185,19 @@ void near_boundary_t(ibdl_s* h, const double* Ub, const T* omega, const T* u, do
   g.ox = h->geom.origin[0];
   g.oy = h->geom.origin[1];
   g.h = h->h;
-  near_boundary<T>(h->X, Ub, h->nq, h->n_ib, g, m1, m2, omega, u, out, h->nb_flag, h->nb_count, h->nb_list, h->st);
+  if (!h->nb_cells_ready) {   // marker cells of the nearest-marker search, once per marker set
+    int ncx, ncy;
+    const int nc = near_cells(g, &ncx, &ncy);
+    if (!h->nb_cell_off) {
+      h->nb_cell_cnt = (int*)h->dalloc<int>(sizeof(int) * nc);
+      h->nb_cell_off = (int*)h->dalloc<int>(sizeof(int) * (nc + 1));
+      h->nb_cell_list = (int*)h->dalloc<int>(sizeof(int) * h->n_ib);
+    }
+    near_bin(h->X, h->n_ib, g, h->nb_cell_cnt, h->nb_cell_off, h->nb_cell_list, h->st);
+    h->nb_cells_ready = true;
+  }
+  near_boundary<T>(h->X, Ub, h->nq, h->n_ib, g, m1, m2, omega, u, out, h->nb_flag, h->nb_count, h->nb_list,
+                   h->nb_cell_off, h->nb_cell_list, h->st);
 }
 
 // (u . grad) u of a 2-D velocity field: the four spectral (or centred-difference) derivatives by

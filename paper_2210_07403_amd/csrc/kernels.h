@@ -365,7 +365,16 @@ int64_t near_list_cap(int64_t n_ib, double m1, int64_t npoints);
 // [near_list_cap].
 template <typename T>
 void near_boundary(const double* X, const double* Ub, int nc, int64_t n_ib, const NearGeom& g, double m1, double m2,
-                   const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st);
+                   const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list,
+                   const int* cell_off, const int* cell_list, hipStream_t st);
+// Marker cells of the near-boundary search (squares of 8 x 8 nodes): their number (and ncx, ncy),
+// and the binning of the n_ib markers X: cell_cnt [cells] scratch, cell_off [cells + 1], cell_list
+// [n_ib] (marker ids by cell).
+int near_cells(const NearGeom& g, int* ncx, int* ncy);
+void near_bin(const double* X, int64_t n_ib, const NearGeom& g, int* cell_cnt, int* cell_off, int* cell_list,
+              hipStream_t st);
+// off[0..n] = exclusive scan of cnt[0..n) (one workgroup)
+void exclusive_scan(const int* cnt, int* off, int n, hipStream_t st);
 
 // ------------------------------------------------------------------ MINRES (device recurrences)
 // State slots of the double-buffered scalar recurrence (MR_NSTATE doubles per copy).

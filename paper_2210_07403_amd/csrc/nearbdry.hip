@@ -2,9 +2,10 @@
 // near-boundary points) and Sec. 5.3.4 (flagging interior and exterior points).
 //
 // The indicator's grid solve runs through the FFT pipeline (ibdl.hip); here are its last step
-// (shift to 0 at the corner node, threshold at 1/2) and the three kernels of the interpolation:
-// marking the nodes within m1 h of a marker, listing the marked nodes of Omega, and the
-// per-node interpolation (three nearest markers by a scan of all markers, one wave per node).
+// (shift to 0 at the corner node, threshold at 1/2) and the kernels of the interpolation: binning
+// the markers into cells, marking the nodes within m1 h of a marker, listing the marked nodes of
+// Omega, and the per-node interpolation (three nearest markers by a search of the cells in rings
+// around the node, one wave per node).
 #include <algorithm>
 #include <cmath>
 
@@ -123,36 +124,102 @@ __device__ double bilinear(const T* __restrict__ u, const NearGeom& g, double bx
 constexpr int kNB = 256;        // threads per block: four waves, one node per wave at a time
 constexpr int kNBBlocks = 2048; // grid-stride over the listed nodes
 
-// One wave per listed node: the lanes scan the markers in a strided split, each keeping its own
-// three nearest by (distance, index), and a butterfly of exchanges merges them; the order is total
-// (indices differ), so every lane ends with the same three markers the sequential scan finds.
+// Markers binned by position into square cells of kCell x kCell grid nodes (cell index clamped to
+// the grid, so markers outside the box land in a border cell): counts, then a cursor fill.
+constexpr int kCell = 8;
+
+__device__ __forceinline__ int cell_of(double v, double o, double w, int nc) {
+  const double c = floor((v - o) / w);
+  return c < 0.0 ? 0 : (c >= (double)nc ? nc - 1 : (int)c);
+}
+
+__global__ void k_cell_count(const double* __restrict__ X, int64_t n_ib, NearGeom g, int ncx, int ncy,
+                             int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_ib) return;
+  const double w = kCell * g.h;
+  atomicAdd(&cnt[cell_of(X[2 * i + 1], g.oy, w, ncy) * ncx + cell_of(X[2 * i], g.ox, w, ncx)], 1);
+}
+
+__global__ void k_cell_fill(const double* __restrict__ X, int64_t n_ib, NearGeom g, int ncx, int ncy,
+                            int* __restrict__ cur, int* __restrict__ list) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_ib) return;
+  const double w = kCell * g.h;
+  list[atomicAdd(&cur[cell_of(X[2 * i + 1], g.oy, w, ncy) * ncx + cell_of(X[2 * i], g.ox, w, ncx)], 1)] = (int)i;
+}
+
+// merge the 64 lanes' lists by a butterfly of exchanges (every lane ends with the same three)
+__device__ __forceinline__ void merge_wave(Near3& nr) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    double od[3];
+    int oi[3];
+    for (int c = 0; c < 3; ++c) {
+      od[c] = __shfl_xor(nr.d[c], off, 64);
+      oi[c] = __shfl_xor(nr.i[c], off, 64);
+    }
+    for (int c = 0; c < 3; ++c) nr.push(od[c], oi[c]);
+  }
+}
+
+// One wave per listed node.  The three nearest markers by (distance, index) are found over the
+// marker cells in square rings around the node's cell: the lanes split a ring's cells, each
+// keeping its own three nearest, and a butterfly merges them into lane 0's list (the other lanes
+// start the next ring empty, so no marker is counted twice).  Every marker of a cell outside rings
+// 0..W is more than W kCell h away along one axis, so once the third-nearest distance is at most
+// that, no unvisited marker can enter the three; the order is total (indices differ), so the
+// result is the three markers a sequential scan of all markers finds.
 template <typename T>
 __global__ __launch_bounds__(kNB) void k_near_fix(const double* __restrict__ X, const double* __restrict__ Ub,
                                                   int ubs, int64_t n_ib, NearGeom g, double m2, const int* __restrict__ count,
-                                                  const int* __restrict__ list, const T* __restrict__ u,
-                                                  T* __restrict__ out) {
+                                                  const int* __restrict__ list, const int* __restrict__ cell_off,
+                                                  const int* __restrict__ cell_list, int ncx, int ncy,
+                                                  const T* __restrict__ u, T* __restrict__ out) {
   const int n = *count;
   const int lane = threadIdx.x & 63;
   const int nwaves = gridDim.x * (kNB / 64);
   const double2* __restrict__ X2 = reinterpret_cast<const double2*>(X);
+  const double cw = kCell * g.h;
+  const int wmax = ncx > ncy ? ncx : ncy;
   for (int k = blockIdx.x * (kNB / 64) + (threadIdx.x >> 6); k < n; k += nwaves) {
     const int e = list[k];
     const int pi = e % g.nx, pj = e / g.nx;
     const double px = g.ox + pi * g.h, py = g.oy + pj * g.h;
+    const int pcx = cell_of(px, g.ox, cw, ncx), pcy = cell_of(py, g.oy, cw, ncy);
     Near3 nr;
     nr.init();
-    for (int64_t m = lane; m < n_ib; m += 64) {
-      const double2 q = X2[m];
-      nr.push(dist2(px, py, q.x, q.y), (int)m);
-    }
-    for (int off = 32; off >= 1; off >>= 1) {
-      double od[3];
-      int oi[3];
-      for (int c = 0; c < 3; ++c) {
-        od[c] = __shfl_xor(nr.d[c], off, 64);
-        oi[c] = __shfl_xor(nr.i[c], off, 64);
+    for (int W = 0; W <= wmax; ++W) {
+      const int ncell = W == 0 ? 1 : 8 * W;   // the ring of cells at Chebyshev distance W
+      for (int c = lane; c < ncell; c += 64) {
+        int dx, dy;
+        if (W == 0) {
+          dx = dy = 0;
+        } else if (c < 2 * W + 1) {            // bottom row
+          dx = c - W;
+          dy = -W;
+        } else if (c < 4 * W + 2) {            // top row
+          dx = c - (2 * W + 1) - W;
+          dy = W;
+        } else {                               // left and right columns without the corners
+          const int r = c - (4 * W + 2);
+          dx = (r & 1) ? W : -W;
+          dy = -W + 1 + (r >> 1);
+        }
+        const int cx = pcx + dx, cy = pcy + dy;
+        if (cx < 0 || cx >= ncx || cy < 0 || cy >= ncy) continue;
+        const int cell = cy * ncx + cx;
+        for (int q = cell_off[cell]; q < cell_off[cell + 1]; ++q) {
+          const int m = cell_list[q];
+          const double2 xm = X2[m];
+          nr.push(dist2(px, py, xm.x, xm.y), m);
+        }
       }
-      for (int c = 0; c < 3; ++c) nr.push(od[c], oi[c]);
+      merge_wave(nr);
+      // a marker outside rings 0..W is more than W cw away (less a margin for the rounding of the
+      // cell assignments)
+      const double bound = W > 0 ? ((double)W - 1e-6) * cw : 0.0;
+      if (W > 0 && nr.d[2] <= bound * bound) break;
+      if (lane != 0) nr.init();
     }
     if (lane != 0) continue;
     int a = nr.i[0], b = nr.i[1];
@@ -209,9 +276,37 @@ int64_t near_list_cap(int64_t n_ib, double m1, int64_t npoints) {
   return std::min(npoints, n_ib * box);
 }
 
+int near_cells(const NearGeom& g, int* ncx, int* ncy) {
+  *ncx = std::max(g.nx / kCell, 1);
+  *ncy = std::max(g.ny / kCell, 1);
+  return *ncx * *ncy;
+}
+
+void near_bin(const double* X, int64_t n_ib, const NearGeom& g, int* cell_cnt, int* cell_off, int* cell_list,
+              hipStream_t st) {
+  int ncx, ncy;
+  const int nc = near_cells(g, &ncx, &ncy);
+  IBDL_HIP(hipMemsetAsync(cell_cnt, 0, sizeof(int) * nc, st));
+  if (n_ib > 0) {
+    hipLaunchKernelGGL(k_cell_count, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, X, n_ib, g, ncx, ncy,
+                       cell_cnt);
+    IBDL_LAUNCH_CHECK();
+  }
+  exclusive_scan(cell_cnt, cell_off, nc, st);
+  IBDL_HIP(hipMemcpyAsync(cell_cnt, cell_off, sizeof(int) * nc, hipMemcpyDeviceToDevice, st));   // fill cursors
+  if (n_ib > 0) {
+    hipLaunchKernelGGL(k_cell_fill, dim3((unsigned)((n_ib + 255) / 256)), dim3(256), 0, st, X, n_ib, g, ncx, ncy,
+                       cell_cnt, cell_list);
+    IBDL_LAUNCH_CHECK();
+  }
+}
+
 template <typename T>
 void near_boundary(const double* X, const double* Ub, int nc, int64_t n_ib, const NearGeom& g, double m1, double m2,
-                   const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list, hipStream_t st) {
+                   const T* omega, const T* u, T* out, unsigned char* flag, int* count, int* list,
+                   const int* cell_off, const int* cell_list, hipStream_t st) {
+  int ncx, ncy;
+  near_cells(g, &ncx, &ncy);
   const int64_t n = (int64_t)g.nx * g.ny;
   IBDL_HIP(hipMemcpyAsync(out, u, sizeof(T) * n * nc, hipMemcpyDeviceToDevice, st));
   IBDL_HIP(hipMemsetAsync(flag, 0, n, st));
@@ -226,7 +321,7 @@ void near_boundary(const double* X, const double* Ub, int nc, int64_t n_ib, cons
   const int64_t nblk = std::min<int64_t>((waves + kNB / 64 - 1) / (kNB / 64), kNBBlocks);
   for (int c = 0; c < nc; ++c) {   // component c: boundary values Ub[i * nc + c], field c
     hipLaunchKernelGGL((k_near_fix<T>), dim3((unsigned)nblk), dim3(kNB), 0, st, X, Ub + c, nc, n_ib, g, m2, count,
-                       list, u + c * n, out + c * n);
+                       list, cell_off, cell_list, ncx, ncy, u + c * n, out + c * n);
     IBDL_LAUNCH_CHECK();
   }
 }
@@ -234,7 +329,8 @@ void near_boundary(const double* X, const double* Ub, int nc, int64_t n_ib, cons
 #define IBDL_NB_INST(T)                                                                                    \
   template void indicator_finish<T>(const T*, int64_t, T*, T*, hipStream_t);                              \
   template void near_boundary<T>(const double*, const double*, int, int64_t, const NearGeom&, double, double, \
-                                 const T*, const T*, T*, unsigned char*, int*, int*, hipStream_t);
+                                 const T*, const T*, T*, unsigned char*, int*, int*, const int*, const int*,    \
+                                 hipStream_t);
 IBDL_NB_INST(float)
 IBDL_NB_INST(double)
 
