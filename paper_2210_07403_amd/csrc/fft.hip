@@ -21,6 +21,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kLdsBytes = 65536;
+// The single-field line passes (strided, and the fused scalar pass) take up to 512 threads and
+// 96 KiB of LDS per workgroup (gfx950 gives a workgroup up to 160 KiB): a tile of 32 lines of 256
+// float points, 256-byte segments per row.  The multi-field passes keep 256 threads, which leaves
+// their lines the registers they need.
+constexpr int kLineBlock = 512;
+constexpr int kLineLds = 98304;
 
 // Stockham plan of a length-N line: RMAX elements per thread (the radix of every stage but the last),
 // T = N / RMAX threads per line
@@ -413,24 +419,27 @@ template <typename T> constexpr int fused_rmax(int N, int nacc) {
   return (sizeof(T) == 8 && nacc >= 2 && N >= 512) ? 4   // double, two accumulators, long lines
          : (plan_rmax(N) > 8 && (nacc >= 2 || (sizeof(T) == 8 && N >= 1024)) ? 8 : rmax_t<T>(N));
 }
-template <typename T, int N, int RX = rmax_t<T>(N)> struct TileCfg {
+template <typename T, int N, int RX = rmax_t<T>(N), int BLK = kBlock, int LDS = kLdsBytes> struct TileCfg {
   static constexpr int RMX = RX;
   static constexpr int T_ = Plan<N, RMX>::T;
-  static constexpr int W0 = kBlock / T_;
-  static constexpr int WL = kLdsBytes / (N * (int)sizeof(cplx<T>));
-  static constexpr int W = (W0 < WL ? W0 : WL) > 0 ? (W0 < WL ? W0 : WL) : 1;
+  static constexpr int W0 = BLK / T_;
+  static constexpr int WL = LDS / (N * (int)sizeof(cplx<T>));
+  // lines per tile: a power of two (the kernels split a thread index into line and element by it)
+  static constexpr int W = pow2floor((W0 < WL ? W0 : WL) > 0 ? (W0 < WL ? W0 : WL) : 1);
   static constexpr int NT = W * T_;  // threads per block
   // twiddles staged in LDS when the table fits beside the widest tile (all but 1024 in double)
-  static constexpr bool TWL = (W * N + N) * (int)sizeof(cplx<T>) <= 65536;
+  static constexpr bool TWL = (W * N + N) * (int)sizeof(cplx<T>) <= LDS;
 };
+// the single-field passes' tile configuration
+template <typename T, int N> using LineCfg = TileCfg<T, N, rmax_t<T>(N), kLineBlock, kLineLds>;
 
 // ------------------------------------------------------------------ strided in-place C2C
 template <typename T, int N, bool INV>
-__global__ __launch_bounds__(kBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
-                                                    int64_t outer, int64_t es, const cplx<T>* __restrict__ twg,
-                                                    int W, RowMask rm, int64_t vinner) {
+__global__ __launch_bounds__(kLineBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
+                                                        int64_t outer, int64_t es, const cplx<T>* __restrict__ twg,
+                                                        int W, RowMask rm, int64_t vinner) {
   using C = cplx<T>;
-  using TC = TileCfg<T, N>;
+  using TC = LineCfg<T, N>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
@@ -611,10 +620,11 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 // Single scalar field (the finite-difference operator and the scalar grid solve): forward FFT,
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
 template <typename T, int N>
-__global__ __launch_bounds__(kBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
-                                                   const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
+__global__ __launch_bounds__(kLineBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
+                                                       const cplx<T>* __restrict__ twg, int W, int64_t bstride,
+                                                       RowMask rm) {
   using C = cplx<T>;
-  using TC = TileCfg<T, N>;   // one field, one real factor: no spills at 16 elements per thread
+  using TC = LineCfg<T, N>;   // one field, one real factor: no spills at 16 elements per thread
   constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -735,7 +745,7 @@ int fft_x_rpb_max(int nx) {
 template <typename T>
 int fft_line_w_max(int n) {
   int r = 0;
-  dispatch_n(n, [&](auto Nc) { r = TileCfg<T, decltype(Nc)::value>::W; });
+  dispatch_n(n, [&](auto Nc) { r = LineCfg<T, decltype(Nc)::value>::W; });
   return r;
 }
 
@@ -792,7 +802,7 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
     throw Error(-2, "strided FFT pass: one launch may not span 4 GiB");
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
-    using TC = TileCfg<T, N>;
+    using TC = LineCfg<T, N>;
     const int W = pick(w, TC::W);
     const int64_t nb = (nlines + W - 1) / W;
     const size_t lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
@@ -839,7 +849,7 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
     } else if (md.mode != 0) {
       throw Error(-2, "fused pass: unsupported transposed multiplier");
     } else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS) {
-      shape(TileCfg<T, N>{}, W, grid, blk, lds);
+      shape(LineCfg<T, N>{}, W, grid, blk, lds);
       hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
     } else if (!md.stokes && no == 1) {
       shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
