@@ -50,7 +50,9 @@ def laplacian_symbol(grid: Grid, disc: str):
     for d in range(grid.dim):
         m = _wavenumber_index(grid.n[d])
         if disc == "fd2":
-            s = (2.0 * np.cos(2 * np.pi * m / grid.n[d]) - 2.0) / grid.h ** 2
+            # the 5-point symbol (2 cos(k h) - 2) / h^2, written as -4 sin^2(k h / 2) / h^2: the same
+            # value without the cancellation that costs the lowest modes ten digits at N = 8192
+            s = -4.0 * np.sin(np.pi * m / grid.n[d]) ** 2 / grid.h ** 2
         else:
             s = -(2 * np.pi * m / grid.L[d]) ** 2
         shape = [1] * grid.dim

@@ -90,3 +90,17 @@ def test_projection():
     phi = _no_nyquist(rng.standard_normal((16, 16)))
     gphi = G.grad(grid, phi, "spectral")
     assert np.abs(G.project(grid, gphi, "spectral")).max() < 1e-10
+
+
+def test_fd_symbol_low_modes_on_long_lines():
+    """The FD symbol (2 cos(2 pi m / N) - 2) / h^2 of the 5-point Laplacian at the lowest modes of an
+    8192-point axis, against the same formula evaluated in extended precision (64-bit significand):
+    relative 1e-12, which the formula evaluated directly in double misses by more than an order (the
+    cancellation leaves 2.5e-11 at m = 1)."""
+    g = Grid(2, (16, 8192), (1.0 / 64, 8.0), (0.0, 0.0))
+    sig = G.laplacian_symbol(g, "fd2")
+    col = sig[:, 0] - sig[0, 0]           # the y component (x index 0 adds nothing)
+    m = np.arange(1, 9, dtype=np.longdouble)
+    th = 2 * np.pi * m / np.longdouble(8192)
+    want = (2 * np.cos(th) - 2) / np.longdouble(g.h) ** 2
+    assert np.all(np.abs(col[1:9] / want.astype(np.float64) - 1) < 1e-12)
