@@ -64,7 +64,9 @@ enum { IBDL_METHOD_DL = 0, IBDL_METHOD_SL = 1 };
 
 typedef struct {
   int32_t dim;        /* 2 or 3                                                             */
-  int64_t n[3];       /* grid points per axis (x, y, z): powers of two in [16, 1024]        */
+  int64_t n[3];       /* grid points per axis (x, y, z): powers of two in [16, 1024]; in 2-D
+                         up to 8192 (the handle entry points; batches and the allocation-free
+                         grid solve keep 1024)                                               */
   double  L[3];       /* box lengths; h = L[d]/n[d] must be equal on every axis (Sec. 2.2.1) */
   double  origin[3];  /* nodes at origin + j*h                                              */
   int32_t pde;        /* IBDL_PDE_SCREENED (L = Delta - kappa^2, kappa > 0),

@@ -228,33 +228,42 @@ __device__ __forceinline__ void fft_line(C* v, int i, C* lds, int es, const C* _
   }
 }
 
-// copy the twiddle table (n entries) into LDS at dst; the first read follows a block barrier
+// copy n twiddles tw[e * tws] into LDS at dst; the first read follows a block barrier
 template <typename C>
-__device__ __forceinline__ const C* stage_table(C* dst, const C* __restrict__ tw, int n, int tid, int nthr) {
-  for (int e = tid; e < n; e += nthr) dst[e] = tw[e];
+__device__ __forceinline__ const C* stage_table(C* dst, const C* __restrict__ tw, int n, int tid, int nthr,
+                                                int tws = 1) {
+  for (int e = tid; e < n; e += nthr) dst[e] = tw[e * tws];
   return dst;
 }
 
 constexpr int pow2floor(int v) { return v >= 2 ? 2 * pow2floor(v / 2) : 1; }
 
-// rows per block of the x-axis passes: as many as fit 256 threads and 64 KiB of LDS beside the
-// twiddle table
+// Rows per block of the x-axis passes (rows of M = nx / 2 complex points).  Up to M = 1024: as many
+// rows as fit 256 threads and 64 KiB of LDS beside the twiddle table.  Longer rows (M = 2048, 4096:
+// 4096 and 8192 points along x) take one row per block and M / 8 threads, and read the twiddle table
+// from global memory (it stays in L2), which leaves the row alone in LDS (up to 72 KiB) and two or
+// more blocks per CU.
+constexpr int kMaxRow = 4096;
 constexpr int xrmax(int M) { return plan_rmax(M) < 8 ? plan_rmax(M) : 8; }   // elements per thread, x passes
 template <typename TR, int M> struct RowCfg {
   static constexpr int RMX = xrmax(M);
   static constexpr int T = Plan<M, RMX>::T;
+  static constexpr int BLK = T > kBlock ? T : kBlock;   // launch bound
+  static constexpr bool TWL = M <= 1024;                 // twiddle table staged in LDS
+  static constexpr int SZ = (int)sizeof(cplx<TR>);
   static constexpr int PAD = 3;      // line exchanges pad one slot every 8 elements
   static constexpr int LS = M + (M >> PAD) + 1;  // LDS row stride (complex elements)
-  static constexpr int R0 = kBlock / T;
-  static constexpr int RL = pow2floor((kLdsBytes - 2 * M * (int)sizeof(cplx<TR>)) / (LS * (int)sizeof(cplx<TR>)));
+  static constexpr int R0 = BLK / T;
+  static constexpr int RL = TWL ? pow2floor((kLdsBytes - 2 * M * SZ) / (LS * SZ)) : 1;
   static constexpr int RPB = (R0 < RL ? R0 : RL) > 0 ? (R0 < RL ? R0 : RL) : 1;
   static constexpr int NT = RPB * T;  // threads per block
-  static_assert((RPB * LS + 2 * M) * (int)sizeof(cplx<TR>) <= 65536, "x pass: LDS over 64 KiB");
+  static constexpr int LDSB = (RPB * LS + (TWL ? 2 * M : 0)) * SZ;
+  static_assert(TWL ? LDSB <= kLdsBytes : LDSB <= 163840, "x pass: LDS over budget");
 };
 
 // ------------------------------------------------------------------ x axis, forward R2C
 template <typename T, int M>
-__global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
+__global__ __launch_bounds__((RowCfg<T, M>::BLK)) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
                                                   int64_t nrows, const cplx<T>* __restrict__ twg, int RPB,
                                                   RowList rl, int64_t pitch) {
   using C = cplx<T>;
@@ -263,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
   const int NT = RPB * RC::T;
-  const C* tw = stage_table(lds + RPB * RC::LS, twg, 2 * M, tid, NT);
+  const C* tw = RC::TWL ? stage_table(lds + RPB * RC::LS, twg, 2 * M, tid, NT) : twg;
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   __shared__ int64_t rbase[kBlock];   // row index of each block row (active-row list or contiguous)
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
   const int row = tid / RC::T, i = tid - row * RC::T;
   C v[RC::RMX];
   if (row < RPB) line_load<M, RC::RMX>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, false, false, RC::RMX, RC::PAD>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
+  fft_line<M, false, !RC::TWL, RC::RMX, RC::PAD>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
   if (row < RPB) {
 #pragma unroll
@@ -326,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, cplx
 
 // ------------------------------------------------------------------ x axis, inverse C2R
 template <typename T, int M>
-__global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
+__global__ __launch_bounds__((RowCfg<T, M>::BLK)) void k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                   int64_t nrows, const cplx<T>* __restrict__ twg, int RPB,
                                                   RowList rl, int64_t pitch) {
   using C = cplx<T>;
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
   const int NT = RPB * RC::T;
-  const C* tw = stage_table(lds + RPB * RC::LS, twg, 2 * M, tid, NT);
+  const C* tw = RC::TWL ? stage_table(lds + RPB * RC::LS, twg, 2 * M, tid, NT) : twg;
   const int64_t row0 = (int64_t)blockIdx.x * RPB;
   const int nvalid = (int)((nrows - row0) < RPB ? (nrows - row0) : RPB);
   __shared__ int64_t rbase[kBlock];
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r(const cplx<T>* __restrict__ in
   const int row = tid / RC::T, i = tid - row * RC::T;
   C v[RC::RMX];
   if (row < RPB) line_load<M, RC::RMX>(v, i, lds + row * RC::LS, 1);
-  fft_line<M, true, false, RC::RMX, RC::PAD>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
+  fft_line<M, true, !RC::TWL, RC::RMX, RC::PAD>(v, i, lds + (row < RPB ? row : 0) * RC::LS, 1, tw, 2);
   __syncthreads();
   if (row < RPB) {
 #pragma unroll
@@ -528,7 +537,45 @@ __device__ __forceinline__ cplx<T> stokes_coef(const MultDesc& md, int fk, int o
   }
 }
 
-template <typename T, int N, int NO, bool STOKES>
+// Where a line of the last-axis passes lives and which modes it holds.  3-D: line l of the (jy, jx)
+// plane, elements strided by P, element e is mode e; 2-D: line jx, elements strided by P = nxp.
+// SPLIT (2-D lines of a four-step y transform, md.split = N1, see fft_fused_last): line
+// (jx, k1 = l / nxp) holds the y modes k1 + N1 e, stored from row k1 N with stride nxp, and takes the
+// twiddles w_n^(e k1) between the two factors' transforms.
+template <int N, bool SPLIT> struct LineGeo {
+  unsigned base, es;   // first element, element stride
+  int k1, ms;
+  __device__ __forceinline__ LineGeo(const MultDesc& md, int l, int64_t P, int jx, int jy2) {
+    if constexpr (SPLIT) {
+      base = (unsigned)(jy2 * N * md.nxp + jx);
+      es = (unsigned)md.nxp;
+      k1 = jy2;
+      ms = md.split;
+    } else {
+      base = (unsigned)l;
+      es = (unsigned)P;
+      k1 = 0;
+      ms = 1;
+    }
+  }
+  __device__ __forceinline__ int mode(int e) const {   // mode index along the line of element e
+    if constexpr (SPLIT) return k1 + ms * e;
+    else return e;
+  }
+  __device__ __forceinline__ int tws() const { return SPLIT ? ms : 1; }   // twiddle stride of the N-point transforms
+};
+
+// the four-step twiddles w_n^(e k1) (conjugated for the inverse) on a line's register elements
+template <int RM, int TT, typename C>
+__device__ __forceinline__ void split_twiddle(C* v, int i, int k1, const C* __restrict__ twn, bool inv) {
+  C w[RM];
+#pragma unroll
+  for (int s = 0; s < RM; ++s) w[s] = twn[(i + s * TT) * k1];
+#pragma unroll
+  for (int s = 0; s < RM; ++s) v[s] = cmul(v[s], inv ? cconj(w[s]) : w[s]);
+}
+
+template <typename T, int N, int NO, bool STOKES, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                   const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
@@ -538,15 +585,18 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
-  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
+  const int tws = SPLIT ? md.split : 1;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
+  const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
   const int l = blockIdx.x * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
-  // mode indices of this line: 2-D l = jx, e = jy; 3-D l = jy*nxh + jx, e = jz
+  // mode indices of this line: 2-D l = jx (+ nxp k1 with a split), e = jy; 3-D l = jy*nxh + jx, e = jz
   const int jx = (int)(valid ? l % md.nxp : 0);
   const int jy2 = (int)(valid ? l / md.nxp : 0);
   const bool d3 = md.dim == 3;
+  const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);   // symbols along the line
   const T* ktl_ = static_cast<const T*>(md.kt[d3 ? 2 : 1]);
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
@@ -569,13 +619,13 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   if constexpr (!STOKES) {
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
-      const T den = (T)md.c2 * (sig_l + sgl[i + s * TT]) - (T)md.c0;
+      const T den = (T)md.c2 * (sig_l + sgl[lg.mode(i + s * TT)]) - (T)md.c0;
       gfac[s] = den == (T)0 ? (T)0 : (T)(md.alpha * md.sc) * recip(den);
     }
   } else {
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
-      const T ell = -(sig_l + sgl[i + s * TT]);
+      const T ell = -(sig_l + sgl[lg.mode(i + s * TT)]);
       gfac[s] = ell == (T)0 ? (T)0 : recip(ell);
       const T lam = (T)md.c2 * ell + (T)md.c0;
       glam[s] = lam == (T)0 ? (T)0 : recip(lam);
@@ -584,8 +634,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 
   for (int f = 0; f < md.nc; ++f) {
     C v[RM];
-    line_gload<N, RM>(v, data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
-    fft_line<N, false, !TC::TWL, RM>(v, i, lds + c, W, tw, 1);
+    line_gload<N, RM>(v, data, (unsigned)(f * FS + lg.base), lg.es, i, valid, rm);
+    if constexpr (SPLIT) split_twiddle<RM, TT>(v, i, lg.k1, twg, false);
+    fft_line<N, false, !TC::TWL, RM>(v, i, lds + c, W, tw, ltws);
     const int fk = md.fk[f];
     if constexpr (!STOKES) {
       if (fk == FK_MASS) {
@@ -593,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
         for (int s = 0; s < RM; ++s) acc[0][s] = cadd(acc[0][s], cscale(v[s], gfac[s]));
       } else if (fk == la) {   // derivative along the line axis: k~ varies per element
 #pragma unroll
-        for (int s = 0; s < RM; ++s) acc[0][s] = cadd(acc[0][s], mul_ir(v[s], gfac[s] * ktl_[i + s * TT]));
+        for (int s = 0; s < RM; ++s) acc[0][s] = cadd(acc[0][s], mul_ir(v[s], gfac[s] * ktl_[lg.mode(i + s * TT)]));
       } else {                 // derivative across lines: k~ is constant on the line
         const T kc = ktl[fk];
 #pragma unroll
@@ -602,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
     } else {
 #pragma unroll
       for (int s = 0; s < RM; ++s) {   // Stokes is two-dimensional: k~ = (k~ across lines, k~ along)
-        const int e = i + s * TT;
+        const int e = lg.mode(i + s * TT);
         const T sig = sig_l + sgl[e];
 #pragma unroll
         for (int o = 0; o < NO; ++o)
@@ -612,14 +663,15 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   }
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    fft_line<N, true, !TC::TWL, RM>(acc[o], i, lds + c, W, tw, 1);
-    line_gstore<N, RM>(acc[o], data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, true, !TC::TWL, RM>(acc[o], i, lds + c, W, tw, ltws);
+    if constexpr (SPLIT) split_twiddle<RM, TT>(acc[o], i, lg.k1, twg, true);
+    line_gstore<N, RM>(acc[o], data, (unsigned)(o * FS + lg.base), lg.es, i, valid, rm);
   }
 }
 
 // Single scalar field (the finite-difference operator and the scalar grid solve): forward FFT,
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
-template <typename T, int N>
+template <typename T, int N, bool SPLIT>
 __global__ __launch_bounds__(kLineBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                        const cplx<T>* __restrict__ twg, int W, int64_t bstride,
                                                        RowMask rm) {
@@ -630,33 +682,38 @@ __global__ __launch_bounds__(kLineBlock) void k_fused1(cplx<T>* __restrict__ dat
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
-  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
+  const int tws = SPLIT ? md.split : 1;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
+  const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
   const int l = blockIdx.x * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int jx = (int)(valid ? l % md.nxp : 0);
   const int jy2 = (int)(valid ? l / md.nxp : 0);
   const bool d3 = md.dim == 3;
+  const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
   if (d3) sig_l += static_cast<const T*>(md.sig[1])[jy2];
   C v[RM];
-  line_gload<N, RM>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
-  fft_line<N, false, !TC::TWL, RM>(v, i, lds + c, W, tw, 1);
+  line_gload<N, RM>(v, data, lg.base, lg.es, i, valid, rm);
+  if constexpr (SPLIT) split_twiddle<RM, TT>(v, i, lg.k1, twg, false);
+  fft_line<N, false, !TC::TWL, RM>(v, i, lds + c, W, tw, ltws);
   const T num = (T)(md.alpha * md.sc), c2 = (T)md.c2, c0 = (T)md.c0;
 #pragma unroll
   for (int s = 0; s < RM; ++s) {
-    const T den = c2 * (sig_l + sgl[i + s * TT]) - c0;
+    const T den = c2 * (sig_l + sgl[lg.mode(i + s * TT)]) - c0;
     v[s] = cscale(v[s], den == (T)0 ? (T)0 : num * recip(den));
   }
-  fft_line<N, true, !TC::TWL, RM>(v, i, lds + c, W, tw, 1);
-  line_gstore<N, RM>(v, data, (unsigned)l, (unsigned)P, i, valid, rm);
+  fft_line<N, true, !TC::TWL, RM>(v, i, lds + c, W, tw, ltws);
+  if constexpr (SPLIT) split_twiddle<RM, TT>(v, i, lg.k1, twg, true);
+  line_gstore<N, RM>(v, data, lg.base, lg.es, i, valid, rm);
 }
 
 // Transposed / multi-output pass: the NI input spectra stay in registers after their forward
 // FFTs and the no outputs are formed, inverse transformed and stored one at a time (inputs are
 // all read before the first store, and each workgroup owns its lines in every field).
-template <typename T, int N, int NI, int MODE>
+template <typename T, int N, int NI, int MODE, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data, int64_t P, int no, MultDesc md,
                                                       const cplx<T>* __restrict__ twg, int W, int64_t bstride, RowMask rm) {
   using C = cplx<T>;
@@ -666,7 +723,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   C* lds = reinterpret_cast<C*>(smem);
   data += (int64_t)blockIdx.y * bstride;   // problem of a batch
   const int tid = threadIdx.x;
-  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
+  const int tws = SPLIT ? md.split : 1;
+  const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
+  const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
   const int l = blockIdx.x * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
@@ -674,6 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   const int jx = (int)(valid ? l % md.nxp : 0);
   const int jy2 = (int)(valid ? l / md.nxp : 0);
   const bool d3 = md.dim == 3;
+  const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
   const T* ktl_ = static_cast<const T*>(md.kt[d3 ? 2 : 1]);
   T sig_l = static_cast<const T*>(md.sig[0])[jx];
@@ -689,14 +749,15 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   C v[NI][RM];
 #pragma unroll
   for (int f = 0; f < NI; ++f) {
-    line_gload<N, RM>(v[f], data, (unsigned)(f * FS + l), (unsigned)P, i, valid, rm);
-    fft_line<N, false, !TC::TWL, RM>(v[f], i, lds + c, W, tw, 1);
+    line_gload<N, RM>(v[f], data, (unsigned)(f * FS + lg.base), lg.es, i, valid, rm);
+    if constexpr (SPLIT) split_twiddle<RM, TT>(v[f], i, lg.k1, twg, false);
+    fft_line<N, false, !TC::TWL, RM>(v[f], i, lds + c, W, tw, ltws);
   }
   for (int o = 0; o < no; ++o) {
     C acc[RM];
 #pragma unroll
     for (int s = 0; s < RM; ++s) {
-      const int e = i + s * TT;
+      const int e = lg.mode(i + s * TT);
       T kt[3] = {ktl[0], ktl[1], ktl[2]};
       kt[la] = ktl_[e];
       const T sig = sig_l + sgl[e];
@@ -711,8 +772,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
         for (int f = 0; f < NI; ++f) acc[s] = cadd(acc[s], cmul(cconj(mult_coef<T>(md, md.fk[o], f, sig, kt)), v[f][s]));
       }
     }
-    fft_line<N, true, !TC::TWL, RM>(acc, i, lds + c, W, tw, 1);
-    line_gstore<N, RM>(acc, data, (unsigned)(o * FS + l), (unsigned)P, i, valid, rm);
+    fft_line<N, true, !TC::TWL, RM>(acc, i, lds + c, W, tw, ltws);
+    if constexpr (SPLIT) split_twiddle<RM, TT>(acc, i, lg.k1, twg, true);
+    line_gstore<N, RM>(acc, data, (unsigned)(o * FS + lg.base), lg.es, i, valid, rm);
   }
 }
 
@@ -730,6 +792,19 @@ template <typename F> void dispatch_n(int n, F&& f) {
     default: throw Error(-2, "unsupported FFT length " + std::to_string(n));
   }
 }
+// x-pass rows: M = nx / 2 up to kMaxRow
+template <typename F> void dispatch_row(int m, F&& f) {
+  switch (m) {
+    case 2048: f(std::integral_constant<int, 2048>{}); break;
+    case 4096: f(std::integral_constant<int, 4096>{}); break;
+    default: dispatch_n(m, f);
+  }
+}
+
+// Lines longer than kMaxLine (2-D y axis of 2048 to 8192 points) run as a four-step transform
+// n = kSplit * (n / kSplit): see fft_fused_last.
+constexpr int kMaxLine = 1024;
+constexpr int kSplit = 8;
 
 }  // namespace
 
@@ -738,14 +813,14 @@ int fft_supported(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
 template <typename T>
 int fft_x_rpb_max(int nx) {
   int r = 0;
-  dispatch_n(nx / 2, [&](auto Mc) { r = RowCfg<T, decltype(Mc)::value>::RPB; });
+  dispatch_row(nx / 2, [&](auto Mc) { r = RowCfg<T, decltype(Mc)::value>::RPB; });
   return r;
 }
 
 template <typename T>
 int fft_line_w_max(int n) {
   int r = 0;
-  dispatch_n(n, [&](auto Nc) { r = LineCfg<T, decltype(Nc)::value>::W; });
+  dispatch_n(n > kMaxLine ? n / kSplit : n, [&](auto Nc) { r = LineCfg<T, decltype(Nc)::value>::W; });
   return r;
 }
 
@@ -762,12 +837,12 @@ template <typename T>
 void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
                const RowList& rl, int64_t pitch) {
   if (pitch <= 0) pitch = nx / 2 + 1;
-  dispatch_n(nx / 2, [&](auto Mc) {
+  dispatch_row(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
     const int R = pick(rpb, RC::RPB);
     const int64_t nb = (nrows + R - 1) / R;
-    const size_t lds = sizeof(cplx<T>) * (R * RC::LS + 2 * M);
+    const size_t lds = sizeof(cplx<T>) * (R * RC::LS + (RC::TWL ? 2 * M : 0));
     if (nb > 0)
       hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
                          pitch);
@@ -779,12 +854,12 @@ template <typename T>
 void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
                const RowList& rl, int64_t pitch) {
   if (pitch <= 0) pitch = nx / 2 + 1;
-  dispatch_n(nx / 2, [&](auto Mc) {
+  dispatch_row(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
     using RC = RowCfg<T, M>;
     const int R = pick(rpb, RC::RPB);
     const int64_t nb = (nrows + R - 1) / R;
-    const size_t lds = sizeof(cplx<T>) * (R * RC::LS + 2 * M);
+    const size_t lds = sizeof(cplx<T>) * (R * RC::LS + (RC::TWL ? 2 * M : 0));
     if (nb > 0)
       hipLaunchKernelGGL((k_x_c2r<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
                          pitch);
@@ -821,6 +896,28 @@ template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw, hipStream_t s,
                     int batch, int64_t bstride, int w, const RowMask& rm) {
   if (batch < 1) return;
+  if (n > kMaxLine) {
+    // Four-step transform of the 2-D y lines, n = N1 N2 (N1 = kSplit): with y = j1 N2 + j2 and mode
+    // k = k1 + N1 k2, the n-point DFT is an N1-point DFT over j1 for each j2 (a strided pass whose
+    // result k1 stays at row k1 N2 + j2), the twiddles w_n^(j2 k1), and an N2-point DFT over j2 for
+    // each k1, which leaves mode k1 + N1 k2 at row k1 N2 + k2.  The fused pass runs on those N2-point
+    // lines (twiddles, transform, multiplier at the modes they hold, inverse, conjugate twiddles) and
+    // an inverse N1-point pass per output field restores natural order.  Row masks do not carry over
+    // to the split lines: the caller provides dense fields (every row valid) and takes every row back.
+    if (md.dim != 2 || batch != 1 || n % kSplit != 0 || n / kSplit > kMaxLine)
+      throw Error(-2, "fused FFT pass: lines over 1024 points are supported for single 2-D problems up to 8192");
+    const int N2 = n / kSplit;
+    const int64_t FS = P * n;
+    const int64_t nin = std::max(md.nc, 1);
+    for (int64_t f = 0; f < nin; ++f)
+      fft_strided<T>(data + f * FS, kSplit, P * N2, P, P, (int64_t)N2 * P, false, tw, s, 0, RowMask(), md.nxh);
+    MultDesc m2 = md;
+    m2.split = kSplit;
+    fft_fused_last<T>(data, N2, P * kSplit, no, m2, tw, s, 1, 0, w, RowMask());
+    for (int o = 0; o < no; ++o)
+      fft_strided<T>(data + o * FS, kSplit, P * N2, P, P, (int64_t)N2 * P, true, tw, s, 0, RowMask(), md.nxh);
+    return;
+  }
   const int64_t nf = std::max<int64_t>(std::max(md.nc, no), 1);
   if (nf * P * n * (int64_t)sizeof(cplx<T>) > (int64_t)UINT32_MAX || P > INT32_MAX)
     throw Error(-2, "fused FFT pass: one problem's fields may not span 4 GiB");
@@ -834,31 +931,45 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       blk = dim3(W * TC::T_);
       lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
     };
-    int W = 0;
-    dim3 grid, blk;
-    size_t lds = 0;
-    if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1) {
-      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
-      hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
-    } else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5) {
-      shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
-      hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
-    } else if (md.mode == 3 && md.stokes && md.dim == 2 && no == 1) {
-      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
-      hipLaunchKernelGGL((k_fused<T, N, 1, true>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    } else if (md.mode != 0) {
-      throw Error(-2, "fused pass: unsupported transposed multiplier");
-    } else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS) {
-      shape(LineCfg<T, N>{}, W, grid, blk, lds);
-      hipLaunchKernelGGL((k_fused1<T, N>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    } else if (!md.stokes && no == 1) {
-      shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
-      hipLaunchKernelGGL((k_fused<T, N, 1, false>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
-    } else if (md.stokes && no == 2) {
-      shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
-      hipLaunchKernelGGL((k_fused<T, N, 2, true>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+    auto run = [&](auto splitc) {
+      constexpr bool SP = decltype(splitc)::value;
+      int W = 0;
+      dim3 grid, blk;
+      size_t lds = 0;
+      if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1) {
+        shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
+        hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1, SP>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
+      } else if (md.mode == 2 && md.stokes && md.nc == 2 && no >= 1 && no <= 5) {
+        shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
+        hipLaunchKernelGGL((k_fused_adj<T, N, 2, 2, SP>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
+      } else if (md.mode == 3 && md.stokes && md.dim == 2 && no == 1) {
+        shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
+        hipLaunchKernelGGL((k_fused<T, N, 1, true, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+      } else if (md.mode != 0) {
+        throw Error(-2, "fused pass: unsupported transposed multiplier");
+      } else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS) {
+        shape(LineCfg<T, N>{}, W, grid, blk, lds);
+        hipLaunchKernelGGL((k_fused1<T, N, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+      } else if (!md.stokes && no == 1) {
+        shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
+        hipLaunchKernelGGL((k_fused<T, N, 1, false, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+      } else if (md.stokes && no == 2) {
+        shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
+        hipLaunchKernelGGL((k_fused<T, N, 2, true, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+      } else {
+        throw Error(-2, "fused pass: unsupported multiplier / output count");
+      }
+    };
+    if (md.split > 1) {
+      // the factor lines of 2048- to 8192-point y axes
+      if constexpr (N >= kMaxLine * 2 / kSplit) {
+        if (md.dim != 2 || batch != 1) throw Error(-2, "fused pass: four-step lines are single 2-D problems");
+        run(std::true_type{});
+      } else {
+        throw Error(-2, "fused pass: four-step lines of " + std::to_string(N) + " points are not built");
+      }
     } else {
-      throw Error(-2, "fused pass: unsupported multiplier / output count");
+      run(std::false_type{});
     }
   });
   IBDL_LAUNCH_CHECK();

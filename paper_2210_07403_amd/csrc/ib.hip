@@ -164,7 +164,8 @@ __global__ void k_wtab(const double* __restrict__ wt, int64_t n_ib, cplx<T>* __r
   tab[e] = t < 6 ? mk<cplx<T>>((T)wt[r * 12 + t], (T)wt[r * 12 + 6 + t]) : mk<cplx<T>>((T)0, (T)0);
 }
 
-// busy tiles along x of each listed row as a bit mask (tile (t, strip of the row) for t < ntx)
+// busy tiles along x of each listed row as a bit mask: bit t >> seg_group_log2 for tile (t, strip of
+// the row), t < ntx
 __global__ void k_row_segments(MarkerGeom g, const int* __restrict__ tile_off, const int* __restrict__ rows,
                                int64_t nact, unsigned long long* __restrict__ seg) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,10 +174,11 @@ __global__ void k_row_segments(MarkerGeom g, const int* __restrict__ tile_off, c
   // z counts planes, or problems of a batch in 2-D (tile[2] = 1 there): tiles are numbered
   // problem-major, so the strip index runs on across a batch's problems
   const int64_t strip = y / g.tile[1] + (int64_t)g.ntile[1] * (z / g.tile[2]);
+  const int gs = seg_group_log2(g);
   unsigned long long m = 0;
   for (int t = 0; t < g.ntile[0]; ++t) {
     const int64_t id = strip * g.ntile[0] + t;
-    if (tile_off[id + 1] > tile_off[id]) m |= 1ull << t;
+    if (tile_off[id + 1] > tile_off[id]) m |= 1ull << (t >> gs);
   }
   seg[r] = m;
 }
@@ -987,7 +989,6 @@ void exclusive_scan(const int* cnt, int* off, int n, hipStream_t st) {
 
 void markers_row_segments(const MarkerGeom& g, const int* tile_off, const int* rows, int64_t nact,
                           unsigned long long* seg, hipStream_t st) {
-  if (g.ntile[0] > 64) throw Error(-2, "markers_row_segments: more than 64 tiles along x");
   if (nact <= 0) return;
   hipLaunchKernelGGL(k_row_segments, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, st, g, tile_off, rows, nact,
                      seg);

@@ -316,13 +316,17 @@ template <typename T>
 void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md,
               int rows = ROWS_DENSE, bool busy_only = false, const T* sub = nullptr, int sub_f0 = 0, int nsub = 0) {
   const int64_t rows_per_field = h->ntot / h->n[0];
-  const bool sin = rows == ROWS_SPARSE, sout = rows != ROWS_DENSE;
+  // 2-D grids of more than 1024 points along y: the last-axis pass is a four-step transform that
+  // reads and writes every row, so the forward x pass covers every row (those the markers do not
+  // reach come out zero without being read) and the y row limits are not applied
+  const bool split = h->dim == 2 && h->n[1] > 1024;
+  const bool sin = rows == ROWS_SPARSE && !split, sout = rows != ROWS_DENSE;
   RowList rl_in, rl_out;
   RowMask fwd, inv, fused;
   rl_in.rpf = rows_per_field;
   if (busy_only) {   // src holds a spread's output: only its busy tiles were written
     rl_in.seg = sin ? h->seg : h->seg_all;
-    rl_in.seg_log2 = __builtin_ctz((unsigned)h->geom.tile[0] / 2);
+    rl_in.seg_log2 = __builtin_ctz((unsigned)h->geom.tile[0] / 2) + seg_group_log2(h->geom);
   }
   rl_in.sub = sub;   // minus a dense forcing on fields sub_f0 .. sub_f0 + nsub - 1
   rl_in.sub_f0 = sub_f0;
@@ -340,7 +344,7 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
       fwd.nplanes = inv.nplanes = h->n[2];
       fwd.load = sin ? 1 : 0;
       inv.store = 1;
-    } else {
+    } else if (!split) {
       fused.load = sin ? 1 : 0;
       fused.store = 1;
       fused.lo = h->lim2d[0];
@@ -397,8 +401,11 @@ SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
   return a;
 }
 
-// the spread with this precision's tables and coefficient scratch
+// the spread with this precision's tables and coefficient scratch.  Where a busy-segment bit covers
+// several x-tiles (2-D grids over 1024 points wide) the idle tiles of a busy segment are read too, so
+// the output fields are cleared first.
 template <typename T> void spread_w(ibdl_s* h, SpreadArgs a, GridWork<T>& W, T* out) {
+  if (seg_group_log2(h->geom) > 0) grid_fill_zero<T>(out, (int64_t)a.nf * h->ntot, h->st);
   spread<T>(a, W.wtab, out, h->st);
 }
 
@@ -1032,7 +1039,9 @@ int backward_t(ibdl_s* h, const double* q, const T* u, const T* psi, double tol,
   return status;
 }
 
-bool pow2_in_range(int64_t v) { return v >= 16 && v <= 1024 && (v & (v - 1)) == 0; }
+// grid points per axis: powers of two from 16 to 1024, and in 2-D up to 8192 (lines over 1024
+// points run as four-step transforms)
+bool pow2_in_range(int64_t v, int dim) { return v >= 16 && v <= (dim == 2 ? 8192 : 1024) && (v & (v - 1)) == 0; }
 
 void validate(const ibdl_config_t* c, int64_t n_ib) {
   if (!c) throw Error(IBDL_ERR_ARG, "cfg is NULL");
@@ -1040,7 +1049,8 @@ void validate(const ibdl_config_t* c, int64_t n_ib) {
   if (n_ib < 1 || n_ib > (int64_t)1 << 30) throw Error(IBDL_ERR_ARG, "n_ib out of range");
   double h0 = 0;
   for (int d = 0; d < c->dim; ++d) {
-    if (!pow2_in_range(c->n[d])) throw Error(IBDL_ERR_UNSUPPORTED, "grid size must be a power of two in [16, 1024]");
+    if (!pow2_in_range(c->n[d], c->dim))
+      throw Error(IBDL_ERR_UNSUPPORTED, "grid size must be a power of two in [16, 1024] (in 2-D up to 8192)");
     if (!(c->L[d] > 0) || !std::isfinite(c->L[d]) || !std::isfinite(c->origin[d]))
       throw Error(IBDL_ERR_ARG, "box lengths must be positive and finite");
     const double hd = c->L[d] / (double)c->n[d];

@@ -76,6 +76,7 @@ struct MultDesc {
   double alpha;     // overall sign / factor
   const void* sig[3];  // per-axis Laplacian symbol components (grid type)
   const void* kt[3];   // per-axis derivative symbols k~ (grid type)
+  int split;           // 2-D lines of a four-step y transform: N1 > 1 (set by fft_fused_last); 0 or 1: none
 };
 
 // Tunable launch shapes: rpb = rows per block of the x passes, w = lines per block of the strided
@@ -103,6 +104,8 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
 // mode 2 (two Stokes components): output o = sum_c conj(m(fk[o], c)) F^_c, the transpose of the
 // forward Stokes multiplier m(kind, component).
 // batch problems with the same multiplier: problem b's fields start bstride elements after b-1's.
+// 2-D lines of 2048 to 8192 points (one problem) run as a four-step transform in three passes; their
+// fields must be valid on every row (rm is not applied) and every output row is written.
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw,
                     hipStream_t s, int batch = 1, int64_t bstride = 0, int w = 0,
@@ -120,6 +123,13 @@ struct MarkerGeom {
   int tile[3];         // tile edge per axis (2-D: 16 x 16; 3-D: 16 x 4 x 8)
   int ntile[3];        // tiles per axis
 };
+// log2 of the x-tiles per bit of the busy-segment masks (RowList::seg): 0 up to 64 tiles along x;
+// wider 2-D grids group 2, 4, ... tiles per bit, since a mask has 64 bits
+__host__ __device__ inline int seg_group_log2(const MarkerGeom& g) {
+  int s = 0;
+  while ((g.ntile[0] >> s) > 64) ++s;
+  return s;
+}
 
 // marker setup: window start s[i][3] (wrapped), fractional offset f[i][3], weight table
 // wt[i][3][12] (kernel weights W[0..5] and centred differences G[0..5] on the window), tile counts
@@ -140,7 +150,7 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
 void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int* hi, int* cnt, int* off, int2* lim,
                   int* rows, hipStream_t st);
 // seg[r] = bit mask of the busy tiles along x that listed row r (rows[r], r < nact; row r itself
-// when rows is NULL) passes through (ntile[0] <= 64)
+// when rows is NULL) passes through, 2^seg_group_log2(g) tiles per bit
 void markers_row_segments(const MarkerGeom& g, const int* tile_off, const int* rows, int64_t nact,
                           unsigned long long* seg, hipStream_t st);
 

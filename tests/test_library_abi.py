@@ -54,7 +54,8 @@ def _cfg(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(dim=4), -1),
     (dict(n=(63, 64, 64)), -2),
-    (dict(n=(2048, 2048, 1)), -2),
+    (dict(n=(16384, 16384, 1)), -2),          # 2-D grids go up to 8192
+    (dict(dim=3, n=(2048, 2048, 2048)), -2),  # 3-D up to 1024
     (dict(L=(1.0, 2.0, 1.0)), -1),
     (dict(kappa=-1.0), -1),
     (dict(kappa=0.0), -1),                    # screened needs kappa > 0
