@@ -31,7 +31,12 @@
  *     run the Krylov iteration and to fill ibdl_info_t.
  *   - One host thread per handle at a time.  Calls that overlap on one handle race.
  *   - Errors: a negative status; outputs are then unspecified and ibdl_last_error() describes the
- *     failure.  Arguments are validated on the host; device data are not inspected.
+ *     failure.  Arguments are validated on the host.  Device data are inspected only when the
+ *     environment holds IBDL_CHECK=1 as the handle is created: then ibdl_create,
+ *     ibdl_set_markers, ibdl_apply, ibdl_apply_transpose, ibdl_grid_solve, ibdl_solve,
+ *     ibdl_solve_refined and ibdl_backward scan the arrays they take and return for NaN and
+ *     infinities (one device pass and one stream synchronisation per array; not for use under
+ *     graph capture) and return IBDL_ERR_NONFINITE on a hit.
  */
 #ifndef IBDL_H
 #define IBDL_H
@@ -51,7 +56,7 @@ typedef enum {
   IBDL_ERR_UNSUPPORTED = -2,   /* valid but not implemented (e.g. 3-D Stokes, N not 2^k)     */
   IBDL_ERR_NOMEM = -3,         /* device allocation failed                                   */
   IBDL_ERR_HIP = -4,           /* a HIP runtime call failed                                  */
-  IBDL_ERR_NONFINITE = -5,     /* non-finite value met on the host side                      */
+  IBDL_ERR_NONFINITE = -5,     /* non-finite value: a residual, or device data under IBDL_CHECK=1 */
   IBDL_ERR_STATE = -6          /* call not valid in the handle's state                       */
 } ibdl_status_t;
 

@@ -909,6 +909,15 @@ __global__ void k_fill(T* __restrict__ y, int64_t n) {
     y[e] = (T)0;
 }
 
+// flag |= 1 when x holds a NaN or an infinity
+template <typename T>
+__global__ void k_nonfinite(const T* __restrict__ x, int64_t n, unsigned* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(x[e]);
+  if (bad) atomicOr(flag, 1u);
+}
+
 template <typename T>
 __global__ void k_add_const(T* __restrict__ y, const double* __restrict__ cdev, int ncomp, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * ncomp; e += (int64_t)gridDim.x * blockDim.x)
@@ -1016,6 +1025,13 @@ void markers_rows(const MarkerGeom& g, int64_t n_ib, const int* s, int* lo, int*
 template <typename T>
 void grid_fill_zero(T* y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_fill<T>), dim3(grid_blocks(n)), dim3(256), 0, st, y, n);
+  IBDL_LAUNCH_CHECK();
+}
+
+template <typename T>
+void nonfinite_flag(const T* x, int64_t n, unsigned* flag, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_nonfinite<T>), dim3(grid_blocks(n)), dim3(256), 0, st, x, n, flag);
   IBDL_LAUNCH_CHECK();
 }
 
@@ -1141,6 +1157,7 @@ void grid_sum(const T* x, int ncomp, int64_t n, double* partial, int nblk, doubl
   template void spread<T>(const SpreadArgs&, const cplx<T>*, T*, hipStream_t);            \
   template void weight_table<T>(const double*, int64_t, cplx<T>*, hipStream_t);           \
   template void grid_fill_zero<T>(T*, int64_t, hipStream_t);                              \
+  template void nonfinite_flag<T>(const T*, int64_t, unsigned*, hipStream_t);             \
   template void interp<T>(const InterpArgs&, const cplx<T>*, const T*, double*, hipStream_t); \
   template void interp_div<T>(const InterpArgs&, const cplx<T>*, const T*, const double*, const double*, double, \
                               double, const double*, double*, hipStream_t);                \

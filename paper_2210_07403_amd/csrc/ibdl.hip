@@ -86,6 +86,8 @@ struct ibdl_s {
   int64_t nact = 0;
   int64_t seg_read = 0;       // (active row, busy x-segment) pairs the apply's forward x pass reads
   int lim2d[2] = {0, -1};     // 2-D: the one plane's limits, on the host
+  bool check = false;         // IBDL_CHECK=1 at creation: device arrays scanned for NaN / Inf
+  unsigned* chk = nullptr;    // the scan's flag
   MarkerGeom geom{};
   std::unique_ptr<GridWork<float>> w32;
   std::unique_ptr<GridWork<double>> w64;
@@ -1034,7 +1036,7 @@ int backward_t(ibdl_s* h, const double* q, const T* u, const T* psi, double tol,
     info->iters = iters;
     info->status = status;
     info->krylov_relres = relres;
-    info->true_relres_fp64 = bn > 0 ? rn / bn : 0.0;
+    info->true_relres_fp64 = (bn > 0 || std::isnan(bn)) ? rn / bn : 0.0;
   }
   return status;
 }
@@ -1134,6 +1136,28 @@ void build_markers(ibdl_s* h) {
   }
   if (h->w32 && h->w32->wtab) weight_table<float>(h->wt, h->n_ib, h->w32->wtab, h->st);
   if (h->w64 && h->w64->wtab) weight_table<double>(h->wt, h->n_ib, h->w64->wtab, h->st);
+}
+
+// IBDL_CHECK=1: the arrays a call takes and returns are scanned on the device for NaN and
+// infinities; one hit makes the call return IBDL_ERR_NONFINITE.  Each scan waits for the stream.
+template <typename T> void check_finite(ibdl_s* h, const T* p, int64_t n, const char* what) {
+  if (!h->check || !p || n <= 0) return;
+  IBDL_HIP(hipMemsetAsync(h->chk, 0, sizeof(unsigned), h->st));
+  nonfinite_flag<T>(p, n, h->chk, h->st);
+  unsigned v = 0;
+  IBDL_HIP(hipMemcpyAsync(&v, h->chk, sizeof(unsigned), hipMemcpyDeviceToHost, h->st));
+  IBDL_HIP(hipStreamSynchronize(h->st));
+  if (v) throw Error(IBDL_ERR_NONFINITE, std::string(what) + " holds a non-finite value");
+}
+// a grid array of nf fields in the handle's grid type
+void check_grid(ibdl_s* h, const void* p, int nf, const char* what) {
+  if (h->mixed()) check_finite<float>(h, (const float*)p, h->ntot * nf, what);
+  else check_finite<double>(h, (const double*)p, h->ntot * nf, what);
+}
+void check_markers(ibdl_s* h) {
+  check_finite<double>(h, h->X, h->n_ib * h->dim, "X");
+  if (!h->sl) check_finite<double>(h, h->nrm, h->n_ib * h->dim, "nrm");
+  check_finite<double>(h, h->ds, h->n_ib, "ds");
 }
 
 template <typename F> ibdl_status_t guarded(ibdl_s* h, F&& fn) {
@@ -1378,6 +1402,12 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     if (!h->sl) IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * n_ib, hipMemcpyDeviceToDevice, h->st));
+    {
+      const char* e = getenv("IBDL_CHECK");
+      h->check = e && strcmp(e, "1") == 0;
+      if (h->check) h->chk = (unsigned*)h->dalloc<unsigned>(sizeof(unsigned));
+    }
+    check_markers(h.get());
     if (h->sl) sl_markers(h.get());
     build_markers(h.get());
     if (h->mixed()) ensure_work<float>(h.get());
@@ -1399,6 +1429,7 @@ ibdl_status_t ibdl_set_markers(ibdl_t h, const double* X, const double* nrm, con
     IBDL_HIP(hipMemcpyAsync(h->X, X, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     if (!h->sl) IBDL_HIP(hipMemcpyAsync(h->nrm, nrm, sizeof(double) * h->n_ib * h->dim, hipMemcpyDeviceToDevice, h->st));
     IBDL_HIP(hipMemcpyAsync(h->ds, ds, sizeof(double) * h->n_ib, hipMemcpyDeviceToDevice, h->st));
+    check_markers(h);
     if (h->sl) sl_markers(h);
     build_markers(h);
     return IBDL_OK;
@@ -1573,8 +1604,10 @@ ibdl_status_t ibdl_interp(ibdl_t h, const void* grid, int32_t nc, double* f) {
 ibdl_status_t ibdl_grid_solve(ibdl_t h, const void* rhs, void* u) {
   return guarded(h, [&]() {
     if (!rhs || !u) throw Error(IBDL_ERR_ARG, "NULL pointer");
+    check_grid(h, rhs, h->nq, "rhs");
     if (h->mixed()) grid_solve_t<float>(h, (const float*)rhs, (float*)u);
     else grid_solve_t<double>(h, (const double*)rhs, (double*)u);
+    check_grid(h, u, h->nq, "u");
     return IBDL_OK;
   });
 }
@@ -1583,7 +1616,9 @@ ibdl_status_t ibdl_apply(ibdl_t h, const double* q, double* y) {
   return guarded(h, [&]() {
     if (!q || !y) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (q == y) throw Error(IBDL_ERR_ARG, "q and y must not alias");
+    check_finite<double>(h, q, h->n_aug, "q");
     apply_any(h, q, y, false);
+    check_finite<double>(h, y, h->n_aug, "y");
     return IBDL_OK;
   });
 }
@@ -1595,6 +1630,8 @@ ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, doubl
     if (!(tol >= 0) || !std::isfinite(tol)) throw Error(IBDL_ERR_ARG, "tol must be finite and >= 0");
     if (maxit < 1 || maxit > (h->sl ? 1000000 : 200))
       throw Error(IBDL_ERR_ARG, h->sl ? "maxit must be in [1, 1000000]" : "maxit must be in [1, 200]");
+    check_finite<double>(h, data, h->n_ib * h->nq, "data");
+    if (g_grid) check_grid(h, g_grid, h->nq, "g");
     if (h->mixed()) rhs_t<float>(h, data, (const float*)g_grid, h->vb);
     else rhs_t<double>(h, data, (const double*)g_grid, h->vb);
     int iters = 0;
@@ -1638,8 +1675,10 @@ ibdl_status_t ibdl_solve(ibdl_t h, const double* data, const void* g_grid, doubl
       info->iters = iters;
       info->status = status;
       info->krylov_relres = relres;
-      info->true_relres_fp64 = bn > 0 ? rn / bn : 0.0;
+      info->true_relres_fp64 = (bn > 0 || std::isnan(bn)) ? rn / bn : 0.0;
     }
+    check_finite<double>(h, q, h->n_aug, "q");
+    if (u_grid) check_grid(h, u_grid, h->nq, "u");
     return status;
   });
 }
@@ -1652,9 +1691,16 @@ ibdl_status_t ibdl_backward(ibdl_t h, const double* q, const void* u_grid, const
     if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
     if (h->neumann()) throw Error(IBDL_ERR_UNSUPPORTED, "the adjoint is implemented for Dirichlet problems");
     if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "the adjoint is implemented for the double layer method");
-    if (h->mixed())
-      return backward_t<float>(h, q, (const float*)u_grid, (const float*)dL_du, tol, maxit, dL_dX, dL_ddata, info);
-    return backward_t<double>(h, q, (const double*)u_grid, (const double*)dL_du, tol, maxit, dL_dX, dL_ddata, info);
+    check_finite<double>(h, q, h->n_aug, "q");
+    check_grid(h, u_grid, h->nq, "u");
+    check_grid(h, dL_du, h->nq, "dL_du");
+    const int st = h->mixed()
+                       ? backward_t<float>(h, q, (const float*)u_grid, (const float*)dL_du, tol, maxit, dL_dX, dL_ddata, info)
+                       : backward_t<double>(h, q, (const double*)u_grid, (const double*)dL_du, tol, maxit, dL_dX, dL_ddata,
+                                            info);
+    check_finite<double>(h, dL_dX, h->n_ib * h->dim, "dL_dX");
+    check_finite<double>(h, dL_ddata, h->n_ib * h->nq, "dL_ddata");
+    return st;
   });
 }
 
@@ -1663,7 +1709,9 @@ ibdl_status_t ibdl_apply_transpose(ibdl_t h, const double* p, double* y) {
     if (!p || !y) throw Error(IBDL_ERR_ARG, "NULL pointer");
     if (p == y) throw Error(IBDL_ERR_ARG, "p and y must not alias");
     if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "the transposed operator is implemented for the double layer method");
+    check_finite<double>(h, p, h->n_aug, "p");
     apply_any(h, p, y, false, true);
+    check_finite<double>(h, y, h->n_aug, "y");
     return IBDL_OK;
   });
 }
@@ -1677,6 +1725,8 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
     if (maxit < 1 || maxit > 200) throw Error(IBDL_ERR_ARG, "maxit must be in [1, 200]");
     if (max_rounds < 1 || max_rounds > 50) throw Error(IBDL_ERR_ARG, "max_rounds must be in [1, 50]");
     if (h->sl) throw Error(IBDL_ERR_UNSUPPORTED, "refinement is implemented for the double layer method");
+    check_finite<double>(h, data, h->n_ib * h->nq, "data");
+    if (g_grid) check_grid(h, g_grid, h->nq, "g");
     const int64_t n = h->n_aug;
     // right-hand side in double: the forcing of a mixed handle is widened first
     const double* g64 = nullptr;
@@ -1782,8 +1832,10 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
       info->iters = total;
       info->status = status;
       info->krylov_relres = krylov;
-      info->true_relres_fp64 = bn > 0 ? rn / bn : 0.0;
+      info->true_relres_fp64 = (bn > 0 || std::isnan(bn)) ? rn / bn : 0.0;
     }
+    check_finite<double>(h, q, n, "q");
+    if (u_grid) check_grid(h, u_grid, h->nq, "u");
     return status;
   });
 }

@@ -186,6 +186,8 @@ struct SpreadArgs {
 // p's fields at out + p * nf * (grid points).  wtab: per-precision weight table
 // [n_ib][3][8] of (W, G) pairs (weight_table).
 template <typename T> void grid_fill_zero(T* y, int64_t n, hipStream_t st);
+// *flag |= 1 when x[0..n) holds a NaN or an infinity (flag cleared by the caller)
+template <typename T> void nonfinite_flag(const T* x, int64_t n, unsigned* flag, hipStream_t st);
 template <typename T> void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st);
 template <typename T> void weight_table(const double* wt, int64_t n_ib, cplx<T>* tab, hipStream_t st);
 // One grid group of a batch for the single-launch spread: its arguments (q is replaced by

@@ -70,11 +70,12 @@ __global__ void k_scale(const double* __restrict__ src, double s, double* __rest
 }
 
 // dst (and dst2 if set) = src / sqrt(max(*nrm2, 0)); 0 where that norm is not above floor (the
-// Arnoldi breakdown, which the host detects from the same value)
+// Arnoldi breakdown, which the host detects from the same value).  Norms clamp a negative rounding
+// residue to 0 but keep a NaN, so that the host sees non-finite data rather than a zero vector.
 __global__ void k_scale_norm(const double* src, const double* __restrict__ nrm2, double floor, double* dst,
                              double* dst2, int64_t n) {
   const double v = *nrm2;
-  const double h = sqrt(v > 0.0 ? v : 0.0);
+  const double h = sqrt(v < 0.0 ? 0.0 : v);
   const double s = (h > floor && h < INFINITY) ? 1.0 / h : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const double x = src[e] * s;
@@ -364,13 +365,13 @@ __device__ void givens_step(const double* __restrict__ h1, const double* __restr
     double* g = gm_g(gs, mx);
     double beta;
     if (j == 0) {
-      beta = sqrt(bnorm2 > 0.0 ? bnorm2 : 0.0);
+      beta = sqrt(bnorm2 < 0.0 ? 0.0 : bnorm2);
       gs[GM_BETA] = beta;
       g[0] = beta;
     } else {
       beta = gs[GM_BETA];
     }
-    const double hn = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+    const double hn = sqrt(nrm2 < 0.0 ? 0.0 : nrm2);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
       const double t = c_s[i] * col[i] + s_s[i] * col[i + 1];
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(kB) void k_publish_scale(double* h, const double* _
       *reinterpret_cast<volatile unsigned*>(tag) = seq;
     }
   }
-  const double hh = sqrt(v > 0.0 ? v : 0.0);
+  const double hh = sqrt(v < 0.0 ? 0.0 : v);
   const double sc = (hh > 0.0 && hh < INFINITY) ? 1.0 / hh : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv; e += (int64_t)gridDim.x * blockDim.x) {
     const double x = w[e] * sc;
@@ -554,7 +555,7 @@ __global__ __launch_bounds__(kB) void k_arnoldi_small(const double* __restrict__
     __threadfence_system();
     *reinterpret_cast<volatile unsigned*>(tag) = seq;
   }
-  const double nr = sqrt(v > 0.0 ? v : 0.0);
+  const double nr = sqrt(v < 0.0 ? 0.0 : v);
   const double sc = (nr > 0.0 && nr < INFINITY) ? 1.0 / nr : 0.0;
   if (in) {
     const double x = we * sc;
@@ -640,7 +641,7 @@ __global__ __launch_bounds__(kB) void k_batch_arnoldi(const double* __restrict__
   const double nrm2 = wg_tree(sq, &red[0][0]);
   givens_step(hv[0], hv[1], nrm2, bn2[p], j, mx, tol, gs);
   __syncthreads();
-  const double hn = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+  const double hn = sqrt(nrm2 < 0.0 ? 0.0 : nrm2);
   const double beta = gs[GM_BETA];
   const double sc = (hn > 1e-300 * beta && hn < INFINITY) ? 1.0 / hn : 0.0;
   for (int64_t e = threadIdx.x; e < n; e += kB) {
@@ -740,7 +741,7 @@ __global__ __launch_bounds__(1024) void k_batch_arnoldi_r(const double* __restri
   const double nrm2 = sq[0];
   givens_step(hv[0], hv[1], nrm2, bn2[p], j, mx, tol, gs);
   __syncthreads();
-  const double hn = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+  const double hn = sqrt(nrm2 < 0.0 ? 0.0 : nrm2);
   const double beta = gs[GM_BETA];
   const double sc = (hn > 1e-300 * beta && hn < INFINITY) ? 1.0 / hn : 0.0;
 #pragma unroll
@@ -772,7 +773,7 @@ __global__ void k_batch_start(const double* __restrict__ b, const int64_t* __res
                               const int64_t* __restrict__ len, const double* __restrict__ bn2,
                               double* __restrict__ v0, double* __restrict__ xin) {
   const int p = blockIdx.x;
-  const double nb = sqrt(bn2[p] > 0.0 ? bn2[p] : 0.0);
+  const double nb = sqrt(bn2[p] < 0.0 ? 0.0 : bn2[p]);
   const double sc = (nb > 0.0 && nb < INFINITY) ? 1.0 / nb : 0.0;
   for (int64_t e = threadIdx.x; e < len[p]; e += blockDim.x) {
     const double x = b[off[p] + e] * sc;
