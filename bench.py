@@ -358,8 +358,8 @@ def _adjoint_timing(dev):
 def _cylinder_drag(dev):
     """Stokes flow past the periodic cylinder array (area fraction 0.1, 1024^2, spectral,
     ds ~ h, eta = 10, tol 1e-10): solve + recovery time, GMRES iterations, net force, flux and
-    the drag D against the reference value of the thesis's drag table (24.8317; the thesis's own
-    IBDL value on 8192^2 is 24.8368)."""
+    the drag D against the reference value of the thesis's drag table (24.8317); and the FP64 solve
+    on 8192^2, the size of the thesis's own IBDL column (24.8368)."""
     import paper_2210_07403_amd as ibdl
     from workloads import problems as P
     s = P.cylinder_array(1024, 0.1)
@@ -382,6 +382,22 @@ def _cylinder_drag(dev):
                      "D_rel_err_vs_reference": round(D / 24.8317 - 1, 6),
                      "net_force_us": round(1e6 * tf, 1), "line_integral_us": round(1e6 * tu, 1)}
         pr.close()
+    s = P.cylinder_array(8192, 0.1)
+    m = s.markers
+    pr = ibdl.Problem(s.dim, s.n, s.L, s.origin, m.X, m.nrm, m.ds, pde=s.pde, kappa=s.kappa, mu=s.mu,
+                      eta=s.eta, kernel=s.kernel, disc=s.disc, precision="fp64", device=dev)
+    g = pr._as_grid(s.g, 2)
+    pr.solve(s.data, g, tol=1e-10, maxit=200)
+    t, (q, u, info) = _timed(lambda: pr.solve(s.data, g, tol=1e-10, maxit=200), 2)
+    F = pr.net_force(q).cpu().tolist()
+    U = float(pr.line_integral(u, 0, 0, 0).cpu()[0])
+    D = F[0] / (s.mu * U)
+    res["fp64_8192"] = {"workload": "c = 0.1 on 8192^2, %d markers" % m.X.shape[0],
+                        "solve_ms": round(1e3 * t, 2), "iters": info.iters, "true_relres": info.true_relres_fp64,
+                        "D": round(D, 6), "D_rel_err_vs_thesis_ibdl_8192": round(D / 24.8368 - 1, 7),
+                        "D_rel_err_vs_reference": round(D / 24.8317 - 1, 6)}
+    pr.close()
+    del q, u, g
     return res
 
 
@@ -791,10 +807,15 @@ def main():
     apply_bytes = sum(v[1] for k, v in cost.items() if v[0] == "hbm")
     mu, mf = model_bytes(spec, prec, pr)
     if args.calibrate_copy:
-        x = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev).fill_(1.0)   # 256 MiB
+        # a device copy of 256 MiB each way, and a second kernel of known size (a float to bfloat16
+        # cast: 256 MiB read, 128 MiB written) to cross-check the counters' scale
+        x = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev).fill_(1.0)
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
+        z = torch.empty(64 * 2 ** 20, dtype=torch.bfloat16, device=dev)
+        for _ in range(3):
+            z.copy_(x)
         torch.cuda.synchronize()
 
     extras = {} if args.no_extras else measure_extras(spec, prec, pr, data, g, tol, dev)

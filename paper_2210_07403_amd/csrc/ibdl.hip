@@ -521,24 +521,33 @@ template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
   hipEvent_t e0, e1;
   IBDL_HIP(hipEventCreate(&e0));
   IBDL_HIP(hipEventCreate(&e1));
+  // Candidates from the widest down to an eighth of it, timed in three interleaved rounds of one
+  // warm-up and eight timed runs each; a candidate's time is its best round (the rounds absorb
+  // clock and neighbour noise, which at 10-30 us per pass is of the size of the differences).
   auto best_of = [&](int wmax, auto&& run) {
-    int best = wmax;
-    float best_ms = 1e30f;
-    for (int w = wmax; w >= 1 && w * 8 >= wmax; w /= 2) {
-      for (int k = 0; k < 2; ++k) run(w);
-      IBDL_HIP(hipEventRecord(e0, h->st));
-      for (int k = 0; k < 5; ++k) run(w);
-      IBDL_HIP(hipEventRecord(e1, h->st));
-      IBDL_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      IBDL_HIP(hipEventElapsedTime(&ms, e0, e1));
-      // a narrower shape must be clearly faster: on ties the wider one moves fewer bytes
-      // (full 128-byte lines)
-      if (ms < 0.97f * best_ms) {
-        best_ms = ms;
-        best = w;
+    std::vector<int> cand;
+    for (int w = wmax; w >= 1 && w * 8 >= wmax; w /= 2) cand.push_back(w);
+    std::vector<float> tmin(cand.size(), 1e30f);
+    for (int round = 0; round < 3; ++round)
+      for (size_t c = 0; c < cand.size(); ++c) {
+        run(cand[c]);
+        IBDL_HIP(hipEventRecord(e0, h->st));
+        for (int k = 0; k < 8; ++k) run(cand[c]);
+        IBDL_HIP(hipEventRecord(e1, h->st));
+        IBDL_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        IBDL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        tmin[c] = std::min(tmin[c], ms);
       }
-    }
+    // a narrower shape must be clearly faster: on ties the wider one moves fewer bytes (full
+    // 128-byte lines)
+    int best = cand[0];
+    float best_ms = tmin[0];
+    for (size_t c = 1; c < cand.size(); ++c)
+      if (tmin[c] < 0.97f * best_ms) {
+        best_ms = tmin[c];
+        best = cand[c];
+      }
     return best;
   };
   LaunchShape sh;
