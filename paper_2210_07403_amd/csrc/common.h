@@ -34,6 +34,15 @@ template <bool INV, typename C> __device__ __forceinline__ C mul_mi(C a) {
 // a * (i * r)
 template <typename C> __device__ __forceinline__ C mul_ir(C a, decltype(C::x) r) { return mk<C>(-a.y * r, a.x * r); }
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b to XCD b mod 8).  This renumbers them
+// so that each XCD takes a contiguous range of [0, n): neighbouring work items, which share markers
+// or cache lines, then share an L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_chunk(int b, int n) {
+  constexpr int X = 8;
+  const int x = b % X, j = b / X, q = n / X, r = n % X;
+  return x * q + (x < r ? x : r) + j;
+}
+
 struct Error : std::runtime_error {
   int code;
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}

@@ -442,6 +442,14 @@ template <typename T, int N, int RX = rmax_t<T>(N), int BLK = kBlock, int LDS = 
 // the single-field passes' tile configuration
 template <typename T, int N> using LineCfg = TileCfg<T, N, rmax_t<T>(N), kLineBlock, kLineLds>;
 
+// Tile of this workgroup in the strided and last-axis passes.  A tile of W lines reads and writes
+// W adjacent elements of each row; when they fill less than a 128-byte cache line the line is
+// shared with the neighbouring tiles, which are then kept on one XCD so that it is fetched into one
+// L2 once rather than into several.
+template <typename C> __device__ __forceinline__ unsigned tile_of_block(int W) {
+  return W * (int)sizeof(C) < 128 ? (unsigned)xcd_chunk((int)blockIdx.x, (int)gridDim.x) : blockIdx.x;
+}
+
 // ------------------------------------------------------------------ strided in-place C2C
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kLineBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(kLineBlock) void k_strided(cplx<T>* __restrict__ da
   const int tid = threadIdx.x;
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
   const int c = tid & (W - 1), i = tid / W;
-  const unsigned l = blockIdx.x * (unsigned)W + c;
+  const unsigned l = tile_of_block<C>(W) * (unsigned)W + c;
   const unsigned lp = l / (unsigned)inner, li = l - lp * (unsigned)inner;
   const bool valid = l < nlines && li < vinner;
   const unsigned base = valid ? lp * (unsigned)outer + li : 0u;
@@ -589,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
   const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = blockIdx.x * W + c;
+  const int l = (int)tile_of_block<C>(W) * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
   // mode indices of this line: 2-D l = jx (+ nxp k1 with a split), e = jy; 3-D l = jy*nxh + jx, e = jz
@@ -686,7 +694,7 @@ __global__ __launch_bounds__(kLineBlock) void k_fused1(cplx<T>* __restrict__ dat
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
   const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = blockIdx.x * W + c;
+  const int l = (int)tile_of_block<C>(W) * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int jx = (int)(valid ? l % md.nxp : 0);
   const int jy2 = (int)(valid ? l / md.nxp : 0);
@@ -727,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
   const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = blockIdx.x * W + c;
+  const int l = (int)tile_of_block<C>(W) * W + c;
   const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
   const int64_t FS = P * N;
   const int jx = (int)(valid ? l % md.nxp : 0);

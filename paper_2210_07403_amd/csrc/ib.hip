@@ -281,14 +281,6 @@ __device__ __forceinline__ double spread_coef(const SpreadArgs& a, int m, int D,
   return 0.0;
 }
 
-// Workgroups are dealt to the 8 XCDs round robin (workgroup b to XCD b mod 8).  This renumbers them
-// so that each XCD takes a contiguous range of [0, n): neighbouring tiles, which share markers, then
-// share an L2.  A bijection of [0, n).
-__device__ __forceinline__ int xcd_chunk(int b, int n) {
-  constexpr int X = 8;
-  const int x = b % X, j = b / X, q = n / X, r = n % X;
-  return x * q + (x < r ? x : r) + j;
-}
 
 // Lanes used per wave for candidates in one pass (LDS budget: 32 KiB / 48 KiB per block).
 template <typename T> constexpr int spread_lanes() { return sizeof(T) == 4 ? 64 : 32; }
