@@ -198,14 +198,29 @@ __global__ void k_busy_ids(const int* __restrict__ cnt, const int* __restrict__ 
 // The busy tiles in decreasing order of their candidate count (ties by tile id): the spread's
 // workgroups then start with the longest tiles and end with the shortest, which evens out the
 // CUs' finishing times.  Rank sort; *nptr = number of busy tiles.
+// groups: the tiles (in tile-id order, i.e. in slabs) are first cut into the 8 XCD-contiguous
+// ranges of xcd_chunk, and each range is ordered on its own, so that a spread reading entry
+// xcd_chunk(b, n) gives each XCD one slab of neighbouring tiles, longest first; their markers'
+// data then stay in that XCD's L2.
+__device__ __forceinline__ int xcd_range_lo(int x, int n) {   // first index of XCD range x of [0, n)
+  const int q = n / 8, r = n % 8;
+  return x * q + (x < r ? x : r);
+}
 __global__ __launch_bounds__(256) void k_busy_order(const int4* __restrict__ in, const int* __restrict__ nptr,
-                                                    int4* __restrict__ out) {
+                                                    int4* __restrict__ out, int groups) {
   __shared__ int sc[256];
   const int n = *nptr;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int4 v = i < n ? in[i] : make_int4(0, 0, 0, 0);
   const int c = v.z - v.y;
-  int r = 0;
+  int lo = 0, hi = n;
+  if (groups) {
+    const int q = n / 8, r = n % 8;
+    const int x = i < r * (q + 1) ? i / (q + 1) : r + (q > 0 ? (i - r * (q + 1)) / q : 0);
+    lo = xcd_range_lo(x, n);
+    hi = xcd_range_lo(x + 1, n);
+  }
+  int rk = 0;
   for (int k0 = 0; k0 < n; k0 += 256) {
     __syncthreads();
     if (k0 + (int)threadIdx.x < n) {
@@ -216,10 +231,11 @@ __global__ __launch_bounds__(256) void k_busy_order(const int4* __restrict__ in,
     const int kn = n - k0 < 256 ? n - k0 : 256;
     for (int k = 0; k < kn; ++k) {
       const int ck = sc[k];
-      r += (ck > c) || (ck == c && k0 + k < i);
+      const int kk = k0 + k;
+      rk += (kk >= lo && kk < hi) && ((ck > c) || (ck == c && kk < i));
     }
   }
-  if (i < n) out[r] = v;
+  if (i < n) out[lo + rk] = v;
 }
 
 // sort each tile's marker list ascending (rank sort; marker indices in a tile are unique)
@@ -345,7 +361,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread3m(SpreadArgs a, const cplx<T
   const MarkerGeom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 bt = a.busy[blockIdx.x];
+  const int4 bt = a.busy[a.xcd ? xcd_chunk((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x];
   const int tile = bt.x;
   const int ntl = g.ntile[0] * g.ntile[1] * g.ntile[2];
   const int prob = tile / ntl, tl = tile - prob * ntl;
@@ -961,7 +977,7 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
 
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count, int* tile_off,
                  int* tile_cur, int* list, int* list_tmp, int4* busy, int4* busy_tmp, int* busy_off, hipStream_t st,
-                 const int* pid, int nprob) {
+                 const int* pid, int nprob, int xcd_groups) {
   const int ntile = g.ntile[0] * g.ntile[1] * g.ntile[2] * nprob;
   hipLaunchKernelGGL(k_busy_flags, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, tile_cur, ntile);
   IBDL_LAUNCH_CHECK();
@@ -972,7 +988,8 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
   hipLaunchKernelGGL(k_busy_ids, dim3((ntile + 255) / 256), dim3(256), 0, st, tile_count, busy_off, tile_off,
                      busy_tmp, ntile);
   IBDL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_busy_order, dim3((ntile + 255) / 256), dim3(256), 0, st, busy_tmp, busy_off + ntile, busy);
+  hipLaunchKernelGGL(k_busy_order, dim3((ntile + 255) / 256), dim3(256), 0, st, busy_tmp, busy_off + ntile, busy,
+                     xcd_groups);
   IBDL_LAUNCH_CHECK();
   IBDL_HIP(hipMemsetAsync(tile_cur, 0, sizeof(int) * ntile, st));
   if (n_ib > 0)

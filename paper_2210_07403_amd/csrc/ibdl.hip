@@ -394,6 +394,7 @@ SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
   a.list = h->list;
   a.busy = h->busy;
   a.nbusy = h->nbusy;
+  a.xcd = h->dim == 3 ? 1 : 0;
   a.s = h->s;
   a.f = h->f;
   a.wt = h->wt;
@@ -1117,7 +1118,7 @@ void build_markers(ibdl_s* h) {
   h->nb_cells_ready = false;
   markers_setup(h->geom, h->cfg.kernel, h->n_ib, h->X, h->s, h->f, h->wt, h->tile_count, h->st);
   markers_bin(h->geom, h->n_ib, h->s, h->tile_count, h->tile_off, h->tile_cur, h->list, h->list_tmp, h->busy,
-              h->busy_tmp, h->busy_off, h->st);
+              h->busy_tmp, h->busy_off, h->st, nullptr, 1, h->dim == 3 ? 1 : 0);
   markers_rows(h->geom, h->n_ib, h->s, h->row_lo, h->row_hi, h->row_cnt, h->row_off, h->row_lim, h->rows, h->st);
   const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
   const int nplanes = h->dim == 3 ? h->n[2] : 1;

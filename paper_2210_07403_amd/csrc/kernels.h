@@ -141,7 +141,7 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
 // order of candidate count (ties by tile id); busy_tmp: scratch of the same size
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count,
                  int* tile_off, int* tile_cur, int* list, int* list_tmp, int4* busy, int4* busy_tmp, int* busy_off,
-                 hipStream_t st, const int* pid = nullptr, int nprob = 1);
+                 hipStream_t st, const int* pid = nullptr, int nprob = 1, int xcd_groups = 0);
 
 
 // Active rows of the markers' windows: lo/hi [planes] (scratch), cnt/off [planes + 1] (scratch),
@@ -173,6 +173,8 @@ struct SpreadArgs {
   const int* list;
   const int4* busy;   // non-empty tiles: (tile id, list begin, list end, 0)
   int nbusy;
+  int xcd;            // busy is ordered in XCD ranges (markers_bin xcd_groups): workgroup b takes
+                      // entry xcd_chunk(b, nbusy) (3-D spread)
   const int* s;
   const double* f;
   const double* wt;   // per-marker weight table [n_ib][3][12]
