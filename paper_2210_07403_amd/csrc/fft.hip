@@ -677,6 +677,108 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   }
 }
 
+// The Stokes pass of 2-D problems with up to five input fields, the transforms of all fields taken
+// together: each radix stage works on every field's registers before one pair of barriers and one
+// LDS exchange (a buffer per field), and the two outputs' inverse transforms likewise.  The line
+// then waits for the latency of two transforms instead of nc + 2 in sequence (k_fused<.., STOKES>),
+// which is what bounds the double-precision 1024-point lines (one line of 256 threads per
+// workgroup, half a thousand lines per problem).  Twiddles are read from global memory (L2).
+constexpr int kStokesFields = 5;
+constexpr int kStokesLds = 81920;   // two workgroups per CU
+template <typename T, int N> struct StokesCfg {
+  static constexpr int RMX = fused_rmax<T>(N, 2);
+  static constexpr int T_ = Plan<N, RMX>::T;
+  static constexpr int W0 = kBlock / T_;
+  static constexpr int WL = kStokesLds / (kStokesFields * N * (int)sizeof(cplx<T>));
+  static constexpr int W = pow2floor((W0 < WL ? W0 : WL) > 0 ? (W0 < WL ? W0 : WL) : 1);
+  static constexpr int NT = W * T_;
+};
+
+template <int N, bool INV, int NF, int RMX, int S = 0, typename C>
+__device__ __forceinline__ void fft_lines_multi(C (&v)[NF][RMX], int nf, int i, C* lds, int es, int fstride,
+                                                const C* __restrict__ tw, int tws) {
+  if constexpr (S < Plan<N, RMX>::NST) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      if (f < nf) stage_compute<N, S, INV, true, RMX>(v[f], i, tw, tws);
+    if constexpr (S + 1 < Plan<N, RMX>::NST) {
+      __syncthreads();
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (f < nf) stage_store<N, S, RMX>(v[f], i, lds + f * fstride, es);
+      __syncthreads();
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (f < nf) line_load<N, RMX>(v[f], i, lds + f * fstride, es);
+    }
+    fft_lines_multi<N, INV, NF, RMX, S + 1>(v, nf, i, lds, es, fstride, tw, tws);
+  }
+}
+
+template <typename T, int N, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_fused_stokes2(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
+                                                          const cplx<T>* __restrict__ twg, int W, int64_t bstride,
+                                                          RowMask rm) {
+  using C = cplx<T>;
+  using SC = StokesCfg<T, N>;
+  constexpr int RM = SC::RMX, TT = SC::T_, NF = kStokesFields;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  data += (int64_t)blockIdx.y * bstride;   // problem of a batch
+  const int tid = threadIdx.x;
+  const int tws = SPLIT ? md.split : 1;
+  const int c = tid & (W - 1), i = tid / W;
+  const int l = (int)tile_of_block<C>(W) * W + c;
+  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
+  const int64_t FS = P * N;
+  const int jx = (int)(valid ? l % md.nxp : 0);
+  const int jy2 = (int)(valid ? l / md.nxp : 0);
+  const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
+  const T* sgl = static_cast<const T*>(md.sig[1]);
+  const T* ktl_ = static_cast<const T*>(md.kt[1]);
+  const T sig_l = static_cast<const T*>(md.sig[0])[jx];
+  const T kx = static_cast<const T*>(md.kt[0])[jx];
+  const int nc = md.nc;
+  C v[NF][RM];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    if (f < nc) {
+      line_gload<N, RM>(v[f], data, (unsigned)(f * FS + lg.base), lg.es, i, valid, rm);
+      if constexpr (SPLIT) split_twiddle<RM, TT>(v[f], i, lg.k1, twg, false);
+    } else {
+#pragma unroll
+      for (int s = 0; s < RM; ++s) v[f][s] = mk<C>(0, 0);
+    }
+  }
+  fft_lines_multi<N, false, NF, RM>(v, nc, i, lds + c, W, N * W, twg, tws);
+  C acc[2][RM];
+#pragma unroll
+  for (int s = 0; s < RM; ++s) {
+    const int e = lg.mode(i + s * TT);
+    const T sig = sig_l + sgl[e];
+    const T ke = ktl_[e];
+    const T ell = -sig;
+    const T il = ell == (T)0 ? (T)0 : recip(ell);
+    const T lam = (T)md.c2 * ell + (T)md.c0;
+    const T is = lam == (T)0 ? (T)0 : recip(lam);
+    acc[0][s] = mk<C>(0, 0);
+    acc[1][s] = mk<C>(0, 0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      if (f < nc) {
+        acc[0][s] = cadd(acc[0][s], cmul(stokes_coef<T>(md, md.fk[f], 0, sig, kx, ke, il, is), v[f][s]));
+        acc[1][s] = cadd(acc[1][s], cmul(stokes_coef<T>(md, md.fk[f], 1, sig, kx, ke, il, is), v[f][s]));
+      }
+    }
+  }
+  fft_lines_multi<N, true, 2, RM>(acc, 2, i, lds + c, W, N * W, twg, tws);
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    if constexpr (SPLIT) split_twiddle<RM, TT>(acc[o], i, lg.k1, twg, true);
+    line_gstore<N, RM>(acc[o], data, (unsigned)(o * FS + lg.base), lg.es, i, valid, rm);
+  }
+}
+
 // Single scalar field (the finite-difference operator and the scalar grid solve): forward FFT,
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
 template <typename T, int N, bool SPLIT>
@@ -961,6 +1063,13 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       } else if (!md.stokes && no == 1) {
         shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
         hipLaunchKernelGGL((k_fused<T, N, 1, false, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+      } else if (md.stokes && no == 2 && md.dim == 2 && md.nc <= kStokesFields) {
+        using SC = StokesCfg<T, N>;
+        W = pick(w, SC::W);
+        grid = dim3((unsigned)((P + W - 1) / W), (unsigned)batch);
+        blk = dim3(W * SC::T_);
+        lds = sizeof(cplx<T>) * (size_t)kStokesFields * N * W;
+        hipLaunchKernelGGL((k_fused_stokes2<T, N, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
       } else if (md.stokes && no == 2) {
         shape(TileCfg<T, N, fused_rmax<T>(N, 2)>{}, W, grid, blk, lds);
         hipLaunchKernelGGL((k_fused<T, N, 2, true, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
