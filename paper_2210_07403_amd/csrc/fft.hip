@@ -262,8 +262,9 @@ template <typename TR, int M> struct RowCfg {
 };
 
 // ------------------------------------------------------------------ x axis, forward R2C
-template <typename T, int M>
-__global__ __launch_bounds__((RowCfg<T, M>::BLK)) void k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
+// TI: element type of the input rows (float rows widened on load for a double transform)
+template <typename T, int M, typename TI = T>
+__global__ __launch_bounds__((RowCfg<T, M>::BLK)) void k_x_r2c(const TI* __restrict__ in, cplx<T>* __restrict__ out,
                                                   int64_t nrows, const cplx<T>* __restrict__ twg, int RPB,
                                                   RowList rl, int64_t pitch) {
   using C = cplx<T>;
@@ -284,7 +285,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::BLK)) void k_x_r2c(const T* __restri
     rsub[r] = r < nvalid ? rl.sub_row(row0 + r) : -1;
   }
   __syncthreads();
-  const C* src = reinterpret_cast<const C*>(in);
+  const cplx<TI>* src = reinterpret_cast<const cplx<TI>*>(in);
   const C* sub = static_cast<const C*>(rl.sub);
   // every load of a thread is issued before the first LDS write (RPB * M values, M / T per thread)
   constexpr int K = M / RC::T;
@@ -293,7 +294,10 @@ __global__ __launch_bounds__((RowCfg<T, M>::BLK)) void k_x_r2c(const T* __restri
   for (int j = 0; j < K; ++j) {
     const int e = tid + j * NT, r = e / M, c = e - r * M;
     ld[j] = mk<C>(0, 0);
-    if ((rseg[r] >> (c >> rl.seg_log2)) & 1ull) ld[j] = src[rbase[r] * M + c];
+    if ((rseg[r] >> (c >> rl.seg_log2)) & 1ull) {
+      const cplx<TI> x = src[rbase[r] * M + c];
+      ld[j] = mk<C>((T)x.x, (T)x.y);
+    }
     if (rsub[r] >= 0) {
       const C f = sub[rsub[r] * M + c];
       ld[j] = mk<C>(ld[j].x - f.x, ld[j].y - f.y);
@@ -943,9 +947,10 @@ int pick(int want, int max) {
 }
 }  // namespace
 
-template <typename T>
-void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
-               const RowList& rl, int64_t pitch) {
+namespace {
+template <typename T, typename TI>
+void x_r2c_launch(const TI* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
+                  const RowList& rl, int64_t pitch) {
   if (pitch <= 0) pitch = nx / 2 + 1;
   dispatch_row(nx / 2, [&](auto Mc) {
     constexpr int M = decltype(Mc)::value;
@@ -954,10 +959,22 @@ void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* 
     const int64_t nb = (nrows + R - 1) / R;
     const size_t lds = sizeof(cplx<T>) * (R * RC::LS + (RC::TWL ? 2 * M : 0));
     if (nb > 0)
-      hipLaunchKernelGGL((k_x_r2c<T, M>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
+      hipLaunchKernelGGL((k_x_r2c<T, M, TI>), dim3((unsigned)nb), dim3(R * RC::T), lds, s, in, out, nrows, tw_x, R, rl,
                          pitch);
   });
   IBDL_LAUNCH_CHECK();
+}
+}  // namespace
+
+template <typename T>
+void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb,
+               const RowList& rl, int64_t pitch) {
+  x_r2c_launch<T, T>(in, out, nx, nrows, tw_x, s, rpb, rl, pitch);
+}
+
+void fft_x_r2c_widen(const float* in, cplx<double>* out, int nx, int64_t nrows, const cplx<double>* tw_x,
+                     hipStream_t s, int rpb, const RowList& rl, int64_t pitch) {
+  x_r2c_launch<double, float>(in, out, nx, nrows, tw_x, s, rpb, rl, pitch);
 }
 
 template <typename T>

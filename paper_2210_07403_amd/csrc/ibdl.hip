@@ -9,6 +9,7 @@
 #include <chrono>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ibdl.h"
@@ -314,9 +315,11 @@ template <typename T> MultDesc base_desc(ibdl_s* h, GridWork<T>& W) {
 // (a right-hand side that is interpolated next).
 enum RowsMode { ROWS_DENSE = 0, ROWS_SPARSE = 1, ROWS_OUT = 2 };
 
+// srcf: float input fields for a double pipeline (widened as the forward x pass reads them; src unused)
 template <typename T>
 void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout, const MultDesc& md,
-              int rows = ROWS_DENSE, bool busy_only = false, const T* sub = nullptr, int sub_f0 = 0, int nsub = 0) {
+              int rows = ROWS_DENSE, bool busy_only = false, const T* sub = nullptr, int sub_f0 = 0, int nsub = 0,
+              const float* srcf = nullptr) {
   const int64_t rows_per_field = h->ntot / h->n[0];
   // 2-D grids of more than 1024 points along y: the last-axis pass is a four-step transform that
   // reads and writes every row, so the forward x pass covers every row (those the markers do not
@@ -358,7 +361,13 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   const int64_t rout = sout ? h->nact * nout : rows_per_field * nout;
   {
     StageTimer t(h, ST_FFT_X_FWD);
-    fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, tuned ? W.shape.rpb : 0, rl_in, h->nxp);
+    if constexpr (std::is_same<T, double>::value) {
+      if (srcf) fft_x_r2c_widen(srcf, W.spec, h->n[0], rin, W.tw[0], h->st, tuned ? W.shape.rpb : 0, rl_in, h->nxp);
+      else fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, tuned ? W.shape.rpb : 0, rl_in, h->nxp);
+    } else {
+      if (srcf) throw Error(IBDL_ERR_UNSUPPORTED, "float input fields are for the double pipeline");
+      fft_x_r2c<T>(src, W.spec, h->n[0], rin, W.tw[0], h->st, tuned ? W.shape.rpb : 0, rl_in, h->nxp);
+    }
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
@@ -594,8 +603,9 @@ template <typename T> void apply_t(ibdl_s* h, const double* q, double* y) {
   }
 }
 
-// u = L^-1 rhs (scalar) or L^-1 P rhs (Stokes)
-template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u, int rows = ROWS_DENSE) {
+// u = L^-1 rhs (scalar) or L^-1 P rhs (Stokes); rhsf: the right-hand side as float fields instead
+template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u, int rows = ROWS_DENSE,
+                                        const float* rhsf = nullptr) {
   GridWork<T>& W = ensure_work<T>(h);
   MultDesc md = base_desc<T>(h, W);
   if (h->stokes()) {
@@ -603,19 +613,26 @@ template <typename T> void grid_solve_t(ibdl_s* h, const T* rhs, T* u, int rows 
     md.fk[0] = FK_G1;
     md.fk[1] = FK_G2;
     md.alpha = -1.0;
-    pipeline<T>(h, W, rhs, 2, u, 2, md, rows);
+    pipeline<T>(h, W, rhs, 2, u, 2, md, rows, false, nullptr, 0, 0, rhsf);
   } else {
     md.nc = 1;
     md.fk[0] = FK_MASS;
     md.alpha = 1.0;
-    pipeline<T>(h, W, rhs, 1, u, 1, md, rows);
+    pipeline<T>(h, W, rhs, 1, u, 1, md, rows, false, nullptr, 0, 0, rhsf);
   }
 }
 
-template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, double* b) {
+// gf: the forcing as float fields (a mixed handle's, for the double right-hand side of the
+// refinement; g is then unused); the Dirichlet solve widens it as it reads it
+template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, double* b, const float* gf = nullptr) {
   GridWork<T>& W = ensure_work<T>(h);
   const int64_t nb = h->n_ib * h->nq;
-  if (h->neumann()) {
+  if (gf && h->neumann()) throw Error(IBDL_ERR_UNSUPPORTED, "float forcing for the double Neumann right-hand side");
+  if (gf) {
+    grid_solve_t<T>(h, nullptr, W.real, ROWS_OUT, gf);
+    InterpArgs ia = interp_args(h, h->nq, -1.0, 1.0, data, nullptr);
+    interp<T>(ia, W.wtab, W.real, b, h->st);
+  } else if (h->neumann()) {
     SpreadArgs a = spread_args(h, SP_PLAIN, 1, data);
     grid_fill_zero<T>(W.real, h->ntot, h->st);
     spread_w<T>(h, a, W, W.real);
@@ -631,10 +648,11 @@ template <typename T> void rhs_t(ibdl_s* h, const double* data, const T* g, doub
     IBDL_HIP(hipMemcpyAsync(b, data, sizeof(double) * nb, hipMemcpyDeviceToDevice, h->st));
   }
   if (h->has_ubar) {
-    if (g) {
+    if (g || gf) {
       const int nblk = 256;
       ensure_partial(h, nblk * h->nq);
-      grid_sum<T>(g, h->nq, h->ntot, h->partial, nblk, b + nb, h->st);
+      if (gf) grid_sum<float>(gf, h->nq, h->ntot, h->partial, nblk, b + nb, h->st);
+      else grid_sum<T>(g, h->nq, h->ntot, h->partial, nblk, b + nb, h->st);
       const double hD = pow(h->h, (double)h->dim) * (h->sl ? h->sl_border : 1.0);
       kr_scale(b + nb, hD, b + nb, h->nq, h->st);
     } else {
@@ -1738,16 +1756,17 @@ ibdl_status_t ibdl_solve_refined(ibdl_t h, const double* data, const void* g_gri
     check_finite<double>(h, data, h->n_ib * h->nq, "data");
     if (g_grid) check_grid(h, g_grid, h->nq, "g");
     const int64_t n = h->n_aug;
-    // right-hand side in double: the forcing of a mixed handle is widened first
-    const double* g64 = nullptr;
-    if (g_grid && h->mixed()) {
+    // right-hand side in double: the float forcing of a mixed handle is widened as the Dirichlet
+    // solve reads it (a Neumann forcing is widened first)
+    if (g_grid && h->mixed() && !h->neumann()) {
+      rhs_t<double>(h, data, nullptr, h->vb, (const float*)g_grid);
+    } else if (g_grid && h->mixed()) {
       if (!h->g64) h->g64 = (double*)h->dalloc<double>(sizeof(double) * h->ntot * h->nq);
       grid_widen((const float*)g_grid, h->g64, h->ntot * h->nq, h->st);
-      g64 = h->g64;
-    } else if (g_grid) {
-      g64 = (const double*)g_grid;
+      rhs_t<double>(h, data, h->g64, h->vb);
+    } else {
+      rhs_t<double>(h, data, (const double*)g_grid, h->vb);
     }
-    rhs_t<double>(h, data, g64, h->vb);
     if (!h->vx) h->vx = (double*)h->dalloc<double>(sizeof(double) * n);
     const int nblk = kr_nblk(n);
     ensure_partial(h, nblk);

@@ -89,6 +89,9 @@ template <typename T> int fft_line_w_max(int n);
 template <typename T>
 void fft_x_r2c(const T* in, cplx<T>* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0,
                const RowList& rl = RowList(), int64_t pitch = 0);
+// the double forward x pass reading float rows (widened on load)
+void fft_x_r2c_widen(const float* in, cplx<double>* out, int nx, int64_t nrows, const cplx<double>* tw_x,
+                     hipStream_t s, int rpb = 0, const RowList& rl = RowList(), int64_t pitch = 0);
 template <typename T>
 void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* tw_x, hipStream_t s, int rpb = 0,
                const RowList& rl = RowList(), int64_t pitch = 0);
