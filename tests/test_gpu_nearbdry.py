@@ -133,10 +133,12 @@ def test_pipeline_reduces_max_error():
     pr.close()
 
 
-def test_full_size_star_sampled():
-    """1024^2 star (4096 markers), FP64: the indicator against the oracle on every node, the
-    interpolation on a sample of 400 corrected nodes computed one by one by the oracle."""
-    spec = P.cfg2_star_poisson(1024, 4096)
+@pytest.mark.parametrize("N,n_ib", [(1024, 4096), (2048, 8192)])
+def test_full_size_star_sampled(N, n_ib):
+    """1024^2 star (4096 markers), and 2048^2 (8192; its y lines go through the four-step
+    transform), FP64: the indicator against the oracle on every node, the interpolation on a
+    sample of 400 corrected nodes computed one by one by the oracle."""
+    spec = P.cfg2_star_poisson(N, n_ib)
     g = _grid(spec)
     m = spec.markers
     pr = make_problem(spec, "fp64")
