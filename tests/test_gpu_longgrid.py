@@ -5,8 +5,9 @@ rows hold up to 4096 complex points.
 * The grid solve (screened Poisson FD and spectral, Poisson, Stokes) against the oracle on narrow
   grids (16 x 8192, 8192 x 16, 32 x 2048, 64 x 4096) and on 2048^2: FP64 1e-12, mixed 2e-5, as on
   the shorter lines.
-* The operator apply and its transpose against the oracle at 2048^2 (Stokes cylinder array) and
-  4096^2 (starfish Poisson, FD), the transpose by sampled entries and adjointness.
+* The operator apply and its transpose against the oracle at 2048^2 (Stokes cylinder array,
+  starfish Poisson FD) and 4096^2 (starfish apply), the transpose by sampled entries and
+  adjointness; the Stokes pressure at 2048^2.
 * The thesis's iteration tables (Sec. 5.4.1 Helmholtz circle, Sec. 5.4.2 starfish, GMRES to 1e-8)
   on every printed row, dx = 2^-6 .. 2^-12 and 2^-4 .. 2^-10, within one iteration.
 * The periodic cylinder array (Sec. 6.5) at N = 2^13, the size of the thesis's drag table, and the
@@ -116,6 +117,47 @@ def test_cylinder_array_2048_apply_and_transpose(precision):
         assert abs(got[i] - want_i) < tol * scale, (i, got[i], want_i)
     lhs, rhs = float(got @ q), float(p @ Aq)
     assert abs(lhs - rhs) < tol * np.linalg.norm(got) * np.linalg.norm(q), (lhs, rhs)
+    pr.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cylinder_array_2048_pressure(precision):
+    """The Stokes pressure (the fused pass's pressure mode on four-step lines) against the oracle's
+    for a random density and a smooth forcing."""
+    from oracle import ns
+    spec = P.cylinder_array(2048, 0.1)
+    o = make_oracle(spec)
+    pr = make_problem(spec, precision)
+    q = P.random_density(spec, seed=6)
+    xs, ys = o.grid.nodes()
+    gf = np.stack([np.sin(2 * np.pi * ys) + 0.3, np.cos(2 * np.pi * xs) * np.sin(4 * np.pi * ys)])
+    gd = gf.astype(np.float64 if precision == "fp64" else np.float32).astype(np.float64)
+    got = to_np(pr.pressure(q, gf))
+    want = ns.pressure(o, q, gd)
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    print(f"# cylinder array 2048^2 pressure {precision}: relerr {err:.2e}", flush=True)
+    assert err < tol
+    pr.close()
+
+
+def test_starfish_2048_apply_transpose():
+    """The scalar transposed apply (FD, Poisson) on 2048^2: sampled entries (A^T p)_i = p . (A e_i)
+    against the oracle's forward apply, and the adjointness against the oracle's A q."""
+    spec = P.starfish_poisson(2048, 0.75)
+    o = make_oracle(spec)
+    pr = make_problem(spec, "fp64")
+    rng = np.random.default_rng(13)
+    p = rng.standard_normal(pr.n_aug)
+    q = P.random_density(spec, seed=7)
+    got = to_np(pr.apply_transpose(p))
+    scale = np.linalg.norm(got) / np.sqrt(got.size)
+    for i in rng.integers(0, pr.n_aug, 2):
+        e = np.zeros(pr.n_aug)
+        e[i] = 1.0
+        assert abs(got[i] - float(p @ o.apply(e))) < 1e-12 * scale, i
+    lhs, rhs = float(got @ q), float(p @ o.apply(q))
+    assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(got) * np.linalg.norm(q), (lhs, rhs)
     pr.close()
 
 
