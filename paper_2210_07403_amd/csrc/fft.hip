@@ -683,10 +683,11 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
 
 // The Stokes pass of 2-D problems with up to five input fields, the transforms of all fields taken
 // together: each radix stage works on every field's registers before one pair of barriers and one
-// LDS exchange (a buffer per field), and the two outputs' inverse transforms likewise.  The line
-// then waits for the latency of two transforms instead of nc + 2 in sequence (k_fused<.., STOKES>),
-// which is what bounds the double-precision 1024-point lines (one line of 256 threads per
-// workgroup, half a thousand lines per problem).  Twiddles are read from global memory (L2).
+// LDS exchange (a buffer per field), and the two outputs' inverse transforms likewise.  A line
+// then waits for the latency of two transforms instead of nc + 2 in sequence (k_fused<.., STOKES>).
+// The double-precision 1024-point lines (one line of 256 threads per workgroup, half a thousand
+// lines per problem) stay bound by the L2 requests of their 16-byte row accesses.  Twiddles are
+// read from global memory (L2).
 constexpr int kStokesFields = 5;
 constexpr int kStokesLds = 81920;   // two workgroups per CU
 template <typename T, int N> struct StokesCfg {
