@@ -945,13 +945,24 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
   step(0);
   int k = 0;
   double res = 1.0;
+  int gated = -1;                       // step behind which a gated finish is queued
+  int done_at = -1;                     // step whose result carried the convergence flag
   std::vector<double> rs(maxit, 1.0);   // residual estimates of the steps the host has seen
   for (int j = 0; j < maxit; ++j) {
     // Step j + 1 is queued ahead unless step j is predicted to converge: the residual ratio of the
     // last two steps, applied once more, brings it to tol.  A step queued after convergence would
-    // delay whatever follows on the stream by a whole apply.
+    // delay whatever follows on the stream by a whole apply.  Behind a step predicted to be the
+    // last, the solution y and x = V y are queued at once, gated on the device's convergence flag,
+    // so that they follow the step without waiting for the host; if the step does not converge
+    // they do nothing and the next step follows them.
     bool ahead = j + 1 < maxit && !(j == 0 && stop_beta > 0.0);
-    if (ahead && j >= 2) ahead = rs[j - 1] * (rs[j - 1] / rs[j - 2]) > tol;
+    if (ahead && j >= 2) {
+      ahead = rs[j - 1] * (rs[j - 1] / rs[j - 2]) > tol;
+      if (!ahead) {
+        kr_gmres_finish(h->gm, mx, h->V, n, x, n, true, h->st);
+        gated = j;
+      }
+    }
     if (ahead) step(j + 1);
     const volatile double* hv = wait_published(h, j & 1, seq[j & 1]);
     const double beta = hv[GM_BETA], hn = hv[GM_HN];
@@ -974,13 +985,15 @@ int gmres(ibdl_s* h, const double* b, double tol, int maxit, double* x, ibdl_inf
     rs[j] = res;
     k = (int)hv[GM_K];
     if (info && info->history && j < info->history_cap) info->history[j] = res;
-    if (hv[GM_DONE] != 0.0) break;
+    if (hv[GM_DONE] != 0.0) {
+      done_at = j;
+      break;
+    }
     if (!ahead && j + 1 < maxit) step(j + 1);
   }
   // y = R^-1 g on the device, then x = V y; both are left to the stream, so the caller's next work
-  // queues behind them
-  kr_gmres_y(h->gm, mx, h->st);
-  kr_lincomb(h->V, n, k, kr_gmres_ydev(h->gm, mx), x, n, h->st);
+  // queues behind them (already queued when the converged step had a gated finish behind it)
+  if (!(done_at >= 0 && done_at == gated)) kr_gmres_finish(h->gm, mx, h->V, n, x, n, false, h->st);
   *iters = k;
   *relres = res;
   return res <= tol ? IBDL_OK : IBDL_NOT_CONVERGED;

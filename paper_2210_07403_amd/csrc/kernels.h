@@ -321,6 +321,10 @@ void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n,
 // y = R^-1 g of the state's GM_K steps, in device memory at kr_gmres_ydev(gs, mx)
 void kr_gmres_y(double* gs, int mx, hipStream_t st);
 const double* kr_gmres_ydev(double* gs, int mx);
+// y = R^-1 g and x = V y over the state's GM_K steps; gate: only if the state's convergence flag is
+// set when the kernels run (queued behind a step predicted to be the last)
+void kr_gmres_finish(double* gs, int mx, const double* V, int64_t ldv, double* x, int64_t n, bool gate,
+                     hipStream_t st);
 
 // ------------------------------------------------------------------ batched Krylov vectors
 // Concatenated per-problem vectors of total length n: seg[e] is element e's problem; dot-product

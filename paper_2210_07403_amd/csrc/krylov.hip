@@ -64,6 +64,21 @@ __global__ void k_lincomb(const double* __restrict__ V, int64_t ldv, int k, cons
   }
 }
 
+// x = V y over the k = gs[GM_K] steps of a GMRES state; gate as in k_gmres_y
+__global__ void k_lincomb_state(const double* __restrict__ V, int64_t ldv, const double* __restrict__ gs,
+                                const double* __restrict__ y, double* __restrict__ x, int64_t n, int gate) {
+  __shared__ double ys[256];
+  if (gate && gs[GM_DONE] == 0.0) return;
+  const int k = (int)gs[GM_K];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) ys[j] = y[j];
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += V[j * ldv + e] * ys[j];
+    x[e] = s;
+  }
+}
+
 __global__ void k_scale(const double* __restrict__ src, double s, double* __restrict__ dst, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = src[e] * s;
@@ -406,10 +421,13 @@ __device__ void givens_step(const double* __restrict__ h1, const double* __restr
 
 // The least-squares solution y = R^-1 g of the k = gs[GM_K] steps, by one workgroup: with k <= 64
 // the triangle is staged in LDS once, otherwise each column is read as the substitution reaches it.
-__global__ __launch_bounds__(kB) void k_gmres_y(double* gs, int mx) {
+// gate: nothing unless the state's convergence flag is set (a finish queued behind a step that the
+// host predicts to be the last, before it has seen that step's result).
+__global__ __launch_bounds__(kB) void k_gmres_y(double* gs, int mx, int gate) {
   __shared__ double tri[64 * 64];
   __shared__ double gv[256];
   __shared__ double yv;
+  if (gate && gs[GM_DONE] == 0.0) return;
   const int k = (int)gs[GM_K];
   const double* R = gm_R(gs, mx);
   const double* g = gm_g(gs, mx);
@@ -846,11 +864,21 @@ void kr_arnoldi_small(const double* V, int64_t ldv, int k, double* w, int64_t n,
 size_t kr_gmres_state_doubles(int mx) { return (size_t)GM_HDR + 4 * (size_t)mx + 2 + (size_t)mx * (mx + 1); }
 
 void kr_gmres_y(double* gs, int mx, hipStream_t st) {
-  hipLaunchKernelGGL(k_gmres_y, dim3(1), dim3(kB), 0, st, gs, mx);
+  hipLaunchKernelGGL(k_gmres_y, dim3(1), dim3(kB), 0, st, gs, mx, 0);
   IBDL_LAUNCH_CHECK();
 }
 
 const double* kr_gmres_ydev(double* gs, int mx) { return gs + GM_HDR + 3 * mx + 1; }
+
+void kr_gmres_finish(double* gs, int mx, const double* V, int64_t ldv, double* x, int64_t n, bool gate,
+                     hipStream_t st) {
+  if (mx > 256) throw Error(-1, "kr_gmres_finish: at most 256 basis vectors");
+  hipLaunchKernelGGL(k_gmres_y, dim3(1), dim3(kB), 0, st, gs, mx, gate ? 1 : 0);
+  IBDL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_lincomb_state, dim3(blocks_for(n)), dim3(256), 0, st, V, ldv, (const double*)gs,
+                     kr_gmres_ydev(gs, mx), x, n, gate ? 1 : 0);
+  IBDL_LAUNCH_CHECK();
+}
 
 int kr_nblk(int64_t n) { return (int)((n + kElemsPerBlock - 1) / kElemsPerBlock) > 0 ? (int)((n + kElemsPerBlock - 1) / kElemsPerBlock) : 1; }
 
