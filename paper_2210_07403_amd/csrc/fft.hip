@@ -444,7 +444,13 @@ template <typename T, int N, int RX = rmax_t<T>(N), int BLK = kBlock, int LDS = 
   static constexpr bool TWL = (W * N + N) * (int)sizeof(cplx<T>) <= LDS;
 };
 // the single-field passes' tile configuration
-template <typename T, int N> using LineCfg = TileCfg<T, N, rmax_t<T>(N), kLineBlock, kLineLds>;
+template <typename T, int N, int RX = rmax_t<T>(N)> using LineCfg = TileCfg<T, N, RX, kLineBlock, kLineLds>;
+// Radix plans of the single-field line passes: plan 0 holds rmax_t elements per thread, plan 1 half
+// as many (twice the threads per line, one more radix stage) where that leaves at least 4 and a line
+// fits a workgroup; the launch-shape timing picks one per pass.
+template <typename T> constexpr int plan_rx(int N, int plan) {
+  return plan == 1 && rmax_t<T>(N) >= 8 && N / (rmax_t<T>(N) / 2) <= kLineBlock ? rmax_t<T>(N) / 2 : rmax_t<T>(N);
+}
 
 // Tile of this workgroup in the strided and last-axis passes.  A tile of W lines reads and writes
 // W adjacent elements of each row; when they fill less than a 128-byte cache line the line is
@@ -455,12 +461,12 @@ template <typename C> __device__ __forceinline__ unsigned tile_of_block(int W) {
 }
 
 // ------------------------------------------------------------------ strided in-place C2C
-template <typename T, int N, bool INV>
+template <typename T, int N, bool INV, int RX = rmax_t<T>(N)>
 __global__ __launch_bounds__(kLineBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
                                                         int64_t outer, int64_t es, const cplx<T>* __restrict__ twg,
                                                         int W, RowMask rm, int64_t vinner) {
   using C = cplx<T>;
-  using TC = LineCfg<T, N>;
+  using TC = LineCfg<T, N, RX>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int tid = threadIdx.x;
@@ -786,12 +792,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_stokes2(cplx<T>* __restrict__ 
 
 // Single scalar field (the finite-difference operator and the scalar grid solve): forward FFT,
 // multiply by the real factor alpha*sc / (c2 sigma - c0) in registers, inverse FFT.
-template <typename T, int N, bool SPLIT>
+template <typename T, int N, bool SPLIT, int RX = rmax_t<T>(N)>
 __global__ __launch_bounds__(kLineBlock) void k_fused1(cplx<T>* __restrict__ data, int64_t P, MultDesc md,
                                                        const cplx<T>* __restrict__ twg, int W, int64_t bstride,
                                                        RowMask rm) {
   using C = cplx<T>;
-  using TC = LineCfg<T, N>;   // one field, one real factor: no spills at 16 elements per thread
+  using TC = LineCfg<T, N, RX>;   // one field, one real factor: no spills at 16 elements per thread
   constexpr int RM = TC::RMX, TT = TC::T_;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -933,9 +939,22 @@ int fft_x_rpb_max(int nx) {
 }
 
 template <typename T>
-int fft_line_w_max(int n) {
+int fft_line_w_max(int n, int plan) {
   int r = 0;
-  dispatch_n(n > kMaxLine ? n / kSplit : n, [&](auto Nc) { r = LineCfg<T, decltype(Nc)::value>::W; });
+  dispatch_n(n > kMaxLine ? n / kSplit : n, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    r = plan == 1 ? LineCfg<T, N, plan_rx<T>(N, 1)>::W : LineCfg<T, N>::W;
+  });
+  return r;
+}
+
+template <typename T>
+int fft_line_plans(int n) {
+  int r = 1;
+  dispatch_n(n > kMaxLine ? n / kSplit : n, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    r = plan_rx<T>(N, 1) != plan_rx<T>(N, 0) ? 2 : 1;
+  });
   return r;
 }
 
@@ -997,7 +1016,7 @@ void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* 
 
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es, bool inverse,
-                 const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm, int64_t vinner) {
+                 const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm, int64_t vinner, int plan) {
   if (vinner <= 0) vinner = inner;
   if (nlines <= 0) return;
   const int64_t span = ((nlines - 1) / inner) * outer + (inner - 1) + (int64_t)(n - 1) * es + 1;
@@ -1005,24 +1024,31 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
     throw Error(-2, "strided FFT pass: one launch may not span 4 GiB");
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
-    using TC = LineCfg<T, N>;
-    const int W = pick(w, TC::W);
-    const int64_t nb = (nlines + W - 1) / W;
-    const size_t lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
-    const dim3 blk(W * TC::T_);
-    if (inverse)
-      hipLaunchKernelGGL((k_strided<T, N, true>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
-                         tw, W, rm, vinner);
+    auto launch = [&](auto rxc) {
+      constexpr int RX = decltype(rxc)::value;
+      using TC = LineCfg<T, N, RX>;
+      const int W = pick(w, TC::W);
+      const int64_t nb = (nlines + W - 1) / W;
+      const size_t lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
+      const dim3 blk(W * TC::T_);
+      if (inverse)
+        hipLaunchKernelGGL((k_strided<T, N, true, RX>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer,
+                           es, tw, W, rm, vinner);
+      else
+        hipLaunchKernelGGL((k_strided<T, N, false, RX>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer,
+                           es, tw, W, rm, vinner);
+    };
+    if (plan == 1 && plan_rx<T>(N, 1) != plan_rx<T>(N, 0))
+      launch(std::integral_constant<int, plan_rx<T>(N, 1)>{});
     else
-      hipLaunchKernelGGL((k_strided<T, N, false>), dim3((unsigned)nb), blk, lds, s, data, nlines, inner, outer, es,
-                         tw, W, rm, vinner);
+      launch(std::integral_constant<int, plan_rx<T>(N, 0)>{});
   });
   IBDL_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw, hipStream_t s,
-                    int batch, int64_t bstride, int w, const RowMask& rm) {
+                    int batch, int64_t bstride, int w, const RowMask& rm, int plan) {
   if (batch < 1) return;
   if (n > kMaxLine) {
     // Four-step transform of the 2-D y lines, n = N1 N2 (N1 = kSplit): with y = j1 N2 + j2 and mode
@@ -1041,7 +1067,7 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       fft_strided<T>(data + f * FS, kSplit, P * N2, P, P, (int64_t)N2 * P, false, tw, s, 0, RowMask(), md.nxh);
     MultDesc m2 = md;
     m2.split = kSplit;
-    fft_fused_last<T>(data, N2, P * kSplit, no, m2, tw, s, 1, 0, w, RowMask());
+    fft_fused_last<T>(data, N2, P * kSplit, no, m2, tw, s, 1, 0, w, RowMask(), plan);
     for (int o = 0; o < no; ++o)
       fft_strided<T>(data + o * FS, kSplit, P * N2, P, P, (int64_t)N2 * P, true, tw, s, 0, RowMask(), md.nxh);
     return;
@@ -1076,8 +1102,14 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       } else if (md.mode != 0) {
         throw Error(-2, "fused pass: unsupported transposed multiplier");
       } else if (!md.stokes && no == 1 && md.nc == 1 && md.fk[0] == FK_MASS) {
-        shape(LineCfg<T, N>{}, W, grid, blk, lds);
-        hipLaunchKernelGGL((k_fused1<T, N, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+        if (plan == 1 && plan_rx<T>(N, 1) != plan_rx<T>(N, 0)) {
+          constexpr int RX = plan_rx<T>(N, 1);
+          shape(LineCfg<T, N, RX>{}, W, grid, blk, lds);
+          hipLaunchKernelGGL((k_fused1<T, N, SP, RX>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+        } else {
+          shape(LineCfg<T, N>{}, W, grid, blk, lds);
+          hipLaunchKernelGGL((k_fused1<T, N, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
+        }
       } else if (!md.stokes && no == 1) {
         shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
         hipLaunchKernelGGL((k_fused<T, N, 1, false, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);
@@ -1116,11 +1148,12 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
   template void fft_x_c2r<T>(const cplx<T>*, T*, int, int64_t, const cplx<T>*, hipStream_t, int,         \
                              const RowList&, int64_t);                                                     \
   template void fft_strided<T>(cplx<T>*, int, int64_t, int64_t, int64_t, int64_t, bool, const cplx<T>*,   \
-                               hipStream_t, int, const RowMask&, int64_t);                                 \
+                               hipStream_t, int, const RowMask&, int64_t, int);                            \
   template void fft_fused_last<T>(cplx<T>*, int, int64_t, int, const MultDesc&, const cplx<T>*, hipStream_t, \
-                                  int, int64_t, int, const RowMask&);                                      \
+                                  int, int64_t, int, const RowMask&, int);                                 \
   template int fft_x_rpb_max<T>(int);                                                                      \
-  template int fft_line_w_max<T>(int);
+  template int fft_line_w_max<T>(int, int);                                                                \
+  template int fft_line_plans<T>(int);
 IBDL_FFT_INST(float)
 IBDL_FFT_INST(double)
 

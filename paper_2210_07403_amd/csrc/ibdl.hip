@@ -10,6 +10,7 @@
 #include <memory>
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/ibdl.h"
@@ -372,18 +373,19 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
-                   W.tw[1], h->st, tuned ? W.shape.wy : 0, fwd, h->nxh);
+                   W.tw[1], h->st, tuned ? W.shape.wy : 0, fwd, h->nxh, tuned ? W.shape.py : 0);
   }
   const int last = h->dim - 1;
   const int64_t P = h->nspec / h->n[last];
   {
     StageTimer t(h, ST_FUSED);
-    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, tuned ? W.shape.wz : 0, fused);
+    fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, tuned ? W.shape.wz : 0, fused,
+                      tuned ? W.shape.pz : 0);
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_INV);
     fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
-                   W.tw[1], h->st, tuned ? W.shape.wy : 0, inv, h->nxh);
+                   W.tw[1], h->st, tuned ? W.shape.wy : 0, inv, h->nxh, tuned ? W.shape.py : 0);
   }
   {
     StageTimer t(h, ST_FFT_X_INV);
@@ -531,27 +533,29 @@ template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
   hipEvent_t e0, e1;
   IBDL_HIP(hipEventCreate(&e0));
   IBDL_HIP(hipEventCreate(&e1));
-  // Candidates from the widest down to an eighth of it, timed in three interleaved rounds of one
-  // warm-up and eight timed runs each; a candidate's time is its best round (the rounds absorb
-  // clock and neighbour noise, which at 10-30 us per pass is of the size of the differences).
-  auto best_of = [&](int wmax, auto&& run) {
-    std::vector<int> cand;
-    for (int w = wmax; w >= 1 && w * 8 >= wmax; w /= 2) cand.push_back(w);
+  // Candidates (radix plan, width) from the widest down to an eighth of it for each plan, timed in
+  // three interleaved rounds of one warm-up and eight timed runs each; a candidate's time is its best
+  // round (the rounds absorb clock and neighbour noise, which at 10-30 us per pass is of the size of
+  // the differences).  A later candidate (narrower, or the second plan) must be clearly faster: on
+  // ties the wider one moves fewer bytes (full 128-byte lines).
+  using Cand = std::pair<int, int>;
+  auto widths = [](int plan, int wmax, std::vector<Cand>& out) {
+    for (int w = wmax; w >= 1 && w * 8 >= wmax; w /= 2) out.push_back(Cand(plan, w));
+  };
+  auto best_of = [&](const std::vector<Cand>& cand, auto&& run) {
     std::vector<float> tmin(cand.size(), 1e30f);
     for (int round = 0; round < 3; ++round)
       for (size_t c = 0; c < cand.size(); ++c) {
-        run(cand[c]);
+        run(cand[c].first, cand[c].second);
         IBDL_HIP(hipEventRecord(e0, h->st));
-        for (int k = 0; k < 8; ++k) run(cand[c]);
+        for (int k = 0; k < 8; ++k) run(cand[c].first, cand[c].second);
         IBDL_HIP(hipEventRecord(e1, h->st));
         IBDL_HIP(hipEventSynchronize(e1));
         float ms = 0;
         IBDL_HIP(hipEventElapsedTime(&ms, e0, e1));
         tmin[c] = std::min(tmin[c], ms);
       }
-    // a narrower shape must be clearly faster: on ties the wider one moves fewer bytes (full
-    // 128-byte lines)
-    int best = cand[0];
+    Cand best = cand[0];
     float best_ms = tmin[0];
     for (size_t c = 1; c < cand.size(); ++c)
       if (tmin[c] < 0.97f * best_ms) {
@@ -561,21 +565,40 @@ template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
     return best;
   };
   LaunchShape sh;
-  sh.rpb = best_of(fft_x_rpb_max<T>(h->n[0]), [&](int r) {
-    fft_x_r2c<T>(W.real, W.spec, h->n[0], h->nact * pl.nf, W.tw[0], h->st, r, rl, h->nxp);
-    fft_x_c2r<T>(W.spec, W.real, h->n[0], h->nact * pl.nout, W.tw[0], h->st, r, rl, h->nxp);
-  });
-  if (h->dim == 3)
-    sh.wy = best_of(fft_line_w_max<T>(h->n[1]), [&](int w) {
+  {
+    std::vector<Cand> cand;
+    widths(0, fft_x_rpb_max<T>(h->n[0]), cand);
+    sh.rpb = best_of(cand, [&](int, int r) {
+      fft_x_r2c<T>(W.real, W.spec, h->n[0], h->nact * pl.nf, W.tw[0], h->st, r, rl, h->nxp);
+      fft_x_c2r<T>(W.spec, W.real, h->n[0], h->nact * pl.nout, W.tw[0], h->st, r, rl, h->nxp);
+    }).second;
+  }
+  if (h->dim == 3) {
+    std::vector<Cand> cand;
+    for (int p = 0; p < fft_line_plans<T>(h->n[1]); ++p) widths(p, fft_line_w_max<T>(h->n[1], p), cand);
+    const Cand c = best_of(cand, [&](int p, int w) {
       fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nf * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
-                     W.tw[1], h->st, w, fwd, h->nxh);
+                     W.tw[1], h->st, w, fwd, h->nxh, p);
       fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
-                     W.tw[1], h->st, w, inv, h->nxh);
+                     W.tw[1], h->st, w, inv, h->nxh, p);
     });
+    sh.py = c.first;
+    sh.wy = c.second;
+  }
   const int last = h->dim - 1;
-  sh.wz = best_of(fft_line_w_max<T>(h->n[last]), [&](int w) {
-    fft_fused_last<T>(W.spec, h->n[last], h->nspec / h->n[last], pl.nout, pl.md, W.tw[last], h->st, 1, 0, w, fused);
-  });
+  {
+    // the second radix plan exists for the single-field scalar pass only
+    const bool single = !pl.md.stokes && pl.nout == 1 && pl.md.nc == 1 && pl.md.fk[0] == FK_MASS;
+    std::vector<Cand> cand;
+    for (int p = 0; p < (single ? fft_line_plans<T>(h->n[last]) : 1); ++p)
+      widths(p, fft_line_w_max<T>(h->n[last], p), cand);
+    const Cand c = best_of(cand, [&](int p, int w) {
+      fft_fused_last<T>(W.spec, h->n[last], h->nspec / h->n[last], pl.nout, pl.md, W.tw[last], h->st, 1, 0, w, fused,
+                        p);
+    });
+    sh.pz = c.first;
+    sh.wz = c.second;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   W.shape = sh;

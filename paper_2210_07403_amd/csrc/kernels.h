@@ -83,7 +83,9 @@ struct MultDesc {
 // and fused passes (powers of two; 0 or anything above the maximum means the maximum that fits
 // 256 threads and 64 KiB of LDS).
 template <typename T> int fft_x_rpb_max(int nx);
-template <typename T> int fft_line_w_max(int n);
+template <typename T> int fft_line_w_max(int n, int plan = 0);
+// radix plans of the single-field line passes of length n (1 or 2; plan 1 halves the elements per thread)
+template <typename T> int fft_line_plans(int n);
 // x passes over nrows rows (with a row list: nrows = active rows per field x fields)
 // pitch: spectrum row pitch in complex values (0: nx/2 + 1)
 template <typename T>
@@ -100,7 +102,7 @@ void fft_x_c2r(const cplx<T>* in, T* out, int nx, int64_t nrows, const cplx<T>* 
 template <typename T>
 void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t outer, int64_t es,
                  bool inverse, const cplx<T>* tw, hipStream_t s, int w = 0, const RowMask& rm = RowMask(),
-                 int64_t vinner = 0);
+                 int64_t vinner = 0, int plan = 0);
 // in-place fused pass along the last axis (length n, plane size P): forward FFT of the nc input
 // fields, multiplier, inverse FFT of the no output fields (written to fields 0..no-1).
 // mode 1 (one scalar input F): outputs i k~_o g F^ for o < dim, then g F^, g = alpha sc/(c2 sigma - c0);
@@ -109,10 +111,11 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
 // batch problems with the same multiplier: problem b's fields start bstride elements after b-1's.
 // 2-D lines of 2048 to 8192 points (one problem) run as a four-step transform in three passes; their
 // fields must be valid on every row (rm is not applied) and every output row is written.
+// plan: radix plan of the single-field scalar pass (fft_line_plans); the other passes keep theirs.
 template <typename T>
 void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md, const cplx<T>* tw,
                     hipStream_t s, int batch = 1, int64_t bstride = 0, int w = 0,
-                    const RowMask& rm = RowMask());
+                    const RowMask& rm = RowMask(), int plan = 0);
 int fft_supported(int n);
 
 // ------------------------------------------------------------------ markers, spread, interp

@@ -1,4 +1,4 @@
-// Launch shapes of the FFT passes and tile widths of the batched 2-D spread, chosen by timing;
+// Launch shapes and radix plans of the FFT passes and tile widths of the batched 2-D spread, chosen by timing;
 // remembered for the life of the process and in a JSON file per kind of GPU (tune.hip).
 #pragma once
 
@@ -12,6 +12,8 @@ struct LaunchShape {
   int wz = 0;    // lines per block of the fused last-axis pass
   int tile = 0;  // 2-D spread tile width along x (batches; 0: not chosen)
   int blocks = 0;  // workgroups of the batched persistent spread (0: not chosen)
+  int py = 0;    // radix plan of the strided y passes (fft_line_plans)
+  int pz = 0;    // radix plan of the single-field last-axis pass
 };
 
 // (kind, dim, n0, n1, n2, bytes per value, fields, size bucket)

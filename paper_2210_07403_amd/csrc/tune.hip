@@ -3,9 +3,9 @@
 //
 // File: $IBDL_TUNE_CACHE if set (an empty value turns the file off), else
 // $XDG_CACHE_HOME/ibdl/tune.json or $HOME/.cache/ibdl/tune.json.  Layout, one entry per line:
-//   {"format": "ibdl-tune-2", "device": "<arch> <CUs>",
+//   {"format": "ibdl-tune-3", "device": "<arch> <CUs>",
 //    "entries": [
-//     {"key": [k0, ..., k7], "rpb": r, "wy": y, "wz": z, "tile": t, "blocks": b},
+//     {"key": [k0, ..., k7], "rpb": r, "wy": y, "wz": z, "tile": t, "blocks": b, "py": p, "pz": q},
 //     ...
 //    ]}
 // A file written for another device, or one that does not parse, is ignored (and replaced at the next
@@ -63,7 +63,7 @@ void load_locked() {
   bool device_ok = false;
   std::map<TuneKey, LaunchShape> got;
   while (fgets(line, sizeof(line), f)) {
-    if (strstr(line, "\"format\": \"ibdl-tune-2\"")) {
+    if (strstr(line, "\"format\": \"ibdl-tune-3\"")) {
       device_ok = strstr(line, want.c_str()) != nullptr;
       continue;
     }
@@ -72,9 +72,10 @@ void load_locked() {
     LaunchShape v;
     const int n = sscanf(line,
                          " {\"key\": [%d, %d, %d, %d, %d, %d, %d, %d], \"rpb\": %d, \"wy\": %d, \"wz\": %d, \"tile\": %d, "
-                         "\"blocks\": %d}",
-                         &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &v.rpb, &v.wy, &v.wz, &v.tile, &v.blocks);
-    if (n == 13) got[k] = v;
+                         "\"blocks\": %d, \"py\": %d, \"pz\": %d}",
+                         &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &v.rpb, &v.wy, &v.wz, &v.tile, &v.blocks,
+                         &v.py, &v.pz);
+    if (n == 15) got[k] = v;
   }
   fclose(f);
   if (device_ok)
@@ -89,15 +90,15 @@ void save_locked() {
   const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
   FILE* f = fopen(tmp.c_str(), "w");
   if (!f) return;
-  fprintf(f, "{\"format\": \"ibdl-tune-2\", \"device\": \"%s\",\n \"entries\": [\n", device_id().c_str());
+  fprintf(f, "{\"format\": \"ibdl-tune-3\", \"device\": \"%s\",\n \"entries\": [\n", device_id().c_str());
   size_t i = 0;
   for (const auto& kv : g_reg) {
     const TuneKey& k = kv.first;
     const LaunchShape& v = kv.second;
     fprintf(f,
             "  {\"key\": [%d, %d, %d, %d, %d, %d, %d, %d], \"rpb\": %d, \"wy\": %d, \"wz\": %d, \"tile\": %d, "
-            "\"blocks\": %d}%s\n",
-            k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], v.rpb, v.wy, v.wz, v.tile, v.blocks,
+            "\"blocks\": %d, \"py\": %d, \"pz\": %d}%s\n",
+            k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], v.rpb, v.wy, v.wz, v.tile, v.blocks, v.py, v.pz,
             ++i < g_reg.size() ? "," : "");
   }
   fprintf(f, " ]}\n");

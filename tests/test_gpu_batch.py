@@ -169,7 +169,7 @@ def test_batch_tuning_persists_in_json_cache(tmp_path):
     r1 = run()
     assert r1.returncode == 0, r1.stderr[-2000:]
     doc = json.loads(cache.read_text())
-    assert doc["format"] == "ibdl-tune-2" and doc["device"]
+    assert doc["format"] == "ibdl-tune-3" and doc["device"]
     tiles = [e for e in doc["entries"] if e["key"][0] == 3]
     assert len(tiles) == 2 and all(e["tile"] in (16, 32, 64) for e in tiles)
     first = json.loads(r1.stdout.strip().splitlines()[-1])
