@@ -504,10 +504,9 @@ void density_to_grid(ibdl_s* h, const double* q, const double* m, const T* g, T*
               g ? (pl.mode == SP_STOKES ? 2 : 1) : 0);
 }
 
-// Launch shapes of the apply's FFT passes by measurement: rows per block of the x passes, lines
-// per block of the y passes and of the fused pass, each from the largest that fits down to an
-// eighth of it, two warm-up and five timed runs per candidate on the handle's own arrays; a
-// narrower shape is taken only when it is at least 3% faster.
+// Launch shapes of the apply's FFT passes by measurement on the handle's own arrays: rows per
+// block of the x passes; lines per block and radix plan of the y passes and of the fused pass.
+// Widths run from the largest that fits down to an eighth of it.
 template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
   const DensityPlan pl = density_plan<T>(h, W, h->cfg.eta > 0);
   const TuneKey key{0, h->dim, h->n[0], h->n[1], h->n[2], (int)sizeof(T), pl.nf, pow2_bucket(h->nact)};
