@@ -54,8 +54,9 @@ def stage_cost(spec, prec, pr):
     """Algorithmic cost per launch of each stage of one operator apply: HBM bytes for the
     memory-bound passes (the x passes touch only the rows the markers' windows meet, the forward
     one only their busy tile segments; the forward y pass reads only those rows, the inverse
-    writes only those), floating-point operations for the spread (a per-tile contraction on the
-    matrix cores)."""
+    writes only those; in 3-D the y passes and the last-axis pass touch only the z planes from
+    the first to the last holding such a row), floating-point operations for the spread (a
+    per-tile contraction on the matrix cores)."""
     t = 4 if prec == "mixed" else 8
     ntot = pr.grid_points
     nxh = spec.n[0] // 2 + 1
@@ -76,9 +77,11 @@ def stage_cost(spec, prec, pr):
         "interp": ("hbm", spec.n_ib * (taps * t * o + 36 + 8 * pr.nq * 2)),
     }
     if spec.dim == 3:
-        b["fft_y_fwd"] = ("hbm", c * (Ca + C))
-        b["fused_last_axis"] = ("hbm", (c + o) * C)
-        b["fft_y_inv"] = ("hbm", o * (C + Ca))
+        z0, z1 = pr.active_span()
+        Cz = C * max(0, z1 - z0 + 1) // spec.n[2]   # half spectra of the planes in the span
+        b["fft_y_fwd"] = ("hbm", c * (Ca + Cz))
+        b["fused_last_axis"] = ("hbm", (c + o) * Cz)
+        b["fft_y_inv"] = ("hbm", o * (Cz + Ca))
     else:
         b["fused_last_axis"] = ("hbm", (c + o) * Ca)
     # spread: per marker and window node, D-1 products per term and one add per term; the

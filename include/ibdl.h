@@ -360,6 +360,14 @@ ibdl_status_t ibdl_query(ibdl_t h, int64_t* n_aug, int64_t* grid_points, int32_t
  * others and the interpolation does not read them.  Either pointer may be NULL. */
 ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total);
 
+/* Range [first, last] of indices along the last grid axis (z in 3-D, y in 2-D) that hold an active
+ * row.  The operator apply's last-axis pass loads and stores only those elements of its lines, and
+ * in 3-D its y passes run over those z planes only; the rest of the spectra is zero on the way in
+ * and not needed on the way out.  2-D grids over 1024 points along y report the whole axis (their
+ * four-step last-axis pass does not mask).  last < first when no row is active.  Either pointer
+ * may be NULL. */
+ibdl_status_t ibdl_active_span(ibdl_t h, int32_t* first, int32_t* last);
+
 /* Tiling of the spread: nbusy = tiles (tile[0] x tile[1] (x tile[2]) nodes) that a marker window
  * meets, which the spread writes whole; segments_read = (active row, busy tile) pairs, i.e. the
  * tile[0]-node row segments the operator apply's forward x pass reads per spread field (it takes

@@ -196,6 +196,13 @@ class Problem:
         B.check(B.load().ibdl_active_rows(self._h, ctypes.byref(a), ctypes.byref(t)), self._h)
         return int(a.value), int(t.value)
 
+    def active_span(self):
+        """(first, last) index along the last grid axis holding an active row: the part of the
+        spectra the operator apply's last-axis pass loads and stores."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        B.check(B.load().ibdl_active_span(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return int(a.value), int(b.value)
+
     def indicator(self, regularized=False):
         """Indicator of the interior of the markers' curve (2-D): chi [ny][nx] of the grid type,
         and the regularized field before the threshold when regularized=True."""

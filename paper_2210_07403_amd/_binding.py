@@ -67,6 +67,7 @@ _SIGS = {
                                    ctypes.POINTER(c_int32)]),
     "ibdl_batch_last_error": (ctypes.c_char_p, [c_void_p]),
     "ibdl_active_rows": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),
+    "ibdl_active_span": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "ibdl_launch_shape": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                     ctypes.POINTER(c_int32)]),
     "ibdl_query": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64), ctypes.POINTER(c_int32)]),

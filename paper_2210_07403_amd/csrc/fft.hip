@@ -473,8 +473,9 @@ __global__ __launch_bounds__(kLineBlock) void k_strided(cplx<T>* __restrict__ da
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_) : twg;
   const int c = tid & (W - 1), i = tid / W;
   const unsigned l = tile_of_block<C>(W) * (unsigned)W + c;
-  const unsigned lp = l / (unsigned)inner, li = l - lp * (unsigned)inner;
+  const unsigned lq = l / (unsigned)inner, li = l - lq * (unsigned)inner;
   const bool valid = l < nlines && li < vinner;
+  const unsigned lp = rm.phys_plane(lq);
   const unsigned base = valid ? lp * (unsigned)outer + li : 0u;
   const RowMask pm = rm.plane(valid ? lp : 0);   // rows of this line's plane that matter
   C v[TC::RMX];
@@ -1019,7 +1020,9 @@ void fft_strided(cplx<T>* data, int n, int64_t nlines, int64_t inner, int64_t ou
                  const cplx<T>* tw, hipStream_t s, int w, const RowMask& rm, int64_t vinner, int plan) {
   if (vinner <= 0) vinner = inner;
   if (nlines <= 0) return;
-  const int64_t span = ((nlines - 1) / inner) * outer + (inner - 1) + (int64_t)(n - 1) * es + 1;
+  int64_t lastp = (nlines - 1) / inner;   // last plane touched
+  if (rm.pspan > 0) lastp = (lastp / rm.pspan) * rm.nplanes + rm.p0 + rm.pspan - 1;
+  const int64_t span = lastp * outer + (inner - 1) + (int64_t)(n - 1) * es + 1;
   if (span * (int64_t)sizeof(cplx<T>) > (int64_t)UINT32_MAX || nlines > INT32_MAX)
     throw Error(-2, "strided FFT pass: one launch may not span 4 GiB");
   dispatch_n(n, [&](auto Nc) {

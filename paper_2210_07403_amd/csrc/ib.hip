@@ -474,6 +474,135 @@ __global__ __launch_bounds__(64 * NW) void k_spread3m(SpreadArgs a, const cplx<T
   }
 }
 
+// The finite-difference dipole field (one output field) with the candidates' weights resolved at
+// the tile's own nodes once per pass.  Each candidate's record holds G_x and W_x at the 16 x columns
+// (the Q operand of terms 0 and 1) and the (W, G) pairs of its 4 y rows and 8 z planes, zero outside
+// its window; the four staging lanes of a candidate fill seven of these 28 positions each, reading
+// the taps the window offsets in lofs select.  A K-step then takes its operands' factors from the
+// record directly: term 0 P = (c_x W_y) W_z, term 1 P = (c_y G_y + c_m W_y) W_z + (c_z W_y) G_z.
+// Same products and accumulation order as k_spread3m.
+template <typename T, int NW, int SC>
+__global__ __launch_bounds__(64 * NW, 8) void k_spread3f(SpreadArgs a, const cplx<T>* __restrict__ wtab,
+                                                      T* __restrict__ out) {
+  using T2 = cplx<T>;
+  using M = Mfma<T>;
+  constexpr int NTH = 64 * NW;
+  constexpr int PER = (SC * 4 + NTH - 1) / NTH;      // staging items (candidate, quarter) per thread
+  constexpr int RS = 56;                             // record: G_x[16], W_x[16], y (W, G)[4], z (W, G)[8]
+  constexpr int STAGE = SC * (RS + 4) * (int)sizeof(T);
+  constexpr int RED = NW * 512 * (int)sizeof(T);
+  __shared__ __align__(16) unsigned char smem[STAGE > RED ? STAGE : RED];
+  T* s_r = reinterpret_cast<T*>(smem);
+  T(*s_c)[4] = reinterpret_cast<T(*)[4]>(smem + SC * RS * sizeof(T));   // c_x, c_y, c_z, c_m
+  const MarkerGeom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int4 bt = a.busy[a.xcd ? xcd_chunk((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x];
+  const int tile = bt.x;
+  const int ntl = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  const int prob = tile / ntl, tl = tile - prob * ntl;
+  const int tx = tl % g.ntile[0];
+  const int ty = (tl / g.ntile[0]) % g.ntile[1];
+  const int tz = tl / (g.ntile[0] * g.ntile[1]);
+  const int x0 = tx * kT3X, y0 = ty * kT3Y, z0 = tz * kT3Z;
+  const double hD = g.h * g.h * g.h;
+  const int mx = g.n[0] - 1, my = g.n[1] - 1, mz = g.n[2] - 1;
+  typename M::v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  const int beg = bt.y, end = bt.z;
+  const int i16 = lane & 15, yy = i16 & 3, zz = i16 >> 2;
+  const bool t0 = ((lane >> 4) & 1) == 0;            // term of this lane's k column
+  const int qoff = (t0 ? 0 : 16) + i16;
+  int m_next[PER], o_next[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int scand = (tid + p * NTH) >> 2;
+    const bool in = scand < SC && scand < end - beg;
+    m_next[p] = in ? a.list[beg + scand] : -1;
+    o_next[p] = in ? a.lofs[beg + scand] : 0;
+  }
+  for (int c0 = beg; c0 < end; c0 += SC) {
+    const int cnt = end - c0 < SC ? end - c0 : SC;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int it = tid + p * NTH, scand = it >> 2, part = it & 3;
+      if (scand >= SC) break;
+      const int m = m_next[p], d = o_next[p];
+      const bool live = m >= 0;
+      const int mm = live ? m : 0;   // padding candidates read marker 0 and store zeros
+      // lane quarter p resolves x columns p, p + 4, p + 8, p + 12, y row p and z planes p, p + 4; the
+      // weight row is read at 32-bit byte offsets from the launch-uniform table
+      const unsigned wrow = (unsigned)mm * 24u * (unsigned)sizeof(T2);
+      const int dx = d & 1023, dy = (d >> 10) & 1023, dz = (d >> 20) & 1023;
+      unsigned slot[7];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) slot[i] = (unsigned)((part + 4 * i - dx) & mx);
+      slot[4] = (unsigned)((part - dy) & my);
+      slot[5] = (unsigned)((part - dz) & mz);
+      slot[6] = (unsigned)((part + 4 - dz) & mz);
+      T2 e[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const unsigned base = i < 4 ? 0u : (i == 4 ? 8u : 16u);
+        const unsigned sl = base + (slot[i] < 6u ? slot[i] : 6u);   // taps 6 and 7 of a row are zero
+        e[i] = *reinterpret_cast<const T2*>(reinterpret_cast<const char*>(wtab) + (wrow + sl * (unsigned)sizeof(T2)));
+      }
+      const T cv = (T)spread_coef(a, mm, 3, a.raw ? 1.0 : a.ds[mm] / hD, part);
+      const bool more = c0 + SC + scand < end;
+      m_next[p] = more ? a.list[c0 + SC + scand] : -1;
+      o_next[p] = more ? a.lofs[c0 + SC + scand] : 0;
+      T* r = s_r + scand * RS;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const T w = live ? e[i].x : (T)0, gd = live ? e[i].y : (T)0;
+        if (i < 4) {            // x column: G_x (term 0), W_x (term 1)
+          r[part + 4 * i] = gd;
+          r[16 + part + 4 * i] = w;
+        } else {                // y row / z plane: (W, G)
+          const int o = i == 4 ? 32 + 2 * part : (i == 5 ? 40 + 2 * part : 48 + 2 * part);
+          r[o] = w;
+          r[o + 1] = gd;
+        }
+      }
+      s_c[scand][part] = live ? cv : (T)0;
+    }
+    __syncthreads();
+    const int nsteps = (cnt + 1) >> 1;
+    for (int st = wave; st < nsteps; st += NW) {
+      const int cand = 2 * st + (lane >> 5);
+      const T* r = s_r + cand * RS;
+      const T q = r[qoff];
+      const T2 yv = *reinterpret_cast<const T2*>(r + 32 + 2 * yy);
+      const T2 za = *reinterpret_cast<const T2*>(r + 40 + 2 * zz);
+      const T2 zb = *reinterpret_cast<const T2*>(r + 48 + 2 * zz);
+      const T cx = s_c[cand][0], cy = s_c[cand][1], cz = s_c[cand][2], cm = s_c[cand][3];
+      const T u = t0 ? cx * yv.x : cy * yv.y + cm * yv.x;
+      const T v = t0 ? (T)0 : cz * yv.x;
+      acc0 = M::mma(u * za.x + v * za.y, q, acc0);
+      acc1 = M::mma(u * zb.x + v * zb.y, q, acc1);
+    }
+    __syncthreads();
+  }
+  // fixed-order sum of the waves' partial tiles
+  T* red = reinterpret_cast<T*>(smem);   // [wave][block][v][lane]
+  const int64_t ntot = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  out += (int64_t)prob * ntot;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[((wave * 2 + 0) * 4 + v) * 64 + lane] = acc0[v];
+    red[((wave * 2 + 1) * 4 + v) * 64 + lane] = acc1[v];
+  }
+  __syncthreads();
+  for (int o = tid; o < 512; o += NTH) {
+    const int b = o >> 8, v = (o >> 6) & 3, l = o & 63;
+    T val = red[(b * 4 + v) * 64 + l];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) val += red[((w * 2 + b) * 4 + v) * 64 + l];
+    const int i = M::row(l, v);
+    const int x = l & 15, y = i & 3, z = (i >> 2) + 4 * b;
+    out[((int64_t)(z0 + z) * g.n[1] + (y0 + y)) * g.n[0] + x0 + x] = val;
+  }
+}
+
 // 2-D: a tile of TX x TY nodes (TX TY = 256, TY = 4 (64 / TX) rows); lane (x, y-group) owns
 // y = 4 yg + j' (j' < 4); the owning lane of a candidate writes its x row and its tile-aligned y
 // column (TY pairs) to LDS; coefficients and the x window start are broadcast.  s_x and s_y are the
@@ -975,6 +1104,32 @@ void markers_setup(const MarkerGeom& g, int kernel, int64_t n_ib, const double* 
   IBDL_LAUNCH_CHECK();
 }
 
+// one workgroup per busy tile: the window starts of its candidates relative to the tile's first node
+__global__ __launch_bounds__(256) void k_list_offsets(MarkerGeom g, const int4* __restrict__ busy,
+                                                      const int* __restrict__ list, const int* __restrict__ s,
+                                                      int* __restrict__ lofs) {
+  const int4 bt = busy[blockIdx.x];
+  const int tl = bt.x % (g.ntile[0] * g.ntile[1] * g.ntile[2]);
+  const int o0 = (tl % g.ntile[0]) * g.tile[0];
+  const int o1 = ((tl / g.ntile[0]) % g.ntile[1]) * g.tile[1];
+  const int o2 = (tl / (g.ntile[0] * g.ntile[1])) * g.tile[2];
+  for (int i = bt.y + (int)threadIdx.x; i < bt.z; i += (int)blockDim.x) {
+    const int m = list[i];
+    const int d0 = (s[3 * m] - o0) & (g.n[0] - 1), d1 = (s[3 * m + 1] - o1) & (g.n[1] - 1);
+    const int d2 = (s[3 * m + 2] - o2) & (g.n[2] - 1);
+    lofs[i] = d0 | (d1 << 10) | (d2 << 20);
+  }
+}
+
+void markers_list_offsets(const MarkerGeom& g, const int4* busy, int nbusy, const int* list, const int* s, int* lofs,
+                          hipStream_t st) {
+  if (g.dim != 3) throw Error(-1, "list offsets: 3-D grids only");
+  if (g.n[0] > 1024 || g.n[1] > 1024 || g.n[2] > 1024) throw Error(-1, "list offsets: axes of at most 1024 nodes");
+  if (nbusy <= 0) return;
+  hipLaunchKernelGGL(k_list_offsets, dim3((unsigned)nbusy), dim3(256), 0, st, g, busy, list, s, lofs);
+  IBDL_LAUNCH_CHECK();
+}
+
 void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* tile_count, int* tile_off,
                  int* tile_cur, int* list, int* list_tmp, int4* busy, int4* busy_tmp, int* busy_off, hipStream_t st,
                  const int* pid, int nprob, int xcd_groups) {
@@ -1055,7 +1210,9 @@ void spread(const SpreadArgs& a, const cplx<T>* wtab, T* out, hipStream_t st) {
   } else {
     if (a.mode == SP_STOKES) throw Error(-1, "3-D spread: the Stokes mode is two-dimensional");
     constexpr int NW = kSpreadWaves, SC = kSpreadCands;
-    if (one && a.mode == SP_FDDIV)
+    if (one && a.mode == SP_FDDIV && a.lofs)
+      hipLaunchKernelGGL((k_spread3f<T, NW, SC>), dim3(a.nbusy), dim3(64 * NW), 0, st, a, wtab, out);
+    else if (one && a.mode == SP_FDDIV)
       hipLaunchKernelGGL((k_spread3m<T, 1, true, NW, SC>), dim3(a.nbusy), dim3(64 * NW), 0, st, a, wtab, out);
     else if (one)
       hipLaunchKernelGGL((k_spread3m<T, 1, false, NW, SC>), dim3(a.nbusy), dim3(64 * NW), 0, st, a, wtab, out);

@@ -76,6 +76,7 @@ struct ibdl_s {
   double* f = nullptr;
   double* wt = nullptr;   // per-marker kernel weight table [n_ib][3][12]
   int *tile_count = nullptr, *tile_off = nullptr, *tile_cur = nullptr, *list = nullptr, *list_tmp = nullptr;
+  int* lofs = nullptr;   // 3-D: window starts of the list entries relative to their tiles
   int4* busy = nullptr;
   int4* busy_tmp = nullptr;
   int* busy_off = nullptr;
@@ -88,6 +89,7 @@ struct ibdl_s {
   int64_t nact = 0;
   int64_t seg_read = 0;       // (active row, busy x-segment) pairs the apply's forward x pass reads
   int lim2d[2] = {0, -1};     // 2-D: the one plane's limits, on the host
+  int zlim[2] = {0, -1};      // 3-D: first and last z plane holding an active row, on the host
   bool check = false;         // IBDL_CHECK=1 at creation: device arrays scanned for NaN / Inf
   unsigned* chk = nullptr;    // the scan's flag
   MarkerGeom geom{};
@@ -346,10 +348,22 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
       rl_in.nact = h->nact;
     }
     if (h->dim == 3) {
+      // only the planes with active rows matter on the way out (the inverse y pass and the
+      // last-axis stores), and on the way in when the input is zero elsewhere
       fwd.lim = inv.lim = h->row_lim;
       fwd.nplanes = inv.nplanes = h->n[2];
       fwd.load = sin ? 1 : 0;
       inv.store = 1;
+      inv.p0 = h->zlim[0];
+      inv.pspan = std::max(0, h->zlim[1] - h->zlim[0] + 1);
+      if (sin) {
+        fwd.p0 = inv.p0;
+        fwd.pspan = inv.pspan;
+      }
+      fused.load = sin ? 1 : 0;
+      fused.store = 1;
+      fused.lo = h->zlim[0];
+      fused.hi = h->zlim[1];
     } else if (!split) {
       fused.load = sin ? 1 : 0;
       fused.store = 1;
@@ -372,8 +386,9 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
   }
   if (h->dim == 3) {
     StageTimer t(h, ST_FFT_Y_FWD);
-    fft_strided<T>(W.spec, h->n[1], (int64_t)nin * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
-                   W.tw[1], h->st, tuned ? W.shape.wy : 0, fwd, h->nxh, tuned ? W.shape.py : 0);
+    fft_strided<T>(W.spec, h->n[1], (int64_t)nin * (fwd.pspan ? fwd.pspan : h->n[2]) * h->nxp, h->nxp,
+                   h->nxp * h->n[1], h->nxp, false, W.tw[1], h->st, tuned ? W.shape.wy : 0, fwd, h->nxh,
+                   tuned ? W.shape.py : 0);
   }
   const int last = h->dim - 1;
   const int64_t P = h->nspec / h->n[last];
@@ -382,10 +397,11 @@ void pipeline(ibdl_s* h, GridWork<T>& W, const T* src, int nin, T* dst, int nout
     fft_fused_last<T>(W.spec, h->n[last], P, nout, md, W.tw[last], h->st, 1, 0, tuned ? W.shape.wz : 0, fused,
                       tuned ? W.shape.pz : 0);
   }
-  if (h->dim == 3) {
+  if (h->dim == 3 && !(sout && inv.pspan == 0)) {
     StageTimer t(h, ST_FFT_Y_INV);
-    fft_strided<T>(W.spec, h->n[1], (int64_t)nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
-                   W.tw[1], h->st, tuned ? W.shape.wy : 0, inv, h->nxh, tuned ? W.shape.py : 0);
+    fft_strided<T>(W.spec, h->n[1], (int64_t)nout * (inv.pspan ? inv.pspan : h->n[2]) * h->nxp, h->nxp,
+                   h->nxp * h->n[1], h->nxp, true, W.tw[1], h->st, tuned ? W.shape.wy : 0, inv, h->nxh,
+                   tuned ? W.shape.py : 0);
   }
   {
     StageTimer t(h, ST_FFT_X_INV);
@@ -406,6 +422,8 @@ SpreadArgs spread_args(ibdl_s* h, int mode, int nf, const double* q) {
   a.busy = h->busy;
   a.nbusy = h->nbusy;
   a.xcd = h->dim == 3 ? 1 : 0;
+  // the tile-aligned FD spread addresses weight rows by 32-bit byte offsets
+  a.lofs = h->n_ib * 24 * (int64_t)sizeof(cplx<double>) <= (int64_t)UINT32_MAX ? h->lofs : nullptr;
   a.s = h->s;
   a.f = h->f;
   a.wt = h->wt;
@@ -524,6 +542,11 @@ template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
     fwd.nplanes = inv.nplanes = h->n[2];
     fwd.load = 1;
     inv.store = 1;
+    fwd.p0 = inv.p0 = h->zlim[0];
+    fwd.pspan = inv.pspan = std::max(0, h->zlim[1] - h->zlim[0] + 1);
+    fused.load = fused.store = 1;
+    fused.lo = h->zlim[0];
+    fused.hi = h->zlim[1];
   } else {
     fused.load = fused.store = 1;
     fused.lo = h->lim2d[0];
@@ -576,9 +599,9 @@ template <typename T> void tune_apply(ibdl_s* h, GridWork<T>& W) {
     std::vector<Cand> cand;
     for (int p = 0; p < fft_line_plans<T>(h->n[1]); ++p) widths(p, fft_line_w_max<T>(h->n[1], p), cand);
     const Cand c = best_of(cand, [&](int p, int w) {
-      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nf * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
+      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nf * fwd.pspan * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, false,
                      W.tw[1], h->st, w, fwd, h->nxh, p);
-      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nout * h->n[2] * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
+      fft_strided<T>(W.spec, h->n[1], (int64_t)pl.nout * inv.pspan * h->nxp, h->nxp, h->nxp * h->n[1], h->nxp, true,
                      W.tw[1], h->st, w, inv, h->nxh, p);
     });
     sh.py = c.first;
@@ -1176,15 +1199,25 @@ void build_markers(ibdl_s* h) {
   const int ntile = h->geom.ntile[0] * h->geom.ntile[1] * h->geom.ntile[2];
   const int nplanes = h->dim == 3 ? h->n[2] : 1;
   int nb = 0, na = 0;
-  int2 l2 = make_int2(1, 0);
+  std::vector<int2> lim(nplanes);
   IBDL_HIP(hipMemcpyAsync(&nb, h->busy_off + ntile, sizeof(int), hipMemcpyDeviceToHost, h->st));
   IBDL_HIP(hipMemcpyAsync(&na, h->row_off + nplanes, sizeof(int), hipMemcpyDeviceToHost, h->st));
-  IBDL_HIP(hipMemcpyAsync(&l2, h->row_lim, sizeof(int2), hipMemcpyDeviceToHost, h->st));
+  IBDL_HIP(hipMemcpyAsync(lim.data(), h->row_lim, sizeof(int2) * nplanes, hipMemcpyDeviceToHost, h->st));
   IBDL_HIP(hipStreamSynchronize(h->st));
   h->nbusy = nb;
   h->nact = na;
-  h->lim2d[0] = l2.x;
-  h->lim2d[1] = l2.y;
+  if (h->lofs) markers_list_offsets(h->geom, h->busy, nb, h->list, h->s, h->lofs, h->st);
+  h->lim2d[0] = lim[0].x;
+  h->lim2d[1] = lim[0].y;
+  // the planes with active rows; planes between them without any are inside the range (a window
+  // wrapping the periodic boundary in z makes it the whole axis)
+  h->zlim[0] = nplanes;
+  h->zlim[1] = -1;
+  for (int z = 0; z < nplanes; ++z)
+    if (lim[z].x <= lim[z].y) {
+      h->zlim[0] = std::min(h->zlim[0], z);
+      h->zlim[1] = std::max(h->zlim[1], z);
+    }
   {   // busy x-segments of the active rows; their count is reported by ibdl_spread_tiles
     markers_row_segments(h->geom, h->tile_off, h->rows, na, h->seg, h->st);
     markers_row_segments(h->geom, h->tile_off, nullptr, (int64_t)h->n[1] * (h->dim == 3 ? h->n[2] : 1), h->seg_all,
@@ -1438,6 +1471,7 @@ ibdl_status_t ibdl_create(const ibdl_config_t* cfg, int64_t n_ib, const double* 
     h->busy_off = (int*)h->dalloc<int>(sizeof(int) * (ntile + 1));
     h->list = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     h->list_tmp = (int*)h->dalloc<int>(sizeof(int) * maxlist);
+    if (h->dim == 3) h->lofs = (int*)h->dalloc<int>(sizeof(int) * maxlist);
     const int nplanes = h->dim == 3 ? h->n[2] : 1;
     h->row_lo = (int*)h->dalloc<int>(sizeof(int) * nplanes);
     h->row_hi = (int*)h->dalloc<int>(sizeof(int) * nplanes);
@@ -1949,6 +1983,18 @@ ibdl_status_t ibdl_active_rows(ibdl_t h, int64_t* nact, int64_t* rows_total) {
   if (!h) return IBDL_ERR_ARG;
   if (nact) *nact = h->nact;
   if (rows_total) *rows_total = h->ntot / h->n[0];
+  return IBDL_OK;
+}
+
+ibdl_status_t ibdl_active_span(ibdl_t h, int32_t* first, int32_t* last) {
+  if (!h) return IBDL_ERR_ARG;
+  int a = h->dim == 3 ? h->zlim[0] : h->lim2d[0], b = h->dim == 3 ? h->zlim[1] : h->lim2d[1];
+  if (h->dim == 2 && h->n[1] > 1024) {
+    a = 0;
+    b = h->n[1] - 1;
+  }
+  if (first) *first = a;
+  if (last) *last = b;
   return IBDL_OK;
 }
 

@@ -48,6 +48,14 @@ struct RowMask {
   int load = 0;                // read only those rows (others are zero)
   int store = 0;               // write only those rows
   int lo = 0, hi = 1 << 30;    // limits of the current plane (2-D: set by the host; else plane())
+  // strided passes: when pspan > 0 the launch covers only planes p0 .. p0 + pspan - 1 of each field;
+  // logical plane j is physical plane (j / pspan) * nplanes + p0 + j % pspan
+  int p0 = 0, pspan = 0;
+  __device__ unsigned phys_plane(unsigned j) const {
+    if (pspan <= 0) return j;
+    const unsigned f = j / (unsigned)pspan;
+    return f * (unsigned)nplanes + (unsigned)p0 + (j - f * (unsigned)pspan);
+  }
   __device__ RowMask plane(int64_t line_plane) const {
     RowMask m = *this;
     if (lim) {
@@ -150,6 +158,11 @@ void markers_bin(const MarkerGeom& g, int64_t n_ib, const int* s, const int* til
                  hipStream_t st, const int* pid = nullptr, int nprob = 1, int xcd_groups = 0);
 
 
+// 3-D: the window starts of every listed candidate relative to its tile's first node, one int per
+// list entry: bits 10a .. 10a + 9 hold (s_a - tile origin_a) mod n_a for axis a (n_a <= 1024)
+void markers_list_offsets(const MarkerGeom& g, const int4* busy, int nbusy, const int* list, const int* s, int* lofs,
+                          hipStream_t st);
+
 // Active rows of the markers' windows: lo/hi [planes] (scratch), cnt/off [planes + 1] (scratch),
 // lim [planes] = (lo, hi) per plane, rows = the row list (up to ny * planes entries), increasing;
 // the count is off[planes].  planes = nz in 3-D, 1 in 2-D.
@@ -181,6 +194,8 @@ struct SpreadArgs {
   int nbusy;
   int xcd;            // busy is ordered in XCD ranges (markers_bin xcd_groups): workgroup b takes
                       // entry xcd_chunk(b, nbusy) (3-D spread)
+  const int* lofs;    // 3-D: window starts of the list entries relative to their tiles
+                      // (markers_list_offsets), or NULL
   const int* s;
   const double* f;
   const double* wt;   // per-marker weight table [n_ib][3][12]

@@ -292,7 +292,13 @@ def _tiles_reference(spec):
         for y in range(lo[z], hi[z] + 1):
             nact += 1
             nseg += int(busy[z // tile[2], y // tile[1]].sum()) if dim == 3 else int(busy[y // tile[1]].sum())
-    return int(busy.sum()), nact, nseg, tile
+    # span along the last axis: the z planes holding an active row (3-D), the active rows (2-D)
+    if dim == 3:
+        zs = np.nonzero(lo <= hi)[0]
+        span = (int(zs.min()), int(zs.max())) if len(zs) else (nplanes, -1)
+    else:
+        span = (int(lo[0]), int(hi[0]))
+    return int(busy.sum()), nact, nseg, tile, span
 
 
 @pytest.mark.parametrize("name", ["sphere_3d", "helmholtz_fd", "stokes_exterior"])
@@ -300,10 +306,56 @@ def test_spread_tiles_and_active_rows(name):
     """The tile binning and the row bookkeeping the apply's x passes rely on, recounted on the host."""
     spec = OPERATORS[name]()
     pr = make_problem(spec, "mixed")
-    nbusy, nact, nseg, tile = _tiles_reference(spec)
+    nbusy, nact, nseg, tile, span = _tiles_reference(spec)
     got_busy, got_seg, got_tile = pr.spread_tiles()
     assert got_tile[:spec.dim] == tile
     assert (got_busy, pr.active_rows()[0], got_seg) == (nbusy, nact, nseg)
+    assert pr.active_span() == span
+    pr.close()
+
+
+def _bodies_3d(centres, r, freq, disc):
+    """Icospheres on a 32^3 unit grid (kappa 10), for the z-plane bookkeeping of the apply."""
+    sph = [geo.icosphere(c, r, freq) for c in centres]
+    X = np.vstack([m.X for m in sph])
+    nrm = np.vstack([m.nrm for m in sph])
+    ds = np.concatenate([m.ds for m in sph])
+    return _spec_like(3, (32, 32, 32), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), X, nrm, ds, kappa=10.0, disc=disc)
+
+
+PLANE_CASES = {
+    # two bodies apart in z: planes without an active row between the first and the last
+    "gap": ([(0.5, 0.5, 0.22), (0.45, 0.55, 0.72)], 0.08, 3),
+    # a body across the periodic seam in z: active planes at both ends of the axis
+    "wrap": ([(0.5, 0.5, 0.02)], 0.15, 5),
+    # one body off the centre: a range starting well inside the axis
+    "offset": ([(0.3, 0.6, 0.7)], 0.15, 5),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("disc", ["fd2", "spectral"])
+@pytest.mark.parametrize("case", sorted(PLANE_CASES))
+def test_apply_plane_range(case, disc, precision):
+    """The 3-D apply runs its y passes over the z planes between the first and the last holding
+    an active row and masks the last-axis pass to them: the span against a host recount, A q and
+    A^T p against the oracle (one spread field with FD symbols, several with spectral ones)."""
+    centres, r, freq = PLANE_CASES[case]
+    spec = _bodies_3d(centres, r, freq, disc)
+    pr = make_problem(spec, precision)
+    *_, span = _tiles_reference(spec)
+    assert pr.active_span() == span
+    if case == "wrap":
+        assert span == (0, 31)
+    else:
+        assert 0 < span[0] and span[1] < 31
+    o = make_oracle(spec)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    q = np.random.default_rng(6).standard_normal(o.n_aug)
+    assert relerr(to_np(pr.apply(q)), o.apply(q)) < tol
+    A = o.assemble()
+    p = np.random.default_rng(8).standard_normal(o.n_aug)
+    assert relerr(to_np(pr.apply_transpose(p)), A.T @ p) < tol
     pr.close()
 
 
@@ -312,7 +364,8 @@ def test_spread_tiles_seam_crossing():
     X, nrm, ds = _markers(3, (32, 16, 16), (2.0, 1.0, 1.0), (0.0, -0.5, 0.0), 517, 5)
     spec = _spec_like(3, (32, 16, 16), (2.0, 1.0, 1.0), (0.0, -0.5, 0.0), X, nrm, ds)
     pr = make_problem(spec, "fp64")
-    nbusy, nact, nseg, _ = _tiles_reference(spec)
+    nbusy, nact, nseg, _, span = _tiles_reference(spec)
     got_busy, got_seg, _ = pr.spread_tiles()
     assert (got_busy, pr.active_rows()[0], got_seg) == (nbusy, nact, nseg)
+    assert pr.active_span() == span
     pr.close()
