@@ -460,6 +460,52 @@ template <typename C> __device__ __forceinline__ unsigned tile_of_block(int W) {
   return W * (int)sizeof(C) < 128 ? (unsigned)xcd_chunk((int)blockIdx.x, (int)gridDim.x) : blockIdx.x;
 }
 
+// Lines of the last-axis passes come in rows of `inner`: x modes 0 .. vinner - 1, then pitch
+// padding.  With tiles of W consecutive lines, a row's last tile holds its last x mode (the Nyquist
+// one) beside W - 1 padding lines: at 256 points along x, one tile in nine.  Where W divides
+// vinner - 1 (both powers of two) the tiles are assigned instead as LineMap on = 1 describes, so that
+// no tile holds padding; the tiles of last modes read W rows' lines (1 / (vinner - 1) of the data,
+// but one cache line per element and row) and come first, so that they do not finish last.  (The
+// strided passes keep the plain assignment: there the gathered last-mode tiles cost more than the
+// padding lines did.)
+inline LineMap line_map(int64_t nlines, int64_t inner, int64_t vinner, int W, int64_t* nblocks) {
+  LineMap m;
+  const int64_t lead = vinner - 1;
+  const auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (inner > vinner && W >= 1 && pow2(W) && lead >= W && lead % W == 0 && pow2(lead / W) && nlines % inner == 0 &&
+      nlines / inner <= (int64_t)UINT32_MAX / 2) {
+    m.on = 1;
+    m.lw = __builtin_ctzll((unsigned long long)W);
+    m.lm = __builtin_ctzll((unsigned long long)(lead / W));
+    m.rows = (unsigned)(nlines / inner);
+    m.nlast = (unsigned)(((int64_t)m.rows + W - 1) / W);
+    *nblocks = (int64_t)m.nlast + (int64_t)m.rows * (lead / W);
+  } else {
+    *nblocks = (nlines + W - 1) / W;
+  }
+  return m;
+}
+
+// row lq and x mode li of column c of tile t; false for padding and for lines past the last row
+__device__ __forceinline__ bool tile_lines(const LineMap& m, unsigned t, int c, int W, unsigned inner,
+                                           unsigned vinner, int64_t nlines, unsigned& lq, unsigned& li) {
+  if (m.on) {
+    if (t < m.nlast) {   // last x modes: strided rows, slower per tile, so dispatched first
+      lq = (t << m.lw) + (unsigned)c;
+      li = vinner - 1;
+      return lq < m.rows;
+    }
+    t -= m.nlast;
+    lq = t >> m.lm;
+    li = ((t & ((1u << m.lm) - 1u)) << m.lw) + (unsigned)c;
+    return true;
+  }
+  const unsigned l = t * (unsigned)W + (unsigned)c;
+  lq = l / inner;
+  li = l - lq * inner;
+  return l < nlines && li < vinner;
+}
+
 // ------------------------------------------------------------------ strided in-place C2C
 template <typename T, int N, bool INV, int RX = rmax_t<T>(N)>
 __global__ __launch_bounds__(kLineBlock) void k_strided(cplx<T>* __restrict__ data, int64_t nlines, int64_t inner,
@@ -608,12 +654,13 @@ __global__ __launch_bounds__(kBlock) void k_fused(cplx<T>* __restrict__ data, in
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
   const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = (int)tile_of_block<C>(W) * W + c;
-  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
+  unsigned lq_, li_;   // row and x mode of this thread's line; padding lines are skipped
+  const bool valid = tile_lines(md.map, tile_of_block<C>(W), c, W, (unsigned)md.nxp, (unsigned)md.nxh, P, lq_, li_);
+  const int l = (int)(lq_ * (unsigned)md.nxp + li_);
   const int64_t FS = P * N;
   // mode indices of this line: 2-D l = jx (+ nxp k1 with a split), e = jy; 3-D l = jy*nxh + jx, e = jz
-  const int jx = (int)(valid ? l % md.nxp : 0);
-  const int jy2 = (int)(valid ? l / md.nxp : 0);
+  const int jx = (int)(valid ? li_ : 0u);
+  const int jy2 = (int)(valid ? lq_ : 0u);
   const bool d3 = md.dim == 3;
   const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);   // symbols along the line
@@ -740,11 +787,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_stokes2(cplx<T>* __restrict__ 
   const int tid = threadIdx.x;
   const int tws = SPLIT ? md.split : 1;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = (int)tile_of_block<C>(W) * W + c;
-  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
+  unsigned lq_, li_;   // row and x mode of this thread's line; padding lines are skipped
+  const bool valid = tile_lines(md.map, tile_of_block<C>(W), c, W, (unsigned)md.nxp, (unsigned)md.nxh, P, lq_, li_);
+  const int l = (int)(lq_ * (unsigned)md.nxp + li_);
   const int64_t FS = P * N;
-  const int jx = (int)(valid ? l % md.nxp : 0);
-  const int jy2 = (int)(valid ? l / md.nxp : 0);
+  const int jx = (int)(valid ? li_ : 0u);
+  const int jy2 = (int)(valid ? lq_ : 0u);
   const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[1]);
   const T* ktl_ = static_cast<const T*>(md.kt[1]);
@@ -808,10 +856,11 @@ __global__ __launch_bounds__(kLineBlock) void k_fused1(cplx<T>* __restrict__ dat
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
   const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = (int)tile_of_block<C>(W) * W + c;
-  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
-  const int jx = (int)(valid ? l % md.nxp : 0);
-  const int jy2 = (int)(valid ? l / md.nxp : 0);
+  unsigned lq_, li_;   // row and x mode of this thread's line; padding lines are skipped
+  const bool valid = tile_lines(md.map, tile_of_block<C>(W), c, W, (unsigned)md.nxp, (unsigned)md.nxh, P, lq_, li_);
+  const int l = (int)(lq_ * (unsigned)md.nxp + li_);
+  const int jx = (int)(valid ? li_ : 0u);
+  const int jy2 = (int)(valid ? lq_ : 0u);
   const bool d3 = md.dim == 3;
   const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
@@ -849,11 +898,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_adj(cplx<T>* __restrict__ data
   const C* tw = TC::TWL ? stage_table(lds + N * W, twg, N, tid, W * TC::T_, tws) : twg;
   const int ltws = TC::TWL ? 1 : tws;
   const int c = tid & (W - 1), i = tid / W;
-  const int l = (int)tile_of_block<C>(W) * W + c;
-  const bool valid = l < P && (l % md.nxp) < md.nxh;   // pitch padding lines are skipped
+  unsigned lq_, li_;   // row and x mode of this thread's line; padding lines are skipped
+  const bool valid = tile_lines(md.map, tile_of_block<C>(W), c, W, (unsigned)md.nxp, (unsigned)md.nxh, P, lq_, li_);
+  const int l = (int)(lq_ * (unsigned)md.nxp + li_);
   const int64_t FS = P * N;
-  const int jx = (int)(valid ? l % md.nxp : 0);
-  const int jy2 = (int)(valid ? l / md.nxp : 0);
+  const int jx = (int)(valid ? li_ : 0u);
+  const int jy2 = (int)(valid ? lq_ : 0u);
   const bool d3 = md.dim == 3;
   const LineGeo<N, SPLIT> lg(md, l, P, jx, jy2);
   const T* sgl = static_cast<const T*>(md.sig[d3 ? 2 : 1]);
@@ -1081,10 +1131,16 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
   dispatch_n(n, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     // launch shape of a kernel whose tile configuration is TC: lines per block, grid, LDS
+    MultDesc mdl = md;   // with the tile map of the chosen width
+    auto tiles = [&](int W) {
+      int64_t nb = 0;
+      mdl.map = line_map(P, md.nxp, md.nxh, W, &nb);
+      return dim3((unsigned)nb, (unsigned)batch);
+    };
     auto shape = [&](auto tc, int& W, dim3& grid, dim3& blk, size_t& lds) {
       using TC = decltype(tc);
       W = pick(w, TC::W);
-      grid = dim3((unsigned)((P + W - 1) / W), (unsigned)batch);
+      grid = tiles(W);
       blk = dim3(W * TC::T_);
       lds = sizeof(cplx<T>) * (N * W + (TC::TWL ? N : 0));
     };
@@ -1093,6 +1149,7 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       int W = 0;
       dim3 grid, blk;
       size_t lds = 0;
+      const MultDesc& md = mdl;
       if (md.mode == 1 && md.nc == 1 && no >= 1 && no <= md.dim + 1) {
         shape(TileCfg<T, N, fused_rmax<T>(N, 1)>{}, W, grid, blk, lds);
         hipLaunchKernelGGL((k_fused_adj<T, N, 1, 1, SP>), grid, blk, lds, s, data, P, no, md, tw, W, bstride, rm);
@@ -1119,7 +1176,7 @@ void fft_fused_last(cplx<T>* data, int n, int64_t P, int no, const MultDesc& md,
       } else if (md.stokes && no == 2 && md.dim == 2 && md.nc <= kStokesFields) {
         using SC = StokesCfg<T, N>;
         W = pick(w, SC::W);
-        grid = dim3((unsigned)((P + W - 1) / W), (unsigned)batch);
+        grid = tiles(W);
         blk = dim3(W * SC::T_);
         lds = sizeof(cplx<T>) * (size_t)kStokesFields * N * W;
         hipLaunchKernelGGL((k_fused_stokes2<T, N, SP>), grid, blk, lds, s, data, P, md, tw, W, bstride, rm);

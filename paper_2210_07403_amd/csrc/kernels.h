@@ -69,6 +69,15 @@ struct RowMask {
   __device__ bool keep_out(int y) const { return !store || (y >= lo && y <= hi); }
 };
 
+// Assignment of tiles of W lines to the lines of a last-axis pass (set by fft_fused_last):
+// on = 0, tile t holds lines t W .. t W + W - 1; on = 1, the first nlast tiles hold the last x mode
+// of W consecutive rows (rows in all) and the others W consecutive x modes below the last of one row
+// (2^lm tiles per row, W = 2^lw)
+struct LineMap {
+  int on = 0, lw = 0, lm = 0;
+  unsigned nlast = 0, rows = 0;
+};
+
 struct MultDesc {
   int mode;         // 0: forward multiplier; 1: scalar gradient outputs; 2: transposed Stokes;
                     // 3: Stokes pressure
@@ -85,6 +94,7 @@ struct MultDesc {
   const void* sig[3];  // per-axis Laplacian symbol components (grid type)
   const void* kt[3];   // per-axis derivative symbols k~ (grid type)
   int split;           // 2-D lines of a four-step y transform: N1 > 1 (set by fft_fused_last); 0 or 1: none
+  LineMap map;         // tiles -> lines (set by fft_fused_last)
 };
 
 // Tunable launch shapes: rpb = rows per block of the x passes, w = lines per block of the strided
