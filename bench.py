@@ -91,7 +91,31 @@ def stage_cost(spec, prec, pr):
     else:
         flops = spec.n_ib * taps * c * spec.dim
     b["spread"] = ("mfma", flops)
+    if spec.dim == 3 and scalar_fd:
+        # its bytes: each marker's weight row (24 (W, G) pairs), density, normal and spacing, each
+        # candidate pair's list entry and window offsets, the busy tiles written; below the matrix
+        # ridge (flop per byte) the roofline that bounds it is the HBM one
+        nbusy, _, tile = pr.spread_tiles()
+        sb = spec.n_ib * (24 * 2 * t + 8 + 8 * spec.dim + 8) + 8 * candidate_pairs(spec, tile) + nbusy * 512 * t
+        ridge = MATRIX_PEAK_TFLOPS[prec] * 1e12 / (HBM_PEAK_GBS * 1e9)
+        if flops / sb < ridge:
+            b["spread"] = ("hbm", sb)
     return b
+
+
+def candidate_pairs(spec, tile):
+    """(tile, marker) pairs of the spread: the tiles each marker's 6-node window meets, counted on
+    the host from the window starts floor((X - origin) / h) - 2 (periodic)."""
+    import numpy as np
+    n = np.asarray(spec.n)
+    h = spec.L[0] / spec.n[0]
+    xi = (np.asarray(spec.markers.X, dtype=np.float64) - np.asarray(spec.origin)) / h
+    s = (np.floor(xi).astype(np.int64) - 2) % n
+    count = np.ones(len(s), dtype=np.int64)
+    for d in range(spec.dim):
+        tiles = np.sort(((s[:, d:d + 1] + np.arange(6)) % n[d]) // tile[d], axis=1)
+        count *= 1 + (np.diff(tiles, axis=1) != 0).sum(axis=1)
+    return int(count.sum())
 
 
 def model_bytes(spec, prec, pr):
