@@ -1,5 +1,5 @@
-"""Host-side arithmetic of bench.py's roofline figures (no GPU): the spread's candidate pair count
-against a brute-force count of the tiles each marker's 6-node window meets."""
+"""Host-side parts of bench.py (no GPU): the spread's candidate pair count against a brute-force
+count of the tiles each marker's 6-node window meets, and the refusal of more than one GPU."""
 import numpy as np
 
 import bench
@@ -35,3 +35,15 @@ def test_candidate_pairs_match_brute_force():
                          "dirichlet", 0.0, "peskin4", "fd2", mk, np.zeros(300), None)
     tile = (16, 4, 8)
     assert bench.candidate_pairs(spec, tile) == _brute_pairs(spec, tile)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits non-zero with a message, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
